@@ -1,0 +1,88 @@
+"""Reduced 2x2 BdG operator of the spin-symmetric problem (paper Sec. 2.3,
+Eq. HpsiEpsi) with the A_sigma = 1 single-particle Hamiltonian
+(Eq. h_sigma_A1): h = -1/2 nabla^2 + U + V_ext.
+
+    H (u, v) = ( (h - mu) u + Delta v ,  Delta^* u - (h - mu)^* v )
+
+For real U and V_ext, (h - mu)^* = h - mu.  The field hfield = U + V_ext - mu
+is passed as one real array.
+"""
+import numpy as np
+from . import lattice as L
+
+
+def apply_h(phi, hfield, delta, lat):
+    """H applied to every state of phi (shape (n, 2, nx, ny, nz)), with the
+    spectral Laplacian (Eq. derivative-spectral, full -k^2)."""
+    u, v = phi[:, 0], phi[:, 1]
+    lap_u = L.laplacian(u, lat)
+    lap_v = L.laplacian(v, lat)
+    hu = -0.5 * lap_u + hfield * u + delta * v
+    hv = np.conj(delta) * u - (-0.5 * lap_v + hfield * v)
+    return np.stack([hu, hv], axis=1)
+
+
+def dense_h(hfield, delta, lat):
+    """2M x 2M matrix of H in the ordering (u, v), built from the dense
+    derivative matrices of Eq. D2 and diagonal matrices for the local
+    fields (Sec. 3.2, matrix form of local fields)."""
+    K = -0.5 * L.dense_laplacian(lat)
+    h = K + np.diag(np.ravel(hfield))
+    d = np.diag(np.ravel(delta))
+    return np.block([[h, d], [np.conj(d), -h]])
+
+
+def eigenstates(hfield, delta, lat):
+    """Diagonalise the dense H.  Returns (E, phi) with E ascending and phi of
+    shape (2M, 2, nx, ny, nz), normalised so int (|u|^2+|v|^2) dV = 1."""
+    H = dense_h(hfield, delta, lat)
+    E, W = np.linalg.eigh(H)
+    M = lat.M
+    phi = W.T.reshape((2 * M, 2) + lat.shape) / np.sqrt(lat.dV)
+    return E, phi
+
+
+def plane_wave_states(lat, kidx, hshift, delta0):
+    """Eigenstates of the uniform H (constant U, Delta): for lattice momentum
+    k, xi = k^2/2 + hshift with hshift = U - mu, E = sqrt(xi^2 + |Delta|^2),
+    positive branch u = sqrt((1 + xi/E)/2), v = sqrt((1 - xi/E)/2) Delta^*/|Delta|,
+    times exp(i k.r)/sqrt(V) with r measured from the lattice corner.
+
+    kidx: integer array (n, 3) of k-grid indices.  Returns (E, phi)."""
+    kidx = np.asarray(kidx)
+    kx = lat.k[0][kidx[:, 0]]
+    ky = lat.k[1][kidx[:, 1]]
+    kz = lat.k[2][kidx[:, 2]]
+    xi = 0.5 * (kx ** 2 + ky ** 2 + kz ** 2) + hshift
+    ad = abs(delta0)
+    E = np.sqrt(xi ** 2 + ad ** 2)
+    uk = np.sqrt(0.5 * (1.0 + xi / E))
+    vk = np.sqrt(0.5 * (1.0 - xi / E)) * (np.conj(delta0) / ad if ad > 0 else 1.0)
+    rx = np.arange(lat.n[0]) * lat.d[0]
+    ry = np.arange(lat.n[1]) * lat.d[1]
+    rz = np.arange(lat.n[2]) * lat.d[2]
+    ph = (np.exp(1j * kx[:, None, None, None] * rx[None, :, None, None])
+          * np.exp(1j * ky[:, None, None, None] * ry[None, None, :, None])
+          * np.exp(1j * kz[:, None, None, None] * rz[None, None, None, :])) / np.sqrt(lat.V)
+    phi = np.stack([uk[:, None, None, None] * ph, vk[:, None, None, None] * ph], axis=1)
+    return E, phi
+
+
+def vortex_phase(lat, vortices):
+    """Phase field theta(x, y) = sum_j q_j atan2(y - y_j, x - x_j) of straight
+    vortex lines along z, in centred coordinates.  vortices: list of
+    (x_j, y_j, q_j)."""
+    X, Y, _ = lat.coords()
+    th = np.zeros(lat.shape)
+    for (x0, y0, q) in vortices:
+        th += q * np.arctan2(Y - y0, X - x0)
+    return th
+
+
+def imprint_phase(phi, theta):
+    """u_n <- exp(i theta) u_n for every state, v unchanged.  Reading of the
+    vortex imprint: Delta is derived from the states in TD, so the phase is
+    put on u, which multiplies nu and hence Delta by exp(i theta)."""
+    out = phi.copy()
+    out[:, 0] = np.exp(1j * theta) * phi[:, 0]
+    return out

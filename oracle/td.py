@@ -1,0 +1,204 @@
+"""Time integration of the TDSLDA equations (paper Sec. 3.3).
+
+Equation of motion with the instantaneous-energy shift (Eqs.
+shorttdproblem-mod and ABM-f):
+
+    d phi_n / dt = f(phi)_n = -i [ H(phi) - <H>_n ] phi_n,
+    <H>_n = int phi_n^dagger H(phi) phi_n dV,
+
+where H(phi) is built from the densities of all states.  Integrators:
+AB3AM4, AB4AM5 and AB5AM5 (Eqs. AB3-AB5, AM4-AM5) in the memory schedule of
+Alg. AB4AM5, started either from a stationary history or by the Taylor
+predictor-corrector of Eq. Taylor-exp.
+"""
+import numpy as np
+from math import factorial
+
+from . import bdg
+from . import densities as D
+from . import functional as F
+
+# Adams-Bashforth predictors (Eqs. AB3, AB4, AB5): weights of f_{k-1}, f_{k-2}, ...
+AB = {
+    3: np.array([23.0, -16.0, 5.0]) / 12.0,
+    4: np.array([55.0, -59.0, 37.0, -9.0]) / 24.0,
+    5: np.array([1901.0, -2774.0, 2616.0, -1274.0, 251.0]) / 720.0,
+}
+# Adams-Moulton correctors (Eqs. AM4, AM5): weights of f(phi^p), f_{k-1}, f_{k-2}, ...
+AM = {
+    4: np.array([9.0, 19.0, -5.0, 1.0]) / 24.0,
+    5: np.array([251.0, 646.0, -264.0, 106.0, -19.0]) / 720.0,
+}
+SCHEMES = {"AB3AM4": (3, 4), "AB4AM5": (4, 5), "AB5AM5": (5, 5)}
+
+
+def history_depth(scheme):
+    """Number of stored f buffers: AB5AM5 keeps five, AB4AM5 four, AB3AM4
+    three (Sec. 3.3), plus the buffer of phi itself."""
+    p, c = SCHEMES[scheme]
+    return max(len(AB[p]), len(AM[c]) - 1)
+
+
+class Geometry3D:
+    """Full 3D mode: states live on the whole lattice."""
+
+    def __init__(self, lat):
+        self.lat = lat
+        self.dV = lat.dV          # measure of the state normalisation
+        self.dV_energy = lat.dV   # measure of energy / particle-number integrals
+        self.shape = lat.shape
+
+    def apply_h(self, phi, hfield, delta):
+        return bdg.apply_h(phi, hfield, delta, self.lat)
+
+    def rho_nu(self, phi, wu, wv):
+        return D.local_densities(phi, wu, wv)
+
+    def full_densities(self, phi, wu, wv):
+        return D.spin_symmetric(phi, wu, wv, self.lat)
+
+
+class TDSystem:
+    """Everything the right-hand side f needs besides the states.
+
+    mu: chemical potential (fixed in TD); vext: external potential (static
+    after t=0); lam: frozen regulator Lambda_c(r) (reading: computed once,
+    never refreshed, so that U is the exact derivative of the energy);
+    wu, wv: frozen thermal weights f(E_n), f(-E_n) (Sec. 2.5).
+    frozen=(hfield, delta) switches to linear mode (fields not rebuilt)."""
+
+    def __init__(self, geom, fun, mu, vext, lam, wu, wv, frozen=None):
+        self.geom, self.fun, self.mu = geom, fun, float(mu)
+        self.vext = np.asarray(vext, float)
+        self.lam = np.asarray(lam, float)
+        self.wu = np.asarray(wu, float)
+        self.wv = np.asarray(wv, float)
+        self.frozen = frozen
+        self.n_f_evals = 0
+
+    def fields(self, phi):
+        """Densities -> potentials -> (hfield = U + V_ext - mu, Delta)."""
+        if self.frozen is not None:
+            return self.frozen
+        rho, nu = self.geom.rho_nu(phi, self.wu, self.wv)
+        U, delta, _ = F.potentials(rho, nu, self.lam, self.fun)
+        return U + self.vext - self.mu, delta
+
+    def expect(self, phi, hphi):
+        ax = tuple(range(1, phi.ndim))
+        return self.geom.dV * np.real(np.sum(np.conj(phi) * hphi, axis=ax))
+
+    def f(self, phi):
+        """f(phi) of Eq. ABM-f for normalised phi."""
+        self.n_f_evals += 1
+        hf, de = self.fields(phi)
+        hphi = self.geom.apply_h(phi, hf, de)
+        e = self.expect(phi, hphi)
+        return -1j * (hphi - _bc(e, phi) * phi)
+
+    def normalize(self, phi):
+        return D.normalize(phi, self.geom.dV)
+
+
+def _bc(x, phi):
+    return np.asarray(x).reshape((-1,) + (1,) * (phi.ndim - 1))
+
+
+def abm_step(sys, phi, hist, dt, scheme="AB4AM5"):
+    """One step of the predictor-corrector in the order of Alg. AB4AM5
+    (the AB3AM4 and AB5AM5 variants follow the same pattern):
+
+      p   = phi + dt * sum_j b_j f_{k-j}                      (predictor)
+      c   = phi + dt * sum_{j>=1} a_j f_{k-j}                 (corrector part)
+      p  <- p / |p|;  phi_new = c + dt a_0 f(p)
+      phi_new <- phi_new / |phi_new|;  f_k = f(phi_new)
+
+    hist[0] = f_{k-1}, hist[1] = f_{k-2}, ...  Returns (phi_new, hist)."""
+    pb, cb = SCHEMES[scheme]
+    b, a = AB[pb], AM[cb]
+    p = phi + dt * sum(b[j] * hist[j] for j in range(len(b)))
+    c = phi + dt * sum(a[j + 1] * hist[j] for j in range(len(a) - 1))
+    p = sys.normalize(p)
+    phi_new = c + dt * a[0] * sys.f(p)
+    phi_new = sys.normalize(phi_new)
+    fk = sys.f(phi_new)
+    return phi_new, [fk] + list(hist[:-1])
+
+
+def taylor_apply(sys, phi, fields, shift, tau, r):
+    """sum_{k=0}^{r} (-i tau)^k / k! (H - shift)^k phi with H fixed by fields."""
+    hf, de = fields
+    term = phi
+    out = phi.copy()
+    for k in range(1, r + 1):
+        hterm = sys.geom.apply_h(term, hf, de) - _bc(shift, phi) * term
+        term = (-1j * tau / k) * hterm
+        out = out + term
+    return out
+
+
+def taylor_step(sys, phi, dt, r=5):
+    """One start-up step by the Taylor predictor-corrector of Eq. Taylor-exp.
+
+    Readings where the paper is silent: the operator is the shifted one,
+    H - <H>_n, with <H>_n taken on the state the H is built from (phi at t
+    for the half step, the mid-point state for the full step), so the start
+    matches the phases of the shifted ABM trajectory; both the mid-point and
+    the end state are renormalised, as the ABM steps are."""
+    fl = sys.fields(phi)
+    e0 = sys.expect(phi, sys.geom.apply_h(phi, *fl))
+    phim = sys.normalize(taylor_apply(sys, phi, fl, e0, 0.5 * dt, r))
+    flm = sys.fields(phim)
+    em = sys.expect(phim, sys.geom.apply_h(phim, *flm))
+    return sys.normalize(taylor_apply(sys, phi, flm, em, dt, r))
+
+
+def start(sys, phi0, dt, scheme="AB4AM5", selfstart=1, r=5):
+    """Initialise the multistep history.
+
+    selfstart = 0: the states are taken as stationary, every history slot
+    holds f(phi_0) (zero for an exact stationary state).
+    selfstart = 1: Hd - 1 Taylor steps (Hd = history depth: 3 for AB4AM5)
+    give phi_1 ... phi_{Hd-1}; the history is f of those states.
+    Returns (phi, hist, n_startup_steps)."""
+    hd = history_depth(scheme)
+    phi0 = sys.normalize(phi0)
+    if selfstart == 0:
+        f0 = sys.f(phi0)
+        return phi0, [f0] * hd, 0
+    phis = [phi0]
+    for _ in range(hd - 1):
+        phis.append(taylor_step(sys, phis[-1], dt, r))
+    hist = [sys.f(p) for p in reversed(phis)]
+    return phis[-1], hist, hd - 1
+
+
+def evolve(sys, phi0, dt, nsteps, scheme="AB4AM5", selfstart=1, r=5, callback=None):
+    """Start-up followed by nsteps ABM steps.  callback(step, phi) is called
+    after every step.  Returns the final states."""
+    phi, hist, _ = start(sys, phi0, dt, scheme, selfstart, r)
+    for s in range(nsteps):
+        phi, hist = abm_step(sys, phi, hist, dt, scheme)
+        if callback is not None:
+            callback(s + 1, phi)
+    return phi
+
+
+def observables(sys, phi):
+    """Energy terms of Sec. 3.2, particle number N = int rho_+ dV and the
+    free-gas normalisation E_FG = 3/5 N eF of the uniform system with the
+    same mean density."""
+    g = sys.geom
+    rho, tau, nu, j = g.full_densities(phi, sys.wu, sys.wv)
+    terms = F.energy_terms(rho, tau, j, nu, sys.lam, sys.vext, sys.fun, g.dV_energy)
+    N = g.dV_energy * np.sum(2.0 * rho)
+    vol = g.dV_energy * np.prod(rho.shape)
+    terms["N"] = N
+    terms["EFG"] = 0.6 * N * F.eF(N / vol)
+    return terms
+
+
+def gram(phi, dV):
+    """Overlap matrix int phi_n^dagger phi_m dV."""
+    A = phi.reshape(phi.shape[0], -1)
+    return dV * (np.conj(A) @ A.T)
