@@ -1,0 +1,199 @@
+"""Benchmark of the TDSLDA step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-mixed] [--no-cpu]
+
+One step = one AB4AM5 step (two right-hand-side evaluations, each with a
+full density rebuild) of every evolved state.  The default workload is the
+plain FP64 32^3 trapped gas with one vortex (32,768 evolved states, 65,536
+represented); the FP32-mixed 48^3 run (8,192 evolved states) is reported in
+the same JSON line under "fp32_mixed".  value = evolved states x steps /
+wall time of the timed region (inputs resident in HBM, start-up excluded).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM = 8.0e12  # MI355X HBM3E, bytes/s
+
+
+def algorithmic_bytes(kernel, S, nst, depth):
+    """Bytes a launch of each kernel must move for nst states of S bytes
+    (its inputs read once and outputs written once)."""
+    table = {
+        "dens": 1, "lap1": 2, "lap2_corr": 4, "lap2_f": 3, "lap2_h": 3,
+        "lap2_full": 2 + (depth - 1) + 3,   # phi, T, f_{k-1..k-D+1}; f_k, p, c
+        "pred": 1 + depth + 2,              # phi, f_{k-1..k-D}; p, c
+        "lap2_taylor": 4, "norm": 1,
+    }
+    return table[kernel] * S * nst if kernel in table else None
+
+
+def run_workload(cfg, steps, warmup, seed_vortex, profile=True):
+    import torch
+    from paper_2602_08982_amd import tdslda as T
+    from paper_2602_08982_amd import workloads as W
+    import synth
+
+    if cfg["name"].startswith("plain"):
+        dx, dy = synth.vortex_offset(seed_vortex)
+        vort = [(dx, dy, 1.0)]
+    else:
+        (x1, y1), (x2, y2) = synth.vortex_pair(seed_vortex)
+        vort = [(x1, y1, 1.0), (x2, y2, -1.0)]
+    stream = torch.cuda.current_stream().cuda_stream
+    ctx, kidx = W.setup(cfg, vort, stream=stream)
+    nst = len(kidx)
+    t0 = time.time()
+    ctx.abm_step(warmup)          # includes the Taylor start-up
+    torch.cuda.synchronize()
+    t_warm = time.time() - t0
+    if profile:
+        ctx.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.abm_step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    stats = ctx.kernel_stats() if profile else {}
+    if profile:
+        ctx.set_profiling(False)
+    st, chk = ctx.check()
+    M = int(np.prod(cfg["n"]))
+    es = 16 if cfg["precision"] == T.FP64 else 8
+    S = 2 * M * es
+    depth = 4
+    kern = {}
+    for k, (n, ms) in stats.items():
+        if n == 0:
+            continue
+        b = algorithmic_bytes(k, S, nst, depth)
+        avg = ms / n
+        kern[k] = dict(launches=n, avg_ms=avg, total_ms=ms,
+                       gbps=(b / (avg * 1e-3) / 1e9) if b else None)
+    ctx.close()
+    del ctx
+    return dict(nst=nst, seconds=dt, warm_seconds=t_warm, value=nst * steps / dt,
+                ms_per_step=1e3 * dt / steps, kernels=kern, check=dict(status=st, **chk), S=S,
+                vortices=vort)
+
+
+def roofline(res):
+    kern = res["kernels"]
+    if not kern:
+        return None
+    dom = max(kern, key=lambda k: kern[k]["total_ms"])
+    g = kern[dom]["gbps"]
+    return dict(bound="hbm", kernel=dom, achieved=g, peak=PEAK_HBM / 1e9, unit="GB/s",
+                frac=(g * 1e9 / PEAK_HBM) if g else None, traffic=None,
+                share_of_step=kern[dom]["total_ms"] / (res["ms_per_step"] * res["steps"]))
+
+
+def cpu_baseline(nsample=64, steps=2):
+    """The FP64 oracle on a bounded sample of the same workload: nsample
+    plane-wave states of the 32^3 trapped gas (trap + vortex), stationary
+    start (one f evaluation), then `steps` AB4AM5 steps; the rate is
+    nsample * steps / time of those steps."""
+    import scipy.fft
+    from oracle import lattice as L, bdg, functional as F, td
+    from paper_2602_08982_amd import workloads as W
+    import synth
+    cfg = W.PLAIN
+    lat = L.Lattice(*cfg["n"])
+    kidx = W.all_kidx(cfg["n"])
+    rng = synth.rng(5)
+    sel = np.sort(rng.choice(len(kidx), size=nsample, replace=False))
+    E, phi = bdg.plane_wave_states(lat, kidx[sel], cfg["u0"] - cfg["mu"], cfg["delta0"])
+    dx, dy = synth.vortex_offset(2)
+    phi = bdg.imprint_phase(phi, bdg.vortex_phase(lat, [(dx, dy, 1.0)]))
+    vext = W.harmonic(cfg["n"], cfg["d"], cfg["omega"])
+    lam = F.lambda_c(vext, cfg["mu"], 0.5 * np.pi ** 2)
+    sysm = td.TDSystem(td.Geometry3D(lat), F.Functional(F.SLDA), cfg["mu"], vext, lam,
+                       F.fermi_weight(E), F.fermi_weight(-E))
+    p, hist, _ = td.start(sysm, phi, cfg["dt"], "AB4AM5", selfstart=0)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        p, hist = td.abm_step(sysm, p, hist, cfg["dt"])
+    dt = time.perf_counter() - t0
+    cores = os.cpu_count()
+    return dict(value=nsample * steps / dt, unit="state-steps/s", cores=cores, kind="oracle",
+                sample=f"{nsample} of 32768 states of the 32^3 FP64 workload, {steps} AB4AM5 steps "
+                       f"after a stationary start; scipy.fft workers={scipy.fft.get_workers()} (all "
+                       f"{cores} host threads)", seconds=dt)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--seed", type=int, default=2)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU; the multi-GPU (state-sharded, "
+              "density all-reduce) path is a design, not code here.", file=sys.stderr)
+        sys.exit(2)
+    if args.warmup < 1:
+        args.warmup = 1
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    from paper_2602_08982_amd import tdslda as T
+    from paper_2602_08982_amd import workloads as W
+    T.load_library()
+
+    plain = run_workload(W.PLAIN, args.steps, args.warmup, args.seed)
+    plain["steps"] = args.steps
+    print(f"# plain fp64 32^3: {plain['value']:.4g} state-steps/s, {plain['ms_per_step']:.2f} ms/step",
+          file=sys.stderr, flush=True)
+    mixed = None
+    if not args.no_mixed:
+        mixed = run_workload(W.MIXED, args.steps, args.warmup, 4)
+        mixed["steps"] = args.steps
+        print(f"# mixed fp32 48^3: {mixed['value']:.4g} state-steps/s, {mixed['ms_per_step']:.2f} ms/step",
+              file=sys.stderr, flush=True)
+    cpu = None if args.no_cpu else cpu_baseline()
+
+    line = {
+        "metric": "TDSLDA quasiparticle state-steps/s + %HBM roofline, FP32-mixed vs FP64",
+        "value": plain["value"],
+        "unit": "state-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": plain["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "plain FP64 32^3 trapped gas, one vortex (AB4AM5, dt=0.005)",
+                   "lattice": [32, 32, 32], "states_evolved": plain["nst"],
+                   "states_represented": 2 * plain["nst"], "integrator": "AB4AM5"},
+        "roofline": roofline(plain),
+        "cpu_baseline": cpu,
+        "kernels": plain["kernels"],
+        "check": plain["check"],
+    }
+    if mixed is not None:
+        line["fp32_mixed"] = {
+            "workload": "FP32-mixed 48^3 elongated trap, vortex pair, 8192 lowest-|E| states",
+            "value": mixed["value"], "unit": "state-steps/s", "ms_per_step": mixed["ms_per_step"],
+            "dtype": "f32 states / f64 sums", "roofline": roofline(mixed), "kernels": mixed["kernels"],
+            "check": mixed["check"],
+        }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

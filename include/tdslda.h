@@ -1,0 +1,201 @@
+/*
+ * tdslda.h - C ABI of libtdslda, the MI355X (gfx950) implementation of the
+ * time-dependent superfluid local density approximation (TDSLDA) step of the
+ * W-SLDA Toolkit paper (arXiv 2602.08982).
+ *
+ * One step applies the lattice BdG Hamiltonian of the spin-symmetric reduced
+ * problem (Sec. 2.3, Eq. HpsiEpsi, with the A_sigma = 1 single-particle
+ * Hamiltonian of Eq. h_sigma_A1) to every quasiparticle state (u_n, v_n),
+ * with the kinetic term done spectrally (Sec. 3.1, Eq. derivative-spectral)
+ * and the mean field U(r) and pairing field Delta(r) applied pointwise;
+ * advances all states with the Adams-Bashforth-Moulton predictor-corrector of
+ * Sec. 3.3 (Alg. AB4AM5, Eqs. AB3-AM5) on the shifted equation of motion
+ * (Eq. ABM-f); and reduces over states to rebuild the densities
+ * (Eqs. nab3D-jab3D) that feed the next evaluation's mean fields.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Units hbar = m = k_B = 1 (Sec. 2.1).
+ *  - Lattice (Sec. 3.1): periodic, N_x x N_y x N_z sites, even sizes, spacing
+ *    dx, dy, dz; flat site index ixyz = (ix*N_y + iy)*N_z + iz (z fastest);
+ *    M = N_x N_y N_z.  Physical coordinates x = (ix - N_x/2) dx (centred).
+ *    Quasi-1D mode (Sec. 3.1, quasi-1D item): states live on the z axis only
+ *    (M = N_z), every state carries its transverse momentum squared
+ *    k_perp^2, and the transverse box is L_x x L_y.
+ *  - A state is (u_n, v_n) = (u_{n,a}, v_{n,b}); host arrays of states are
+ *    double precision, layout [n][2][M][2] (state, component u|v, site,
+ *    re|im).  States are normalised as int (|u|^2 + |v|^2) dV = 1.
+ *  - Only the E_n > 0 half of the spectrum is evolved (spin-symmetric
+ *    reduction, Sec. 2.3); weights f(E_n), f(-E_n) are frozen (Sec. 2.5).
+ *  - Host pointers are caller-owned and only read / written during the call.
+ *    Device pointers passed in are borrowed: the caller keeps them alive and
+ *    orders them on the context's stream.  The context owns everything it
+ *    allocates and frees it in tdslda_destroy.
+ *  - Every call returns a tdslda_status; on failure tdslda_last_error() gives
+ *    a context-owned message valid until the next call on that context.
+ *    No call throws across the ABI.  A context is not thread-safe; use one
+ *    context per stream.
+ */
+#ifndef TDSLDA_H
+#define TDSLDA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TDSLDA_OK = 0,
+  TDSLDA_EINVAL = -1,    /* bad argument, unsupported shape or option */
+  TDSLDA_ENOMEM = -2,    /* device allocation failed */
+  TDSLDA_EDEVICE = -3,   /* HIP runtime error */
+  TDSLDA_EORDER = -4,    /* call out of order (e.g. abm_step before load) */
+  TDSLDA_EUNSTABLE = -5  /* conservation or NaN check failed (Sec. 4.5.1) */
+} tdslda_status;
+
+enum { TDSLDA_MODE_3D = 3, TDSLDA_MODE_Q1D = 1 };
+enum { TDSLDA_FUNC_SLDA = 1, TDSLDA_FUNC_BDG = 2 };
+enum { TDSLDA_FP64 = 0, TDSLDA_FP32_MIXED = 1 };
+enum { TDSLDA_AB3AM4 = 34, TDSLDA_AB4AM5 = 45, TDSLDA_AB5AM5 = 55 };
+
+typedef struct tdslda_ctx tdslda_ctx;
+
+typedef struct {
+  int mode;             /* TDSLDA_MODE_3D or TDSLDA_MODE_Q1D */
+  int nx, ny, nz;       /* 3D: lattice sizes; Q1D: nx = ny = 1, nz = N_z */
+  double dx, dy, dz;    /* spacings (Q1D: dz only) */
+  double lx_perp, ly_perp; /* Q1D: transverse box L_x, L_y (densities carry 1/(L_x L_y)) */
+} tdslda_lattice;
+
+typedef struct {
+  int functional;       /* TDSLDA_FUNC_SLDA (Sec. 2.4, ASLDA at p=0) or TDSLDA_FUNC_BDG (Eq. HBdG) */
+  double A, B, C;       /* SLDA constants; the TD path requires A = 1 (Eq. h_sigma_A1) */
+  double inv_g_bdg;     /* BdG: 1/(4 pi a_s) */
+  double ec_reg;        /* cut-off energy E_c of the regulator Lambda_c (Eq. Creg) */
+  double mu;            /* chemical potential, fixed during TD */
+  double temperature;   /* T of the frozen weights f(E) = 1/(exp(E/T)+1); 0 = step */
+} tdslda_functional;
+
+typedef struct {
+  int precision;        /* TDSLDA_FP64 or TDSLDA_FP32_MIXED (states, transforms and H.psi
+                           in FP32; densities, norms, <H>_n, energy in FP64) */
+  int integrator;       /* TDSLDA_AB3AM4, TDSLDA_AB4AM5 (default), TDSLDA_AB5AM5 */
+  double dt;            /* time step (internal units) */
+  int selfstart;        /* 0: states stationary (every history slot = f(phi_0));
+                           1: Taylor predictor-corrector start-up (Eq. Taylor-exp) */
+  int taylor_order;     /* r of the Taylor start-up (0 selects 5) */
+  double tol_N, tol_E;  /* relative tolerances of the conservation check done by
+                           tdslda_check (<= 0 disables that check) */
+  void* hip_stream;     /* borrowed hipStream_t (NULL = the null stream) */
+} tdslda_run;
+
+/* Create a context for up to `capacity` evolved states and allocate its
+ * device buffers: (history depth + 1) state buffers plus one intermediate
+ * buffer (the x-derivative of every state), per-state scalars and the FP64
+ * fields.  Supported shapes: cubic N^3 with N in {4,6,8,12,16,24,32,48},
+ * 8x8x16 (3D); N_z in {16,32,64,128,256} (Q1D).  Errors: EINVAL, ENOMEM. */
+tdslda_status tdslda_create(const tdslda_lattice* lat, const tdslda_functional* fun,
+                            const tdslda_run* run, int64_t capacity, tdslda_ctx** out);
+tdslda_status tdslda_destroy(tdslda_ctx* ctx);
+const char* tdslda_last_error(const tdslda_ctx* ctx);
+
+/* Bytes of device memory tdslda_create would allocate for `nstates`
+ * (the td-memory estimate of Sec. 4.5.3, for this library's buffers). */
+tdslda_status tdslda_memory_plan(const tdslda_lattice* lat, const tdslda_run* run,
+                                 int64_t nstates, int64_t* bytes_out);
+
+/* External potential V_ext[M] (host, FP64), switched on from now on.  If
+ * freeze_regulator != 0 the regulator Lambda_c(r) of Eq. Creg is (re)computed
+ * from it with V_+ = V_ext and then kept frozen (the regulator is never
+ * refreshed during TD). */
+tdslda_status tdslda_set_external(tdslda_ctx* ctx, const double* vext, int freeze_regulator);
+/* Set the frozen regulator Lambda_c[M] directly (host, FP64). */
+tdslda_status tdslda_set_regulator(tdslda_ctx* ctx, const double* lam);
+
+/* Load n <= capacity states (host, [n][2][M][2] FP64, copied and rounded to
+ * the context precision) with their static quasiparticle energies E[n] (the
+ * frozen weights f(E), f(-E) are computed from them) and, in Q1D mode,
+ * kperp2[n] (else NULL).  Resets the integrator. */
+tdslda_status tdslda_load_states(tdslda_ctx* ctx, int64_t n, const double* uv, const double* E,
+                                 const double* kperp2);
+/* Same from a device array of the context precision ([n][2][M] complex of
+ * double or float, interleaved re/im), copied. */
+tdslda_status tdslda_load_states_device(tdslda_ctx* ctx, int64_t n, const void* uv_dev,
+                                        const double* E, const double* kperp2);
+
+/* Uniform-system start (Sec. 4.5.1 "uniform-system solution"): n plane-wave
+ * eigenstates of the uniform H with constant U = u0 and Delta = delta0
+ * (real, > 0) at momenta k = 2 pi m / L with integer triples kidx[n][3]
+ * (grid indices 0..N-1 of Sec. 3.1), generated on the device:
+ * u = sqrt((1 + xi/E)/2), v = sqrt((1 - xi/E)/2), xi = k^2/2 + u0 - mu,
+ * times exp(i k.r)/sqrt(V).  E_n of each state sets its frozen weights. */
+tdslda_status tdslda_init_plane_waves(tdslda_ctx* ctx, int64_t n, const int32_t* kidx,
+                                      double u0, double delta0);
+/* Vortex imprint on every loaded state: u_n <- exp(i theta(r)) u_n with
+ * theta = sum_j q_j atan2(y - y_j, x - x_j) (straight lines along z, centred
+ * coordinates).  xyq: [nv][3] host array of (x_j, y_j, q_j).  3D only. */
+tdslda_status tdslda_imprint_vortices(tdslda_ctx* ctx, int nv, const double* xyq);
+
+/* Freeze the mean fields (linear mode): U[M] and Delta[M][2] (host FP64) are
+ * used by every later H application and never rebuilt.  Pass NULLs to go
+ * back to self-consistent fields. */
+tdslda_status tdslda_set_fields(tdslda_ctx* ctx, const double* U, const double* delta_reim);
+
+/* Densities of the current states (Eqs. nab3D-jab3D, per spin component),
+ * FP64, host outputs (any may be NULL): rho[M], tau[M], nu[M][2], j[3][M].
+ * tau gives the Nyquist mode its full weight (pi/dx)^2 with the Nyquist
+ * momentum taken symmetrically; j uses the first derivative with the Nyquist
+ * mode zeroed (Sec. 3.1).  Also refreshes the mean fields from rho, nu
+ * unless they are frozen. */
+tdslda_status tdslda_densities(tdslda_ctx* ctx, double* rho, double* tau, double* nu_reim, double* j);
+/* Current mean fields (host FP64 out, any may be NULL): U[M], Delta[M][2]. */
+tdslda_status tdslda_get_fields(tdslda_ctx* ctx, double* U, double* delta_reim);
+
+/* H psi with the current fields, unshifted and unnormalised, for n states of
+ * device arrays in the context precision (layout as the loaded states).
+ * n <= capacity; in and out must not overlap.  Q1D: kperp2 of the loaded
+ * states with the same index is used. */
+tdslda_status tdslda_apply_hbdg(tdslda_ctx* ctx, const void* in_dev, void* out_dev, int64_t n);
+
+/* Advance the loaded states by nsteps steps of the selected ABM integrator.
+ * The first call after a load runs the start-up (selfstart), which is not
+ * counted in nsteps.  Errors: EORDER before any load. */
+tdslda_status tdslda_abm_step(tdslda_ctx* ctx, int64_t nsteps);
+
+/* Energy terms of Sec. 3.2 for the current states, host out[8]:
+ * {E_kin, E_pot, E_pair, E_curr, E_pot.ext, E_total, N, E_FG} with
+ * N = int rho_+ dV and E_FG = 3/5 N eF of the uniform gas of the same mean
+ * density.  Quasi-1D integrals include the transverse area. */
+tdslda_status tdslda_energy(tdslda_ctx* ctx, double terms_out[8]);
+
+/* Conservation check of Sec. 4.5.1 against the values at the first call
+ * after a load: returns EUNSTABLE if |N-N0|/N0 > tol_N, |E-E0|/E_FG > tol_E,
+ * or a state norm is not finite.  out[3] (may be NULL) = {dN/N0, dE/E_FG,
+ * max |norm - 1|}. */
+tdslda_status tdslda_check(tdslda_ctx* ctx, double out[3]);
+
+/* Copy the current normalised states to the host ([n][2][M][2] FP64). */
+tdslda_status tdslda_get_states(tdslda_ctx* ctx, double* uv);
+/* Current state count, steps taken since load, elapsed time. */
+tdslda_status tdslda_info(tdslda_ctx* ctx, int64_t* nstates, int64_t* steps, double* time);
+
+/* Checkpoint / resume (Sec. 4.5.1): states, integrator history, per-state
+ * scalars, weights, fields and the step counter, written raw in the context
+ * precision.  tdslda_load requires a context created with the same lattice,
+ * precision, integrator and capacity >= the saved state count. */
+tdslda_status tdslda_save(tdslda_ctx* ctx, const char* path);
+tdslda_status tdslda_load(tdslda_ctx* ctx, const char* path);
+
+/* Kernel timing.  With profiling on, every kernel launch is bracketed by HIP
+ * events on the context stream; tdslda_kernel_stats returns, for kernel class
+ * k (see tdslda_kernel_name), the launch count and the summed milliseconds
+ * since the last reset.  Returns EINVAL for k out of range. */
+tdslda_status tdslda_set_profiling(tdslda_ctx* ctx, int enable);
+tdslda_status tdslda_kernel_stats(tdslda_ctx* ctx, int k, int64_t* launches, double* total_ms);
+const char* tdslda_kernel_name(int k); /* NULL past the last class */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TDSLDA_H */

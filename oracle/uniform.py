@@ -3,7 +3,7 @@ self-consistent uniform state on a periodic lattice.
 
 Both are scalar problems; they serve as pins for the lattice machinery and
 as plane-wave starting points (the paper's uniform-system solution used to
-start TD runs quickly, Sec. 4.3).
+start TD runs quickly, Sec. 4.5.1).
 """
 import numpy as np
 from scipy import integrate, optimize

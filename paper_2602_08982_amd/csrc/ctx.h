@@ -1,0 +1,224 @@
+// Context of libtdslda and the per-shape kernel-set interface (shared by
+// the C-ABI translation unit and the engine instantiation units).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/tdslda.h"
+#include "kernels3d.h"
+
+namespace tdslda {
+
+// ----------------------------------------------------------------------------
+// kernel classes for the profiling counters
+enum KClass {
+  KC_DENS = 0, KC_REDUCE_POT, KC_LAP1, KC_FINALIZE, KC_LAP2_CORR, KC_LAP2_FULL, KC_LAP2_F,
+  KC_LAP2_H, KC_LAP2_TAYLOR, KC_PRED, KC_NORM, KC_GRAD, KC_ENERGY, KC_SETUP, KC_Q1D_FUSED,
+  KC_COUNT
+};
+inline const char* const kKernelNames[KC_COUNT] = {
+    "dens", "reduce_pot", "lap1", "finalize", "lap2_corr", "lap2_full", "lap2_f", "lap2_h",
+    "lap2_taylor", "pred", "norm", "grad", "energy", "setup", "q1d_fused"};
+
+struct Fail {
+  tdslda_status st;
+  std::string msg;
+};
+
+#define HIPCHK(x)                                                                      \
+  do {                                                                                 \
+    hipError_t e_ = (x);                                                               \
+    if (e_ != hipSuccess)                                                              \
+      throw Fail{TDSLDA_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_)};      \
+  } while (0)
+
+inline void require(bool ok, tdslda_status st, const std::string& msg) {
+  if (!ok) throw Fail{st, msg};
+}
+
+struct L2Desc {
+  int mode = L2_H;
+  const void* X = nullptr;
+  void* Xout = nullptr;
+  const void* T = nullptr;
+  const double* scale = nullptr;
+  const double* hshift = nullptr;
+  void* out = nullptr;
+  void* acc = nullptr;
+  const void* hist[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  void* cout = nullptr;
+  double* nrm_part = nullptr;
+  double tay_re = 0, tay_im = 0;
+  int init_acc = 0;
+};
+
+struct PwDesc {
+  int mode = PW_NORM;
+  void* X = nullptr;
+  const double* scale = nullptr;
+  const void* hist[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  void* cout = nullptr;
+  double* nrm_part = nullptr;
+  void* out64 = nullptr;
+};
+
+using Ctx = ::tdslda_ctx;
+
+// Per-shape / per-precision kernel set.
+struct Engine {
+  virtual ~Engine() = default;
+  virtual int ngx() const = 0;    // norm-partial slots per state (slab groups)
+  virtual int ncb() const = 0;    // lap1 column blocks per state
+  virtual int group() const = 0;  // states per density group
+  virtual void dens(Ctx& c, const void* X, const double* scale, int64_t nst) = 0;
+  virtual void reduce_pot(Ctx& c, bool update) = 0;
+  virtual void lap1(Ctx& c, const void* X, const double* scale, bool hpart, int64_t nst) = 0;
+  virtual void lap2(Ctx& c, const L2Desc& d, int64_t nst) = 0;
+  virtual void pointwise(Ctx& c, const PwDesc& d, int64_t nst) = 0;
+  virtual void grad(Ctx& c, const void* X, const double* scale, int64_t n0, int64_t nchunk) = 0;
+  virtual size_t elem_size() const = 0;
+};
+
+}  // namespace tdslda
+
+using namespace tdslda;
+
+struct tdslda_ctx {
+  tdslda_lattice lat{};
+  tdslda_functional fun{};
+  tdslda_run run{};
+  int q1d = 0;
+  int64_t M = 0, cap = 0, nst = 0;
+  double dV = 1, dVe = 1, vol = 1, ainv = 1;
+  hipStream_t stream = nullptr;
+  std::unique_ptr<Engine> eng;
+  size_t esz = 16;
+  int depth = 4, np = 4, nq = 5;
+  double bco[5] = {0}, aco[5] = {0};
+
+  // device memory
+  std::vector<void*> allocs;
+  void* sb[6] = {nullptr};
+  double* sscale[6] = {nullptr};
+  void* T = nullptr;
+  double *wu = nullptr, *wv = nullptr, *E = nullptr, *kperp2 = nullptr;
+  double *nrm_part = nullptr, *h_part = nullptr, *hshift = nullptr;
+  int nrm_stride = 1, h_stride = 1;
+  double* dens_part = nullptr;
+  int nsg_max = 1, nsg_used = 1;
+  double *rho = nullptr, *nu = nullptr, *tau = nullptr, *jc = nullptr;
+  double *U = nullptr, *delta = nullptr, *vext = nullptr, *lam = nullptr, *theta = nullptr;
+  void *hA = nullptr, *hD = nullptr;
+  double* gscratch = nullptr;  // [gchunk][4][M] doubles (tau_s, j_s); also FP64 staging
+  int64_t gchunk = 1;
+  double* eout = nullptr;
+  int* dflag = nullptr;
+  int32_t* kidx_dev = nullptr;
+  int64_t kidx_cap = 0;
+
+  // integrator state
+  int phi = 0;
+  int hist[5] = {1, 2, 3, 4, 5};
+  bool loaded = false, started = false, frozen = false, fields_valid = false;
+  int64_t steps = 0;
+  double time = 0;
+  bool have_ref = false;
+  double N0 = 0, E0 = 0;
+
+  // profiling
+  bool prof = false;
+  struct Ev {
+    int k;
+    hipEvent_t a, b;
+  };
+  std::vector<Ev> events;
+  std::vector<hipEvent_t> pool;
+  int64_t klaunch[KC_COUNT] = {0};
+  double kms[KC_COUNT] = {0};
+
+  std::string err;
+
+  void* dalloc(size_t bytes) {
+    void* p = nullptr;
+    if (bytes == 0) bytes = 16;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      throw Fail{TDSLDA_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
+    }
+    allocs.push_back(p);
+    return p;
+  }
+  hipEvent_t ev() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    return e;
+  }
+  // bracket a launch with events when profiling
+  template <class F>
+  void launch(int k, F&& f) {
+    if (prof) {
+      hipEvent_t a = ev(), b = ev();
+      HIPCHK(hipEventRecord(a, stream));
+      f();
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipEventRecord(b, stream));
+      events.push_back({k, a, b});
+    } else {
+      f();
+      HIPCHK(hipGetLastError());
+    }
+  }
+  void harvest() {
+    for (auto& e : events) {
+      HIPCHK(hipEventSynchronize(e.b));
+      float ms = 0;
+      HIPCHK(hipEventElapsedTime(&ms, e.a, e.b));
+      klaunch[e.k] += 1;
+      kms[e.k] += ms;
+      pool.push_back(e.a);
+      pool.push_back(e.b);
+    }
+    events.clear();
+  }
+  StateScalars scalars(double* scale) {
+    StateScalars s;
+    s.nrm_part = nrm_part;
+    s.nrm_stride = nrm_stride;
+    s.h_part = h_part;
+    s.h_stride = h_stride;
+    s.h_lap1_off = eng->ngx();
+    s.scale = scale;
+    s.hshift = hshift;
+    return s;
+  }
+  ~tdslda_ctx() {
+    for (auto& e : events) {
+      (void)hipEventDestroy(e.a);
+      (void)hipEventDestroy(e.b);
+    }
+    for (auto e : pool) (void)hipEventDestroy(e);
+    for (void* p : allocs) (void)hipFree(p);
+  }
+};
+
+namespace tdslda {
+inline unsigned cdiv(int64_t a, int64_t b) { return unsigned((a + b - 1) / b); }
+
+// factories of the instantiation units (nullptr when the shape is not theirs)
+std::unique_ptr<Engine> make3d_f64_small(int nx, int ny, int nz);
+std::unique_ptr<Engine> make3d_f64_large(int nx, int ny, int nz);
+std::unique_ptr<Engine> make3d_f32_small(int nx, int ny, int nz);
+std::unique_ptr<Engine> make3d_f32_large(int nx, int ny, int nz);
+std::unique_ptr<Engine> make_q1d_f64(int nz);
+std::unique_ptr<Engine> make_q1d_f32(int nz);
+}  // namespace tdslda

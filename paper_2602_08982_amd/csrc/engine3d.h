@@ -1,0 +1,142 @@
+// Full-3D kernel set for one (precision, lattice shape): launches of the
+// kernels of kernels3d.h with the shape-dependent tiling.
+#pragma once
+
+#include "ctx.h"
+
+namespace tdslda {
+
+// ----------------------------------------------------------------------------
+// full-3D engine for one (precision, shape)
+template <typename R, int NX, int NY, int NZ>
+struct Engine3D final : Engine {
+  using CFG = SlabCfg<NX, NY, NZ>;
+  static constexpr int G = 32;     // states per density group
+  static constexpr int TB1 = 64;   // lap1 block
+  static constexpr int M = NX * NY * NZ;
+  static constexpr int NYZ = NY * NZ;
+  int ngx() const override { return CFG::NGX; }
+  int ncb() const override { return int(cdiv(NYZ, TB1)); }
+  int group() const override { return G; }
+  size_t elem_size() const override { return sizeof(cpx<R>); }
+
+  double cx2(const Ctx& c) const { double k = 2 * kPi / (NX * c.lat.dx); return k * k; }
+  double cy2(const Ctx& c) const { double k = 2 * kPi / (NY * c.lat.dy); return k * k; }
+  double cz2(const Ctx& c) const { double k = 2 * kPi / (NZ * c.lat.dz); return k * k; }
+
+  void dens(Ctx& c, const void* X, const double* scale, int64_t nst) override {
+    dim3 grid(CFG::NGX, cdiv(nst, G));
+    c.launch(KC_DENS, [&] {
+      hipLaunchKernelGGL((k_dens<R, NX, NY, NZ, G>), grid, dim3(CFG::TB), 0, c.stream,
+                         (const cpx<R>*)X, nst, c.wu, c.wv, c.scalars(const_cast<double*>(scale)),
+                         c.dens_part, cy2(c), cz2(c), c.dV);
+    });
+    c.nsg_used = int(cdiv(nst, G));
+  }
+  void reduce_pot(Ctx& c, bool update) override {
+    FunParams fp{c.fun.functional, c.fun.B, c.fun.C, c.fun.inv_g_bdg, c.fun.mu, c.ainv};
+    c.launch(KC_REDUCE_POT, [&] {
+      hipLaunchKernelGGL((k_reduce_pot<R>), dim3(cdiv(M, 256)), dim3(256), 0, c.stream, c.dens_part,
+                         c.nsg_used, int64_t(M), fp, c.lam, c.vext, c.rho, c.nu, c.U, c.delta, (R*)c.hA,
+                         (cpx<R>*)c.hD, int(update));
+    });
+  }
+  void lap1(Ctx& c, const void* X, const double* scale, bool hpart, int64_t nst) override {
+    dim3 grid(cdiv(NYZ, TB1), nst);
+    c.launch(KC_LAP1, [&] {
+      hipLaunchKernelGGL((k_lap1<R, NX, NYZ, TB1>), grid, dim3(TB1), 0, c.stream, (const cpx<R>*)X,
+                         scale, (cpx<R>*)c.T, (const R*)c.hA, (const cpx<R>*)c.hD,
+                         hpart ? c.h_part : nullptr, c.h_stride, CFG::NGX, cx2(c), c.dV);
+    });
+  }
+  void lap2(Ctx& c, const L2Desc& d, int64_t nst) override {
+    Lap2Args<R> A{};
+    A.X = (const cpx<R>*)d.X;
+    A.Xout = (cpx<R>*)d.Xout;
+    A.T = (const cpx<R>*)d.T;
+    A.hA = (const R*)c.hA;
+    A.hD = (const cpx<R>*)c.hD;
+    A.scale = d.scale;
+    A.hshift = d.hshift;
+    A.out = (cpx<R>*)d.out;
+    A.acc = (cpx<R>*)d.acc;
+    for (int i = 0; i < 5; ++i) A.hist[i] = (const cpx<R>*)d.hist[i];
+    A.cout = (cpx<R>*)d.cout;
+    A.nrm_part = d.nrm_part;
+    A.nrm_stride = c.nrm_stride;
+    A.np = c.np;
+    A.nq = c.nq;
+    for (int i = 0; i < 5; ++i) {
+      A.b[i] = c.bco[i];
+      A.a[i] = c.aco[i];
+    }
+    A.tay_re = d.tay_re;
+    A.tay_im = d.tay_im;
+    A.init_acc = d.init_acc;
+    A.cy2 = cy2(c);
+    A.cz2 = cz2(c);
+    dim3 grid(CFG::NGX, nst), block(CFG::TB);
+    switch (d.mode) {
+      case L2_H:
+        c.launch(KC_LAP2_H, [&] { hipLaunchKernelGGL((k_lap2<R, NX, NY, NZ, L2_H>), grid, block, 0, c.stream, A); });
+        break;
+      case L2_F:
+        c.launch(KC_LAP2_F, [&] { hipLaunchKernelGGL((k_lap2<R, NX, NY, NZ, L2_F>), grid, block, 0, c.stream, A); });
+        break;
+      case L2_CORR:
+        c.launch(KC_LAP2_CORR, [&] { hipLaunchKernelGGL((k_lap2<R, NX, NY, NZ, L2_CORR>), grid, block, 0, c.stream, A); });
+        break;
+      case L2_FULL:
+        c.launch(KC_LAP2_FULL, [&] { hipLaunchKernelGGL((k_lap2<R, NX, NY, NZ, L2_FULL>), grid, block, 0, c.stream, A); });
+        break;
+      default:
+        c.launch(KC_LAP2_TAYLOR, [&] { hipLaunchKernelGGL((k_lap2<R, NX, NY, NZ, L2_TAYLOR>), grid, block, 0, c.stream, A); });
+    }
+  }
+  void pointwise(Ctx& c, const PwDesc& d, int64_t nst) override {
+    PwArgs<R> A{};
+    A.X = (cpx<R>*)d.X;
+    A.scale = d.scale;
+    for (int i = 0; i < 5; ++i) A.hist[i] = (const cpx<R>*)d.hist[i];
+    A.cout = (cpx<R>*)d.cout;
+    A.nrm_part = d.nrm_part;
+    A.nrm_stride = c.nrm_stride;
+    A.np = c.np;
+    A.nq = c.nq;
+    for (int i = 0; i < 5; ++i) {
+      A.b[i] = c.bco[i];
+      A.a[i] = c.aco[i];
+    }
+    A.out64 = (cpx<double>*)d.out64;
+    dim3 grid(CFG::NGX, nst), block(CFG::TB);
+    if (d.mode == PW_NORM)
+      c.launch(KC_NORM, [&] { hipLaunchKernelGGL((k_pointwise<R, NX, NY, NZ, PW_NORM>), grid, block, 0, c.stream, A); });
+    else if (d.mode == PW_PRED)
+      c.launch(KC_PRED, [&] { hipLaunchKernelGGL((k_pointwise<R, NX, NY, NZ, PW_PRED>), grid, block, 0, c.stream, A); });
+    else
+      c.launch(KC_SETUP, [&] { hipLaunchKernelGGL((k_pointwise<R, NX, NY, NZ, PW_SCALE>), grid, block, 0, c.stream, A); });
+  }
+  void grad(Ctx& c, const void* X, const double* scale, int64_t n0, int64_t nchunk) override {
+    constexpr int TBG = 64;
+    double* ts = c.gscratch;
+    double* js = c.gscratch + nchunk * M;
+    const double px = kPi / c.lat.dx, py = kPi / c.lat.dy, pz = kPi / c.lat.dz;
+    c.launch(KC_GRAD, [&] {
+      hipLaunchKernelGGL((k_grad_axis<R, NX, 0, TBG>), dim3(cdiv(M / NX, TBG), nchunk), dim3(TBG), 0,
+                         c.stream, (const cpx<R>*)X, n0, nchunk, int64_t(M), int64_t(NYZ), int64_t(NYZ),
+                         scale, c.wu, c.wv, 2 * kPi / (NX * c.lat.dx), px * px, ts, js);
+    });
+    c.launch(KC_GRAD, [&] {
+      hipLaunchKernelGGL((k_grad_axis<R, NY, 1, TBG>), dim3(cdiv(M / NY, TBG), nchunk), dim3(TBG), 0,
+                         c.stream, (const cpx<R>*)X, n0, nchunk, int64_t(M), int64_t(NZ), int64_t(NZ),
+                         scale, c.wu, c.wv, 2 * kPi / (NY * c.lat.dy), py * py, ts, js);
+    });
+    c.launch(KC_GRAD, [&] {
+      hipLaunchKernelGGL((k_grad_axis<R, NZ, 2, TBG>), dim3(cdiv(M / NZ, TBG), nchunk), dim3(TBG), 0,
+                         c.stream, (const cpx<R>*)X, n0, nchunk, int64_t(M), int64_t(1), int64_t(1),
+                         scale, c.wu, c.wv, 2 * kPi / (NZ * c.lat.dz), pz * pz, ts, js);
+    });
+  }
+};
+
+}  // namespace tdslda

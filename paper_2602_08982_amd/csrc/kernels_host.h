@@ -1,0 +1,134 @@
+// Non-template kernels used only by the C-ABI translation unit: per-state
+// scalar finalisation, gradient-density reduction, energy terms and set-up.
+#pragma once
+
+#include "kernels3d.h"
+
+namespace tdslda {
+
+// finalize per-state scalars
+__global__ void k_finalize(int64_t nstates, StateScalars sc, int n_nrm, int n_h, int do_scale, int do_h) {
+  const int64_t n = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (n >= nstates) return;
+  if (do_scale) {
+    double s = 0.0;
+    for (int i = 0; i < n_nrm; ++i) s += sc.nrm_part[n * sc.nrm_stride + i];
+    sc.scale[n] = 1.0 / sqrt(s);
+  }
+  if (do_h) {
+    double s = 0.0;
+    for (int i = 0; i < n_h; ++i) s += sc.h_part[n * sc.h_stride + i];
+    sc.hshift[n] = s;
+  }
+}
+
+// sum the per-state scratch over the chunk (fixed order) into tau, j
+__global__ void k_grad_reduce(int64_t nchunk, int64_t M, double ainv, const double* __restrict__ tau_s,
+                              const double* __restrict__ j_s, double* __restrict__ tau,
+                              double* __restrict__ j, int init) {
+  const int64_t r = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (r >= M) return;
+  double t = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+  for (int64_t c = 0; c < nchunk; ++c) {
+    t += tau_s[c * M + r];
+    jx += j_s[(c * 3 + 0) * M + r];
+    jy += j_s[(c * 3 + 1) * M + r];
+    jz += j_s[(c * 3 + 2) * M + r];
+  }
+  if (init) {
+    tau[r] = ainv * t;
+    j[r] = ainv * jx;
+    j[M + r] = ainv * jy;
+    j[2 * M + r] = ainv * jz;
+  } else {
+    tau[r] += ainv * t;
+    j[r] += ainv * jx;
+    j[M + r] += ainv * jy;
+    j[2 * M + r] += ainv * jz;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Energy terms of Sec. 3.2 (A = 1, spin-symmetric) reduced in one block:
+// out = {E_kin, E_pot, E_pair, E_curr, E_ext, N}
+__global__ __launch_bounds__(1024) void k_energy(int64_t M, const double* __restrict__ rho,
+                                                 const double* __restrict__ tau,
+                                                 const double* __restrict__ nu,
+                                                 const double* __restrict__ j,
+                                                 const double* __restrict__ delta,
+                                                 const double* __restrict__ vext, double B,
+                                                 int slda, double dVe, double* __restrict__ out) {
+  __shared__ double red[1024 / kWave];
+  double ek = 0, ep = 0, epa = 0, ec = 0, ee = 0, nn = 0;
+  for (int64_t r = threadIdx.x; r < M; r += 1024) {
+    const double rs = fmax(rho[r], 0.5e-14);
+    const double jsq = j[r] * j[r] + j[M + r] * j[M + r] + j[2 * M + r] * j[2 * M + r];
+    ek += (tau[r] - jsq / rs);
+    if (slda) ep += 0.6 * B * (2.0 * rho[r]) * 0.5 * pow(3.0 * kPi * kPi * (2.0 * rho[r]), 2.0 / 3.0);
+    epa -= delta[2 * r] * nu[2 * r] + delta[2 * r + 1] * nu[2 * r + 1];
+    ec += jsq / rs;
+    ee += vext[r] * 2.0 * rho[r];
+    nn += 2.0 * rho[r];
+  }
+  double v[6] = {ek, ep, epa, ec, ee, nn};
+  for (int k = 0; k < 6; ++k) {
+    const double t = block_sum<1024>(v[k], red);
+    if (threadIdx.x == 0) out[k] = t * dVe;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// set-up kernels
+// Lambda_c of Eq. Creg with V_+ = vext (A = 1); k_0^2 < 0 continued
+// analytically (k_0 = i kappa).
+__global__ void k_lambda(int64_t M, const double* __restrict__ vext, double mu, double ec,
+                         double* __restrict__ lam, int* __restrict__ bad) {
+  const int64_t r = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (r >= M) return;
+  const double k0sq = 2.0 * (mu - vext[r]);
+  const double kcsq = 2.0 * (ec + mu - vext[r]);
+  if (kcsq <= 0.0) {
+    bad[0] = 1;
+    lam[r] = 0.0;
+    return;
+  }
+  const double kc = sqrt(kcsq);
+  double br;
+  if (k0sq > 0.0) {
+    const double k0 = sqrt(k0sq);
+    br = 1.0 - k0 / (2.0 * kc) * log((kc + k0) / (kc - k0));
+  } else {
+    const double ka = sqrt(-k0sq);
+    br = 1.0 + ka / kc * atan(ka / kc);
+  }
+  lam[r] = kc / (2.0 * kPi * kPi) * br;
+}
+
+// theta(x, y) of straight vortex lines along z (centred coordinates)
+__global__ void k_vortex_phase(int64_t M, int nx, int ny, int nz, double dx, double dy, int nv,
+                               const double* __restrict__ xyq, double* __restrict__ theta) {
+  const int64_t r = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (r >= M) return;
+  const int ix = int(r / (int64_t(ny) * nz)), iy = int((r / nz) % ny);
+  const double x = (ix - nx / 2) * dx, y = (iy - ny / 2) * dy;
+  double th = 0.0;
+  for (int v = 0; v < nv; ++v) th += xyq[3 * v + 2] * atan2(y - xyq[3 * v + 1], x - xyq[3 * v]);
+  theta[r] = th;
+}
+
+// Fermi weights of the frozen static energies
+__global__ void k_weights(int64_t n, const double* __restrict__ E, double T, double* __restrict__ wu,
+                          double* __restrict__ wv) {
+  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= n) return;
+  const double e = E[i];
+  if (T <= 0.0) {
+    wu[i] = e < 0 ? 1.0 : (e > 0 ? 0.0 : 0.5);
+    wv[i] = e > 0 ? 1.0 : (e < 0 ? 0.0 : 0.5);
+  } else {
+    wu[i] = 1.0 / (exp(fmin(fmax(e / T, -700.0), 700.0)) + 1.0);
+    wv[i] = 1.0 / (exp(fmin(fmax(-e / T, -700.0), 700.0)) + 1.0);
+  }
+}
+
+}  // namespace tdslda

@@ -1,0 +1,909 @@
+// libtdslda: host side of the C ABI declared in include/tdslda.h.
+//
+// A context owns (history depth + 1) state buffers, the intermediate buffer
+// T (x-derivative of every state) and the FP64 fields.  The integrator
+// keeps buffer roles by index: phi (current state, raw with a per-buffer
+// normalisation scale) and hist[0..D-1] (f_{k-1}, ..., f_{k-D}).  One ABM
+// step is two right-hand-side evaluations, each
+//     dens -> reduce_pot -> lap1 -> finalize(<H>) -> lap2(mode),
+// where lap2 fuses H.psi, the <H>_n shift and the integrator arithmetic
+// (Alg. AB4AM5: the corrector after the first evaluation, the next step's
+// predictor and partial corrector after the second).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "ctx.h"
+#include "kernels_host.h"
+
+namespace {
+
+std::unique_ptr<Engine> make_engine(const tdslda_lattice& lat, int prec) {
+  std::unique_ptr<Engine> e;
+  if (lat.mode == TDSLDA_MODE_3D) {
+    if (prec == TDSLDA_FP64) {
+      e = make3d_f64_small(lat.nx, lat.ny, lat.nz);
+      if (!e) e = make3d_f64_large(lat.nx, lat.ny, lat.nz);
+    } else {
+      e = make3d_f32_small(lat.nx, lat.ny, lat.nz);
+      if (!e) e = make3d_f32_large(lat.nx, lat.ny, lat.nz);
+    }
+  } else {
+    e = prec == TDSLDA_FP64 ? make_q1d_f64(lat.nz) : make_q1d_f32(lat.nz);
+  }
+  return e;
+}
+
+// integrator constants (Eqs. AB3-AB5, AM4-AM5)
+void set_scheme(Ctx& c) {
+  static const double ab3[] = {23.0 / 12, -16.0 / 12, 5.0 / 12};
+  static const double ab4[] = {55.0 / 24, -59.0 / 24, 37.0 / 24, -9.0 / 24};
+  static const double ab5[] = {1901.0 / 720, -2774.0 / 720, 2616.0 / 720, -1274.0 / 720, 251.0 / 720};
+  static const double am4[] = {9.0 / 24, 19.0 / 24, -5.0 / 24, 1.0 / 24};
+  static const double am5[] = {251.0 / 720, 646.0 / 720, -264.0 / 720, 106.0 / 720, -19.0 / 720};
+  const double* b;
+  const double* a;
+  switch (c.run.integrator) {
+    case TDSLDA_AB3AM4: c.np = 3; c.nq = 4; b = ab3; a = am4; break;
+    case TDSLDA_AB5AM5: c.np = 5; c.nq = 5; b = ab5; a = am5; break;
+    case TDSLDA_AB4AM5: c.np = 4; c.nq = 5; b = ab4; a = am5; break;
+    default: throw Fail{TDSLDA_EINVAL, "unknown integrator"};
+  }
+  c.depth = std::max(c.np, c.nq - 1);
+  for (int i = 0; i < 5; ++i) {
+    c.bco[i] = i < c.np ? c.run.dt * b[i] : 0.0;
+    c.aco[i] = i < c.nq ? c.run.dt * a[i] : 0.0;
+  }
+}
+
+int64_t memory_bytes(const tdslda_lattice& lat, const tdslda_run& run, int64_t n, Engine* eng,
+                     int depth, int64_t gchunk) {
+  const int64_t M = lat.mode == TDSLDA_MODE_3D ? int64_t(lat.nx) * lat.ny * lat.nz : lat.nz;
+  const int64_t es = int64_t(eng->elem_size());
+  const int64_t S = 2 * M * es;
+  int64_t b = (depth + 2) * n * S;                               // state buffers + T
+  b += n * 8 * (4 + (depth + 1) + 1);                            // per-state arrays
+  b += n * 8 * (eng->ngx() + eng->ngx() + eng->ncb());           // partial slots
+  b += int64_t(cdiv(n, eng->group())) * 3 * M * 8;              // density partials
+  b += M * 8 * 16 + M * (es / 2 + es);                          // fields
+  b += gchunk * 4 * M * 8;                                      // gradient scratch
+  (void)run;
+  return b;
+}
+
+// ----------------------------------------------------------------------------
+// integrator pieces
+void fin(Ctx& c, int64_t nst, double* scale, bool do_scale, bool do_h) {
+  StateScalars s = c.scalars(scale);
+  const int nh = c.eng->ngx() + c.eng->ncb();
+  c.launch(KC_FINALIZE, [&] {
+    hipLaunchKernelGGL(k_finalize, dim3(cdiv(nst, 256)), dim3(256), 0, c.stream, nst, s, c.eng->ngx(), nh,
+                       int(do_scale), int(do_h));
+  });
+}
+
+// fields and <H>_n of buffer b (its scale must be current); leaves T = D2x
+void prepare(Ctx& c, int b) {
+  c.eng->dens(c, c.sb[b], c.sscale[b], c.nst);
+  c.eng->reduce_pot(c, !c.frozen);
+  c.eng->lap1(c, c.sb[b], c.sscale[b], true, c.nst);
+  fin(c, c.nst, c.sscale[b], false, true);
+  c.fields_valid = true;
+}
+
+void norm_of(Ctx& c, int b) {
+  PwDesc d;
+  d.mode = PW_NORM;
+  d.X = c.sb[b];
+  d.nrm_part = c.nrm_part;
+  c.eng->pointwise(c, d, c.nst);
+  fin(c, c.nst, c.sscale[b], true, false);
+}
+
+void f_into(Ctx& c, int src, int dst) {
+  L2Desc d;
+  d.mode = L2_F;
+  d.X = c.sb[src];
+  d.T = c.T;
+  d.scale = c.sscale[src];
+  d.hshift = c.hshift;
+  d.out = c.sb[dst];
+  c.eng->lap2(c, d, c.nst);
+}
+
+// Taylor series sum_{k<=r} (-i tau)^k/k! (H - h)^k phi with H, h already
+// prepared (fields, hshift).  t_ready: T already holds D2x of phi.  Writes
+// into buffer acc and finalises its scale; psi_k is formed in place in pa.
+void taylor_series(Ctx& c, int phi, int acc, int pa, double tau, bool t_ready) {
+  const int r = c.run.taylor_order > 0 ? c.run.taylor_order : 5;
+  for (int k = 1; k <= r; ++k) {
+    const bool first = k == 1;
+    const int in = first ? phi : pa;
+    if (!first || !t_ready) c.eng->lap1(c, c.sb[in], first ? c.sscale[phi] : nullptr, false, c.nst);
+    L2Desc d;
+    d.mode = L2_TAYLOR;
+    d.X = c.sb[in];
+    d.T = c.T;
+    d.scale = first ? c.sscale[phi] : nullptr;
+    d.hshift = c.hshift;
+    d.out = c.sb[pa];
+    d.acc = c.sb[acc];
+    d.init_acc = first ? 1 : 0;
+    d.tay_re = 0.0;
+    d.tay_im = -tau / k;  // (-i tau / k)
+    d.nrm_part = (k == r) ? c.nrm_part : nullptr;
+    c.eng->lap2(c, d, c.nst);
+  }
+  fin(c, c.nst, c.sscale[acc], true, false);
+}
+
+// One start-up step phi -> new buffer, by the Taylor predictor-corrector of
+// Eq. Taylor-exp (H at the mid point, shifted operator H - <H>_n with <H>_n
+// on the state the H is built from; mid point and result renormalised).
+// Requires prepare(phi) done.  Returns the new buffer.
+int taylor_step(Ctx& c, int phi, std::vector<int>& freeb) {
+  require(freeb.size() >= 2, TDSLDA_EINVAL, "internal: not enough buffers for the start-up");
+  int pa = freeb.back(); freeb.pop_back();
+  int acc = freeb.back(); freeb.pop_back();
+  taylor_series(c, phi, acc, pa, 0.5 * c.run.dt, true);  // mid-point state
+  prepare(c, acc);                                        // fields and <H> at the mid point
+  taylor_series(c, phi, acc, pa, c.run.dt, false);        // full step from phi
+  freeb.push_back(pa);
+  return acc;
+}
+
+void start(Ctx& c) {
+  const int D = c.depth;
+  std::vector<int> freeb;
+  for (int b = 0; b <= D; ++b)
+    if (b != c.phi) freeb.push_back(b);
+  norm_of(c, c.phi);
+  std::vector<int> hl;  // newest first
+  if (c.run.selfstart == 0) {
+    prepare(c, c.phi);
+    int f0 = freeb.back();
+    freeb.pop_back();
+    f_into(c, c.phi, f0);
+    hl.push_back(f0);
+    while ((int)hl.size() < D) {
+      int b = freeb.back();
+      freeb.pop_back();
+      HIPCHK(hipMemcpyAsync(c.sb[b], c.sb[f0], size_t(c.nst) * 2 * c.M * c.esz, hipMemcpyDeviceToDevice, c.stream));
+      hl.push_back(b);
+    }
+  } else {
+    // phi_0 .. phi_{D-1} by Taylor steps; history f(phi_j), newest first
+    int cur = c.phi;
+    for (int j = 0; j < D; ++j) {
+      int nxt = -1;
+      if (j < D - 1) {
+        prepare(c, cur);
+        nxt = taylor_step(c, cur, freeb);
+      }
+      prepare(c, cur);
+      int fs = freeb.back();
+      freeb.pop_back();
+      f_into(c, cur, fs);
+      hl.insert(hl.begin(), fs);
+      if (nxt >= 0) {
+        freeb.push_back(cur);
+        cur = nxt;
+        c.time += c.run.dt;
+      }
+    }
+    c.phi = cur;
+  }
+  for (int j = 0; j < D; ++j) c.hist[j] = hl[j];
+  c.started = true;
+}
+
+void abm(Ctx& c, int64_t nsteps) {
+  if (!c.started) start(c);
+  if (nsteps <= 0) return;
+  const int D = c.depth;
+  // predictor + partial corrector of the first step
+  {
+    PwDesc d;
+    d.mode = PW_PRED;
+    d.X = c.sb[c.phi];
+    d.scale = c.sscale[c.phi];
+    for (int j = 0; j < D; ++j) d.hist[j] = c.sb[c.hist[j]];
+    d.cout = c.sb[c.hist[D - 1]];
+    d.nrm_part = c.nrm_part;
+    c.eng->pointwise(c, d, c.nst);
+    fin(c, c.nst, c.sscale[c.phi], true, false);
+  }
+  for (int64_t s = 0; s < nsteps; ++s) {
+    // evaluation at the predicted state; corrector
+    prepare(c, c.phi);
+    {
+      L2Desc d;
+      d.mode = L2_CORR;
+      d.X = c.sb[c.phi];
+      d.Xout = c.sb[c.phi];
+      d.T = c.T;
+      d.scale = c.sscale[c.phi];
+      d.hshift = c.hshift;
+      d.hist[0] = c.sb[c.hist[D - 1]];  // partial corrector c
+      d.nrm_part = c.nrm_part;
+      c.eng->lap2(c, d, c.nst);
+      fin(c, c.nst, c.sscale[c.phi], true, false);
+    }
+    // rotate: the slot of c becomes the slot of the new f
+    {
+      int freed = c.hist[D - 1];
+      for (int j = D - 1; j > 0; --j) c.hist[j] = c.hist[j - 1];
+      c.hist[0] = freed;
+    }
+    // evaluation at the corrected state
+    prepare(c, c.phi);
+    L2Desc d;
+    d.X = c.sb[c.phi];
+    d.T = c.T;
+    d.scale = c.sscale[c.phi];
+    d.hshift = c.hshift;
+    d.out = c.sb[c.hist[0]];
+    if (s + 1 < nsteps) {
+      d.mode = L2_FULL;
+      d.Xout = c.sb[c.phi];
+      for (int j = 1; j < D; ++j) d.hist[j] = c.sb[c.hist[j]];
+      d.cout = c.sb[c.hist[D - 1]];
+      d.nrm_part = c.nrm_part;
+      c.eng->lap2(c, d, c.nst);
+      fin(c, c.nst, c.sscale[c.phi], true, false);
+    } else {
+      d.mode = L2_F;
+      c.eng->lap2(c, d, c.nst);
+    }
+    c.steps += 1;
+    c.time += c.run.dt;
+  }
+}
+
+// rho, tau, nu, j of the current states into the device fields; refresh
+// the mean fields unless frozen.
+void full_densities(Ctx& c) {
+  const int b = c.phi;
+  c.eng->dens(c, c.sb[b], c.sscale[b], c.nst);
+  c.eng->reduce_pot(c, !c.frozen);
+  if (!c.frozen) c.fields_valid = true;
+  for (int64_t n0 = 0; n0 < c.nst; n0 += c.gchunk) {
+    const int64_t nch = std::min(c.gchunk, c.nst - n0);
+    c.eng->grad(c, c.sb[b], c.sscale[b], n0, nch);
+    c.launch(KC_GRAD, [&] {
+      hipLaunchKernelGGL(k_grad_reduce, dim3(cdiv(c.M, 256)), dim3(256), 0, c.stream, nch, c.M, c.ainv,
+                         c.gscratch, c.gscratch + nch * c.M, c.tau, c.jc, int(n0 == 0));
+    });
+  }
+}
+
+void energy(Ctx& c, double* out8) {
+  full_densities(c);
+  c.launch(KC_ENERGY, [&] {
+    hipLaunchKernelGGL(k_energy, dim3(1), dim3(1024), 0, c.stream, c.M, c.rho, c.tau, c.nu, c.jc, c.delta,
+                       c.vext, c.fun.B, int(c.fun.functional == TDSLDA_FUNC_SLDA), c.dVe, c.eout);
+  });
+  double h[6];
+  HIPCHK(hipMemcpyAsync(h, c.eout, sizeof(h), hipMemcpyDeviceToHost, c.stream));
+  HIPCHK(hipStreamSynchronize(c.stream));
+  const double N = h[5];
+  const double ef = 0.5 * std::pow(3.0 * kPi * kPi * N / c.vol, 2.0 / 3.0);
+  out8[0] = h[0];
+  out8[1] = h[1];
+  out8[2] = h[2];
+  out8[3] = h[3];
+  out8[4] = h[4];
+  out8[5] = h[0] + h[1] + h[2] + h[3] + h[4];
+  out8[6] = N;
+  out8[7] = 0.6 * N * ef;
+}
+
+void after_load(Ctx& c) {
+  c.loaded = true;
+  c.started = false;
+  c.steps = 0;
+  c.time = 0;
+  c.have_ref = false;
+  c.phi = 0;
+  for (int j = 0; j < 5; ++j) c.hist[j] = j + 1;
+  norm_of(c, c.phi);
+  if (!c.frozen) {
+    c.eng->dens(c, c.sb[c.phi], c.sscale[c.phi], c.nst);
+    c.eng->reduce_pot(c, true);
+    c.fields_valid = true;
+  }
+}
+
+void set_weights(Ctx& c, int64_t n, const double* E_host) {
+  if (E_host) HIPCHK(hipMemcpyAsync(c.E, E_host, n * 8, hipMemcpyHostToDevice, c.stream));
+  c.launch(KC_SETUP, [&] {
+    hipLaunchKernelGGL(k_weights, dim3(cdiv(n, 256)), dim3(256), 0, c.stream, n, c.E, c.fun.temperature, c.wu, c.wv);
+  });
+}
+
+template <class F>
+tdslda_status guard(tdslda_ctx* c, F&& f) {
+  if (!c) return TDSLDA_EINVAL;
+  try {
+    c->err.clear();
+    f();
+    return TDSLDA_OK;
+  } catch (const Fail& e) {
+    c->err = e.msg;
+    return e.st;
+  } catch (const std::bad_alloc&) {
+    c->err = "host allocation failed";
+    return TDSLDA_ENOMEM;
+  } catch (...) {
+    c->err = "unknown error";
+    return TDSLDA_EDEVICE;
+  }
+}
+
+void check_lattice(const tdslda_lattice& lat) {
+  if (lat.mode == TDSLDA_MODE_3D) {
+    require(lat.nx > 0 && lat.ny > 0 && lat.nz > 0 && lat.nx % 2 == 0 && lat.ny % 2 == 0 && lat.nz % 2 == 0,
+            TDSLDA_EINVAL, "lattice sizes must be positive and even");
+    require(lat.dx > 0 && lat.dy > 0 && lat.dz > 0, TDSLDA_EINVAL, "lattice spacings must be positive");
+  } else if (lat.mode == TDSLDA_MODE_Q1D) {
+    require(lat.nz > 0 && lat.nz % 2 == 0 && lat.dz > 0, TDSLDA_EINVAL, "bad quasi-1D lattice");
+    require(lat.lx_perp > 0 && lat.ly_perp > 0, TDSLDA_EINVAL, "quasi-1D needs the transverse box");
+  } else {
+    throw Fail{TDSLDA_EINVAL, "unknown lattice mode"};
+  }
+}
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+extern "C" {
+
+const char* tdslda_kernel_name(int k) { return (k >= 0 && k < KC_COUNT) ? kKernelNames[k] : nullptr; }
+
+const char* tdslda_last_error(const tdslda_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+tdslda_status tdslda_memory_plan(const tdslda_lattice* lat, const tdslda_run* run, int64_t nstates,
+                                 int64_t* bytes_out) {
+  if (!lat || !run || !bytes_out || nstates < 0) return TDSLDA_EINVAL;
+  try {
+    check_lattice(*lat);
+    auto eng = make_engine(*lat, run->precision);
+    if (!eng) return TDSLDA_EINVAL;
+    tdslda_ctx tmp;
+    tmp.run = *run;
+    set_scheme(tmp);
+    const int64_t M = lat->mode == TDSLDA_MODE_3D ? int64_t(lat->nx) * lat->ny * lat->nz : lat->nz;
+    (void)M;
+    *bytes_out = memory_bytes(*lat, *run, nstates, eng.get(), tmp.depth, std::min<int64_t>(nstates, 64));
+    return TDSLDA_OK;
+  } catch (...) {
+    return TDSLDA_EINVAL;
+  }
+}
+
+tdslda_status tdslda_create(const tdslda_lattice* lat, const tdslda_functional* fun, const tdslda_run* run,
+                            int64_t capacity, tdslda_ctx** out) {
+  if (!lat || !fun || !run || !out || capacity <= 0) return TDSLDA_EINVAL;
+  *out = nullptr;
+  tdslda_ctx* c = new (std::nothrow) tdslda_ctx();
+  if (!c) return TDSLDA_ENOMEM;
+  tdslda_status st = guard(c, [&] {
+    check_lattice(*lat);
+    require(run->precision == TDSLDA_FP64 || run->precision == TDSLDA_FP32_MIXED, TDSLDA_EINVAL,
+            "unknown precision");
+    require(fun->functional == TDSLDA_FUNC_SLDA || fun->functional == TDSLDA_FUNC_BDG, TDSLDA_EINVAL,
+            "unknown functional");
+    require(fun->functional != TDSLDA_FUNC_SLDA || std::fabs(fun->A - 1.0) < 1e-15, TDSLDA_EINVAL,
+            "the TD path implements A_sigma = 1 only");
+    require(std::isfinite(run->dt) && run->dt != 0.0, TDSLDA_EINVAL, "dt must be finite and non-zero");
+    c->lat = *lat;
+    c->fun = *fun;
+    c->run = *run;
+    c->q1d = lat->mode == TDSLDA_MODE_Q1D;
+    c->stream = (hipStream_t)run->hip_stream;
+    set_scheme(*c);
+    c->eng = make_engine(*lat, run->precision);
+    require(c->eng != nullptr, TDSLDA_EINVAL, "unsupported lattice shape");
+    c->esz = c->eng->elem_size();
+    if (c->q1d) {
+      c->M = lat->nz;
+      c->dV = lat->dz;
+      c->ainv = 1.0 / (lat->lx_perp * lat->ly_perp);
+      c->dVe = lat->dz * lat->lx_perp * lat->ly_perp;
+      c->vol = lat->nz * lat->dz * lat->lx_perp * lat->ly_perp;
+    } else {
+      c->M = int64_t(lat->nx) * lat->ny * lat->nz;
+      c->dV = lat->dx * lat->dy * lat->dz;
+      c->ainv = 1.0;
+      c->dVe = c->dV;
+      c->vol = c->M * c->dV;
+    }
+    c->cap = capacity;
+    const int64_t M = c->M;
+    const size_t S = size_t(2 * M) * c->esz;
+    for (int b = 0; b <= c->depth; ++b) c->sb[b] = c->dalloc(S * capacity);
+    c->T = c->dalloc(S * capacity);
+    for (int b = 0; b <= c->depth; ++b) c->sscale[b] = (double*)c->dalloc(8 * capacity);
+    c->wu = (double*)c->dalloc(8 * capacity);
+    c->wv = (double*)c->dalloc(8 * capacity);
+    c->E = (double*)c->dalloc(8 * capacity);
+    c->kperp2 = (double*)c->dalloc(8 * capacity);
+    HIPCHK(hipMemsetAsync(c->kperp2, 0, 8 * capacity, c->stream));
+    c->hshift = (double*)c->dalloc(8 * capacity);
+    c->nrm_stride = c->eng->ngx();
+    c->h_stride = c->eng->ngx() + c->eng->ncb();
+    c->nrm_part = (double*)c->dalloc(8 * capacity * c->nrm_stride);
+    c->h_part = (double*)c->dalloc(8 * capacity * c->h_stride);
+    c->nsg_max = int(cdiv(capacity, c->eng->group()));
+    c->dens_part = (double*)c->dalloc(size_t(c->nsg_max) * 3 * M * 8);
+    c->rho = (double*)c->dalloc(8 * M);
+    c->nu = (double*)c->dalloc(16 * M);
+    c->tau = (double*)c->dalloc(8 * M);
+    c->jc = (double*)c->dalloc(24 * M);
+    c->U = (double*)c->dalloc(8 * M);
+    c->delta = (double*)c->dalloc(16 * M);
+    c->vext = (double*)c->dalloc(8 * M);
+    c->lam = (double*)c->dalloc(8 * M);
+    c->theta = (double*)c->dalloc(8 * M);
+    c->hA = c->dalloc(M * c->esz / 2);
+    c->hD = c->dalloc(M * c->esz);
+    HIPCHK(hipMemsetAsync(c->vext, 0, 8 * M, c->stream));
+    HIPCHK(hipMemsetAsync(c->lam, 0, 8 * M, c->stream));
+    c->gchunk = std::min<int64_t>(capacity, 64);
+    c->gscratch = (double*)c->dalloc(size_t(c->gchunk) * 4 * M * 8);
+    c->eout = (double*)c->dalloc(64);
+    c->dflag = (int*)c->dalloc(16);
+    HIPCHK(hipStreamSynchronize(c->stream));
+  });
+  if (st != TDSLDA_OK) {
+    // report through a stderr line: the context cannot outlive the failure
+    std::fprintf(stderr, "tdslda_create: %s\n", c->err.c_str());
+    delete c;
+    return st;
+  }
+  *out = c;
+  return TDSLDA_OK;
+}
+
+tdslda_status tdslda_destroy(tdslda_ctx* ctx) {
+  if (!ctx) return TDSLDA_EINVAL;
+  (void)hipStreamSynchronize(ctx->stream);
+  delete ctx;
+  return TDSLDA_OK;
+}
+
+tdslda_status tdslda_set_external(tdslda_ctx* c, const double* vext, int freeze_regulator) {
+  return guard(c, [&] {
+    require(vext != nullptr, TDSLDA_EINVAL, "vext is NULL");
+    HIPCHK(hipMemcpyAsync(c->vext, vext, 8 * c->M, hipMemcpyHostToDevice, c->stream));
+    if (freeze_regulator) {
+      HIPCHK(hipMemsetAsync(c->dflag, 0, 4, c->stream));
+      c->launch(KC_SETUP, [&] {
+        hipLaunchKernelGGL(k_lambda, dim3(cdiv(c->M, 256)), dim3(256), 0, c->stream, c->M, c->vext, c->fun.mu,
+                           c->fun.ec_reg, c->lam, c->dflag);
+      });
+      int bad = 0;
+      HIPCHK(hipMemcpyAsync(&bad, c->dflag, 4, hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(hipStreamSynchronize(c->stream));
+      require(!bad, TDSLDA_EINVAL, "E_c below the local band bottom in Lambda_c");
+    }
+    if (c->loaded && !c->frozen) {
+      c->eng->dens(*c, c->sb[c->phi], c->sscale[c->phi], c->nst);
+      c->eng->reduce_pot(*c, true);
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
+  });
+}
+
+tdslda_status tdslda_set_regulator(tdslda_ctx* c, const double* lam) {
+  return guard(c, [&] {
+    require(lam != nullptr, TDSLDA_EINVAL, "lam is NULL");
+    HIPCHK(hipMemcpyAsync(c->lam, lam, 8 * c->M, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+  });
+}
+
+static void load_common(tdslda_ctx* c, int64_t n, const double* E, const double* kperp2) {
+  require(n > 0 && n <= c->cap, TDSLDA_EINVAL, "state count out of range [1, capacity]");
+  require(E != nullptr, TDSLDA_EINVAL, "E is NULL");
+  if (c->q1d) {
+    require(kperp2 != nullptr, TDSLDA_EINVAL, "quasi-1D states need kperp2");
+    HIPCHK(hipMemcpyAsync(c->kperp2, kperp2, 8 * n, hipMemcpyHostToDevice, c->stream));
+  }
+  c->nst = n;
+  set_weights(*c, n, E);
+}
+
+tdslda_status tdslda_load_states(tdslda_ctx* c, int64_t n, const double* uv, const double* E,
+                                 const double* kperp2) {
+  return guard(c, [&] {
+    require(uv != nullptr, TDSLDA_EINVAL, "uv is NULL");
+    load_common(c, n, E, kperp2);
+    const int64_t per = 2 * c->M;  // complex elements per state
+    if (c->esz == 16) {
+      HIPCHK(hipMemcpyAsync(c->sb[0], uv, size_t(n) * per * 16, hipMemcpyHostToDevice, c->stream));
+    } else {
+      // stage through the gradient scratch (gchunk states of FP64) and round
+      for (int64_t n0 = 0; n0 < n; n0 += c->gchunk) {
+        const int64_t k = std::min(c->gchunk, n - n0);
+        HIPCHK(hipMemcpyAsync(c->gscratch, uv + n0 * per * 2, size_t(k) * per * 16, hipMemcpyHostToDevice, c->stream));
+        c->launch(KC_SETUP, [&] {
+          hipLaunchKernelGGL((k_convert_in<float>), dim3(cdiv(k * per, 256)), dim3(256), 0, c->stream, k * per,
+                             (const cpx<double>*)c->gscratch, (cpx<float>*)c->sb[0] + n0 * per);
+        });
+      }
+    }
+    after_load(*c);
+    HIPCHK(hipStreamSynchronize(c->stream));
+  });
+}
+
+tdslda_status tdslda_load_states_device(tdslda_ctx* c, int64_t n, const void* uv_dev, const double* E,
+                                        const double* kperp2) {
+  return guard(c, [&] {
+    require(uv_dev != nullptr, TDSLDA_EINVAL, "uv_dev is NULL");
+    load_common(c, n, E, kperp2);
+    HIPCHK(hipMemcpyAsync(c->sb[0], uv_dev, size_t(n) * 2 * c->M * c->esz, hipMemcpyDeviceToDevice, c->stream));
+    after_load(*c);
+    HIPCHK(hipStreamSynchronize(c->stream));
+  });
+}
+
+tdslda_status tdslda_init_plane_waves(tdslda_ctx* c, int64_t n, const int32_t* kidx, double u0, double delta0) {
+  return guard(c, [&] {
+    require(!c->q1d, TDSLDA_EINVAL, "plane-wave start is a 3D option");
+    require(kidx != nullptr && n > 0 && n <= c->cap, TDSLDA_EINVAL, "bad plane-wave list");
+    require(delta0 > 0, TDSLDA_EINVAL, "delta0 must be > 0");
+    for (int64_t i = 0; i < n; ++i) {
+      require(kidx[3 * i] >= 0 && kidx[3 * i] < c->lat.nx && kidx[3 * i + 1] >= 0 && kidx[3 * i + 1] < c->lat.ny &&
+                  kidx[3 * i + 2] >= 0 && kidx[3 * i + 2] < c->lat.nz,
+              TDSLDA_EINVAL, "k index out of range");
+    }
+    if (c->kidx_cap < n) {
+      c->kidx_dev = (int32_t*)c->dalloc(size_t(n) * 12);
+      c->kidx_cap = n;
+    }
+    HIPCHK(hipMemcpyAsync(c->kidx_dev, kidx, size_t(n) * 12, hipMemcpyHostToDevice, c->stream));
+    c->nst = n;
+    const double kx = 2 * kPi / (c->lat.nx * c->lat.dx), ky = 2 * kPi / (c->lat.ny * c->lat.dy),
+                 kz = 2 * kPi / (c->lat.nz * c->lat.dz);
+    const double isv = 1.0 / std::sqrt(c->vol);
+    c->launch(KC_SETUP, [&] {
+      if (c->esz == 16)
+        hipLaunchKernelGGL((k_plane_waves<double>), dim3(cdiv(c->M, 256), n), dim3(256), 0, c->stream, c->M,
+                           c->lat.nx, c->lat.ny, c->lat.nz, c->kidx_dev, u0 - c->fun.mu, delta0, kx, ky, kz, isv,
+                           (cpx<double>*)c->sb[0], c->E);
+      else
+        hipLaunchKernelGGL((k_plane_waves<float>), dim3(cdiv(c->M, 256), n), dim3(256), 0, c->stream, c->M,
+                           c->lat.nx, c->lat.ny, c->lat.nz, c->kidx_dev, u0 - c->fun.mu, delta0, kx, ky, kz, isv,
+                           (cpx<float>*)c->sb[0], c->E);
+    });
+    set_weights(*c, n, nullptr);
+    after_load(*c);
+    HIPCHK(hipStreamSynchronize(c->stream));
+  });
+}
+
+tdslda_status tdslda_imprint_vortices(tdslda_ctx* c, int nv, const double* xyq) {
+  return guard(c, [&] {
+    require(!c->q1d, TDSLDA_EINVAL, "vortex imprint is a 3D option");
+    require(c->loaded, TDSLDA_EORDER, "load states first");
+    require(nv > 0 && nv <= 64 && xyq, TDSLDA_EINVAL, "bad vortex list");
+    double* buf = c->gscratch;
+    HIPCHK(hipMemcpyAsync(buf, xyq, nv * 3 * 8, hipMemcpyHostToDevice, c->stream));
+    c->launch(KC_SETUP, [&] {
+      hipLaunchKernelGGL(k_vortex_phase, dim3(cdiv(c->M, 256)), dim3(256), 0, c->stream, c->M, c->lat.nx,
+                         c->lat.ny, c->lat.nz, c->lat.dx, c->lat.dy, nv, buf, c->theta);
+    });
+    c->launch(KC_SETUP, [&] {
+      if (c->esz == 16)
+        hipLaunchKernelGGL((k_imprint<double>), dim3(cdiv(c->M, 256), c->nst), dim3(256), 0, c->stream, c->M,
+                           c->nst, c->theta, (cpx<double>*)c->sb[c->phi]);
+      else
+        hipLaunchKernelGGL((k_imprint<float>), dim3(cdiv(c->M, 256), c->nst), dim3(256), 0, c->stream, c->M,
+                           c->nst, c->theta, (cpx<float>*)c->sb[c->phi]);
+    });
+    // a new initial state: restart the integrator from it
+    c->started = false;
+    c->steps = 0;
+    c->time = 0;
+    c->have_ref = false;
+    norm_of(*c, c->phi);
+    if (!c->frozen) {
+      c->eng->dens(*c, c->sb[c->phi], c->sscale[c->phi], c->nst);
+      c->eng->reduce_pot(*c, true);
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
+  });
+}
+
+tdslda_status tdslda_set_fields(tdslda_ctx* c, const double* U, const double* delta_reim) {
+  return guard(c, [&] {
+    if (!U && !delta_reim) {
+      c->frozen = false;
+      c->fields_valid = false;
+      if (c->loaded) {
+        c->eng->dens(*c, c->sb[c->phi], c->sscale[c->phi], c->nst);
+        c->eng->reduce_pot(*c, true);
+        c->fields_valid = true;
+      }
+      HIPCHK(hipStreamSynchronize(c->stream));
+      return;
+    }
+    require(U && delta_reim, TDSLDA_EINVAL, "give both U and Delta, or neither");
+    HIPCHK(hipMemcpyAsync(c->U, U, 8 * c->M, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->delta, delta_reim, 16 * c->M, hipMemcpyHostToDevice, c->stream));
+    c->launch(KC_SETUP, [&] {
+      if (c->esz == 16)
+        hipLaunchKernelGGL((k_set_fields<double>), dim3(cdiv(c->M, 256)), dim3(256), 0, c->stream, c->M, c->U,
+                           c->delta, c->vext, c->fun.mu, (double*)c->hA, (cpx<double>*)c->hD);
+      else
+        hipLaunchKernelGGL((k_set_fields<float>), dim3(cdiv(c->M, 256)), dim3(256), 0, c->stream, c->M, c->U,
+                           c->delta, c->vext, c->fun.mu, (float*)c->hA, (cpx<float>*)c->hD);
+    });
+    c->frozen = true;
+    c->fields_valid = true;
+    HIPCHK(hipStreamSynchronize(c->stream));
+  });
+}
+
+tdslda_status tdslda_densities(tdslda_ctx* c, double* rho, double* tau, double* nu_reim, double* j) {
+  return guard(c, [&] {
+    require(c->loaded, TDSLDA_EORDER, "load states first");
+    full_densities(*c);
+    if (rho) HIPCHK(hipMemcpyAsync(rho, c->rho, 8 * c->M, hipMemcpyDeviceToHost, c->stream));
+    if (tau) HIPCHK(hipMemcpyAsync(tau, c->tau, 8 * c->M, hipMemcpyDeviceToHost, c->stream));
+    if (nu_reim) HIPCHK(hipMemcpyAsync(nu_reim, c->nu, 16 * c->M, hipMemcpyDeviceToHost, c->stream));
+    if (j) HIPCHK(hipMemcpyAsync(j, c->jc, 24 * c->M, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+  });
+}
+
+tdslda_status tdslda_get_fields(tdslda_ctx* c, double* U, double* delta_reim) {
+  return guard(c, [&] {
+    require(c->fields_valid, TDSLDA_EORDER, "no fields yet");
+    if (U) HIPCHK(hipMemcpyAsync(U, c->U, 8 * c->M, hipMemcpyDeviceToHost, c->stream));
+    if (delta_reim) HIPCHK(hipMemcpyAsync(delta_reim, c->delta, 16 * c->M, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+  });
+}
+
+tdslda_status tdslda_apply_hbdg(tdslda_ctx* c, const void* in_dev, void* out_dev, int64_t n) {
+  return guard(c, [&] {
+    require(in_dev && out_dev && in_dev != out_dev, TDSLDA_EINVAL, "bad in/out pointers");
+    require(n > 0 && n <= c->cap, TDSLDA_EINVAL, "n out of range");
+    require(c->fields_valid, TDSLDA_EORDER, "no fields yet (load states or set fields)");
+    c->eng->lap1(*c, in_dev, nullptr, false, n);
+    L2Desc d;
+    d.mode = L2_H;
+    d.X = in_dev;
+    d.T = c->T;
+    d.out = out_dev;
+    c->eng->lap2(*c, d, n);
+    HIPCHK(hipStreamSynchronize(c->stream));
+  });
+}
+
+tdslda_status tdslda_abm_step(tdslda_ctx* c, int64_t nsteps) {
+  return guard(c, [&] {
+    require(c->loaded, TDSLDA_EORDER, "abm_step before any state load");
+    require(nsteps >= 0, TDSLDA_EINVAL, "nsteps < 0");
+    abm(*c, nsteps);
+    HIPCHK(hipStreamSynchronize(c->stream));
+  });
+}
+
+tdslda_status tdslda_energy(tdslda_ctx* c, double terms_out[8]) {
+  return guard(c, [&] {
+    require(c->loaded, TDSLDA_EORDER, "load states first");
+    require(terms_out != nullptr, TDSLDA_EINVAL, "terms_out is NULL");
+    energy(*c, terms_out);
+  });
+}
+
+tdslda_status tdslda_check(tdslda_ctx* c, double out[3]) {
+  tdslda_status extra = TDSLDA_OK;
+  tdslda_status st = guard(c, [&] {
+    require(c->loaded, TDSLDA_EORDER, "load states first");
+    double e[8];
+    energy(*c, e);
+    // norms of the stored state: 1/scale^2 must be 1 for a normalised state
+    std::vector<double> sc(c->nst);
+    norm_of(*c, c->phi);
+    HIPCHK(hipMemcpyAsync(sc.data(), c->sscale[c->phi], 8 * c->nst, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    double worst = 0;
+    bool finite = std::isfinite(e[5]) && std::isfinite(e[6]);
+    for (double s : sc) {
+      if (!std::isfinite(s) || s <= 0) {
+        finite = false;
+        continue;
+      }
+      worst = std::max(worst, std::fabs(1.0 / (s * s) - 1.0));
+    }
+    if (!c->have_ref) {
+      c->have_ref = true;
+      c->N0 = e[6];
+      c->E0 = e[5];
+    }
+    const double dn = std::fabs(e[6] - c->N0) / std::fabs(c->N0);
+    const double de = std::fabs(e[5] - c->E0) / std::fabs(e[7]);
+    if (out) {
+      out[0] = dn;
+      out[1] = de;
+      out[2] = worst;
+    }
+    if (!finite) {
+      c->err = "non-finite state norm or energy";
+      extra = TDSLDA_EUNSTABLE;
+    } else if ((c->run.tol_N > 0 && dn > c->run.tol_N) || (c->run.tol_E > 0 && de > c->run.tol_E)) {
+      c->err = "conservation check failed: dN/N=" + std::to_string(dn) + " dE/E_FG=" + std::to_string(de);
+      extra = TDSLDA_EUNSTABLE;
+    }
+  });
+  return st != TDSLDA_OK ? st : extra;
+}
+
+tdslda_status tdslda_get_states(tdslda_ctx* c, double* uv) {
+  return guard(c, [&] {
+    require(c->loaded, TDSLDA_EORDER, "load states first");
+    require(uv != nullptr, TDSLDA_EINVAL, "uv is NULL");
+    const int64_t per = 2 * c->M;
+    for (int64_t n0 = 0; n0 < c->nst; n0 += c->gchunk) {
+      const int64_t k = std::min(c->gchunk, c->nst - n0);
+      // scale into FP64 staging (per chunk, offset so state n0 lands at 0)
+      PwDesc d;
+      d.mode = PW_SCALE;
+      d.X = (char*)c->sb[c->phi] + size_t(n0) * per * c->esz;
+      d.scale = c->sscale[c->phi] + n0;
+      d.out64 = c->gscratch;
+      c->eng->pointwise(*c, d, k);
+      HIPCHK(hipMemcpyAsync(uv + n0 * per * 2, c->gscratch, size_t(k) * per * 16, hipMemcpyDeviceToHost, c->stream));
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
+  });
+}
+
+tdslda_status tdslda_info(tdslda_ctx* c, int64_t* nstates, int64_t* steps, double* time) {
+  return guard(c, [&] {
+    if (nstates) *nstates = c->nst;
+    if (steps) *steps = c->steps;
+    if (time) *time = c->time;
+  });
+}
+
+tdslda_status tdslda_save(tdslda_ctx* c, const char* path) {
+  return guard(c, [&] {
+    require(c->loaded && path, TDSLDA_EINVAL, "nothing to save or no path");
+    FILE* f = std::fopen(path, "wb");
+    require(f != nullptr, TDSLDA_EINVAL, std::string("cannot open ") + path);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    const int64_t per = 2 * c->M * c->esz;
+    int64_t hdr[8] = {0x5444534c4441LL, c->nst, c->M, int64_t(c->esz), c->depth, c->steps, int64_t(c->started), int64_t(c->frozen)};
+    std::vector<char> host(size_t(per) * std::min<int64_t>(c->nst, 256));
+    bool ok = std::fwrite(hdr, sizeof(hdr), 1, f) == 1 && std::fwrite(&c->time, 8, 1, f) == 1;
+    int roles[6] = {c->phi, c->hist[0], c->hist[1], c->hist[2], c->hist[3], c->hist[4]};
+    ok = ok && std::fwrite(roles, sizeof(roles), 1, f) == 1;
+    auto dump = [&](const void* dev, size_t bytes) {
+      std::vector<char> h(bytes);
+      HIPCHK(hipMemcpy(h.data(), dev, bytes, hipMemcpyDeviceToHost));
+      ok = ok && std::fwrite(h.data(), 1, bytes, f) == bytes;
+    };
+    for (int b = 0; b <= c->depth; ++b) {
+      for (int64_t n0 = 0; n0 < c->nst; n0 += 256) {
+        const int64_t k = std::min<int64_t>(256, c->nst - n0);
+        HIPCHK(hipMemcpy(host.data(), (char*)c->sb[b] + n0 * per, size_t(k) * per, hipMemcpyDeviceToHost));
+        ok = ok && std::fwrite(host.data(), 1, size_t(k) * per, f) == size_t(k) * per;
+      }
+      dump(c->sscale[b], 8 * c->nst);
+    }
+    dump(c->E, 8 * c->nst);
+    dump(c->kperp2, 8 * c->nst);
+    dump(c->vext, 8 * c->M);
+    dump(c->lam, 8 * c->M);
+    dump(c->U, 8 * c->M);
+    dump(c->delta, 16 * c->M);
+    std::fclose(f);
+    require(ok, TDSLDA_EINVAL, "short write");
+  });
+}
+
+tdslda_status tdslda_load(tdslda_ctx* c, const char* path) {
+  return guard(c, [&] {
+    require(path != nullptr, TDSLDA_EINVAL, "no path");
+    FILE* f = std::fopen(path, "rb");
+    require(f != nullptr, TDSLDA_EINVAL, std::string("cannot open ") + path);
+    int64_t hdr[8];
+    double t;
+    int roles[6];
+    bool ok = std::fread(hdr, sizeof(hdr), 1, f) == 1 && std::fread(&t, 8, 1, f) == 1 &&
+              std::fread(roles, sizeof(roles), 1, f) == 1;
+    if (!ok || hdr[0] != 0x5444534c4441LL || hdr[2] != c->M || hdr[3] != int64_t(c->esz) || hdr[4] != c->depth ||
+        hdr[1] > c->cap || hdr[1] <= 0) {
+      std::fclose(f);
+      throw Fail{TDSLDA_EINVAL, "checkpoint does not match this context"};
+    }
+    const int64_t n = hdr[1];
+    const int64_t per = 2 * c->M * c->esz;
+    std::vector<char> host(size_t(per) * std::min<int64_t>(n, 256));
+    auto undump = [&](void* dev, size_t bytes) {
+      std::vector<char> h(bytes);
+      ok = ok && std::fread(h.data(), 1, bytes, f) == bytes;
+      if (ok) HIPCHK(hipMemcpy(dev, h.data(), bytes, hipMemcpyHostToDevice));
+    };
+    for (int b = 0; b <= c->depth && ok; ++b) {
+      for (int64_t n0 = 0; n0 < n && ok; n0 += 256) {
+        const int64_t k = std::min<int64_t>(256, n - n0);
+        ok = std::fread(host.data(), 1, size_t(k) * per, f) == size_t(k) * per;
+        if (ok) HIPCHK(hipMemcpy((char*)c->sb[b] + n0 * per, host.data(), size_t(k) * per, hipMemcpyHostToDevice));
+      }
+      undump(c->sscale[b], 8 * n);
+    }
+    std::vector<double> E(n);
+    ok = ok && std::fread(E.data(), 8, n, f) == size_t(n);
+    undump(c->kperp2, 8 * n);
+    undump(c->vext, 8 * c->M);
+    undump(c->lam, 8 * c->M);
+    undump(c->U, 8 * c->M);
+    undump(c->delta, 16 * c->M);
+    std::fclose(f);
+    require(ok, TDSLDA_EINVAL, "short read");
+    c->nst = n;
+    set_weights(*c, n, E.data());
+    c->phi = roles[0];
+    for (int j = 0; j < 5; ++j) c->hist[j] = roles[j + 1];
+    c->steps = hdr[5];
+    c->started = hdr[6] != 0;
+    c->time = t;
+    c->loaded = true;
+    c->have_ref = false;
+    if (hdr[7]) {
+      c->launch(KC_SETUP, [&] {
+        if (c->esz == 16)
+          hipLaunchKernelGGL((k_set_fields<double>), dim3(cdiv(c->M, 256)), dim3(256), 0, c->stream, c->M, c->U,
+                             c->delta, c->vext, c->fun.mu, (double*)c->hA, (cpx<double>*)c->hD);
+        else
+          hipLaunchKernelGGL((k_set_fields<float>), dim3(cdiv(c->M, 256)), dim3(256), 0, c->stream, c->M, c->U,
+                             c->delta, c->vext, c->fun.mu, (float*)c->hA, (cpx<float>*)c->hD);
+      });
+      c->frozen = true;
+    } else {
+      c->frozen = false;
+      c->eng->dens(*c, c->sb[c->phi], c->sscale[c->phi], c->nst);
+      c->eng->reduce_pot(*c, true);
+    }
+    c->fields_valid = true;
+    HIPCHK(hipStreamSynchronize(c->stream));
+  });
+}
+
+tdslda_status tdslda_set_profiling(tdslda_ctx* c, int enable) {
+  return guard(c, [&] {
+    c->harvest();
+    c->prof = enable != 0;
+    for (int k = 0; k < KC_COUNT; ++k) {
+      c->klaunch[k] = 0;
+      c->kms[k] = 0;
+    }
+  });
+}
+
+tdslda_status tdslda_kernel_stats(tdslda_ctx* c, int k, int64_t* launches, double* total_ms) {
+  if (!c) return TDSLDA_EINVAL;
+  if (k < 0 || k >= KC_COUNT) return TDSLDA_EINVAL;
+  return guard(c, [&] {
+    c->harvest();
+    if (launches) *launches = c->klaunch[k];
+    if (total_ms) *total_ms = c->kms[k];
+  });
+}
+
+}  // extern "C"

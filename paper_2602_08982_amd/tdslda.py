@@ -1,0 +1,292 @@
+"""ctypes binding of libtdslda (include/tdslda.h).  Argument marshalling only:
+every step of the computation runs in the library's HIP kernels.
+
+Host arrays are numpy float64 / complex128 in C order; states are
+(n, 2, *grid) complex128 (component 0 = u, 1 = v).  Device arrays passed to
+apply_hbdg are torch tensors (or raw integer device pointers).
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtdslda.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, EORDER, EUNSTABLE = 0, -1, -2, -3, -4, -5
+MODE_3D, MODE_Q1D = 3, 1
+FUNC_SLDA, FUNC_BDG = 1, 2
+FP64, FP32_MIXED = 0, 1
+AB3AM4, AB4AM5, AB5AM5 = 34, 45, 55
+
+
+class Lattice(C.Structure):
+    _fields_ = [("mode", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
+                ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
+                ("lx_perp", C.c_double), ("ly_perp", C.c_double)]
+
+
+class Functional(C.Structure):
+    _fields_ = [("functional", C.c_int), ("A", C.c_double), ("B", C.c_double), ("C", C.c_double),
+                ("inv_g_bdg", C.c_double), ("ec_reg", C.c_double), ("mu", C.c_double),
+                ("temperature", C.c_double)]
+
+
+class Run(C.Structure):
+    _fields_ = [("precision", C.c_int), ("integrator", C.c_int), ("dt", C.c_double),
+                ("selfstart", C.c_int), ("taylor_order", C.c_int), ("tol_N", C.c_double),
+                ("tol_E", C.c_double), ("hip_stream", C.c_void_p)]
+
+
+class TdsldaError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"libtdslda status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+_SIGS = {
+    "tdslda_create": [C.POINTER(Lattice), C.POINTER(Functional), C.POINTER(Run), C.c_int64, C.POINTER(C.c_void_p)],
+    "tdslda_destroy": [C.c_void_p],
+    "tdslda_last_error": [C.c_void_p],
+    "tdslda_memory_plan": [C.POINTER(Lattice), C.POINTER(Run), C.c_int64, C.POINTER(C.c_int64)],
+    "tdslda_set_external": [C.c_void_p, C.c_void_p, C.c_int],
+    "tdslda_set_regulator": [C.c_void_p, C.c_void_p],
+    "tdslda_load_states": [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p],
+    "tdslda_load_states_device": [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p],
+    "tdslda_init_plane_waves": [C.c_void_p, C.c_int64, C.c_void_p, C.c_double, C.c_double],
+    "tdslda_imprint_vortices": [C.c_void_p, C.c_int, C.c_void_p],
+    "tdslda_set_fields": [C.c_void_p, C.c_void_p, C.c_void_p],
+    "tdslda_densities": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
+    "tdslda_get_fields": [C.c_void_p, C.c_void_p, C.c_void_p],
+    "tdslda_apply_hbdg": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64],
+    "tdslda_abm_step": [C.c_void_p, C.c_int64],
+    "tdslda_energy": [C.c_void_p, C.c_void_p],
+    "tdslda_check": [C.c_void_p, C.c_void_p],
+    "tdslda_get_states": [C.c_void_p, C.c_void_p],
+    "tdslda_info": [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_double)],
+    "tdslda_save": [C.c_void_p, C.c_char_p],
+    "tdslda_load": [C.c_void_p, C.c_char_p],
+    "tdslda_set_profiling": [C.c_void_p, C.c_int],
+    "tdslda_kernel_stats": [C.c_void_p, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_double)],
+    "tdslda_kernel_name": [C.c_int],
+}
+
+EXPORTED = tuple(_SIGS)
+
+
+def load_library(path=None):
+    """Load libtdslda.so (raises if it is not built: there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = path or LIB_PATH
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run python -m paper_2602_08982_amd.build")
+    lib = C.CDLL(path)
+    for name, args in _SIGS.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = C.c_char_p if name in ("tdslda_last_error", "tdslda_kernel_name") else C.c_int
+    _lib = lib
+    return lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _c128_as_f64(a):
+    a = np.ascontiguousarray(a, dtype=np.complex128)
+    return a.view(np.float64)
+
+
+def _dev_ptr(t):
+    if isinstance(t, int):
+        return C.c_void_p(t)
+    return C.c_void_p(t.data_ptr())
+
+
+def kernel_names():
+    lib = load_library()
+    out, k = [], 0
+    while True:
+        s = lib.tdslda_kernel_name(k)
+        if s is None:
+            return out
+        out.append(s.decode())
+        k += 1
+
+
+def memory_plan(lattice, run, nstates):
+    lib = load_library()
+    b = C.c_int64()
+    st = lib.tdslda_memory_plan(C.byref(lattice), C.byref(run), int(nstates), C.byref(b))
+    if st != OK:
+        raise TdsldaError(st, "memory_plan rejected the arguments")
+    return b.value
+
+
+class Context:
+    """One libtdslda context (one stream)."""
+
+    def __init__(self, lattice, functional, run, capacity):
+        self.lib = load_library()
+        self.lattice, self.functional, self.run = lattice, functional, run
+        h = C.c_void_p()
+        st = self.lib.tdslda_create(C.byref(lattice), C.byref(functional), C.byref(run), int(capacity), C.byref(h))
+        if st != OK:
+            raise TdsldaError(st, "tdslda_create failed (message on stderr)")
+        self.h = h
+        if lattice.mode == MODE_3D:
+            self.grid = (lattice.nx, lattice.ny, lattice.nz)
+        else:
+            self.grid = (lattice.nz,)
+        self.M = int(np.prod(self.grid))
+        self.capacity = int(capacity)
+
+    def _chk(self, st):
+        if st != OK:
+            msg = self.lib.tdslda_last_error(self.h)
+            raise TdsldaError(st, msg.decode() if msg else "")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.tdslda_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # --- set-up -----------------------------------------------------------
+    def set_external(self, vext, freeze_regulator=True):
+        v = _f64(vext).ravel()
+        self._chk(self.lib.tdslda_set_external(self.h, _p(v), int(freeze_regulator)))
+
+    def set_regulator(self, lam):
+        v = _f64(lam).ravel()
+        self._chk(self.lib.tdslda_set_regulator(self.h, _p(v)))
+
+    def load_states(self, phi, E, kperp2=None):
+        phi = np.asarray(phi)
+        n = phi.shape[0]
+        uv = _c128_as_f64(phi.reshape(n, 2, self.M))
+        e = _f64(E)
+        k = None if kperp2 is None else _f64(kperp2)
+        self._chk(self.lib.tdslda_load_states(self.h, n, _p(uv), _p(e), _p(k)))
+
+    def load_states_device(self, tensor, n, E, kperp2=None):
+        e = _f64(E)
+        k = None if kperp2 is None else _f64(kperp2)
+        self._chk(self.lib.tdslda_load_states_device(self.h, int(n), _dev_ptr(tensor), _p(e), _p(k)))
+
+    def init_plane_waves(self, kidx, u0, delta0):
+        k = np.ascontiguousarray(kidx, dtype=np.int32)
+        self._chk(self.lib.tdslda_init_plane_waves(self.h, k.shape[0], _p(k), float(u0), float(delta0)))
+
+    def imprint_vortices(self, vortices):
+        v = _f64(vortices).reshape(-1, 3)
+        self._chk(self.lib.tdslda_imprint_vortices(self.h, v.shape[0], _p(v)))
+
+    def set_fields(self, U=None, delta=None):
+        if U is None and delta is None:
+            self._chk(self.lib.tdslda_set_fields(self.h, None, None))
+            return
+        u = _f64(U).ravel()
+        d = _c128_as_f64(np.asarray(delta).ravel())
+        self._chk(self.lib.tdslda_set_fields(self.h, _p(u), _p(d)))
+
+    # --- evaluation ---------------------------------------------------------
+    def densities(self):
+        rho = np.empty(self.M)
+        tau = np.empty(self.M)
+        nu = np.empty(2 * self.M)
+        j = np.empty(3 * self.M)
+        self._chk(self.lib.tdslda_densities(self.h, _p(rho), _p(tau), _p(nu), _p(j)))
+        g = self.grid
+        return dict(rho=rho.reshape(g), tau=tau.reshape(g), nu=nu.view(np.complex128).reshape(g),
+                    j=[j[i * self.M:(i + 1) * self.M].reshape(g) for i in range(3)])
+
+    def get_fields(self):
+        U = np.empty(self.M)
+        d = np.empty(2 * self.M)
+        self._chk(self.lib.tdslda_get_fields(self.h, _p(U), _p(d)))
+        return U.reshape(self.grid), d.view(np.complex128).reshape(self.grid)
+
+    def apply_hbdg(self, x_dev, y_dev, n):
+        self._chk(self.lib.tdslda_apply_hbdg(self.h, _dev_ptr(x_dev), _dev_ptr(y_dev), int(n)))
+
+    def abm_step(self, nsteps=1):
+        self._chk(self.lib.tdslda_abm_step(self.h, int(nsteps)))
+
+    def energy(self):
+        out = np.empty(8)
+        self._chk(self.lib.tdslda_energy(self.h, _p(out)))
+        keys = ("kin", "pot", "pair", "curr", "potext", "total", "N", "EFG")
+        return dict(zip(keys, out.tolist()))
+
+    def check(self):
+        out = np.zeros(3)
+        st = self.lib.tdslda_check(self.h, _p(out))
+        return st, dict(dN=out[0], dE=out[1], norm=out[2])
+
+    def get_states(self, n=None):
+        nst, _, _ = self.info()
+        out = np.empty((nst, 2) + self.grid, dtype=np.complex128)
+        self._chk(self.lib.tdslda_get_states(self.h, _p(out.view(np.float64))))
+        return out
+
+    def info(self):
+        n, s, t = C.c_int64(), C.c_int64(), C.c_double()
+        self._chk(self.lib.tdslda_info(self.h, C.byref(n), C.byref(s), C.byref(t)))
+        return n.value, s.value, t.value
+
+    def save(self, path):
+        self._chk(self.lib.tdslda_save(self.h, os.fsencode(path)))
+
+    def load(self, path):
+        self._chk(self.lib.tdslda_load(self.h, os.fsencode(path)))
+
+    # --- profiling ----------------------------------------------------------
+    def set_profiling(self, on=True):
+        self._chk(self.lib.tdslda_set_profiling(self.h, int(on)))
+
+    def kernel_stats(self):
+        out = {}
+        for k, name in enumerate(kernel_names()):
+            n, ms = C.c_int64(), C.c_double()
+            self._chk(self.lib.tdslda_kernel_stats(self.h, k, C.byref(n), C.byref(ms)))
+            out[name] = (n.value, ms.value)
+        return out
+
+
+def lattice_3d(n, d=1.0):
+    nx, ny, nz = (n, n, n) if np.isscalar(n) else n
+    dx, dy, dz = (d, d, d) if np.isscalar(d) else d
+    return Lattice(MODE_3D, nx, ny, nz, dx, dy, dz, 0.0, 0.0)
+
+
+def lattice_q1d(nz, dz, lx, ly):
+    return Lattice(MODE_Q1D, 1, 1, nz, 1.0, 1.0, dz, lx, ly)
+
+
+def functional_slda(mu, ec_reg, B=-0.4332978244473528, C_=-11.11, temperature=0.0):
+    """Unitary-gas SLDA with A = 1 (B recomputed from the ASLDA formula at p=0)."""
+    return Functional(FUNC_SLDA, 1.0, B, C_, 0.0, ec_reg, mu, temperature)
+
+
+def functional_bdg(mu, ec_reg, a_s, temperature=0.0):
+    return Functional(FUNC_BDG, 1.0, 0.0, 0.0, 1.0 / (4.0 * np.pi * a_s), ec_reg, mu, temperature)
+
+
+def run_config(precision=FP64, integrator=AB4AM5, dt=0.005, selfstart=1, taylor_order=5,
+               tol_N=0.0, tol_E=0.0, stream=None):
+    return Run(precision, integrator, dt, selfstart, taylor_order, tol_N, tol_E, stream)

@@ -1,0 +1,68 @@
+"""Synthetic trapped-gas workloads of the benchmark (host-side set-up only:
+lattice momenta to start from, external potentials, vortex positions).
+The states themselves are generated and evolved by libtdslda.
+
+  plain_fp64_32 : 32^3, dx = 1, V_ext = omega^2 r^2 / 2 (omega = 0.05), one
+                  vortex along z at the centre + a seeded offset in
+                  [-2, 2)^2, all 32,768 plane-wave states of the uniform H
+                  (U = 0, Delta = 0.5, mu = 1), complex128.
+  mixed_fp32_48 : 48^3, dx = 1, V_ext = (w_perp^2 (x^2 + y^2) + w_z^2 z^2)/2
+                  with w_perp = 0.08, w_z = 0.02, a seeded vortex pair, the
+                  8,192 plane-wave states with the smallest |xi_k| (16,384
+                  quasiparticle states of both signs), complex64.
+"""
+import numpy as np
+
+from . import tdslda as T
+
+
+def centered(n, d):
+    return (np.arange(n) - n // 2) * float(d)
+
+
+def all_kidx(n):
+    nx, ny, nz = n
+    return np.array(np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij"),
+                    dtype=np.int32).reshape(3, -1).T.copy()
+
+
+def lowest_xi_kidx(n, d, mu, u0, count):
+    """The `count` lattice momenta with the smallest |k^2/2 + u0 - mu|;
+    ties broken by the lexicographic order of the integer indices."""
+    kid = all_kidx(n)
+    m = np.where(kid < np.array(n) // 2, kid, kid - np.array(n))
+    k2 = sum((2 * np.pi * m[:, a] / (n[a] * d[a])) ** 2 for a in range(3))
+    xi = np.abs(0.5 * k2 + u0 - mu)
+    order = np.lexsort((kid[:, 2], kid[:, 1], kid[:, 0], xi))
+    return kid[np.sort(order[:count])]
+
+
+def harmonic(n, d, omega):
+    X, Y, Z = np.meshgrid(*[centered(a, b) for a, b in zip(n, d)], indexing="ij")
+    wx, wy, wz = omega
+    return 0.5 * (wx ** 2 * X ** 2 + wy ** 2 * Y ** 2 + wz ** 2 * Z ** 2)
+
+
+PLAIN = dict(name="plain_fp64_32", n=(32, 32, 32), d=(1.0, 1.0, 1.0), mu=1.0, u0=0.0, delta0=0.5,
+             omega=(0.05, 0.05, 0.05), precision=T.FP64, dt=0.005, nstates=32768)
+MIXED = dict(name="mixed_fp32_48", n=(48, 48, 48), d=(1.0, 1.0, 1.0), mu=1.0, u0=0.0, delta0=0.5,
+             omega=(0.08, 0.08, 0.02), precision=T.FP32_MIXED, dt=0.005, nstates=8192)
+
+
+def setup(cfg, vortices, stream=None, precision=None, integrator=T.AB4AM5):
+    """Create a context, switch on the trap (regulator frozen with V_+ =
+    V_ext), generate the plane-wave states on the device and imprint the
+    vortices.  Returns (ctx, kidx)."""
+    n, d = cfg["n"], cfg["d"]
+    prec = cfg["precision"] if precision is None else precision
+    ec = 0.5 * (np.pi / d[0]) ** 2
+    if cfg["nstates"] == n[0] * n[1] * n[2]:
+        kidx = all_kidx(n)
+    else:
+        kidx = lowest_xi_kidx(n, d, cfg["mu"], cfg["u0"], cfg["nstates"])
+    run = T.run_config(precision=prec, integrator=integrator, dt=cfg["dt"], selfstart=1, stream=stream)
+    ctx = T.Context(T.lattice_3d(n, d), T.functional_slda(cfg["mu"], ec), run, len(kidx))
+    ctx.set_external(harmonic(n, d, cfg["omega"]), freeze_regulator=True)
+    ctx.init_plane_waves(kidx, cfg["u0"], cfg["delta0"])
+    ctx.imprint_vortices(vortices)
+    return ctx, kidx
