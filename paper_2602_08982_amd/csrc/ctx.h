@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
 #include <memory>
 #include <string>
 #include <vector>
@@ -151,6 +152,11 @@ struct tdslda_ctx {
       throw Fail{TDSLDA_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
     }
     allocs.push_back(p);
+    static const bool zero = std::getenv("TDSLDA_ZERO_ALLOC") != nullptr;
+    if (zero) {
+      HIPCHK(hipMemset(p, 0, bytes));
+      HIPCHK(hipDeviceSynchronize());
+    }
     return p;
   }
   hipEvent_t ev() {
@@ -177,6 +183,9 @@ struct tdslda_ctx {
       f();
       HIPCHK(hipGetLastError());
     }
+#ifdef TDSLDA_DEBUG_SYNC
+    HIPCHK(hipStreamSynchronize(stream));
+#endif
   }
   void harvest() {
     for (auto& e : events) {

@@ -87,7 +87,14 @@ struct Engine3D final : Engine {
         c.launch(KC_LAP2_CORR, [&] { hipLaunchKernelGGL((k_lap2<R, NX, NY, NZ, L2_CORR>), grid, block, 0, c.stream, A); });
         break;
       case L2_FULL:
-        c.launch(KC_LAP2_FULL, [&] { hipLaunchKernelGGL((k_lap2<R, NX, NY, NZ, L2_FULL>), grid, block, 0, c.stream, A); });
+        c.launch(KC_LAP2_FULL, [&] {
+          if (c.np == 3)
+            hipLaunchKernelGGL((k_lap2<R, NX, NY, NZ, L2_FULL, 3, 4>), grid, block, 0, c.stream, A);
+          else if (c.np == 5)
+            hipLaunchKernelGGL((k_lap2<R, NX, NY, NZ, L2_FULL, 5, 5>), grid, block, 0, c.stream, A);
+          else
+            hipLaunchKernelGGL((k_lap2<R, NX, NY, NZ, L2_FULL, 4, 5>), grid, block, 0, c.stream, A);
+        });
         break;
       default:
         c.launch(KC_LAP2_TAYLOR, [&] { hipLaunchKernelGGL((k_lap2<R, NX, NY, NZ, L2_TAYLOR>), grid, block, 0, c.stream, A); });
@@ -112,7 +119,14 @@ struct Engine3D final : Engine {
     if (d.mode == PW_NORM)
       c.launch(KC_NORM, [&] { hipLaunchKernelGGL((k_pointwise<R, NX, NY, NZ, PW_NORM>), grid, block, 0, c.stream, A); });
     else if (d.mode == PW_PRED)
-      c.launch(KC_PRED, [&] { hipLaunchKernelGGL((k_pointwise<R, NX, NY, NZ, PW_PRED>), grid, block, 0, c.stream, A); });
+      c.launch(KC_PRED, [&] {
+        if (c.np == 3)
+          hipLaunchKernelGGL((k_pointwise<R, NX, NY, NZ, PW_PRED, 3, 4>), grid, block, 0, c.stream, A);
+        else if (c.np == 5)
+          hipLaunchKernelGGL((k_pointwise<R, NX, NY, NZ, PW_PRED, 5, 5>), grid, block, 0, c.stream, A);
+        else
+          hipLaunchKernelGGL((k_pointwise<R, NX, NY, NZ, PW_PRED, 4, 5>), grid, block, 0, c.stream, A);
+      });
     else
       c.launch(KC_SETUP, [&] { hipLaunchKernelGGL((k_pointwise<R, NX, NY, NZ, PW_SCALE>), grid, block, 0, c.stream, A); });
   }

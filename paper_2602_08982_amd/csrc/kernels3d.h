@@ -373,7 +373,9 @@ struct Lap2Args {
   double cy2, cz2;       // (2 pi / L_y)^2, (2 pi / L_z)^2
 };
 
-template <typename R, int NX, int NY, int NZ, int MODE>
+// NP, NQ: predictor / corrector lengths of the integrator (FULL mode only),
+// compile-time so that the history buffers are addressed without branches.
+template <typename R, int NX, int NY, int NZ, int MODE, int NP = 4, int NQ = 5>
 __global__ __launch_bounds__((SlabCfg<NX, NY, NZ>::TB)) void k_lap2(Lap2Args<R> A) {
   using CFG = SlabCfg<NX, NY, NZ>;
   constexpr int TB = CFG::TB, P = CFG::P, SS = CFG::SS;
@@ -434,15 +436,17 @@ __global__ __launch_bounds__((SlabCfg<NX, NY, NZ>::TB)) void k_lap2(Lap2Args<R> 
   const bi32x4 rT = make_rsrc(A.T + so, SB);
   const bi32x4 rA = make_rsrc(A.hA, M * RS);
   const bi32x4 rD = make_rsrc(A.hD, M * ES);
-  bi32x4 rO{}, rC{}, rAcc{}, rH[5] = {};
+  constexpr int HD = (NP > NQ - 1) ? NP : NQ - 1;  // history depth
+  bi32x4 rO{}, rC{}, rAcc{}, rH[HD] = {};
   if constexpr (MODE != L2_CORR) rO = make_rsrc(A.out + so, SB);
   if constexpr (MODE == L2_TAYLOR) rAcc = make_rsrc(A.acc + so, SB);
   if constexpr (MODE == L2_CORR) rH[0] = make_rsrc(A.hist[0] + so, SB);
   if constexpr (MODE == L2_FULL) {
     rC = make_rsrc(A.cout + so, SB);
-#pragma unroll
-    for (int j = 1; j < 5; ++j)
-      if (j < A.np || j + 1 < A.nq) rH[j] = make_rsrc(A.hist[j] + so, SB);
+    sfor<1, HD>::run([&](auto jc) {
+      constexpr int j = decltype(jc)::value;
+      rH[j] = make_rsrc(A.hist[j] + so, SB);
+    });
   }
   double nacc = 0.0;
 #pragma unroll
@@ -500,21 +504,18 @@ __global__ __launch_bounds__((SlabCfg<NX, NY, NZ>::TB)) void k_lap2(Lap2Args<R> 
             bstore<R>(fv, rO, vt, ov);
             cpx<R> pu = u + R(A.b[0]) * fu, pv = v + R(A.b[0]) * fv;
             cpx<R> cu = u + R(A.a[1]) * fu, cv = v + R(A.a[1]) * fv;
-#pragma unroll
-            for (int j = 1; j < 5; ++j) {
-              const bool inp = j < A.np, inc = j + 1 < A.nq;
-              if (inp || inc) {
-                const cpx<R> hu = bload<R>(rH[j], vt, ou), hv = bload<R>(rH[j], vt, ov);
-                if (inp) {
-                  pu = pu + R(A.b[j]) * hu;
-                  pv = pv + R(A.b[j]) * hv;
-                }
-                if (inc) {
-                  cu = cu + R(A.a[j + 1]) * hu;
-                  cv = cv + R(A.a[j + 1]) * hv;
-                }
+            sfor<1, HD>::run([&](auto jc) {
+              constexpr int j = decltype(jc)::value;
+              const cpx<R> hu = bload<R>(rH[j], vt, ou), hv = bload<R>(rH[j], vt, ov);
+              if constexpr (j < NP) {
+                pu = pu + R(A.b[j]) * hu;
+                pv = pv + R(A.b[j]) * hv;
               }
-            }
+              if constexpr (j + 1 < NQ) {
+                cu = cu + R(A.a[j + 1]) * hu;
+                cv = cv + R(A.a[j + 1]) * hv;
+              }
+            });
             bstore<R>(pu, rX, vt, ou);
             bstore<R>(pv, rX, vt, ov);
             bstore<R>(cu, rC, vt, ou);
@@ -548,7 +549,7 @@ struct PwArgs {
   cpx<double>* out64;     // SCALE: FP64 copy of the normalised state
 };
 
-template <typename R, int NX, int NY, int NZ, int MODE>
+template <typename R, int NX, int NY, int NZ, int MODE, int NP = 4, int NQ = 5>
 __global__ __launch_bounds__((SlabCfg<NX, NY, NZ>::TB)) void k_pointwise(PwArgs<R> A) {
   using CFG = SlabCfg<NX, NY, NZ>;
   constexpr int TB = CFG::TB, P = CFG::P, SS = CFG::SS;
@@ -560,12 +561,14 @@ __global__ __launch_bounds__((SlabCfg<NX, NY, NZ>::TB)) void k_pointwise(PwArgs<
   const int64_t so = n * 2 * M;
   const uint32_t SB = 2 * M * ES;
   const bi32x4 rX = make_rsrc(A.X + so, SB);
-  bi32x4 rH[5] = {}, rC{};
+  constexpr int HD = (NP > NQ - 1) ? NP : NQ - 1;
+  bi32x4 rH[HD] = {}, rC{};
   if constexpr (MODE == PW_PRED) {
     rC = make_rsrc(A.cout + so, SB);
-#pragma unroll
-    for (int j = 0; j < 5; ++j)
-      if (j < A.np || j + 1 < A.nq) rH[j] = make_rsrc(A.hist[j] + so, SB);
+    sfor<0, HD>::run([&](auto jc) {
+      constexpr int j = decltype(jc)::value;
+      rH[j] = make_rsrc(A.hist[j] + so, SB);
+    });
   }
   const int vt = tid * ES;
   double nacc = 0.0;
@@ -586,15 +589,12 @@ __global__ __launch_bounds__((SlabCfg<NX, NY, NZ>::TB)) void k_pointwise(PwArgs<
           const R s = R(A.scale[n]);
           const cpx<R> phi = s * bload<R>(rX, vt, o);
           cpx<R> pp = phi, cc = phi;
-#pragma unroll
-          for (int j = 0; j < 5; ++j) {
-            const bool inp = j < A.np, inc = j + 1 < A.nq;
-            if (inp || inc) {
-              const cpx<R> f = bload<R>(rH[j], vt, o);
-              if (inp) pp = pp + R(A.b[j]) * f;
-              if (inc) cc = cc + R(A.a[j + 1]) * f;
-            }
-          }
+          sfor<0, HD>::run([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            const cpx<R> f = bload<R>(rH[j], vt, o);
+            if constexpr (j < NP) pp = pp + R(A.b[j]) * f;
+            if constexpr (j + 1 < NQ) cc = cc + R(A.a[j + 1]) * f;
+          });
           bstore<R>(pp, rX, vt, o);
           bstore<R>(cc, rC, vt, o);
           nacc += norm2(pp);

@@ -7,13 +7,15 @@
 namespace tdslda {
 
 // finalize per-state scalars
-__global__ void k_finalize(int64_t nstates, StateScalars sc, int n_nrm, int n_h, int do_scale, int do_h) {
+// (norm^2 = dV sum |phi|^2; the partials hold the plain sums)
+__global__ void k_finalize(int64_t nstates, StateScalars sc, int n_nrm, int n_h, int do_scale, int do_h,
+                           double dV) {
   const int64_t n = int64_t(blockIdx.x) * 256 + threadIdx.x;
   if (n >= nstates) return;
   if (do_scale) {
     double s = 0.0;
     for (int i = 0; i < n_nrm; ++i) s += sc.nrm_part[n * sc.nrm_stride + i];
-    sc.scale[n] = 1.0 / sqrt(s);
+    sc.scale[n] = 1.0 / sqrt(dV * s);
   }
   if (do_h) {
     double s = 0.0;

@@ -1,7 +1,545 @@
-// Quasi-1D kernel set (placeholder until the batched quasi-1D kernels land).
+// Quasi-1D kernel set (paper Sec. 3.1, quasi-1D item): every state is a line
+// of N_z = A*A sites carrying its transverse momentum k_perp^2; all the
+// problems of the transverse grid form one flat batch of states, so uneven
+// per-problem state counts need no special handling.
+//
+// A state is owned by a group of A lanes; lane a holds sites z = a + A*b,
+// b = 0..A-1.  Transforms along z are four-step DFTs: A-point DFTs in
+// registers, a twiddle, and a transpose through LDS.
 #include "ctx.h"
 
 namespace tdslda {
-std::unique_ptr<Engine> make_q1d_f64(int) { return nullptr; }
-std::unique_ptr<Engine> make_q1d_f32(int) { return nullptr; }
+namespace {
+
+// twiddle table w[m] = exp(+2 pi i m / N), m = 0..N-1 (host-filled)
+template <typename R, int A>
+struct Q1DCfg {
+  static constexpr int N = A * A;
+  static constexpr int TB = 256;
+  static constexpr int WS = TB / A;    // states in flight per workgroup
+  static constexpr int PAD = A + 1;    // LDS row pitch
+};
+
+// forward four-step DFT (sign -1, unnormalised).  In: v[b] = x[a + A b].
+// Out: v[p] = X[l + A k1] with k1 = freq_of_pos<A>(p), l = this lane.
+template <typename R, int A>
+__device__ __forceinline__ void q_fwd(cpx<R> (&v)[A], int a, cpx<R>* lds, const cpx<R>* tw) {
+  constexpr int N = A * A, PAD = A + 1;
+  fwd<A>(v);
+  sfor<0, A>::run([&](auto pc) {
+    constexpr int p = decltype(pc)::value;
+    constexpr int k2 = freq_of_pos<A>(p);
+    const cpx<R> w = tw[(a * k2) % N];
+    lds[a * PAD + k2] = v[p] * cpx<R>{w.x, -w.y};  // exp(-2 pi i a k2 / N)
+  });
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < A; ++j) v[j] = lds[j * PAD + a];
+  __syncthreads();
+  fwd<A>(v);
+}
+
+// inverse of q_fwd (sign +1, unnormalised): back to v[b] = x[a + A b]
+template <typename R, int A>
+__device__ __forceinline__ void q_inv(cpx<R> (&v)[A], int a, cpx<R>* lds, const cpx<R>* tw) {
+  constexpr int N = A * A, PAD = A + 1;
+  inv<A>(v);  // v[j] = Y1[j][l = a]
+#pragma unroll
+  for (int j = 0; j < A; ++j) lds[j * PAD + a] = v[j] * tw[(j * a) % N];
+  __syncthreads();
+  sfor<0, A>::run([&](auto pc) {
+    constexpr int p = decltype(pc)::value;
+    v[p] = lds[a * PAD + freq_of_pos<A>(p)];
+  });
+  __syncthreads();
+  inv<A>(v);
+}
+
+// wave number of the frequency held at position p of lane l after q_fwd
+template <int A>
+__device__ __forceinline__ int q_wavenum(int l, int p_k1) {
+  constexpr int N = A * A;
+  const int k = l + A * p_k1;
+  return k < N / 2 ? k : k - N;
+}
+
+// ---------------------------------------------------------------------------
+// dens: rho, nu partials over a group of G states per workgroup and the
+// kinetic part 1/2 (int |d u|^2 - int |d v|^2) of <H>_n (slot 0).
+template <typename R, int A, int G>
+__global__ __launch_bounds__(256) void q_dens(const cpx<R>* __restrict__ X, int64_t nstates,
+                                              const double* __restrict__ wu, const double* __restrict__ wv,
+                                              StateScalars sc, double* __restrict__ dens_part,
+                                              const cpx<R>* __restrict__ tw, double kz2, double dz) {
+  using CFG = Q1DCfg<R, A>;
+  constexpr int N = CFG::N, WS = CFG::WS;
+  constexpr int NW = CFG::TB / kWave;
+  __shared__ cpx<R> lds_all[WS][A * CFG::PAD];
+  __shared__ double red[NW][3 * N];
+  const int tid = threadIdx.x, grp = tid / A, a = tid % A;
+  cpx<R>* lds = lds_all[grp];
+  double ar[A], anr[A], ani[A];
+#pragma unroll
+  for (int b = 0; b < A; ++b) ar[b] = anr[b] = ani[b] = 0.0;
+  const int64_t nbeg = int64_t(blockIdx.x) * G;
+  for (int it = 0; it < G / WS; ++it) {
+    const int64_t n = nbeg + it * WS + grp;
+    const bool live = n < nstates;
+    const int64_t nn = live ? n : 0;
+    const R s = live ? R(sc.scale[nn]) : R(0);
+    const double fu = live ? wu[nn] : 0.0, fv = live ? wv[nn] : 0.0;
+    const cpx<R>* Xn = X + nn * 2 * N;
+    cpx<R> u[A], v[A];
+#pragma unroll
+    for (int b = 0; b < A; ++b) {
+      u[b] = s * Xn[a + A * b];
+      v[b] = s * Xn[N + a + A * b];
+      const double ur = u[b].x, ui = u[b].y, vr = v[b].x, vi = v[b].y;
+      ar[b] += fv * (vr * vr + vi * vi) + fu * (ur * ur + ui * ui);
+      const double dw = fv - fu;
+      anr[b] += dw * (ur * vr + ui * vi);
+      ani[b] += dw * (ui * vr - ur * vi);
+    }
+    q_fwd<R, A>(u, a, lds, tw);
+    q_fwd<R, A>(v, a, lds, tw);
+    double ku = 0.0, kv = 0.0;
+    sfor<0, A>::run([&](auto pc) {
+      constexpr int p = decltype(pc)::value;
+      const int m = q_wavenum<A>(a, freq_of_pos<A>(p));
+      ku += double(m * m) * norm2(u[p]);
+      kv += double(m * m) * norm2(v[p]);
+    });
+    double kin = 0.5 * (ku - kv) * kz2 / double(N) * dz;
+#pragma unroll
+    for (int o = A / 2; o > 0; o >>= 1) kin += __shfl_xor(kin, o, A);
+    if (live && a == 0) sc.h_part[n * sc.h_stride + 0] = kin;
+  }
+  // sum the lane groups: within a wave by shuffles (lanes a, a+A, ... hold
+  // the same sites), then over the waves in LDS (fixed order)
+#pragma unroll
+  for (int b = 0; b < A; ++b) {
+#pragma unroll
+    for (int o = A; o < kWave; o <<= 1) {
+      ar[b] += __shfl_xor(ar[b], o, kWave);
+      anr[b] += __shfl_xor(anr[b], o, kWave);
+      ani[b] += __shfl_xor(ani[b], o, kWave);
+    }
+  }
+  const int w = tid / kWave, lw = tid % kWave;
+  if (lw < A) {
+#pragma unroll
+    for (int b = 0; b < A; ++b) {
+      red[w][a + A * b] = ar[b];
+      red[w][N + a + A * b] = anr[b];
+      red[w][2 * N + a + A * b] = ani[b];
+    }
+  }
+  __syncthreads();
+  double* out = dens_part + int64_t(blockIdx.x) * 3 * N;
+  for (int i = tid; i < 3 * N; i += CFG::TB) {
+    double t = 0.0;
+#pragma unroll
+    for (int w2 = 0; w2 < NW; ++w2) t += red[w2][i];
+    out[i] = t;
+  }
+}
+
+// lap1: T = D2z phi and the potential part of <H>_n (slot 1):
+// int [ (A + k_perp^2/2) (|u|^2 - |v|^2) + 2 Re(u^* Delta v) ]
+template <typename R, int A>
+__global__ __launch_bounds__(256) void q_lap1(const cpx<R>* __restrict__ X, int64_t nstates,
+                                              const double* __restrict__ scale, cpx<R>* __restrict__ T,
+                                              const R* __restrict__ hA, const cpx<R>* __restrict__ hD,
+                                              const double* __restrict__ kperp2, double* __restrict__ h_part,
+                                              int h_stride, const cpx<R>* __restrict__ tw, double kz2, double dz) {
+  using CFG = Q1DCfg<R, A>;
+  constexpr int N = CFG::N, WS = CFG::WS;
+  __shared__ cpx<R> lds_all[WS][A * CFG::PAD];
+  const int tid = threadIdx.x, grp = tid / A, a = tid % A;
+  cpx<R>* lds = lds_all[grp];
+  const int64_t n = int64_t(blockIdx.x) * WS + grp;
+  const bool live = n < nstates;
+  const int64_t nn = live ? n : 0;
+  const R s = scale ? R(scale[nn]) : R(1);
+  const double half_kp = 0.5 * kperp2[nn];
+  const cpx<R>* Xn = X + nn * 2 * N;
+  cpx<R> u[A], v[A];
+  double pot = 0.0;
+#pragma unroll
+  for (int b = 0; b < A; ++b) {
+    const int z = a + A * b;
+    u[b] = s * Xn[z];
+    v[b] = s * Xn[N + z];
+    const cpx<R> dv = hD[z] * v[b];
+    pot += (double(hA[z]) + half_kp) * (norm2(u[b]) - norm2(v[b]));
+    pot += 2.0 * (double(u[b].x) * double(dv.x) + double(u[b].y) * double(dv.y));
+  }
+  const R f = R(-kz2 / double(N));
+  auto d2 = [&](cpx<R>(&w)[A], int comp) {
+    q_fwd<R, A>(w, a, lds, tw);
+    sfor<0, A>::run([&](auto pc) {
+      constexpr int p = decltype(pc)::value;
+      const int m = q_wavenum<A>(a, freq_of_pos<A>(p));
+      w[p] = (f * R(m * m)) * w[p];
+    });
+    q_inv<R, A>(w, a, lds, tw);
+    if (live) {
+      cpx<R>* Tn = T + nn * 2 * N + comp * N;
+#pragma unroll
+      for (int b = 0; b < A; ++b) Tn[a + A * b] = w[b];
+    }
+  };
+  d2(u, 0);
+  d2(v, 1);
+  double t = pot * dz;
+#pragma unroll
+  for (int o = A / 2; o > 0; o >>= 1) t += __shfl_xor(t, o, A);
+  if (live && a == 0 && h_part) h_part[n * h_stride + 1] = t;
+}
+
+// lap2: pointwise H from T and the integrator modes (see k_lap2)
+template <typename R, int A, int MODE, int NP = 4, int NQ = 5>
+__global__ __launch_bounds__(256) void q_lap2(Lap2Args<R> P, int64_t nstates, const double* __restrict__ kperp2) {
+  constexpr int HD = (NP > NQ - 1) ? NP : NQ - 1;
+  using CFG = Q1DCfg<R, A>;
+  constexpr int N = CFG::N, WS = CFG::WS;
+  const int tid = threadIdx.x, grp = tid / A, a = tid % A;
+  const int64_t n = int64_t(blockIdx.x) * WS + grp;
+  if (n >= nstates) return;  // whole lane groups leave together; no barriers below
+  const R s = P.scale ? R(P.scale[n]) : R(1);
+  const R h = P.hshift ? R(P.hshift[n]) : R(0);
+  const R hk = R(0.5 * kperp2[n]);
+  const int64_t so = n * 2 * N;
+  double nacc = 0.0;
+#pragma unroll
+  for (int b = 0; b < A; ++b) {
+    const int z = a + A * b;
+    const int64_t iu = so + z, iv = so + N + z;
+    const cpx<R> u = s * P.X[iu], v = s * P.X[iv];
+    const cpx<R> lu = P.T[iu], lv = P.T[iv];
+    const R fa = P.hA[z] + hk;
+    const cpx<R> D = P.hD[z];
+    const cpx<R> Hu = R(-0.5) * lu + fa * u + D * v;
+    const cpx<R> Hv = conj(D) * u + R(0.5) * lv - fa * v;
+    if constexpr (MODE == L2_H) {
+      P.out[iu] = Hu;
+      P.out[iv] = Hv;
+    } else {
+      const cpx<R> gu = Hu - h * u, gv = Hv - h * v;
+      if constexpr (MODE == L2_TAYLOR) {
+        const cpx<R> c{R(P.tay_re), R(P.tay_im)};
+        const cpx<R> ou = c * gu, ov = c * gv;
+        P.out[iu] = ou;
+        P.out[iv] = ov;
+        const cpx<R> su = P.init_acc ? u + ou : P.acc[iu] + ou;
+        const cpx<R> sv = P.init_acc ? v + ov : P.acc[iv] + ov;
+        P.acc[iu] = su;
+        P.acc[iv] = sv;
+        nacc += norm2(su) + norm2(sv);
+      } else {
+        const cpx<R> fu{gu.y, -gu.x}, fv{gv.y, -gv.x};
+        if constexpr (MODE == L2_F) {
+          P.out[iu] = fu;
+          P.out[iv] = fv;
+        } else if constexpr (MODE == L2_CORR) {
+          const R a0 = R(P.a[0]);
+          const cpx<R> nu_ = P.hist[0][iu] + a0 * fu, nv_ = P.hist[0][iv] + a0 * fv;
+          P.Xout[iu] = nu_;
+          P.Xout[iv] = nv_;
+          nacc += norm2(nu_) + norm2(nv_);
+        } else {  // L2_FULL
+          P.out[iu] = fu;
+          P.out[iv] = fv;
+          cpx<R> pu = u + R(P.b[0]) * fu, pv = v + R(P.b[0]) * fv;
+          cpx<R> cu = u + R(P.a[1]) * fu, cv = v + R(P.a[1]) * fv;
+          sfor<1, HD>::run([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            const cpx<R> hu = P.hist[j][iu], hv = P.hist[j][iv];
+            if constexpr (j < NP) {
+              pu = pu + R(P.b[j]) * hu;
+              pv = pv + R(P.b[j]) * hv;
+            }
+            if constexpr (j + 1 < NQ) {
+              cu = cu + R(P.a[j + 1]) * hu;
+              cv = cv + R(P.a[j + 1]) * hv;
+            }
+          });
+          P.Xout[iu] = pu;
+          P.Xout[iv] = pv;
+          P.cout[iu] = cu;
+          P.cout[iv] = cv;
+          nacc += norm2(pu) + norm2(pv);
+        }
+      }
+    }
+  }
+  if (P.nrm_part) {
+#pragma unroll
+    for (int o = A / 2; o > 0; o >>= 1) nacc += __shfl_xor(nacc, o, A);
+    if (a == 0) P.nrm_part[n * P.nrm_stride] = nacc;
+  }
+}
+
+template <typename R, int A, int MODE, int NP = 4, int NQ = 5>
+__global__ __launch_bounds__(256) void q_pointwise(PwArgs<R> P, int64_t nstates) {
+  constexpr int HD = (NP > NQ - 1) ? NP : NQ - 1;
+  using CFG = Q1DCfg<R, A>;
+  constexpr int N = CFG::N, WS = CFG::WS;
+  const int tid = threadIdx.x, grp = tid / A, a = tid % A;
+  const int64_t n = int64_t(blockIdx.x) * WS + grp;
+  if (n >= nstates) return;
+  const int64_t so = n * 2 * N;
+  double nacc = 0.0;
+#pragma unroll
+  for (int b = 0; b < 2 * A; ++b) {
+    const int64_t ix = so + a + A * b;  // both components: b < A is u, b >= A is v
+    if constexpr (MODE == PW_NORM) {
+      nacc += norm2(P.X[ix]);
+    } else if constexpr (MODE == PW_SCALE) {
+      const double sc = P.scale[n];
+      const cpx<R> x = P.X[ix];
+      P.out64[ix] = cpx<double>{sc * double(x.x), sc * double(x.y)};
+    } else {
+      const R sc = R(P.scale[n]);
+      const cpx<R> phi = sc * P.X[ix];
+      cpx<R> pp = phi, cc = phi;
+      sfor<0, HD>::run([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        const cpx<R> f = P.hist[j][ix];
+        if constexpr (j < NP) pp = pp + R(P.b[j]) * f;
+        if constexpr (j + 1 < NQ) cc = cc + R(P.a[j + 1]) * f;
+      });
+      P.X[ix] = pp;
+      P.cout[ix] = cc;
+      nacc += norm2(pp);
+    }
+  }
+  if (MODE != PW_SCALE && P.nrm_part) {
+#pragma unroll
+    for (int o = A / 2; o > 0; o >>= 1) nacc += __shfl_xor(nacc, o, A);
+    if (a == 0) P.nrm_part[n * P.nrm_stride] = nacc;
+  }
+}
+
+// kinetic / current densities of a chunk of states into per-state scratch:
+// tau_n = w_v (k_perp^2 |v|^2 + |D1 v|^2 + (pi/dz)^2 |c_v|^2) + (same for u, w_u)
+// j_z  = w_v Im(v D1 v^*) - w_u Im(u D1 u^*);  j_x = j_y = 0
+template <typename R, int A>
+__global__ __launch_bounds__(256) void q_grad(const cpx<R>* __restrict__ X, int64_t n0, int64_t nchunk,
+                                              const double* __restrict__ scale, const double* __restrict__ wu,
+                                              const double* __restrict__ wv, const double* __restrict__ kperp2,
+                                              const cpx<R>* __restrict__ tw, double kz, double nyq2,
+                                              double* __restrict__ tau_s, double* __restrict__ j_s) {
+  using CFG = Q1DCfg<R, A>;
+  constexpr int N = CFG::N, WS = CFG::WS;
+  __shared__ cpx<R> lds_all[WS][A * CFG::PAD];
+  __shared__ cpx<R> nyq_s[WS];
+  const int tid = threadIdx.x, grp = tid / A, a = tid % A;
+  cpx<R>* lds = lds_all[grp];
+  const int64_t c = int64_t(blockIdx.x) * WS + grp;
+  const bool live = c < nchunk;
+  const int64_t cc = live ? c : 0;
+  const int64_t n = n0 + cc;
+  const R s = R(scale[n]);
+  const double kp = kperp2[n];
+  double* ts = tau_s + cc * N;
+  double* js = j_s + cc * 3 * N;
+#pragma unroll 1
+  for (int comp = 0; comp < 2; ++comp) {
+    const double w = comp ? wv[n] : wu[n];
+    const double sg = comp ? 1.0 : -1.0;
+    const cpx<R>* src = X + n * 2 * N + comp * N;
+    cpx<R> d[A];
+#pragma unroll
+    for (int b = 0; b < A; ++b) d[b] = s * src[a + A * b];
+    q_fwd<R, A>(d, a, lds, tw);
+    // Nyquist bin N/2 = l + A k1 with l = (N/2) % A, k1 = (N/2) / A
+    const R f = R(kz / double(N));
+    sfor<0, A>::run([&](auto pc) {
+      constexpr int p = decltype(pc)::value;
+      const int k1 = freq_of_pos<A>(p);
+      const int k = a + A * k1;
+      if (k == N / 2) {
+        nyq_s[grp] = (R(1) / R(N)) * d[p];
+        d[p] = cpx<R>{R(0), R(0)};
+      } else {
+        const int m = k < N / 2 ? k : k - N;
+        d[p] = (f * R(m)) * mul_i(d[p]);
+      }
+    });
+    q_inv<R, A>(d, a, lds, tw);  // contains barriers: nyq_s is visible after it
+    const double cn = nyq2 * norm2(nyq_s[grp]);
+    if (live) {
+#pragma unroll
+      for (int b = 0; b < A; ++b) {
+        const int z = a + A * b;
+        const cpx<R> x = s * src[z];
+        const double tv = w * (kp * norm2(x) + norm2(d[b]) + cn);
+        const double jv = sg * w * (double(x.y) * double(d[b].x) - double(x.x) * double(d[b].y));
+        if (comp == 0) {
+          ts[z] = tv;
+          js[z] = 0.0;
+          js[N + z] = 0.0;
+          js[2 * N + z] = jv;
+        } else {
+          ts[z] += tv;
+          js[2 * N + z] += jv;
+        }
+      }
+    }
+    __syncthreads();  // nyq_s reused by the next component
+  }
+}
+
+template <typename R, int A>
+struct EngineQ1D final : Engine {
+  using CFG = Q1DCfg<R, A>;
+  static constexpr int N = CFG::N;
+  static constexpr int G = 512;  // states per density group
+  cpx<R>* tw = nullptr;
+  int ngx() const override { return 1; }
+  int ncb() const override { return 1; }
+  int group() const override { return G; }
+  size_t elem_size() const override { return sizeof(cpx<R>); }
+
+  void twiddles(Ctx& c) {
+    if (tw) return;
+    tw = (cpx<R>*)c.dalloc(sizeof(cpx<R>) * N);
+    std::vector<cpx<R>> h(N);
+    for (int m = 0; m < N; ++m) {
+      const ct::cs w = ct::cossin(m, N);
+      h[m] = cpx<R>{R(w.c), R(w.s)};
+    }
+    HIPCHK(hipMemcpy(tw, h.data(), sizeof(cpx<R>) * N, hipMemcpyHostToDevice));
+  }
+  double kz2(const Ctx& c) const { double k = 2 * kPi / (N * c.lat.dz); return k * k; }
+
+  void dens(Ctx& c, const void* X, const double* scale, int64_t nst) override {
+    twiddles(c);
+    const unsigned ng = cdiv(nst, G);
+    c.launch(KC_DENS, [&] {
+      hipLaunchKernelGGL((q_dens<R, A, G>), dim3(ng), dim3(CFG::TB), 0, c.stream, (const cpx<R>*)X, nst, c.wu,
+                         c.wv, c.scalars(const_cast<double*>(scale)), c.dens_part, tw, kz2(c), c.lat.dz);
+    });
+    c.nsg_used = int(ng);
+  }
+  void reduce_pot(Ctx& c, bool update) override {
+    FunParams fp{c.fun.functional, c.fun.B, c.fun.C, c.fun.inv_g_bdg, c.fun.mu, c.ainv};
+    c.launch(KC_REDUCE_POT, [&] {
+      hipLaunchKernelGGL((k_reduce_pot<R>), dim3(cdiv(N, 256)), dim3(256), 0, c.stream, c.dens_part, c.nsg_used,
+                         int64_t(N), fp, c.lam, c.vext, c.rho, c.nu, c.U, c.delta, (R*)c.hA, (cpx<R>*)c.hD,
+                         int(update));
+    });
+  }
+  void lap1(Ctx& c, const void* X, const double* scale, bool hpart, int64_t nst) override {
+    twiddles(c);
+    c.launch(KC_LAP1, [&] {
+      hipLaunchKernelGGL((q_lap1<R, A>), dim3(cdiv(nst, CFG::WS)), dim3(CFG::TB), 0, c.stream, (const cpx<R>*)X,
+                         nst, scale, (cpx<R>*)c.T, (const R*)c.hA, (const cpx<R>*)c.hD, c.kperp2,
+                         hpart ? c.h_part : nullptr, c.h_stride, tw, kz2(c), c.lat.dz);
+    });
+  }
+  void lap2(Ctx& c, const L2Desc& d, int64_t nst) override {
+    Lap2Args<R> P{};
+    P.X = (const cpx<R>*)d.X;
+    P.Xout = (cpx<R>*)d.Xout;
+    P.T = (const cpx<R>*)d.T;
+    P.hA = (const R*)c.hA;
+    P.hD = (const cpx<R>*)c.hD;
+    P.scale = d.scale;
+    P.hshift = d.hshift;
+    P.out = (cpx<R>*)d.out;
+    P.acc = (cpx<R>*)d.acc;
+    for (int i = 0; i < 5; ++i) P.hist[i] = (const cpx<R>*)d.hist[i];
+    P.cout = (cpx<R>*)d.cout;
+    P.nrm_part = d.nrm_part;
+    P.nrm_stride = c.nrm_stride;
+    P.np = c.np;
+    P.nq = c.nq;
+    for (int i = 0; i < 5; ++i) {
+      P.b[i] = c.bco[i];
+      P.a[i] = c.aco[i];
+    }
+    P.tay_re = d.tay_re;
+    P.tay_im = d.tay_im;
+    P.init_acc = d.init_acc;
+    dim3 grid(cdiv(nst, CFG::WS)), block(CFG::TB);
+    switch (d.mode) {
+      case L2_H:
+        c.launch(KC_LAP2_H, [&] { hipLaunchKernelGGL((q_lap2<R, A, L2_H>), grid, block, 0, c.stream, P, nst, c.kperp2); });
+        break;
+      case L2_F:
+        c.launch(KC_LAP2_F, [&] { hipLaunchKernelGGL((q_lap2<R, A, L2_F>), grid, block, 0, c.stream, P, nst, c.kperp2); });
+        break;
+      case L2_CORR:
+        c.launch(KC_LAP2_CORR, [&] { hipLaunchKernelGGL((q_lap2<R, A, L2_CORR>), grid, block, 0, c.stream, P, nst, c.kperp2); });
+        break;
+      case L2_FULL:
+        c.launch(KC_LAP2_FULL, [&] {
+          if (c.np == 3)
+            hipLaunchKernelGGL((q_lap2<R, A, L2_FULL, 3, 4>), grid, block, 0, c.stream, P, nst, c.kperp2);
+          else if (c.np == 5)
+            hipLaunchKernelGGL((q_lap2<R, A, L2_FULL, 5, 5>), grid, block, 0, c.stream, P, nst, c.kperp2);
+          else
+            hipLaunchKernelGGL((q_lap2<R, A, L2_FULL, 4, 5>), grid, block, 0, c.stream, P, nst, c.kperp2);
+        });
+        break;
+      default:
+        c.launch(KC_LAP2_TAYLOR, [&] { hipLaunchKernelGGL((q_lap2<R, A, L2_TAYLOR>), grid, block, 0, c.stream, P, nst, c.kperp2); });
+    }
+  }
+  void pointwise(Ctx& c, const PwDesc& d, int64_t nst) override {
+    PwArgs<R> P{};
+    P.X = (cpx<R>*)d.X;
+    P.scale = d.scale;
+    for (int i = 0; i < 5; ++i) P.hist[i] = (const cpx<R>*)d.hist[i];
+    P.cout = (cpx<R>*)d.cout;
+    P.nrm_part = d.nrm_part;
+    P.nrm_stride = c.nrm_stride;
+    P.np = c.np;
+    P.nq = c.nq;
+    for (int i = 0; i < 5; ++i) {
+      P.b[i] = c.bco[i];
+      P.a[i] = c.aco[i];
+    }
+    P.out64 = (cpx<double>*)d.out64;
+    dim3 grid(cdiv(nst, CFG::WS)), block(CFG::TB);
+    if (d.mode == PW_NORM)
+      c.launch(KC_NORM, [&] { hipLaunchKernelGGL((q_pointwise<R, A, PW_NORM>), grid, block, 0, c.stream, P, nst); });
+    else if (d.mode == PW_PRED)
+      c.launch(KC_PRED, [&] {
+        if (c.np == 3)
+          hipLaunchKernelGGL((q_pointwise<R, A, PW_PRED, 3, 4>), grid, block, 0, c.stream, P, nst);
+        else if (c.np == 5)
+          hipLaunchKernelGGL((q_pointwise<R, A, PW_PRED, 5, 5>), grid, block, 0, c.stream, P, nst);
+        else
+          hipLaunchKernelGGL((q_pointwise<R, A, PW_PRED, 4, 5>), grid, block, 0, c.stream, P, nst);
+      });
+    else
+      c.launch(KC_SETUP, [&] { hipLaunchKernelGGL((q_pointwise<R, A, PW_SCALE>), grid, block, 0, c.stream, P, nst); });
+  }
+  void grad(Ctx& c, const void* X, const double* scale, int64_t n0, int64_t nchunk) override {
+    twiddles(c);
+    const double pz = kPi / c.lat.dz;
+    c.launch(KC_GRAD, [&] {
+      hipLaunchKernelGGL((q_grad<R, A>), dim3(cdiv(nchunk, CFG::WS)), dim3(CFG::TB), 0, c.stream, (const cpx<R>*)X,
+                         n0, nchunk, scale, c.wu, c.wv, c.kperp2, tw, 2 * kPi / (N * c.lat.dz), pz * pz, c.gscratch,
+                         c.gscratch + nchunk * N);
+    });
+  }
+};
+
+template <typename R>
+std::unique_ptr<Engine> make_q1d(int nz) {
+  if (nz == 16) return std::unique_ptr<Engine>(new EngineQ1D<R, 4>());
+  if (nz == 64) return std::unique_ptr<Engine>(new EngineQ1D<R, 8>());
+  if (nz == 256) return std::unique_ptr<Engine>(new EngineQ1D<R, 16>());
+  return nullptr;
+}
+
+}  // namespace
+
+std::unique_ptr<Engine> make_q1d_f64(int nz) { return make_q1d<double>(nz); }
+std::unique_ptr<Engine> make_q1d_f32(int nz) { return make_q1d<float>(nz); }
+
 }  // namespace tdslda

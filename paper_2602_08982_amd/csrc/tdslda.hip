@@ -15,6 +15,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <cstdlib>
 #include <memory>
 #include <new>
 #include <string>
@@ -85,7 +86,7 @@ void fin(Ctx& c, int64_t nst, double* scale, bool do_scale, bool do_h) {
   const int nh = c.eng->ngx() + c.eng->ncb();
   c.launch(KC_FINALIZE, [&] {
     hipLaunchKernelGGL(k_finalize, dim3(cdiv(nst, 256)), dim3(256), 0, c.stream, nst, s, c.eng->ngx(), nh,
-                       int(do_scale), int(do_h));
+                       int(do_scale), int(do_h), c.dV);
   });
 }
 
@@ -250,7 +251,20 @@ void abm(Ctx& c, int64_t nsteps) {
     d.scale = c.sscale[c.phi];
     d.hshift = c.hshift;
     d.out = c.sb[c.hist[0]];
-    if (s + 1 < nsteps) {
+    static const bool no_fuse = std::getenv("TDSLDA_NO_FUSE") != nullptr;
+    if (s + 1 < nsteps && no_fuse) {
+      d.mode = L2_F;
+      c.eng->lap2(c, d, c.nst);
+      PwDesc q;
+      q.mode = PW_PRED;
+      q.X = c.sb[c.phi];
+      q.scale = c.sscale[c.phi];
+      for (int j = 0; j < D; ++j) q.hist[j] = c.sb[c.hist[j]];
+      q.cout = c.sb[c.hist[D - 1]];
+      q.nrm_part = c.nrm_part;
+      c.eng->pointwise(c, q, c.nst);
+      fin(c, c.nst, c.sscale[c.phi], true, false);
+    } else if (s + 1 < nsteps) {
       d.mode = L2_FULL;
       d.Xout = c.sb[c.phi];
       for (int j = 1; j < D; ++j) d.hist[j] = c.sb[c.hist[j]];

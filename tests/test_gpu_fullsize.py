@@ -56,7 +56,9 @@ def test_fullsize_start_and_steps(which):
     st, info = ctx.check()
     ctx.abm_step(2)
     st, info = ctx.check()
-    assert info["norm"] < (1e-12 if which == "plain" else 1e-6)
+    # the stored state is the unnormalised corrector output: its norm
+    # deviation is the integrator's per-step norm error
+    assert info["norm"] < (1e-9 if which == "plain" else 1e-5)
     e1 = ctx.energy()
     ctx.abm_step(3)
     e2 = ctx.energy()
