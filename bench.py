@@ -35,7 +35,7 @@ def algorithmic_bytes(kernel, S, nst, depth):
     return table[kernel] * S * nst if kernel in table else None
 
 
-def run_workload(cfg, steps, warmup, seed_vortex, profile=True):
+def run_workload(cfg, steps, warmup, seed_vortex, profile=True, precision=None, observe=False):
     import torch
     from paper_2602_08982_amd import tdslda as T
     from paper_2602_08982_amd import workloads as W
@@ -48,7 +48,7 @@ def run_workload(cfg, steps, warmup, seed_vortex, profile=True):
         (x1, y1), (x2, y2) = synth.vortex_pair(seed_vortex)
         vort = [(x1, y1, 1.0), (x2, y2, -1.0)]
     stream = torch.cuda.current_stream().cuda_stream
-    ctx, kidx = W.setup(cfg, vort, stream=stream)
+    ctx, kidx = W.setup(cfg, vort, stream=stream, precision=precision)
     nst = len(kidx)
     t0 = time.time()
     ctx.abm_step(warmup)          # includes the Taylor start-up
@@ -65,8 +65,13 @@ def run_workload(cfg, steps, warmup, seed_vortex, profile=True):
     if profile:
         ctx.set_profiling(False)
     st, chk = ctx.check()
+    obs = None
+    if observe:
+        d = ctx.densities()
+        obs = dict(rho=d["rho"], nu=d["nu"], energy=ctx.energy())
     M = int(np.prod(cfg["n"]))
-    es = 16 if cfg["precision"] == T.FP64 else 8
+    prec = cfg["precision"] if precision is None else precision
+    es = 16 if prec == T.FP64 else 8
     S = 2 * M * es
     depth = 4
     kern = {}
@@ -81,7 +86,7 @@ def run_workload(cfg, steps, warmup, seed_vortex, profile=True):
     del ctx
     return dict(nst=nst, seconds=dt, warm_seconds=t_warm, value=nst * steps / dt,
                 ms_per_step=1e3 * dt / steps, kernels=kern, check=dict(status=st, **chk), S=S,
-                vortices=vort)
+                vortices=vort, obs=obs)
 
 
 def roofline(res):
@@ -95,12 +100,11 @@ def roofline(res):
                 share_of_step=kern[dom]["total_ms"] / (res["ms_per_step"] * res["steps"]))
 
 
-def cpu_baseline(nsample=64, steps=2):
+def cpu_baseline(nsample=1024, steps=3):
     """The FP64 oracle on a bounded sample of the same workload: nsample
     plane-wave states of the 32^3 trapped gas (trap + vortex), stationary
     start (one f evaluation), then `steps` AB4AM5 steps; the rate is
     nsample * steps / time of those steps."""
-    import scipy.fft
     from oracle import lattice as L, bdg, functional as F, td
     from paper_2602_08982_amd import workloads as W
     import synth
@@ -123,9 +127,9 @@ def cpu_baseline(nsample=64, steps=2):
     dt = time.perf_counter() - t0
     cores = os.cpu_count()
     return dict(value=nsample * steps / dt, unit="state-steps/s", cores=cores, kind="oracle",
-                sample=f"{nsample} of 32768 states of the 32^3 FP64 workload, {steps} AB4AM5 steps "
-                       f"after a stationary start; scipy.fft workers={scipy.fft.get_workers()} (all "
-                       f"{cores} host threads)", seconds=dt)
+                sample=f"{nsample} of the 32768 states of the 32^3 FP64 workload (seeded choice), "
+                       f"{steps} AB4AM5 steps after a stationary start, timed steps only; "
+                       f"scipy.fft with workers=-1 ({cores} host threads)", seconds=dt)
 
 
 def main():
@@ -136,6 +140,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="only run a device-to-device copy of 4 GiB (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; the multi-GPU (state-sharded, "
@@ -148,6 +154,15 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.copy_calib:
+        a = torch.ones(1 << 29, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calib_bytes_read_per_launch": a.numel() * 8,
+                          "copy_calib_bytes_written_per_launch": b.numel() * 8, "launches": 3}))
+        return
     from paper_2602_08982_amd import tdslda as T
     from paper_2602_08982_amd import workloads as W
     T.load_library()
@@ -158,10 +173,21 @@ def main():
           file=sys.stderr, flush=True)
     mixed = None
     if not args.no_mixed:
-        mixed = run_workload(W.MIXED, args.steps, args.warmup, 4)
+        mixed = run_workload(W.MIXED, args.steps, args.warmup, 4, observe=True)
         mixed["steps"] = args.steps
         print(f"# mixed fp32 48^3: {mixed['value']:.4g} state-steps/s, {mixed['ms_per_step']:.2f} ms/step",
               file=sys.stderr, flush=True)
+        ref64 = run_workload(W.MIXED, args.steps, args.warmup, 4, profile=False, precision=T.FP64,
+                             observe=True)
+        print(f"# fp64 48^3 (same states): {ref64['value']:.4g} state-steps/s, "
+              f"{ref64['ms_per_step']:.2f} ms/step", file=sys.stderr, flush=True)
+        o, r = mixed["obs"], ref64["obs"]
+        mixed["vs_fp64"] = dict(
+            fp64_value=ref64["value"], fp64_ms_per_step=ref64["ms_per_step"],
+            speedup=mixed["value"] / ref64["value"],
+            rho_rel_err=float(np.abs(o["rho"] - r["rho"]).max() / np.abs(r["rho"]).max()),
+            nu_rel_err=float(np.abs(o["nu"] - r["nu"]).max() / np.abs(r["nu"]).max()),
+            energy_rel_err=float(abs(o["energy"]["total"] - r["energy"]["total"]) / abs(r["energy"]["EFG"])))
     cpu = None if args.no_cpu else cpu_baseline()
 
     line = {
@@ -190,7 +216,7 @@ def main():
             "workload": "FP32-mixed 48^3 elongated trap, vortex pair, 8192 lowest-|E| states",
             "value": mixed["value"], "unit": "state-steps/s", "ms_per_step": mixed["ms_per_step"],
             "dtype": "f32 states / f64 sums", "roofline": roofline(mixed), "kernels": mixed["kernels"],
-            "check": mixed["check"],
+            "check": mixed["check"], "vs_fp64_same_workload": mixed["vs_fp64"],
         }
     print(json.dumps(line))
 

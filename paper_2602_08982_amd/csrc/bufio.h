@@ -46,16 +46,22 @@ __device__ __forceinline__ cpx<R> bload(bi32x4 rs, int voff, int soff) {
   return c;
 }
 
+// Stores take the scalar offset through the lane offset and pass a zero
+// soffset: a 128-bit store whose soffset is an SGPR is not protected by the
+// compiler's store-data hazard handling (a VALU write of the data VGPRs right
+// after the store), and on gfx950 such stores have been seen to commit the
+// overwritten value for some lanes.  With an immediate soffset the compiler
+// inserts the required wait state.
 template <typename R>
 __device__ __forceinline__ void bstore(cpx<R> c, bi32x4 rs, int voff, int soff) {
   if constexpr (sizeof(R) == 8) {
     bi32x4 v;
     __builtin_memcpy(&v, &c, 16);
-    tds_raw_store_b128(v, rs, voff, soff, 0);
+    tds_raw_store_b128(v, rs, voff + soff, 0, 0);
   } else {
     bi32x2 v;
     __builtin_memcpy(&v, &c, 8);
-    tds_raw_store_b64(v, rs, voff, soff, 0);
+    tds_raw_store_b64(v, rs, voff + soff, 0, 0);
   }
 }
 

@@ -152,11 +152,6 @@ struct tdslda_ctx {
       throw Fail{TDSLDA_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
     }
     allocs.push_back(p);
-    static const bool zero = std::getenv("TDSLDA_ZERO_ALLOC") != nullptr;
-    if (zero) {
-      HIPCHK(hipMemset(p, 0, bytes));
-      HIPCHK(hipDeviceSynchronize());
-    }
     return p;
   }
   hipEvent_t ev() {

@@ -251,20 +251,7 @@ void abm(Ctx& c, int64_t nsteps) {
     d.scale = c.sscale[c.phi];
     d.hshift = c.hshift;
     d.out = c.sb[c.hist[0]];
-    static const bool no_fuse = std::getenv("TDSLDA_NO_FUSE") != nullptr;
-    if (s + 1 < nsteps && no_fuse) {
-      d.mode = L2_F;
-      c.eng->lap2(c, d, c.nst);
-      PwDesc q;
-      q.mode = PW_PRED;
-      q.X = c.sb[c.phi];
-      q.scale = c.sscale[c.phi];
-      for (int j = 0; j < D; ++j) q.hist[j] = c.sb[c.hist[j]];
-      q.cout = c.sb[c.hist[D - 1]];
-      q.nrm_part = c.nrm_part;
-      c.eng->pointwise(c, q, c.nst);
-      fin(c, c.nst, c.sscale[c.phi], true, false);
-    } else if (s + 1 < nsteps) {
+    if (s + 1 < nsteps) {
       d.mode = L2_FULL;
       d.Xout = c.sb[c.phi];
       for (int j = 1; j < D; ++j) d.hist[j] = c.sb[c.hist[j]];

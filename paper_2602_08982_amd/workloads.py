@@ -64,5 +64,6 @@ def setup(cfg, vortices, stream=None, precision=None, integrator=T.AB4AM5):
     ctx = T.Context(T.lattice_3d(n, d), T.functional_slda(cfg["mu"], ec), run, len(kidx))
     ctx.set_external(harmonic(n, d, cfg["omega"]), freeze_regulator=True)
     ctx.init_plane_waves(kidx, cfg["u0"], cfg["delta0"])
-    ctx.imprint_vortices(vortices)
+    if len(vortices):
+        ctx.imprint_vortices(vortices)
     return ctx, kidx
