@@ -19,11 +19,11 @@ namespace tdslda {
 enum KClass {
   KC_DENS = 0, KC_REDUCE_POT, KC_LAP1, KC_FINALIZE, KC_LAP2_CORR, KC_LAP2_FULL, KC_LAP2_F,
   KC_LAP2_H, KC_LAP2_TAYLOR, KC_PRED, KC_NORM, KC_GRAD, KC_ENERGY, KC_SETUP, KC_Q1D_FUSED,
-  KC_COUNT
+  KC_DENS_KIN, KC_COUNT
 };
 inline const char* const kKernelNames[KC_COUNT] = {
     "dens", "reduce_pot", "lap1", "finalize", "lap2_corr", "lap2_full", "lap2_f", "lap2_h",
-    "lap2_taylor", "pred", "norm", "grad", "energy", "setup", "q1d_fused"};
+    "lap2_taylor", "pred", "norm", "grad", "energy", "setup", "q1d_fused", "dens_kin"};
 
 struct Fail {
   tdslda_status st;
@@ -76,6 +76,13 @@ struct Engine {
   virtual int ncb() const = 0;    // lap1 column blocks per state
   virtual int group() const = 0;  // states per density group
   virtual void dens(Ctx& c, const void* X, const double* scale, int64_t nst) = 0;
+  // densities only, for a buffer whose (y,z) kinetic <H> partials were left
+  // in the h slots by the kernel that wrote it (see producer_kinetic)
+  virtual void dens_sum(Ctx& c, const void* X, const double* scale, int64_t nst) { dens(c, X, scale, nst); }
+  // true when CORR / FULL write the kinetic partials of their output
+  virtual bool producer_kinetic() const { return false; }
+  // h slots that hold partials of the unscaled state
+  virtual int raw_h_slots() const { return 0; }
   virtual void reduce_pot(Ctx& c, bool update) = 0;
   virtual void lap1(Ctx& c, const void* X, const double* scale, bool hpart, int64_t nst) = 0;
   virtual void lap2(Ctx& c, const L2Desc& d, int64_t nst) = 0;
@@ -122,6 +129,7 @@ struct tdslda_ctx {
   int64_t kidx_cap = 0;
 
   // integrator state
+  bool kin_ready[6] = {false, false, false, false, false, false};  // h slots hold this buffer's partials
   int phi = 0;
   int hist[5] = {1, 2, 3, 4, 5};
   bool loaded = false, started = false, frozen = false, fields_valid = false;

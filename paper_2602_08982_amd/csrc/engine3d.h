@@ -26,13 +26,24 @@ struct Engine3D final : Engine {
 
   void dens(Ctx& c, const void* X, const double* scale, int64_t nst) override {
     dim3 grid(CFG::NGX, cdiv(nst, G));
-    c.launch(KC_DENS, [&] {
+    c.launch(KC_DENS_KIN, [&] {
       hipLaunchKernelGGL((k_dens<R, NX, NY, NZ, G>), grid, dim3(CFG::TB), 0, c.stream,
                          (const cpx<R>*)X, nst, c.wu, c.wv, c.scalars(const_cast<double*>(scale)),
                          c.dens_part, cy2(c), cz2(c), c.dV);
     });
     c.nsg_used = int(cdiv(nst, G));
   }
+  static constexpr int DG = sizeof(R) == 8 ? 64 : 128;  // states per dens_sum group
+  void dens_sum(Ctx& c, const void* X, const double* scale, int64_t nst) override {
+    dim3 grid(cdiv(M, DS_TB * DS_P), cdiv(nst, DG));
+    c.launch(KC_DENS, [&] {
+      hipLaunchKernelGGL((k_dens_sum<R, DG>), grid, dim3(DS_TB), 0, c.stream, (const cpx<R>*)X, nst,
+                         int64_t(M), c.wu, c.wv, scale, c.dens_part);
+    });
+    c.nsg_used = int(cdiv(nst, DG));
+  }
+  bool producer_kinetic() const override { return true; }
+  int raw_h_slots() const override { return CFG::NGX; }
   void reduce_pot(Ctx& c, bool update) override {
     FunParams fp{c.fun.functional, c.fun.B, c.fun.C, c.fun.inv_g_bdg, c.fun.mu, c.ainv};
     c.launch(KC_REDUCE_POT, [&] {
@@ -75,6 +86,9 @@ struct Engine3D final : Engine {
     A.init_acc = d.init_acc;
     A.cy2 = cy2(c);
     A.cz2 = cz2(c);
+    A.h_part = c.h_part;
+    A.h_stride = c.h_stride;
+    A.dV = c.dV;
     dim3 grid(CFG::NGX, nst), block(CFG::TB);
     switch (d.mode) {
       case L2_H:

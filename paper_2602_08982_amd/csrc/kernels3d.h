@@ -101,6 +101,35 @@ __device__ __forceinline__ void lds_zlines(cpx<R>* lds) {
   }
 }
 
+// (y,z) kinetic part of <H> from a slab whose z-lines were forward
+// transformed in place: each y-line task transforms its column forward and
+// returns (+1/2 for u, -1/2 for v) sum_k (ky^2 + kz^2) |phi_k|^2 dV / (NY NZ)
+// (Parseval; zero for threads without a task).
+template <class CFG, typename R>
+__device__ __forceinline__ double lds_yz_kinetic(const cpx<R>* lds, double cy2, double cz2, double dV) {
+  constexpr int NY = CFG::NYv, NZ = CFG::NZv;
+  constexpr int tasks = 2 * CFG::SX * NZ;
+  const int tid = threadIdx.x;
+  if (tid >= tasks) return 0.0;
+  const int comp = tid / (CFG::SX * NZ);
+  const int rem = tid - comp * CFG::SX * NZ;
+  const int sx = rem / NZ, kz = rem - sx * NZ;
+  const cpx<R>* base = lds + ((comp * CFG::SX + sx) * NY) * CFG::PADZ + kz;
+  cpx<R> a[NY];
+#pragma unroll
+  for (int j = 0; j < NY; ++j) a[j] = base[j * CFG::PADZ];
+  fwd<NY>(a);
+  const int mz = wavenum_at<NZ>(kz);  // kz: digit-reversed position
+  const double ez = cz2 * double(mz * mz);
+  double acc = 0.0;
+  sfor<0, NY>::run([&](auto jc) {
+    constexpr int j = decltype(jc)::value;
+    constexpr int my = wavenum_at<NY>(j);
+    acc += (cy2 * double(my * my) + ez) * norm2(a[j]);
+  });
+  return (comp == 0 ? 0.5 : -0.5) * acc * dV / double(CFG::NYZ);
+}
+
 // ---------------------------------------------------------------------------
 // Per-state scalars: norm^2 partials (one slot per slab group) and <H>_n
 // partials (slab-group slots from dens, column-block slots from lap1).
@@ -117,7 +146,7 @@ struct StateScalars {
 // ---------------------------------------------------------------------------
 // dens: densities rho, nu of the normalised states (Eqs. nab3D and the
 // anomalous density of the spin-symmetric case) as per-state-group partial
-// sums, plus the y,z kinetic part of <H>_n.
+// sums, plus the y,z kinetic part of <H>_n of the stored (unscaled) state.
 //   grid = (NGX, number of state groups), block = CFG::TB
 //   dens_part layout [group][3][M] (rho, Re nu, Im nu)
 template <typename R, int NX, int NY, int NZ, int G>
@@ -150,14 +179,17 @@ __global__ __launch_bounds__((SlabCfg<NX, NY, NZ>::TB)) void k_dens(
         const int p = tid + i * TB;
         if (p < SS) {
           const int so = int(site0 + i * TB) * ES;
-          cpx<R> u = R(s) * bload<R>(rX, tid * ES, so), v = R(s) * bload<R>(rX, tid * ES, so + M * ES);
+          const cpx<R> xu = bload<R>(rX, tid * ES, so), xv = bload<R>(rX, tid * ES, so + M * ES);
+          const cpx<R> u = R(s) * xu, v = R(s) * xv;
           const double ur = u.x, ui = u.y, vr = v.x, vi = v.y;
           ar[i] += fv * (vr * vr + vi * vi) + fu * (ur * ur + ui * ui);
           const double dw = fv - fu;  // u v^*
           anr[i] += dw * (ur * vr + ui * vi);
           ani[i] += dw * (ui * vr - ur * vi);
-          lds[CFG::lds_index(0, p)] = u;
-          lds[CFG::lds_index(1, p)] = v;
+          // the kinetic partial is taken on the stored (unscaled) values;
+          // the finalisation multiplies it by scale^2
+          lds[CFG::lds_index(0, p)] = xu;
+          lds[CFG::lds_index(1, p)] = xv;
         }
       }
     }
@@ -165,29 +197,7 @@ __global__ __launch_bounds__((SlabCfg<NX, NY, NZ>::TB)) void k_dens(
     if (live) lds_zlines<CFG, -1>(lds);
     __syncthreads();
     double kv = 0.0;
-    if (live) {
-      // y-lines of the z-transformed slab: sum_k (ky^2 + kz^2) |phi_k|^2
-      constexpr int tasks = 2 * CFG::SX * NZ;
-      if (tid < tasks) {
-        const int comp = tid / (CFG::SX * NZ);
-        const int rem = tid - comp * CFG::SX * NZ;
-        const int sx = rem / NZ, kz = rem - sx * NZ;
-        cpx<R>* base = lds + ((comp * CFG::SX + sx) * NY) * CFG::PADZ + kz;
-        cpx<R> a[NY];
-#pragma unroll
-        for (int j = 0; j < NY; ++j) a[j] = base[j * CFG::PADZ];
-        fwd<NY>(a);
-        const int mz = wavenum_at<NZ>(kz);  // kz: digit-reversed position
-        const double ez = cz2 * double(mz * mz);
-        double acc = 0.0;
-        sfor<0, NY>::run([&](auto jc) {
-          constexpr int j = decltype(jc)::value;
-          constexpr int my = wavenum_at<NY>(j);
-          acc += (cy2 * double(my * my) + ez) * norm2(a[j]);
-        });
-        kv = (comp == 0 ? 0.5 : -0.5) * acc * dV / double(NYZ);
-      }
-    }
+    if (live) kv = lds_yz_kinetic<CFG, R>(lds, cy2, cz2, dV);
     kv = wave_sum(kv);
     if (tid % kWave == 0) kin[ls][tid / kWave] = kv;
     __syncthreads();
@@ -210,6 +220,55 @@ __global__ __launch_bounds__((SlabCfg<NX, NY, NZ>::TB)) void k_dens(
 #pragma unroll
       for (int w = 0; w < NW; ++w) s += kin[tid][w];
       sc.h_part[n * sc.h_stride + g] = s;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// dens_sum: the density partials only (rho, nu of the normalised states), for
+// states whose (y,z) kinetic partial was already produced by the kernel that
+// wrote them.  Site-parallel, no LDS: a thread owns DS_P sites (stride TB) and
+// walks the DG states of its group, so every load is a coalesced row.
+//   grid = (ceil(M / (TB DS_P)), ceil(nstates / DG)), block = TB
+//   dens_part layout [group][3][M]
+constexpr int DS_TB = 256, DS_P = 2;
+template <typename R, int DG>
+__global__ __launch_bounds__(DS_TB) void k_dens_sum(
+    const cpx<R>* __restrict__ X, int64_t nstates, int64_t M, const double* __restrict__ wu,
+    const double* __restrict__ wv, const double* __restrict__ scale, double* __restrict__ dens_part) {
+  const int tid = threadIdx.x;
+  const int64_t site0 = int64_t(blockIdx.x) * (DS_TB * DS_P) + tid;
+  const int64_t nbeg = int64_t(blockIdx.y) * DG;
+  const int nloc = int(nstates - nbeg < DG ? nstates - nbeg : DG);
+  double ar[DS_P], anr[DS_P], ani[DS_P];
+#pragma unroll
+  for (int i = 0; i < DS_P; ++i) ar[i] = anr[i] = ani[i] = 0.0;
+  const cpx<R>* xb = X + nbeg * 2 * M;
+#pragma unroll 4
+  for (int ls = 0; ls < nloc; ++ls) {
+    const double s = scale[nbeg + ls], fu = wu[nbeg + ls], fv = wv[nbeg + ls];
+    const double s2 = s * s, cu = fu * s2, cv = fv * s2, cw = (fv - fu) * s2;
+    const cpx<R>* xs = xb + int64_t(ls) * 2 * M;
+#pragma unroll
+    for (int i = 0; i < DS_P; ++i) {
+      const int64_t r = site0 + i * DS_TB;
+      if (r < M) {
+        const cpx<R> u = xs[r], v = xs[M + r];
+        const double ur = u.x, ui = u.y, vr = v.x, vi = v.y;
+        ar[i] += cv * (vr * vr + vi * vi) + cu * (ur * ur + ui * ui);
+        anr[i] += cw * (ur * vr + ui * vi);  // u v^*
+        ani[i] += cw * (ui * vr - ur * vi);
+      }
+    }
+  }
+  double* out = dens_part + int64_t(blockIdx.y) * 3 * M;
+#pragma unroll
+  for (int i = 0; i < DS_P; ++i) {
+    const int64_t r = site0 + i * DS_TB;
+    if (r < M) {
+      out[r] = ar[i];
+      out[M + r] = anr[i];
+      out[2 * M + r] = ani[i];
     }
   }
 }
@@ -371,6 +430,9 @@ struct Lap2Args {
   double tay_re, tay_im; // TAYLOR: coefficient of (H - h) psi
   int init_acc;
   double cy2, cz2;       // (2 pi / L_y)^2, (2 pi / L_z)^2
+  double* h_part;        // CORR / FULL: (y,z) kinetic partial of the written state
+  int h_stride;
+  double dV;
 };
 
 // NP, NQ: predictor / corrector lengths of the integrator (FULL mode only),
@@ -499,6 +561,9 @@ __global__ __launch_bounds__((SlabCfg<NX, NY, NZ>::TB)) void k_lap2(Lap2Args<R> 
             bstore<R>(nu_, rX, vt, ou);
             bstore<R>(nv_, rX, vt, ov);
             nacc += norm2(nu_) + norm2(nv_);
+            // the written state replaces this thread's own LDS sites
+            lds[CFG::lds_index(0, p)] = nu_;
+            lds[CFG::lds_index(1, p)] = nv_;
           } else {  // L2_FULL: f_k, next predictor p (over the input), partial corrector c
             bstore<R>(fu, rO, vt, ou);
             bstore<R>(fv, rO, vt, ov);
@@ -521,10 +586,22 @@ __global__ __launch_bounds__((SlabCfg<NX, NY, NZ>::TB)) void k_lap2(Lap2Args<R> 
             bstore<R>(cu, rC, vt, ou);
             bstore<R>(cv, rC, vt, ov);
             nacc += norm2(pu) + norm2(pv);
+            lds[CFG::lds_index(0, p)] = pu;
+            lds[CFG::lds_index(1, p)] = pv;
           }
         }
       }
     }
+  }
+  if constexpr (MODE == L2_CORR || MODE == L2_FULL) {
+    // (y,z) kinetic partial of the state just written (unscaled), so that
+    // the next evaluation's density pass needs no transform
+    __syncthreads();
+    lds_zlines<CFG, -1>(lds);
+    __syncthreads();
+    const double kv = lds_yz_kinetic<CFG, R>(lds, A.cy2, A.cz2, A.dV);
+    const double t = block_sum<TB>(kv, red);
+    if (tid == 0) A.h_part[n * A.h_stride + g] = t;
   }
   if (A.nrm_part) {
     const double t = block_sum<TB>(nacc, red);

@@ -7,9 +7,11 @@
 namespace tdslda {
 
 // finalize per-state scalars
-// (norm^2 = dV sum |phi|^2; the partials hold the plain sums)
-__global__ void k_finalize(int64_t nstates, StateScalars sc, int n_nrm, int n_h, int do_scale, int do_h,
-                           double dV) {
+// (norm^2 = dV sum |phi|^2; the partials hold the plain sums).  <H>_n: the
+// first n_raw h slots hold partials of the stored (unscaled) state and are
+// multiplied by scale^2; the others are already on the normalised state.
+__global__ void k_finalize(int64_t nstates, StateScalars sc, int n_nrm, int n_h, int n_raw, int do_scale,
+                           int do_h, double dV) {
   const int64_t n = int64_t(blockIdx.x) * 256 + threadIdx.x;
   if (n >= nstates) return;
   if (do_scale) {
@@ -18,9 +20,11 @@ __global__ void k_finalize(int64_t nstates, StateScalars sc, int n_nrm, int n_h,
     sc.scale[n] = 1.0 / sqrt(dV * s);
   }
   if (do_h) {
-    double s = 0.0;
-    for (int i = 0; i < n_h; ++i) s += sc.h_part[n * sc.h_stride + i];
-    sc.hshift[n] = s;
+    double r = 0.0, s = 0.0;
+    for (int i = 0; i < n_raw; ++i) r += sc.h_part[n * sc.h_stride + i];
+    for (int i = n_raw; i < n_h; ++i) s += sc.h_part[n * sc.h_stride + i];
+    const double sn = sc.scale[n];
+    sc.hshift[n] = sn * sn * r + s;
   }
 }
 

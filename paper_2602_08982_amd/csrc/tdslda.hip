@@ -86,13 +86,19 @@ void fin(Ctx& c, int64_t nst, double* scale, bool do_scale, bool do_h) {
   const int nh = c.eng->ngx() + c.eng->ncb();
   c.launch(KC_FINALIZE, [&] {
     hipLaunchKernelGGL(k_finalize, dim3(cdiv(nst, 256)), dim3(256), 0, c.stream, nst, s, c.eng->ngx(), nh,
-                       int(do_scale), int(do_h), c.dV);
+                       c.eng->raw_h_slots(), int(do_scale), int(do_h), c.dV);
   });
 }
 
+// buffer b was rewritten by a kernel that leaves no kinetic partials
+inline void touched(Ctx& c, int b) { c.kin_ready[b] = false; }
+
 // fields and <H>_n of buffer b (its scale must be current); leaves T = D2x
 void prepare(Ctx& c, int b) {
-  c.eng->dens(c, c.sb[b], c.sscale[b], c.nst);
+  if (c.kin_ready[b])
+    c.eng->dens_sum(c, c.sb[b], c.sscale[b], c.nst);
+  else
+    c.eng->dens(c, c.sb[b], c.sscale[b], c.nst);
   c.eng->reduce_pot(c, !c.frozen);
   c.eng->lap1(c, c.sb[b], c.sscale[b], true, c.nst);
   fin(c, c.nst, c.sscale[b], false, true);
@@ -117,6 +123,7 @@ void f_into(Ctx& c, int src, int dst) {
   d.hshift = c.hshift;
   d.out = c.sb[dst];
   c.eng->lap2(c, d, c.nst);
+  touched(c, dst);
 }
 
 // Taylor series sum_{k<=r} (-i tau)^k/k! (H - h)^k phi with H, h already
@@ -142,6 +149,8 @@ void taylor_series(Ctx& c, int phi, int acc, int pa, double tau, bool t_ready) {
     d.nrm_part = (k == r) ? c.nrm_part : nullptr;
     c.eng->lap2(c, d, c.nst);
   }
+  touched(c, pa);
+  touched(c, acc);
   fin(c, c.nst, c.sscale[acc], true, false);
 }
 
@@ -177,6 +186,7 @@ void start(Ctx& c) {
       int b = freeb.back();
       freeb.pop_back();
       HIPCHK(hipMemcpyAsync(c.sb[b], c.sb[f0], size_t(c.nst) * 2 * c.M * c.esz, hipMemcpyDeviceToDevice, c.stream));
+      touched(c, b);
       hl.push_back(b);
     }
   } else {
@@ -220,6 +230,8 @@ void abm(Ctx& c, int64_t nsteps) {
     d.nrm_part = c.nrm_part;
     c.eng->pointwise(c, d, c.nst);
     fin(c, c.nst, c.sscale[c.phi], true, false);
+    touched(c, c.phi);
+    touched(c, c.hist[D - 1]);
   }
   for (int64_t s = 0; s < nsteps; ++s) {
     // evaluation at the predicted state; corrector
@@ -236,6 +248,7 @@ void abm(Ctx& c, int64_t nsteps) {
       d.nrm_part = c.nrm_part;
       c.eng->lap2(c, d, c.nst);
       fin(c, c.nst, c.sscale[c.phi], true, false);
+      c.kin_ready[c.phi] = c.eng->producer_kinetic();
     }
     // rotate: the slot of c becomes the slot of the new f
     {
@@ -259,10 +272,13 @@ void abm(Ctx& c, int64_t nsteps) {
       d.nrm_part = c.nrm_part;
       c.eng->lap2(c, d, c.nst);
       fin(c, c.nst, c.sscale[c.phi], true, false);
+      c.kin_ready[c.phi] = c.eng->producer_kinetic();
+      touched(c, c.hist[D - 1]);
     } else {
       d.mode = L2_F;
       c.eng->lap2(c, d, c.nst);
     }
+    touched(c, c.hist[0]);
     c.steps += 1;
     c.time += c.run.dt;
   }
@@ -307,6 +323,7 @@ void energy(Ctx& c, double* out8) {
 }
 
 void after_load(Ctx& c) {
+  for (bool& k : c.kin_ready) k = false;
   c.loaded = true;
   c.started = false;
   c.steps = 0;
@@ -613,6 +630,7 @@ tdslda_status tdslda_imprint_vortices(tdslda_ctx* c, int nv, const double* xyq) 
                            c->nst, c->theta, (cpx<float>*)c->sb[c->phi]);
     });
     // a new initial state: restart the integrator from it
+    touched(*c, c->phi);
     c->started = false;
     c->steps = 0;
     c->time = 0;
@@ -788,7 +806,7 @@ tdslda_status tdslda_save(tdslda_ctx* c, const char* path) {
     require(f != nullptr, TDSLDA_EINVAL, std::string("cannot open ") + path);
     HIPCHK(hipStreamSynchronize(c->stream));
     const int64_t per = 2 * c->M * c->esz;
-    int64_t hdr[8] = {0x5444534c4441LL, c->nst, c->M, int64_t(c->esz), c->depth, c->steps, int64_t(c->started), int64_t(c->frozen)};
+    int64_t hdr[8] = {0x5444534c4442LL, c->nst, c->M, int64_t(c->esz), c->depth, c->steps, int64_t(c->started), int64_t(c->frozen)};
     std::vector<char> host(size_t(per) * std::min<int64_t>(c->nst, 256));
     bool ok = std::fwrite(hdr, sizeof(hdr), 1, f) == 1 && std::fwrite(&c->time, 8, 1, f) == 1;
     int roles[6] = {c->phi, c->hist[0], c->hist[1], c->hist[2], c->hist[3], c->hist[4]};
@@ -812,6 +830,12 @@ tdslda_status tdslda_save(tdslda_ctx* c, const char* path) {
     dump(c->lam, 8 * c->M);
     dump(c->U, 8 * c->M);
     dump(c->delta, 16 * c->M);
+    // kinetic <H> partials left by the last producer kernel, so a resumed
+    // run continues with exactly the arithmetic of an uninterrupted one
+    int kin[6];
+    for (int b = 0; b < 6; ++b) kin[b] = c->kin_ready[b] ? 1 : 0;
+    ok = ok && std::fwrite(kin, sizeof(kin), 1, f) == 1;
+    dump(c->h_part, 8 * size_t(c->nst) * c->h_stride);
     std::fclose(f);
     require(ok, TDSLDA_EINVAL, "short write");
   });
@@ -827,7 +851,7 @@ tdslda_status tdslda_load(tdslda_ctx* c, const char* path) {
     int roles[6];
     bool ok = std::fread(hdr, sizeof(hdr), 1, f) == 1 && std::fread(&t, 8, 1, f) == 1 &&
               std::fread(roles, sizeof(roles), 1, f) == 1;
-    if (!ok || hdr[0] != 0x5444534c4441LL || hdr[2] != c->M || hdr[3] != int64_t(c->esz) || hdr[4] != c->depth ||
+    if (!ok || hdr[0] != 0x5444534c4442LL || hdr[2] != c->M || hdr[3] != int64_t(c->esz) || hdr[4] != c->depth ||
         hdr[1] > c->cap || hdr[1] <= 0) {
       std::fclose(f);
       throw Fail{TDSLDA_EINVAL, "checkpoint does not match this context"};
@@ -855,6 +879,10 @@ tdslda_status tdslda_load(tdslda_ctx* c, const char* path) {
     undump(c->lam, 8 * c->M);
     undump(c->U, 8 * c->M);
     undump(c->delta, 16 * c->M);
+    int kin[6] = {0, 0, 0, 0, 0, 0};
+    ok = ok && std::fread(kin, sizeof(kin), 1, f) == 1;
+    std::vector<double> hp(size_t(n) * c->h_stride);
+    ok = ok && std::fread(hp.data(), 8, hp.size(), f) == hp.size();
     std::fclose(f);
     require(ok, TDSLDA_EINVAL, "short read");
     c->nst = n;
@@ -882,6 +910,8 @@ tdslda_status tdslda_load(tdslda_ctx* c, const char* path) {
       c->eng->reduce_pot(*c, true);
     }
     c->fields_valid = true;
+    HIPCHK(hipMemcpyAsync(c->h_part, hp.data(), 8 * hp.size(), hipMemcpyHostToDevice, c->stream));
+    for (int b = 0; b < 6; ++b) c->kin_ready[b] = kin[b] != 0;
     HIPCHK(hipStreamSynchronize(c->stream));
   });
 }
