@@ -89,15 +89,39 @@ def run_workload(cfg, steps, warmup, seed_vortex, profile=True, precision=None, 
                 vortices=vort, obs=obs)
 
 
-def roofline(res):
+def copy_bandwidth():
+    """Bytes moved per second by a plain device-to-device copy of 4 GiB
+    (read + write), median of 5: the practical HBM ceiling on this device."""
+    import torch
+    a = torch.ones(1 << 29, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    ts = []
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e-3)
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * (1 << 29) * 8 / sorted(ts)[2]
+
+
+def roofline(res, copy_bps=None):
     kern = res["kernels"]
     if not kern:
         return None
     dom = max(kern, key=lambda k: kern[k]["total_ms"])
     g = kern[dom]["gbps"]
-    return dict(bound="hbm", kernel=dom, achieved=g, peak=PEAK_HBM / 1e9, unit="GB/s",
-                frac=(g * 1e9 / PEAK_HBM) if g else None, traffic=None,
-                share_of_step=kern[dom]["total_ms"] / (res["ms_per_step"] * res["steps"]))
+    out = dict(bound="hbm", kernel=dom, achieved=g, peak=PEAK_HBM / 1e9, unit="GB/s",
+               frac=(g * 1e9 / PEAK_HBM) if g else None, traffic=None,
+               share_of_step=kern[dom]["total_ms"] / (res["ms_per_step"] * res["steps"]))
+    if copy_bps:
+        out["copy_GBps"] = copy_bps / 1e9
+        out["frac_of_copy"] = g * 1e9 / copy_bps if g else None
+    return out
 
 
 def cpu_baseline(nsample=1024, steps=3):
@@ -167,6 +191,7 @@ def main():
     from paper_2602_08982_amd import workloads as W
     T.load_library()
 
+    copy_bps = copy_bandwidth()
     plain = run_workload(W.PLAIN, args.steps, args.warmup, args.seed)
     plain["steps"] = args.steps
     print(f"# plain fp64 32^3: {plain['value']:.4g} state-steps/s, {plain['ms_per_step']:.2f} ms/step",
@@ -206,7 +231,7 @@ def main():
         "config": {"workload": "plain FP64 32^3 trapped gas, one vortex (AB4AM5, dt=0.005)",
                    "lattice": [32, 32, 32], "states_evolved": plain["nst"],
                    "states_represented": 2 * plain["nst"], "integrator": "AB4AM5"},
-        "roofline": roofline(plain),
+        "roofline": roofline(plain, copy_bps),
         "cpu_baseline": cpu,
         "kernels": plain["kernels"],
         "check": plain["check"],
@@ -215,7 +240,7 @@ def main():
         line["fp32_mixed"] = {
             "workload": "FP32-mixed 48^3 elongated trap, vortex pair, 8192 lowest-|E| states",
             "value": mixed["value"], "unit": "state-steps/s", "ms_per_step": mixed["ms_per_step"],
-            "dtype": "f32 states / f64 sums", "roofline": roofline(mixed), "kernels": mixed["kernels"],
+            "dtype": "f32 states / f64 sums", "roofline": roofline(mixed, copy_bps), "kernels": mixed["kernels"],
             "check": mixed["check"], "vs_fp64_same_workload": mixed["vs_fp64"],
         }
     print(json.dumps(line))

@@ -380,10 +380,11 @@ __global__ __launch_bounds__(TB1) void k_lap1(
 #pragma unroll
       for (int x = 0; x < NX; ++x) bstore<R>(a[x], rT, vq, int(comp * M + x * NYZ) * ES);
     }
-    // potential part A (|u|^2 - |v|^2) + 2 Re(u^* Delta v); phi is re-read
-    // (it comes from cache)
+    // potential part A (|u|^2 - |v|^2) + 2 Re(u^* Delta v), only when <H>_n
+    // is wanted; phi is re-read (keeping the u line for the v pass costs more
+    // in occupancy than the second read)
 #pragma unroll 4
-    for (int x = 0; x < NX; ++x) {
+    for (int x = 0; x < (h_part ? NX : 0); ++x) {
       const cpx<R> u = s * bload<R>(rX, vq, x * NYZ * ES), v = s * bload<R>(rX, vq, int(M + x * NYZ) * ES);
       const cpx<R> dv = bload<R>(rD, vq, x * NYZ * ES) * v;
       pot += double(bload_real<R>(rA, vqa, x * NYZ * RS)) * (norm2(u) - norm2(v));
