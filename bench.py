@@ -89,6 +89,44 @@ def run_workload(cfg, steps, warmup, seed_vortex, profile=True, precision=None, 
                 vortices=vort, obs=obs)
 
 
+def run_q1d(steps, warmup, seed=7, profile_steps=2):
+    """Batched quasi-1D workload: set-up (device eigensolver), start-up and
+    warm-up steps, launch-shape tuning, then `steps` steps recorded as one
+    HIP graph and launched once (timed from launch to completion)."""
+    import torch
+    from paper_2602_08982_amd import tdslda as T
+    from paper_2602_08982_amd import workloads as W
+    t0 = time.perf_counter()
+    ctx, info = W.setup_q1d(W.Q1D, seed, stream=torch.cuda.current_stream().cuda_stream)
+    t_setup = time.perf_counter() - t0
+    nst = info["states"]
+    ctx.abm_step(warmup)
+    tuned = ctx.autotune()
+    torch.cuda.synchronize()
+    rec_ms, run_ms = ctx.abm_graph(steps)
+    dt = run_ms * 1e-3
+    kern = {}
+    if profile_steps:
+        ctx.set_profiling(True)
+        ctx.abm_step(profile_steps)
+        stats = ctx.kernel_stats()
+        ctx.set_profiling(False)
+        S = 2 * W.Q1D["nz"] * 8
+        for k, (n, ms) in stats.items():
+            if n == 0:
+                continue
+            b = algorithmic_bytes(k, S, nst, 4)
+            avg = ms / n
+            kern[k] = dict(launches=n, avg_ms=avg, total_ms=ms, gbps=(b / (avg * 1e-3) / 1e9) if b else None)
+    st, chk = ctx.check()
+    ctx.close()
+    info = {k: v for k, v in info.items() if k not in ("kperp2", "counts")}
+    return dict(nst=nst, steps=steps, seconds=dt, value=nst * steps / dt, ms_per_step=1e3 * dt / steps,
+                graph_record_ms=rec_ms, setup_seconds=t_setup, tuned=tuned, kernels=kern,
+                profile_steps=profile_steps,
+                check=dict(status=st, **chk), problems=info)
+
+
 def copy_bandwidth():
     """Bytes moved per second by a plain device-to-device copy of 4 GiB
     (read + write), median of 5: the practical HBM ceiling on this device."""
@@ -164,6 +202,9 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--no-q1d", action="store_true")
+    ap.add_argument("--q1d-steps", type=int, default=200,
+                    help="steps of the batched quasi-1D run (one graph launch)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a device-to-device copy of 4 GiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -213,6 +254,11 @@ def main():
             rho_rel_err=float(np.abs(o["rho"] - r["rho"]).max() / np.abs(r["rho"]).max()),
             nu_rel_err=float(np.abs(o["nu"] - r["nu"]).max() / np.abs(r["nu"]).max()),
             energy_rel_err=float(abs(o["energy"]["total"] - r["energy"]["total"]) / abs(r["energy"]["EFG"])))
+    q1d = None
+    if not args.no_q1d:
+        q1d = run_q1d(args.q1d_steps, max(1, args.warmup))
+        print(f"# batched q1d: {q1d['value']:.4g} state-steps/s over {q1d['steps']} steps "
+              f"({q1d['nst']} states), graph record {q1d['graph_record_ms']:.0f} ms", file=sys.stderr, flush=True)
     cpu = None if args.no_cpu else cpu_baseline()
 
     line = {
@@ -242,6 +288,16 @@ def main():
             "value": mixed["value"], "unit": "state-steps/s", "ms_per_step": mixed["ms_per_step"],
             "dtype": "f32 states / f64 sums", "roofline": roofline(mixed, copy_bps), "kernels": mixed["kernels"],
             "check": mixed["check"], "vs_fp64_same_workload": mixed["vs_fp64"],
+        }
+    if q1d is not None:
+        line["batched_q1d"] = {
+            "workload": "2,304 quasi-1D problems (48x48 k_perp), N_z=256, |E|<12, FP32 states / FP64 sums, "
+                        f"{q1d['steps']} AB4AM5 steps in one HIP-graph launch",
+            "value": q1d["value"], "unit": "state-steps/s", "ms_per_step": q1d["ms_per_step"],
+            "states_evolved": q1d["nst"], "graph_record_ms": q1d["graph_record_ms"],
+            "setup_seconds": q1d["setup_seconds"], "tuned_workgroups": q1d["tuned"],
+            "problems": q1d["problems"], "kernels": q1d["kernels"], "check": q1d["check"],
+            "roofline": roofline(dict(q1d, steps=q1d["profile_steps"]), copy_bps) if q1d["kernels"] else None,
         }
     print(json.dumps(line))
 

@@ -163,6 +163,43 @@ tdslda_status tdslda_apply_hbdg(tdslda_ctx* ctx, const void* in_dev, void* out_d
  * counted in nsteps.  Errors: EORDER before any load. */
 tdslda_status tdslda_abm_step(tdslda_ctx* ctx, int64_t nsteps);
 
+/* The same advance as tdslda_abm_step, recorded once as a HIP graph on the
+ * context's stream (a private stream when the context uses the null stream)
+ * and submitted as one launch: every kernel boundary of the recording is a
+ * grid-wide synchronisation point (density reductions included).  Requires
+ * a started integrator (one tdslda_abm_step call, nsteps >= 0, after the
+ * load) and profiling off.  graph_ms (may be NULL) = {record + instantiate
+ * time, launch-to-completion time} in milliseconds.
+ * Errors: EORDER before the start-up or with profiling on. */
+tdslda_status tdslda_abm_graph(tdslda_ctx* ctx, int64_t nsteps, double graph_ms[2]);
+
+/* Launch-shape tuner: times each candidate workgroup size of every tunable
+ * kernel class on the loaded states and keeps the fastest for the rest of
+ * the context's life.  Quasi-1D kernel sets tune 4 classes (density pass,
+ * z-derivative pass, fused H.psi/integrator pass, pointwise pass) over
+ * 64/128/256 threads; full-3D sets have fixed shapes (nclasses = 0).  Only
+ * scratch buffers are written.  choice[4], ms[4] (host, may be NULL): chosen
+ * workgroup size and its median time per class.  Errors: EORDER before a load. */
+tdslda_status tdslda_autotune(tdslda_ctx* ctx, int* nclasses, int32_t choice[4], double ms[4]);
+
+/* Static states of the batched quasi-1D problems (Sec. 3.1, quasi-1D item;
+ * Sec. 2.3, Eq. HpsiEpsi): for each of nprob transverse momenta kperp2[p]
+ * (host) the real 2N_z x 2N_z BdG matrix with
+ *   h = -1/2 D2 + hfield(z) + kperp2[p]/2   (D2 of Eq. D2 along z, Nyquist kept)
+ * and the real pairing field delta(z) (both host [N_z]; hfield includes
+ * U + V - mu) is diagonalised on the device (rocSOLVER, batched) and the
+ * eigenpairs with 0 < E < ecut are kept, normalised to int |phi|^2 dz = 1.
+ * tdslda_q1d_count: per-problem counts (host int32[nprob]) and their sum,
+ * eigenvalues only.  tdslda_q1d_load_static: loads the kept states of all
+ * problems, problem by problem in ascending E, as the context's states with
+ * their E (weights) and kperp2, like tdslda_load_states; the context must be
+ * quasi-1D with capacity >= the total.  Errors: EINVAL (mode, sizes,
+ * capacity), EDEVICE (eigensolver failure), ENOMEM. */
+tdslda_status tdslda_q1d_count(const tdslda_lattice* lat, int nprob, const double* kperp2, const double* hfield,
+                               const double* delta, double ecut, int32_t* counts, int64_t* total);
+tdslda_status tdslda_q1d_load_static(tdslda_ctx* ctx, int nprob, const double* kperp2, const double* hfield,
+                                     const double* delta, double ecut, int64_t* nloaded);
+
 /* Energy terms of Sec. 3.2 for the current states, host out[8]:
  * {E_kin, E_pot, E_pair, E_curr, E_pot.ext, E_total, N, E_FG} with
  * N = int rho_+ dV and E_FG = 3/5 N eF of the uniform gas of the same mean

@@ -83,6 +83,9 @@ struct Engine {
   virtual bool producer_kinetic() const { return false; }
   // h slots that hold partials of the unscaled state
   virtual int raw_h_slots() const { return 0; }
+  // choose launch shapes by timing them on the loaded states; returns the
+  // number of kernel classes tuned (0: this kernel set has no choices)
+  virtual int autotune(Ctx& c, int32_t* out, double* ms_out) { (void)c; (void)out; (void)ms_out; return 0; }
   virtual void reduce_pot(Ctx& c, bool update) = 0;
   virtual void lap1(Ctx& c, const void* X, const double* scale, bool hpart, int64_t nst) = 0;
   virtual void lap2(Ctx& c, const L2Desc& d, int64_t nst) = 0;
@@ -233,4 +236,10 @@ std::unique_ptr<Engine> make3d_f32_small(int nx, int ny, int nz);
 std::unique_ptr<Engine> make3d_f32_large(int nx, int ny, int nz);
 std::unique_ptr<Engine> make_q1d_f64(int nz);
 std::unique_ptr<Engine> make_q1d_f32(int nz);
+// quasi-1D static states (q1dstatic.hip): counts per problem and, when X is
+// given, the kept eigenvectors written at X (slots 0 .. total-1) with E and
+// k_perp^2 per slot; returns the total number kept
+int64_t q1d_static(hipStream_t st, int N, double dz, int nprob, const double* kperp2, const double* hfield,
+                   const double* delta, double ecut, int32_t* counts, void* X, size_t esz, double* E_dev,
+                   double* kp_dev, int64_t cap);
 }  // namespace tdslda

@@ -6,16 +6,20 @@
 // A state is owned by a group of A lanes; lane a holds sites z = a + A*b,
 // b = 0..A-1.  Transforms along z are four-step DFTs: A-point DFTs in
 // registers, a twiddle, and a transpose through LDS.
+#include <algorithm>
+#include <type_traits>
+#include <vector>
+
 #include "ctx.h"
 
 namespace tdslda {
 namespace {
 
 // twiddle table w[m] = exp(+2 pi i m / N), m = 0..N-1 (host-filled)
-template <typename R, int A>
+template <typename R, int A, int TBv = 256>
 struct Q1DCfg {
   static constexpr int N = A * A;
-  static constexpr int TB = 256;
+  static constexpr int TB = TBv;      // threads per workgroup (autotuned)
   static constexpr int WS = TB / A;    // states in flight per workgroup
   static constexpr int PAD = A + 1;    // LDS row pitch
 };
@@ -66,12 +70,12 @@ __device__ __forceinline__ int q_wavenum(int l, int p_k1) {
 // ---------------------------------------------------------------------------
 // dens: rho, nu partials over a group of G states per workgroup and the
 // kinetic part 1/2 (int |d u|^2 - int |d v|^2) of <H>_n (slot 0).
-template <typename R, int A, int G>
-__global__ __launch_bounds__(256) void q_dens(const cpx<R>* __restrict__ X, int64_t nstates,
+template <typename R, int A, int G, int TB>
+__global__ __launch_bounds__(TB) void q_dens(const cpx<R>* __restrict__ X, int64_t nstates,
                                               const double* __restrict__ wu, const double* __restrict__ wv,
                                               StateScalars sc, double* __restrict__ dens_part,
                                               const cpx<R>* __restrict__ tw, double kz2, double dz) {
-  using CFG = Q1DCfg<R, A>;
+  using CFG = Q1DCfg<R, A, TB>;
   constexpr int N = CFG::N, WS = CFG::WS;
   constexpr int NW = CFG::TB / kWave;
   __shared__ cpx<R> lds_all[WS][A * CFG::PAD];
@@ -146,13 +150,13 @@ __global__ __launch_bounds__(256) void q_dens(const cpx<R>* __restrict__ X, int6
 
 // lap1: T = D2z phi and the potential part of <H>_n (slot 1):
 // int [ (A + k_perp^2/2) (|u|^2 - |v|^2) + 2 Re(u^* Delta v) ]
-template <typename R, int A>
-__global__ __launch_bounds__(256) void q_lap1(const cpx<R>* __restrict__ X, int64_t nstates,
+template <typename R, int A, int TB>
+__global__ __launch_bounds__(TB) void q_lap1(const cpx<R>* __restrict__ X, int64_t nstates,
                                               const double* __restrict__ scale, cpx<R>* __restrict__ T,
                                               const R* __restrict__ hA, const cpx<R>* __restrict__ hD,
                                               const double* __restrict__ kperp2, double* __restrict__ h_part,
                                               int h_stride, const cpx<R>* __restrict__ tw, double kz2, double dz) {
-  using CFG = Q1DCfg<R, A>;
+  using CFG = Q1DCfg<R, A, TB>;
   constexpr int N = CFG::N, WS = CFG::WS;
   __shared__ cpx<R> lds_all[WS][A * CFG::PAD];
   const int tid = threadIdx.x, grp = tid / A, a = tid % A;
@@ -198,10 +202,10 @@ __global__ __launch_bounds__(256) void q_lap1(const cpx<R>* __restrict__ X, int6
 }
 
 // lap2: pointwise H from T and the integrator modes (see k_lap2)
-template <typename R, int A, int MODE, int NP = 4, int NQ = 5>
-__global__ __launch_bounds__(256) void q_lap2(Lap2Args<R> P, int64_t nstates, const double* __restrict__ kperp2) {
+template <typename R, int A, int TB, int MODE, int NP = 4, int NQ = 5>
+__global__ __launch_bounds__(TB) void q_lap2(Lap2Args<R> P, int64_t nstates, const double* __restrict__ kperp2) {
   constexpr int HD = (NP > NQ - 1) ? NP : NQ - 1;
-  using CFG = Q1DCfg<R, A>;
+  using CFG = Q1DCfg<R, A, TB>;
   constexpr int N = CFG::N, WS = CFG::WS;
   const int tid = threadIdx.x, grp = tid / A, a = tid % A;
   const int64_t n = int64_t(blockIdx.x) * WS + grp;
@@ -280,10 +284,10 @@ __global__ __launch_bounds__(256) void q_lap2(Lap2Args<R> P, int64_t nstates, co
   }
 }
 
-template <typename R, int A, int MODE, int NP = 4, int NQ = 5>
-__global__ __launch_bounds__(256) void q_pointwise(PwArgs<R> P, int64_t nstates) {
+template <typename R, int A, int TB, int MODE, int NP = 4, int NQ = 5>
+__global__ __launch_bounds__(TB) void q_pointwise(PwArgs<R> P, int64_t nstates) {
   constexpr int HD = (NP > NQ - 1) ? NP : NQ - 1;
-  using CFG = Q1DCfg<R, A>;
+  using CFG = Q1DCfg<R, A, TB>;
   constexpr int N = CFG::N, WS = CFG::WS;
   const int tid = threadIdx.x, grp = tid / A, a = tid % A;
   const int64_t n = int64_t(blockIdx.x) * WS + grp;
@@ -391,12 +395,25 @@ __global__ __launch_bounds__(256) void q_grad(const cpx<R>* __restrict__ X, int6
   }
 }
 
+// workgroup sizes the tuner chooses from (states per workgroup = TB / A)
+template <class F>
+void with_tb(int tb, F&& f) {
+  switch (tb) {
+    case 64: f(std::integral_constant<int, 64>{}); break;
+    case 128: f(std::integral_constant<int, 128>{}); break;
+    default: f(std::integral_constant<int, 256>{});
+  }
+}
+constexpr int kTbCand[3] = {64, 128, 256};
+
 template <typename R, int A>
 struct EngineQ1D final : Engine {
   using CFG = Q1DCfg<R, A>;
   static constexpr int N = CFG::N;
   static constexpr int G = 512;  // states per density group
   cpx<R>* tw = nullptr;
+  // workgroup size per kernel class: dens, lap1, lap2, pointwise
+  int tb[4] = {256, 256, 256, 256};
   int ngx() const override { return 1; }
   int ncb() const override { return 1; }
   int group() const override { return G; }
@@ -417,9 +434,12 @@ struct EngineQ1D final : Engine {
   void dens(Ctx& c, const void* X, const double* scale, int64_t nst) override {
     twiddles(c);
     const unsigned ng = cdiv(nst, G);
-    c.launch(KC_DENS, [&] {
-      hipLaunchKernelGGL((q_dens<R, A, G>), dim3(ng), dim3(CFG::TB), 0, c.stream, (const cpx<R>*)X, nst, c.wu,
-                         c.wv, c.scalars(const_cast<double*>(scale)), c.dens_part, tw, kz2(c), c.lat.dz);
+    with_tb(tb[0], [&](auto t) {
+      constexpr int TB = decltype(t)::value;
+      c.launch(KC_DENS, [&] {
+        hipLaunchKernelGGL((q_dens<R, A, G, TB>), dim3(ng), dim3(TB), 0, c.stream, (const cpx<R>*)X, nst, c.wu,
+                           c.wv, c.scalars(const_cast<double*>(scale)), c.dens_part, tw, kz2(c), c.lat.dz);
+      });
     });
     c.nsg_used = int(ng);
   }
@@ -433,10 +453,13 @@ struct EngineQ1D final : Engine {
   }
   void lap1(Ctx& c, const void* X, const double* scale, bool hpart, int64_t nst) override {
     twiddles(c);
-    c.launch(KC_LAP1, [&] {
-      hipLaunchKernelGGL((q_lap1<R, A>), dim3(cdiv(nst, CFG::WS)), dim3(CFG::TB), 0, c.stream, (const cpx<R>*)X,
-                         nst, scale, (cpx<R>*)c.T, (const R*)c.hA, (const cpx<R>*)c.hD, c.kperp2,
-                         hpart ? c.h_part : nullptr, c.h_stride, tw, kz2(c), c.lat.dz);
+    with_tb(tb[1], [&](auto t) {
+      constexpr int TB = decltype(t)::value;
+      c.launch(KC_LAP1, [&] {
+        hipLaunchKernelGGL((q_lap1<R, A, TB>), dim3(cdiv(nst, TB / A)), dim3(TB), 0, c.stream, (const cpx<R>*)X,
+                           nst, scale, (cpx<R>*)c.T, (const R*)c.hA, (const cpx<R>*)c.hD, c.kperp2,
+                           hpart ? c.h_part : nullptr, c.h_stride, tw, kz2(c), c.lat.dz);
+      });
     });
   }
   void lap2(Ctx& c, const L2Desc& d, int64_t nst) override {
@@ -463,30 +486,33 @@ struct EngineQ1D final : Engine {
     P.tay_re = d.tay_re;
     P.tay_im = d.tay_im;
     P.init_acc = d.init_acc;
-    dim3 grid(cdiv(nst, CFG::WS)), block(CFG::TB);
-    switch (d.mode) {
-      case L2_H:
-        c.launch(KC_LAP2_H, [&] { hipLaunchKernelGGL((q_lap2<R, A, L2_H>), grid, block, 0, c.stream, P, nst, c.kperp2); });
-        break;
-      case L2_F:
-        c.launch(KC_LAP2_F, [&] { hipLaunchKernelGGL((q_lap2<R, A, L2_F>), grid, block, 0, c.stream, P, nst, c.kperp2); });
-        break;
-      case L2_CORR:
-        c.launch(KC_LAP2_CORR, [&] { hipLaunchKernelGGL((q_lap2<R, A, L2_CORR>), grid, block, 0, c.stream, P, nst, c.kperp2); });
-        break;
-      case L2_FULL:
-        c.launch(KC_LAP2_FULL, [&] {
-          if (c.np == 3)
-            hipLaunchKernelGGL((q_lap2<R, A, L2_FULL, 3, 4>), grid, block, 0, c.stream, P, nst, c.kperp2);
-          else if (c.np == 5)
-            hipLaunchKernelGGL((q_lap2<R, A, L2_FULL, 5, 5>), grid, block, 0, c.stream, P, nst, c.kperp2);
-          else
-            hipLaunchKernelGGL((q_lap2<R, A, L2_FULL, 4, 5>), grid, block, 0, c.stream, P, nst, c.kperp2);
-        });
-        break;
-      default:
-        c.launch(KC_LAP2_TAYLOR, [&] { hipLaunchKernelGGL((q_lap2<R, A, L2_TAYLOR>), grid, block, 0, c.stream, P, nst, c.kperp2); });
-    }
+    with_tb(tb[2], [&](auto t) {
+      constexpr int TB = decltype(t)::value;
+      dim3 grid(cdiv(nst, TB / A)), block(TB);
+      switch (d.mode) {
+        case L2_H:
+          c.launch(KC_LAP2_H, [&] { hipLaunchKernelGGL((q_lap2<R, A, TB, L2_H>), grid, block, 0, c.stream, P, nst, c.kperp2); });
+          break;
+        case L2_F:
+          c.launch(KC_LAP2_F, [&] { hipLaunchKernelGGL((q_lap2<R, A, TB, L2_F>), grid, block, 0, c.stream, P, nst, c.kperp2); });
+          break;
+        case L2_CORR:
+          c.launch(KC_LAP2_CORR, [&] { hipLaunchKernelGGL((q_lap2<R, A, TB, L2_CORR>), grid, block, 0, c.stream, P, nst, c.kperp2); });
+          break;
+        case L2_FULL:
+          c.launch(KC_LAP2_FULL, [&] {
+            if (c.np == 3)
+              hipLaunchKernelGGL((q_lap2<R, A, TB, L2_FULL, 3, 4>), grid, block, 0, c.stream, P, nst, c.kperp2);
+            else if (c.np == 5)
+              hipLaunchKernelGGL((q_lap2<R, A, TB, L2_FULL, 5, 5>), grid, block, 0, c.stream, P, nst, c.kperp2);
+            else
+              hipLaunchKernelGGL((q_lap2<R, A, TB, L2_FULL, 4, 5>), grid, block, 0, c.stream, P, nst, c.kperp2);
+          });
+          break;
+        default:
+          c.launch(KC_LAP2_TAYLOR, [&] { hipLaunchKernelGGL((q_lap2<R, A, TB, L2_TAYLOR>), grid, block, 0, c.stream, P, nst, c.kperp2); });
+      }
+    });
   }
   void pointwise(Ctx& c, const PwDesc& d, int64_t nst) override {
     PwArgs<R> P{};
@@ -503,20 +529,23 @@ struct EngineQ1D final : Engine {
       P.a[i] = c.aco[i];
     }
     P.out64 = (cpx<double>*)d.out64;
-    dim3 grid(cdiv(nst, CFG::WS)), block(CFG::TB);
-    if (d.mode == PW_NORM)
-      c.launch(KC_NORM, [&] { hipLaunchKernelGGL((q_pointwise<R, A, PW_NORM>), grid, block, 0, c.stream, P, nst); });
-    else if (d.mode == PW_PRED)
-      c.launch(KC_PRED, [&] {
-        if (c.np == 3)
-          hipLaunchKernelGGL((q_pointwise<R, A, PW_PRED, 3, 4>), grid, block, 0, c.stream, P, nst);
-        else if (c.np == 5)
-          hipLaunchKernelGGL((q_pointwise<R, A, PW_PRED, 5, 5>), grid, block, 0, c.stream, P, nst);
-        else
-          hipLaunchKernelGGL((q_pointwise<R, A, PW_PRED, 4, 5>), grid, block, 0, c.stream, P, nst);
-      });
-    else
-      c.launch(KC_SETUP, [&] { hipLaunchKernelGGL((q_pointwise<R, A, PW_SCALE>), grid, block, 0, c.stream, P, nst); });
+    with_tb(tb[3], [&](auto t) {
+      constexpr int TB = decltype(t)::value;
+      dim3 grid(cdiv(nst, TB / A)), block(TB);
+      if (d.mode == PW_NORM)
+        c.launch(KC_NORM, [&] { hipLaunchKernelGGL((q_pointwise<R, A, TB, PW_NORM>), grid, block, 0, c.stream, P, nst); });
+      else if (d.mode == PW_PRED)
+        c.launch(KC_PRED, [&] {
+          if (c.np == 3)
+            hipLaunchKernelGGL((q_pointwise<R, A, TB, PW_PRED, 3, 4>), grid, block, 0, c.stream, P, nst);
+          else if (c.np == 5)
+            hipLaunchKernelGGL((q_pointwise<R, A, TB, PW_PRED, 5, 5>), grid, block, 0, c.stream, P, nst);
+          else
+            hipLaunchKernelGGL((q_pointwise<R, A, TB, PW_PRED, 4, 5>), grid, block, 0, c.stream, P, nst);
+        });
+      else
+        c.launch(KC_SETUP, [&] { hipLaunchKernelGGL((q_pointwise<R, A, TB, PW_SCALE>), grid, block, 0, c.stream, P, nst); });
+    });
   }
   void grad(Ctx& c, const void* X, const double* scale, int64_t n0, int64_t nchunk) override {
     twiddles(c);
@@ -526,6 +555,73 @@ struct EngineQ1D final : Engine {
                          n0, nchunk, scale, c.wu, c.wv, c.kperp2, tw, 2 * kPi / (N * c.lat.dz), pz * pz, c.gscratch,
                          c.gscratch + nchunk * N);
     });
+  }
+
+  // Time every workgroup size of each kernel class on the loaded states
+  // (median of 5 after a warm launch) and keep the fastest.  Only scratch
+  // buffers are written (dens_part, T, h slots, norm slots), all of which the
+  // next evaluation recomputes.
+  int autotune(Ctx& c, int32_t* out, double* ms_out) override {
+    twiddles(c);
+    const int b = c.phi;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    auto timeit = [&](auto&& run) {
+      run();
+      std::vector<float> t;
+      for (int r = 0; r < 5; ++r) {
+        HIPCHK(hipEventRecord(e0, c.stream));
+        run();
+        HIPCHK(hipEventRecord(e1, c.stream));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        t.push_back(ms);
+      }
+      std::sort(t.begin(), t.end());
+      return double(t[2]);
+    };
+    const bool prof = c.prof;
+    c.prof = false;
+    for (int k = 0; k < 4; ++k) {
+      double best = 1e30;
+      int bt = tb[k];
+      for (int cand : kTbCand) {
+        tb[k] = cand;
+        double ms = 0;
+        if (k == 0) {
+          ms = timeit([&] { dens(c, c.sb[b], c.sscale[b], c.nst); });
+        } else if (k == 1) {
+          ms = timeit([&] { lap1(c, c.sb[b], c.sscale[b], true, c.nst); });
+        } else if (k == 2) {
+          L2Desc d;
+          d.mode = L2_H;
+          d.X = c.sb[b];
+          d.T = c.T;
+          d.scale = c.sscale[b];
+          d.out = c.T;  // in place over T: each thread reads then writes its own sites
+          ms = timeit([&] { lap2(c, d, c.nst); });
+        } else {
+          PwDesc d;
+          d.mode = PW_NORM;
+          d.X = c.sb[b];
+          d.nrm_part = c.nrm_part;
+          ms = timeit([&] { pointwise(c, d, c.nst); });
+        }
+        if (ms < best) {
+          best = ms;
+          bt = cand;
+        }
+      }
+      tb[k] = bt;
+      if (out) out[k] = bt;
+      if (ms_out) ms_out[k] = best;
+    }
+    c.prof = prof;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return 4;
   }
 };
 

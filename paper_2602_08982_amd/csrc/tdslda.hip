@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -716,6 +717,93 @@ tdslda_status tdslda_abm_step(tdslda_ctx* c, int64_t nsteps) {
     require(c->loaded, TDSLDA_EORDER, "abm_step before any state load");
     require(nsteps >= 0, TDSLDA_EINVAL, "nsteps < 0");
     abm(*c, nsteps);
+    HIPCHK(hipStreamSynchronize(c->stream));
+  });
+}
+
+tdslda_status tdslda_abm_graph(tdslda_ctx* c, int64_t nsteps, double graph_ms[2]) {
+  return guard(c, [&] {
+    require(c->loaded && c->started, TDSLDA_EORDER, "abm_graph needs a started integrator (call abm_step first)");
+    require(!c->prof, TDSLDA_EORDER, "switch profiling off before recording a graph");
+    require(nsteps >= 0, TDSLDA_EINVAL, "nsteps < 0");
+    if (nsteps == 0) return;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    hipStream_t user = c->stream, cs = c->stream;
+    if (cs == nullptr) HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    c->stream = cs;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    auto cleanup = [&] {
+      if (ge) (void)hipGraphExecDestroy(ge);
+      if (g) (void)hipGraphDestroy(g);
+      c->stream = user;
+      if (cs != user) (void)hipStreamDestroy(cs);
+    };
+    try {
+      const auto t0 = std::chrono::steady_clock::now();
+      HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+      try {
+        abm(*c, nsteps);
+      } catch (...) {
+        (void)hipStreamEndCapture(cs, &g);
+        throw;
+      }
+      HIPCHK(hipStreamEndCapture(cs, &g));
+      HIPCHK(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+      const auto t1 = std::chrono::steady_clock::now();
+      HIPCHK(hipGraphLaunch(ge, cs));
+      HIPCHK(hipStreamSynchronize(cs));
+      const auto t2 = std::chrono::steady_clock::now();
+      if (graph_ms) {
+        graph_ms[0] = std::chrono::duration<double, std::milli>(t1 - t0).count();
+        graph_ms[1] = std::chrono::duration<double, std::milli>(t2 - t1).count();
+      }
+    } catch (...) {
+      cleanup();
+      throw;
+    }
+    cleanup();
+  });
+}
+
+tdslda_status tdslda_autotune(tdslda_ctx* c, int* nclasses, int32_t choice[4], double ms[4]) {
+  return guard(c, [&] {
+    require(c->loaded, TDSLDA_EORDER, "load states before tuning");
+    const int k = c->eng->autotune(*c, choice, ms);
+    if (nclasses) *nclasses = k;
+    HIPCHK(hipStreamSynchronize(c->stream));
+  });
+}
+
+tdslda_status tdslda_q1d_count(const tdslda_lattice* lat, int nprob, const double* kperp2, const double* hfield,
+                               const double* delta, double ecut, int32_t* counts, int64_t* total) {
+  if (!lat || !kperp2 || !hfield || !delta || nprob <= 0 || lat->mode != TDSLDA_MODE_Q1D) return TDSLDA_EINVAL;
+  try {
+    check_lattice(*lat);
+    const int64_t t = q1d_static(nullptr, lat->nz, lat->dz, nprob, kperp2, hfield, delta, ecut, counts, nullptr, 0,
+                                 nullptr, nullptr, 0);
+    if (total) *total = t;
+    return TDSLDA_OK;
+  } catch (const Fail& e) {
+    std::fprintf(stderr, "tdslda_q1d_count: %s\n", e.msg.c_str());
+    return e.st;
+  } catch (...) {
+    return TDSLDA_EDEVICE;
+  }
+}
+
+tdslda_status tdslda_q1d_load_static(tdslda_ctx* c, int nprob, const double* kperp2, const double* hfield,
+                                     const double* delta, double ecut, int64_t* nloaded) {
+  return guard(c, [&] {
+    require(c->q1d, TDSLDA_EINVAL, "static quasi-1D states need a quasi-1D context");
+    require(kperp2 && hfield && delta && nprob > 0, TDSLDA_EINVAL, "bad problem list");
+    const int64_t n = q1d_static(c->stream, c->lat.nz, c->lat.dz, nprob, kperp2, hfield, delta, ecut, nullptr,
+                                 c->sb[0], c->esz, c->E, c->kperp2, c->cap);
+    require(n > 0, TDSLDA_EINVAL, "no state below the cutoff");
+    c->nst = n;
+    set_weights(*c, n, nullptr);
+    after_load(*c);
+    if (nloaded) *nloaded = n;
     HIPCHK(hipStreamSynchronize(c->stream));
   });
 }

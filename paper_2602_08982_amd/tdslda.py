@@ -71,6 +71,12 @@ _SIGS = {
     "tdslda_set_profiling": [C.c_void_p, C.c_int],
     "tdslda_kernel_stats": [C.c_void_p, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_double)],
     "tdslda_kernel_name": [C.c_int],
+    "tdslda_abm_graph": [C.c_void_p, C.c_int64, C.c_void_p],
+    "tdslda_autotune": [C.c_void_p, C.POINTER(C.c_int), C.c_void_p, C.c_void_p],
+    "tdslda_q1d_count": [C.POINTER(Lattice), C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
+                         C.c_void_p, C.POINTER(C.c_int64)],
+    "tdslda_q1d_load_static": [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
+                               C.POINTER(C.c_int64)],
 }
 
 EXPORTED = tuple(_SIGS)
@@ -255,6 +261,33 @@ class Context:
     def load(self, path):
         self._chk(self.lib.tdslda_load(self.h, os.fsencode(path)))
 
+    def abm_graph(self, nsteps):
+        """abm_step(nsteps) recorded as one HIP graph and launched once;
+        returns (record + instantiate ms, launch-to-completion ms)."""
+        ms = np.zeros(2)
+        self._chk(self.lib.tdslda_abm_graph(self.h, int(nsteps), _p(ms)))
+        return float(ms[0]), float(ms[1])
+
+    def autotune(self):
+        """Tune the launch shapes on the loaded states; returns a list of
+        (workgroup size, median ms) per tuned kernel class."""
+        n = C.c_int()
+        ch = np.zeros(4, dtype=np.int32)
+        ms = np.zeros(4)
+        self._chk(self.lib.tdslda_autotune(self.h, C.byref(n), _p(ch), _p(ms)))
+        return [(int(ch[i]), float(ms[i])) for i in range(n.value)]
+
+    def q1d_load_static(self, kperp2, hfield, delta, ecut):
+        """Load the static states (0 < E < ecut) of every quasi-1D problem;
+        returns the number loaded."""
+        kp = _f64(kperp2).ravel()
+        hf = _f64(hfield).ravel()
+        de = _f64(delta).ravel()
+        n = C.c_int64()
+        self._chk(self.lib.tdslda_q1d_load_static(self.h, kp.size, _p(kp), _p(hf), _p(de), float(ecut),
+                                                  C.byref(n)))
+        return n.value
+
     # --- profiling ----------------------------------------------------------
     def set_profiling(self, on=True):
         self._chk(self.lib.tdslda_set_profiling(self.h, int(on)))
@@ -266,6 +299,22 @@ class Context:
             self._chk(self.lib.tdslda_kernel_stats(self.h, k, C.byref(n), C.byref(ms)))
             out[name] = (n.value, ms.value)
         return out
+
+
+def q1d_count(lattice, kperp2, hfield, delta, ecut):
+    """Per-problem counts of static states with 0 < E < ecut (eigenvalues
+    only, on the device) and their total."""
+    lib = load_library()
+    kp = _f64(kperp2).ravel()
+    hf = _f64(hfield).ravel()
+    de = _f64(delta).ravel()
+    counts = np.zeros(kp.size, dtype=np.int32)
+    tot = C.c_int64()
+    st = lib.tdslda_q1d_count(C.byref(lattice), kp.size, _p(kp), _p(hf), _p(de), float(ecut), _p(counts),
+                              C.byref(tot))
+    if st != OK:
+        raise TdsldaError(st, "tdslda_q1d_count failed")
+    return counts, tot.value
 
 
 def lattice_3d(n, d=1.0):

@@ -67,3 +67,79 @@ def setup(cfg, vortices, stream=None, precision=None, integrator=T.AB4AM5):
     if len(vortices):
         ctx.imprint_vortices(vortices)
     return ctx, kidx
+
+
+# ---------------------------------------------------------------------------
+# Batched quasi-1D workload: N_z = 256, dz = 1, transverse momenta on a
+# 48 x 48 grid (2,304 independent problems), FP32 states with FP64 sums.
+Q1D = dict(name="batched_q1d_256", nz=256, dz=1.0, nk=48, mu=1.0, delta0=0.5, omega_z=0.0175, ecut=12.0,
+           precision=T.FP32_MIXED, dt=0.005, corner_range=(32, 48))
+
+
+def q1d_kperp2(nk, dperp):
+    """k_perp^2 of every problem: k = 2 pi m / (nk dperp), m in [-nk/2, nk/2),
+    x index slow (no de-duplication of equal k_perp^2)."""
+    m = np.arange(nk) - nk // 2
+    k = 2.0 * np.pi * m / (nk * dperp)
+    return (k[:, None] ** 2 + k[None, :] ** 2).ravel()
+
+
+def q1d_potentials(cfg, bump):
+    """(V_trap, V_static = V_trap + bump) on the centred z lattice."""
+    z = centered(cfg["nz"], cfg["dz"])
+    vt = 0.5 * cfg["omega_z"] ** 2 * z * z
+    vb, wb, zb = bump
+    return vt, vt + vb * np.exp(-((z - zb) ** 2) / (2.0 * wb * wb))
+
+
+def q1d_dperp(cfg, hstatic, lo=0.3, hi=3.0, iters=40):
+    """Transverse spacing d_perp by bisection on the corner problem (largest
+    k_perp^2) so that its kept-state count lies in cfg['corner_range'];
+    the count grows with d_perp."""
+    lat = T.lattice_q1d(cfg["nz"], cfg["dz"], 1.0, 1.0)
+    delta = np.full(cfg["nz"], cfg["delta0"])
+    want_lo, want_hi = cfg["corner_range"]
+
+    def count(d):
+        kc = 2.0 * (np.pi * (cfg["nk"] // 2) * 2.0 / (cfg["nk"] * d)) ** 2
+        _, tot = T.q1d_count(lat, [kc], hstatic, delta, cfg["ecut"])
+        return tot
+
+    a, b = lo, hi
+    for _ in range(iters):
+        m = 0.5 * (a + b)
+        c = count(m)
+        if c < want_lo:
+            a = m
+        elif c > want_hi:
+            b = m
+        else:
+            return m, c
+    raise RuntimeError("no d_perp gives a corner count in range")
+
+
+def setup_q1d(cfg, seed, stream=None, precision=None, nk=None):
+    """Create the batched quasi-1D context: static states of every problem
+    (bump on, U = 0, Delta = delta0) loaded on the device, trap-only V_ext
+    for the evolution (bump removed at t = 0), regulator frozen with
+    E_c = ecut.  Returns (ctx, info)."""
+    import synth
+    nk = cfg["nk"] if nk is None else nk
+    bump = synth.gaussian_bump(seed)
+    vt, vs = q1d_potentials(cfg, bump)
+    hstatic = vs - cfg["mu"]
+    dperp, corner = q1d_dperp(dict(cfg, nk=nk), hstatic)
+    kp2 = q1d_kperp2(nk, dperp)
+    delta = np.full(cfg["nz"], cfg["delta0"])
+    lat = T.lattice_q1d(cfg["nz"], cfg["dz"], nk * dperp, nk * dperp)
+    counts, total = T.q1d_count(lat, kp2, hstatic, delta, cfg["ecut"])
+    prec = cfg["precision"] if precision is None else precision
+    run = T.run_config(precision=prec, integrator=T.AB4AM5, dt=cfg["dt"], selfstart=1, stream=stream)
+    ctx = T.Context(lat, T.functional_slda(cfg["mu"], cfg["ecut"]), run, int(total))
+    ctx.set_external(vt, freeze_regulator=True)
+    n = ctx.q1d_load_static(kp2, hstatic, delta, cfg["ecut"])
+    assert n == total
+    info = dict(dperp=dperp, corner_count=int(corner), nproblems=int(kp2.size), states=int(total),
+                count_min=int(counts.min()), count_mean=float(counts.mean()), count_max=int(counts.max()),
+                histogram=np.histogram(counts, bins=8)[0].tolist(), bump=bump, kperp2=kp2, counts=counts)
+    return ctx, info
