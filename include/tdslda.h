@@ -200,6 +200,72 @@ tdslda_status tdslda_q1d_count(const tdslda_lattice* lat, int nprob, const doubl
 tdslda_status tdslda_q1d_load_static(tdslda_ctx* ctx, int nprob, const double* kperp2, const double* hfield,
                                      const double* delta, double ecut, int64_t* nloaded);
 
+/* Static self-consistent solve, quasi-2D geometry (Sec. 3.4, Alg. MapK;
+ * Sec. 3.1 quasi-2D item): an nx x ny periodic x-y lattice (spacings dx, dy)
+ * and nz plane-wave momenta along z (spacing dz, L_z = nz dz); the
+ * nz/2 + 1 distinct |k_z| are diagonalised once per iteration (real BdG
+ * matrices of order 2 nx ny, one batched rocSOLVER call) with multiplicity
+ * weights.  T = 0: every E > 0 eigenpair is occupied.  The map K returns the
+ * potentials of the SLDA (A = 1) or BdG functional with the regulator
+ * Lambda_c(V_+ = V_ext + U_in, mu, ec).  Iteration: linear mixing of (U,
+ * Delta) with parameter mix; fixed-N mode when a_mu != 0 (Eq. update-mu with
+ * N = int rho_+ d^3r); converged when max(|U_out - U_in|_inf,
+ * |Delta_out - Delta_in|_inf) / eF_ref < tol and |N - N_req| / N_req < tol.
+ * Delta is real.  All arrays are host FP64 [nx*ny], flat index ix*ny + iy. */
+typedef struct {
+  int nx, ny, nz;
+  double dx, dy, dz;
+  double ec;     /* regulator cutoff E_c */
+  double mix;    /* linear mixing parameter m_p in (0, 1] */
+  double a_mu;   /* step of Eq. update-mu; 0 = fixed mu */
+  double N_req;  /* required particle number (fixed-N mode) */
+  double tol;    /* residual threshold */
+  double eF_ref; /* Fermi energy of the reference uniform system */
+  int maxit;
+} tdslda_static;
+
+/* One application of K at (U, delta, mu): U_out, delta_out, rho (per spin),
+ * nu (any output may be NULL) and N. */
+tdslda_status tdslda_static_map(const tdslda_static* s, const tdslda_functional* fun, const double* vext,
+                                const double* U, const double* delta, double mu, double* U_out,
+                                double* delta_out, double* rho, double* nu, double* N);
+/* Iterate from (U, delta, mu) (updated in place: the converged K output, or
+ * the last mixed iterate when maxit is reached).  iters, converged and
+ * hist[maxit][4] = {r, |N - N_req|/N_req, mu, N} per iteration may be NULL.
+ * Errors: EINVAL, ENOMEM, EDEVICE (eigensolver), EUNSTABLE (non-finite
+ * residual or undefined regulator). */
+tdslda_status tdslda_static_solve(const tdslda_static* s, const tdslda_functional* fun, const double* vext,
+                                  double* U, double* delta, double* mu, int* iters, int* converged,
+                                  double* hist);
+
+/* Warm-start network of the static workflow (learned initial guess for
+ * the fixed-point iteration of Alg. MapK; Sec. 4.6 on initial guesses).
+ * A small convolutional network maps the normalised external potential of
+ * an H x W x-y lattice (host float [B][H][W]) to normalised (U, Delta) maps
+ * ([B][2][H][W]) and a chemical potential ([B]):
+ *   h1 = relu(conv3(x)), h2 = relu(conv3(h1)), h3 = relu(conv3(h2)) (C
+ *   channels each, 3x3 kernels with periodic padding), maps = 1x1 conv of
+ *   h3, mu = mean over sites of h3 . w_mu + b_mu.
+ * Loss L = mean((maps - Y)^2) + lam_mu mean((mu - y_mu)^2); Adam (beta1 0.9,
+ * beta2 0.999, eps 1e-8) on FP32 master weights.  Flat parameter order
+ * W1 b1 W2 b2 W3 b3 Wm bm w_mu b_mu (conv weights [Cout][Cin][3][3]);
+ * tdslda_nn_nparams(C) gives the count.  Initial weights are the caller's.
+ * All buffers are device-resident and owned by the network object; host
+ * arrays are copied.  Errors: EINVAL (sizes, B > batch_max), ENOMEM, EDEVICE. */
+typedef struct tdslda_nn tdslda_nn;
+int64_t tdslda_nn_nparams(int C);
+tdslda_status tdslda_nn_create(int H, int W, int C, int batch_max, const float* theta0, tdslda_nn** out);
+tdslda_status tdslda_nn_destroy(tdslda_nn* nn);
+tdslda_status tdslda_nn_params(tdslda_nn* nn, float* theta_out, int64_t* count);
+/* replaces the weights and resets the Adam moments and step count */
+tdslda_status tdslda_nn_set_params(tdslda_nn* nn, const float* theta);
+tdslda_status tdslda_nn_forward(tdslda_nn* nn, int B, const float* x, float* maps, float* mu);
+tdslda_status tdslda_nn_loss_grad(tdslda_nn* nn, int B, const float* x, const float* Y, const float* y_mu,
+                                  float lam_mu, float* loss, float* grad);
+/* loss_grad followed by one Adam step with learning rate lr */
+tdslda_status tdslda_nn_train_step(tdslda_nn* nn, int B, const float* x, const float* Y, const float* y_mu,
+                                   float lam_mu, float lr, float* loss);
+
 /* Energy terms of Sec. 3.2 for the current states, host out[8]:
  * {E_kin, E_pot, E_pair, E_curr, E_pot.ext, E_total, N, E_FG} with
  * N = int rho_+ dV and E_FG = 3/5 N eF of the uniform gas of the same mean

@@ -1,0 +1,101 @@
+"""Static self-consistent solve of the quasi-2D problem (test infrastructure:
+only tests/, the smoke check and the benchmark's CPU leg use the oracle).
+
+Geometry (Sec. 3.1, quasi-2D item): an N_x x N_y periodic lattice in the x-y
+plane and plane waves exp(i k_z z) / sqrt(L_z) along z, with the N_z lattice
+momenta k_z = 2 pi m / (N_z dz), m in [-N_z/2, N_z/2).  Equal |k_z| give the
+same BdG problem, so the N_z/2 + 1 distinct |k_z| are diagonalised once and
+weighted by their multiplicity (1 for m = 0 and m = -N_z/2, 2 otherwise).
+
+The map K of Alg. MapK (H -> eigenpairs -> densities -> potentials), the
+linear mixing of the potentials, the fixed-N chemical-potential update of
+Eq. update-mu and the convergence test (residual of the potentials and of
+N; readings in the design notes) are written out plainly: dense matrices,
+numpy.linalg.eigh, FP64.
+"""
+import numpy as np
+
+from . import functional as F
+from . import lattice as L
+
+
+class GeometryQ2D:
+    def __init__(self, nx, ny, nz, dx=1.0, dy=1.0, dz=1.0):
+        self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        self.dx, self.dy, self.dz = float(dx), float(dy), float(dz)
+        self.M = self.nx * self.ny
+        self.shape = (self.nx, self.ny)
+        self.Lz = self.nz * self.dz
+        self.dA = self.dx * self.dy
+        # -1/2 (D2_x (x) 1 + 1 (x) D2_y) on the flat index ix*N_y + iy (Eq. D2)
+        d2x = L.d2_matrix(self.nx, self.dx)
+        d2y = L.d2_matrix(self.ny, self.dy)
+        self.K = -0.5 * (np.kron(d2x, np.eye(self.ny)) + np.kron(np.eye(self.nx), d2y))
+        m = np.arange(0, self.nz // 2 + 1)
+        self.kz = 2.0 * np.pi * m / (self.nz * self.dz)
+        self.mult = np.where((m == 0) | (m == self.nz // 2), 1.0, 2.0)
+
+    def coords(self):
+        x = (np.arange(self.nx) - self.nx // 2) * self.dx
+        y = (np.arange(self.ny) - self.ny // 2) * self.dy
+        return np.meshgrid(x, y, indexing="ij")
+
+
+def build_h(geom, hfield, delta, kz):
+    """2M x 2M BdG matrix of one k_z (Eq. HpsiEpsi, spin-symmetric reduced
+    form): h = K + diag(hfield) + k_z^2 / 2 with hfield = V_ext + U - mu."""
+    h = geom.K + np.diag(np.ravel(hfield) + 0.5 * kz * kz)
+    d = np.diag(np.ravel(delta))
+    return np.block([[h, d], [np.conj(d), -h]])
+
+
+def densities(geom, hfield, delta):
+    """rho (per spin) and nu of the T = 0 state: every E > 0 eigenpair of
+    every k_z, v occupied (f(-E) = 1, f(E) = 0), states normalised in the
+    x-y plane (eigenvectors / sqrt(dx dy)), and the 1 / L_z of the plane
+    waves along z."""
+    rho = np.zeros(geom.M)
+    nu = np.zeros(geom.M, dtype=complex)
+    for kz, w in zip(geom.kz, geom.mult):
+        E, W = np.linalg.eigh(build_h(geom, hfield, delta, kz))
+        sel = E > 0
+        u = W[:geom.M, sel] / np.sqrt(geom.dA)
+        v = W[geom.M:, sel] / np.sqrt(geom.dA)
+        rho += w * np.sum(np.abs(v) ** 2, axis=1)
+        nu += w * np.sum(u * np.conj(v), axis=1)
+    return (rho / geom.Lz).reshape(geom.shape), (nu / geom.Lz).reshape(geom.shape)
+
+
+def map_k(geom, fun, vext, U, delta, mu, ec):
+    """One application of Alg. MapK.  The regulator uses V_+ = V_ext + U_in
+    (the static iteration order).  Returns (U_out, Delta_out, rho, nu, N)
+    with N = int rho_+ d^3r = L_z sum 2 rho dx dy."""
+    lam = F.lambda_c(vext + U, mu, ec)
+    rho, nu = densities(geom, vext + U - mu, delta)
+    Uo, Do, _ = F.potentials(rho, nu, lam, fun)
+    N = geom.Lz * geom.dA * np.sum(2.0 * rho)
+    return Uo, Do, rho, nu, N
+
+
+def solve(geom, fun, vext, U, delta, mu, ec, mix=0.5, a_mu=0.5, N_req=None, tol=1e-8, eF_ref=0.5,
+          maxit=500, history=None):
+    """Linear mixing p_{n+1} = m K[p_n] + (1 - m) p_n on p = (U, Delta); in
+    fixed-N mode (N_req given) mu follows Eq. update-mu each iteration.
+    Converged when max(|U_out - U_in|_inf, |Delta_out - Delta_in|_inf) /
+    eF_ref < tol and (fixed N) |N - N_req| / N_req < tol.  Returns
+    (U, Delta, mu, iterations, converged)."""
+    U = np.array(U, float)
+    delta = np.array(delta, complex)
+    for it in range(1, maxit + 1):
+        Uo, Do, rho, nu, N = map_k(geom, fun, vext, U, delta, mu, ec)
+        r = max(np.abs(Uo - U).max(), np.abs(Do - delta).max()) / eF_ref
+        rn = 0.0 if N_req is None else abs(N - N_req) / N_req
+        if history is not None:
+            history.append((r, rn, mu, N))
+        if r < tol and rn < tol:
+            return Uo, Do, mu, it, True
+        U = mix * Uo + (1.0 - mix) * U
+        delta = mix * Do + (1.0 - mix) * delta
+        if N_req is not None:
+            mu = mu + a_mu / N_req * (N_req - N)
+    return U, delta, mu, maxit, False

@@ -23,6 +23,8 @@ SOURCES = [
     "inst3d_f32_large.hip",
     "q1d.hip",
     "q1dstatic.hip",
+    "static.hip",
+    "nn.hip",
 ]
 
 FLAGS = [

@@ -242,4 +242,5 @@ std::unique_ptr<Engine> make_q1d_f32(int nz);
 int64_t q1d_static(hipStream_t st, int N, double dz, int nprob, const double* kperp2, const double* hfield,
                    const double* delta, double ecut, int32_t* counts, void* X, size_t esz, double* E_dev,
                    double* kp_dev, int64_t cap);
+struct StaticSolver;
 }  // namespace tdslda

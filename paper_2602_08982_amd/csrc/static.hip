@@ -1,0 +1,366 @@
+// Static self-consistent solve of the quasi-2D problem on the device
+// (Sec. 3.4, Alg. MapK; Sec. 3.1 quasi-2D item): an N_x x N_y lattice in the
+// x-y plane with plane waves along z.  Every iteration builds the real BdG
+// matrices of the N_z/2 + 1 distinct |k_z| (Eq. HpsiEpsi with the exact
+// spectral D2 of Eq. D2 in x and y), diagonalises them in one batched
+// rocSOLVER call, accumulates the T = 0 densities of the E > 0 eigenpairs
+// (weighted by the |k_z| multiplicity and 1/L_z), maps them to the
+// potentials (regulator with V_+ = V_ext + U_in), mixes linearly and updates
+// mu for a fixed particle number (Eq. update-mu).
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <functional>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "ctx.h"
+
+namespace tdslda {
+
+std::vector<double> spectral_d2_circulant(int N, double dz);  // q1dstatic.hip
+
+namespace {
+
+__global__ void k_add_shift(int M, const double* __restrict__ a, const double* __restrict__ b, double c,
+                            double* __restrict__ out) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  if (r < M) out[r] = a[r] + b[r] + c;
+}
+
+// H of every |k_z| class, column-major 2M x 2M (symmetric):
+//   [ K + diag(hf) + kz^2/2        diag(D)               ]
+//   [ diag(D)               -(K + diag(hf) + kz^2/2)     ]
+// K = -1/2 (D2_x (x) 1 + 1 (x) D2_y) from the circulants d2x, d2y.
+__global__ void k_st_build(double* __restrict__ H, int nclass, int nx, int ny, const double* __restrict__ kz2,
+                           const double* __restrict__ hf, const double* __restrict__ dl,
+                           const double* __restrict__ d2x, const double* __restrict__ d2y) {
+  const int M = nx * ny, N2 = 2 * M;
+  const int64_t per = int64_t(N2) * N2;
+  const int64_t idx = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (idx >= per * nclass) return;
+  const int c = int(idx / per);
+  const int rem = int(idx - int64_t(c) * per);
+  const int col = rem / N2, row = rem - col * N2;
+  const int ib = row / M, jb = col / M, i = row - ib * M, j = col - jb * M;
+  double v = 0.0;
+  if (ib == jb) {
+    const int ix = i / ny, iy = i - ix * ny, jx = j / ny, jy = j - jx * ny;
+    double h = 0.0;
+    if (iy == jy) h += -0.5 * d2x[((ix - jx) % nx + nx) % nx];
+    if (ix == jx) h += -0.5 * d2y[((iy - jy) % ny + ny) % ny];
+    if (i == j) h += hf[i] + 0.5 * kz2[c];
+    v = ib == 0 ? h : -h;
+  } else if (i == j) {
+    v = dl[i];
+  }
+  H[idx] = v;
+}
+
+// T = 0 densities: rho = sum_c w_c / L_z sum_{E>0} v^2 / dA,
+// nu = sum_c w_c / L_z sum_{E>0} u v / dA  (real eigenvectors)
+__global__ void k_st_dens(const double* __restrict__ H, const double* __restrict__ Ev, int nclass, int M,
+                          const double* __restrict__ wc, double scale, double* __restrict__ rho,
+                          double* __restrict__ nu) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  if (r >= M) return;
+  const int N2 = 2 * M;
+  double sr = 0.0, sn = 0.0;
+  for (int c = 0; c < nclass; ++c) {
+    const double* A = H + int64_t(c) * N2 * N2;
+    const double* E = Ev + int64_t(c) * N2;
+    double cr = 0.0, cn = 0.0;
+    for (int k = 0; k < N2; ++k) {
+      if (E[k] <= 0.0) continue;
+      const double u = A[int64_t(k) * N2 + r], v = A[int64_t(k) * N2 + M + r];
+      cr += v * v;
+      cn += u * v;
+    }
+    sr += wc[c] * cr;
+    sn += wc[c] * cn;
+  }
+  rho[r] = scale * sr;
+  nu[r] = scale * sn;
+}
+
+// potentials of the SLDA (A = 1) or BdG functional from rho, nu; regulator
+// Lambda_c with V_+ = V_ext + U_in (k_0^2 < 0 continued analytically)
+__global__ void k_st_pot(int M, const double* __restrict__ rho, const double* __restrict__ nu,
+                         const double* __restrict__ vext, const double* __restrict__ Uin, double mu, double ec,
+                         int kind, double B, double C, double inv_g, double* __restrict__ Uo,
+                         double* __restrict__ Do, int* __restrict__ bad) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  if (r >= M) return;
+  const double vp = vext[r] + Uin[r];
+  const double k0sq = 2.0 * (mu - vp), kcsq = 2.0 * (ec + mu - vp);
+  double lam = 0.0;
+  if (kcsq <= 0.0) {
+    bad[0] = 1;
+  } else {
+    const double kc = sqrt(kcsq);
+    double br;
+    if (k0sq > 0.0) {
+      const double k0 = sqrt(k0sq);
+      br = 1.0 - k0 / (2.0 * kc) * log((kc + k0) / (kc - k0));
+    } else {
+      const double ka = sqrt(-k0sq);
+      br = 1.0 + ka / kc * atan(ka / kc);
+    }
+    lam = kc / (2.0 * kPi * kPi) * br;
+  }
+  const double rp = fmax(2.0 * rho[r], 1e-14);
+  const double ig = (kind == 1 ? cbrt(rp) / C : inv_g) - lam;
+  const double d = -nu[r] / ig;
+  double u = 0.0;
+  if (kind == 1) {
+    const double ef = 0.5 * pow(3.0 * kPi * kPi * (2.0 * rho[r]), 2.0 / 3.0);
+    const double c23 = cbrt(rp);
+    u = B * ef - d * d / (3.0 * C * c23 * c23);
+  }
+  Uo[r] = u;
+  Do[r] = d;
+}
+
+// one block: N = L_z dA sum 2 rho, max |U_out - U_in|, max |D_out - D_in|
+__global__ __launch_bounds__(1024) void k_st_reduce(int M, const double* __restrict__ rho,
+                                                    const double* __restrict__ Uo, const double* __restrict__ Ui,
+                                                    const double* __restrict__ Do, const double* __restrict__ Di,
+                                                    double vol_factor, double* __restrict__ out) {
+  __shared__ double sn[1024], su[1024], sd[1024];
+  double n = 0.0, du = 0.0, dd = 0.0;
+  for (int r = threadIdx.x; r < M; r += 1024) {
+    n += 2.0 * rho[r];
+    du = fmax(du, fabs(Uo[r] - Ui[r]));
+    dd = fmax(dd, fabs(Do[r] - Di[r]));
+  }
+  sn[threadIdx.x] = n;
+  su[threadIdx.x] = du;
+  sd[threadIdx.x] = dd;
+  __syncthreads();
+  for (int s = 512; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      sn[threadIdx.x] += sn[threadIdx.x + s];
+      su[threadIdx.x] = fmax(su[threadIdx.x], su[threadIdx.x + s]);
+      sd[threadIdx.x] = fmax(sd[threadIdx.x], sd[threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = sn[0] * vol_factor;
+    out[1] = su[0];
+    out[2] = sd[0];
+  }
+}
+
+}  // namespace
+__global__ void k_st_mix(int M, double m, const double* __restrict__ Uo, const double* __restrict__ Do,
+                         double* __restrict__ U, double* __restrict__ D) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  if (r >= M) return;
+  U[r] = m * Uo[r] + (1.0 - m) * U[r];
+  D[r] = m * Do[r] + (1.0 - m) * D[r];
+}
+namespace {
+
+struct Handle {
+  rocblas_handle h = nullptr;
+  Handle() {
+    if (rocblas_create_handle(&h) != rocblas_status_success) throw Fail{TDSLDA_EDEVICE, "rocblas_create_handle failed"};
+  }
+  ~Handle() {
+    if (h) rocblas_destroy_handle(h);
+  }
+};
+
+}  // namespace
+
+// One solver instance: device buffers for a geometry, reused over iterations.
+struct StaticSolver {
+  const tdslda_static s;
+  const tdslda_functional f;
+  int M = 0, N2 = 0, nclass = 0;
+  std::vector<void*> owned;
+  double *H = nullptr, *Ev = nullptr, *Ew = nullptr, *kz2 = nullptr, *wc = nullptr, *d2x = nullptr, *d2y = nullptr;
+  double *vext = nullptr, *U = nullptr, *D = nullptr, *Uo = nullptr, *Do = nullptr, *hf = nullptr;
+  double *rho = nullptr, *nu = nullptr, *red = nullptr;
+  int* bad = nullptr;
+  rocblas_int* info = nullptr;
+  Handle rb;
+
+  void* alloc(size_t bytes) {
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      throw Fail{TDSLDA_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed (static solve)"};
+    }
+    owned.push_back(p);
+    return p;
+  }
+  StaticSolver(const tdslda_static& s_, const tdslda_functional& f_, const double* vext_h) : s(s_), f(f_) {
+    require(s.nx > 0 && s.ny > 0 && s.nz > 0 && s.nz % 2 == 0 && s.nx % 2 == 0 && s.ny % 2 == 0, TDSLDA_EINVAL,
+            "static lattice sizes must be positive and even");
+    require(s.dx > 0 && s.dy > 0 && s.dz > 0 && s.ec > 0 && s.mix > 0 && s.mix <= 1, TDSLDA_EINVAL,
+            "bad static solver parameters");
+    require(f.functional == TDSLDA_FUNC_SLDA || f.functional == TDSLDA_FUNC_BDG, TDSLDA_EINVAL, "unknown functional");
+    M = s.nx * s.ny;
+    N2 = 2 * M;
+    nclass = s.nz / 2 + 1;
+    H = (double*)alloc(sizeof(double) * size_t(N2) * N2 * nclass);
+    Ev = (double*)alloc(sizeof(double) * size_t(N2) * nclass);
+    Ew = (double*)alloc(sizeof(double) * size_t(N2) * nclass);
+    info = (rocblas_int*)alloc(sizeof(rocblas_int) * nclass);
+    kz2 = (double*)alloc(sizeof(double) * nclass);
+    wc = (double*)alloc(sizeof(double) * nclass);
+    d2x = (double*)alloc(sizeof(double) * s.nx);
+    d2y = (double*)alloc(sizeof(double) * s.ny);
+    for (double** p : {&vext, &U, &D, &Uo, &Do, &hf, &rho, &nu}) *p = (double*)alloc(sizeof(double) * M);
+    red = (double*)alloc(sizeof(double) * 4);
+    bad = (int*)alloc(sizeof(int));
+    std::vector<double> k2(nclass), w(nclass);
+    for (int m = 0; m < nclass; ++m) {
+      const double k = 2.0 * kPi * m / (s.nz * s.dz);
+      k2[m] = k * k;
+      w[m] = (m == 0 || m == s.nz / 2) ? 1.0 : 2.0;
+    }
+    const auto cx = spectral_d2_circulant(s.nx, s.dx), cy = spectral_d2_circulant(s.ny, s.dy);
+    HIPCHK(hipMemcpy(kz2, k2.data(), sizeof(double) * nclass, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(wc, w.data(), sizeof(double) * nclass, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(d2x, cx.data(), sizeof(double) * s.nx, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(d2y, cy.data(), sizeof(double) * s.ny, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(vext, vext_h, sizeof(double) * M, hipMemcpyHostToDevice));
+  }
+  ~StaticSolver() {
+    (void)hipDeviceSynchronize();
+    for (void* p : owned) (void)hipFree(p);
+  }
+
+  // K[p] for the potentials in U, D at mu: Uo, Do, rho, nu and
+  // red = {N, max|dU|, max|dD|}
+  void map(double mu) {
+    const unsigned gb = cdiv(M, 256);
+    hipLaunchKernelGGL(k_add_shift, dim3(gb), dim3(256), 0, 0, M, vext, U, -mu, hf);
+    HIPCHK(hipGetLastError());
+    const int64_t per = int64_t(N2) * N2;
+    hipLaunchKernelGGL(k_st_build, dim3(cdiv(per * nclass, 256)), dim3(256), 0, 0, H, nclass, s.nx, s.ny, kz2, hf,
+                       D, d2x, d2y);
+    HIPCHK(hipGetLastError());
+    const rocblas_status rs = rocsolver_dsyevd_strided_batched(rb.h, rocblas_evect_original, rocblas_fill_lower, N2,
+                                                               H, N2, per, Ev, N2, Ew, N2, info, nclass);
+    require(rs == rocblas_status_success, TDSLDA_EDEVICE, "rocsolver_dsyevd_strided_batched failed");
+    const double scale = 1.0 / (s.nz * s.dz * s.dx * s.dy);
+    hipLaunchKernelGGL(k_st_dens, dim3(gb), dim3(256), 0, 0, H, Ev, nclass, M, wc, scale, rho, nu);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemset(bad, 0, sizeof(int)));
+    hipLaunchKernelGGL(k_st_pot, dim3(gb), dim3(256), 0, 0, M, rho, nu, vext, U, mu, s.ec, f.functional, f.B, f.C,
+                       f.inv_g_bdg, Uo, Do, bad);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_st_reduce, dim3(1), dim3(1024), 0, 0, M, rho, Uo, U, Do, D, s.nz * s.dz * s.dx * s.dy,
+                       red);
+    HIPCHK(hipGetLastError());
+    std::vector<rocblas_int> ih(nclass);
+    int b = 0;
+    HIPCHK(hipMemcpy(ih.data(), info, sizeof(rocblas_int) * nclass, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(&b, bad, sizeof(int), hipMemcpyDeviceToHost));
+    for (int c = 0; c < nclass; ++c) require(ih[c] == 0, TDSLDA_EDEVICE, "eigensolver did not converge");
+    require(b == 0, TDSLDA_EUNSTABLE, "regulator undefined (E_c + mu - V_+ <= 0 somewhere)");
+  }
+};
+
+}  // namespace tdslda
+
+// ============================================================================
+// C ABI
+using tdslda::Fail;
+using tdslda::StaticSolver;
+
+extern "C" {
+
+static tdslda_status static_guard(const char* who, const std::function<void()>& f) {
+  try {
+    f();
+    return TDSLDA_OK;
+  } catch (const Fail& e) {
+    std::fprintf(stderr, "%s: %s\n", who, e.msg.c_str());
+    return e.st;
+  } catch (const std::bad_alloc&) {
+    return TDSLDA_ENOMEM;
+  } catch (...) {
+    return TDSLDA_EDEVICE;
+  }
+}
+
+tdslda_status tdslda_static_map(const tdslda_static* s, const tdslda_functional* fun, const double* vext,
+                                const double* U, const double* delta, double mu, double* U_out,
+                                double* delta_out, double* rho, double* nu, double* N) {
+  if (!s || !fun || !vext || !U || !delta) return TDSLDA_EINVAL;
+  return static_guard("tdslda_static_map", [&] {
+    StaticSolver S(*s, *fun, vext);
+    const size_t b = sizeof(double) * S.M;
+    HIPCHK(hipMemcpy(S.U, U, b, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(S.D, delta, b, hipMemcpyHostToDevice));
+    S.map(mu);
+    double red[3];
+    HIPCHK(hipMemcpy(red, S.red, sizeof(red), hipMemcpyDeviceToHost));
+    if (U_out) HIPCHK(hipMemcpy(U_out, S.Uo, b, hipMemcpyDeviceToHost));
+    if (delta_out) HIPCHK(hipMemcpy(delta_out, S.Do, b, hipMemcpyDeviceToHost));
+    if (rho) HIPCHK(hipMemcpy(rho, S.rho, b, hipMemcpyDeviceToHost));
+    if (nu) HIPCHK(hipMemcpy(nu, S.nu, b, hipMemcpyDeviceToHost));
+    if (N) *N = red[0];
+  });
+}
+
+tdslda_status tdslda_static_solve(const tdslda_static* s, const tdslda_functional* fun, const double* vext,
+                                  double* U, double* delta, double* mu, int* iters, int* converged,
+                                  double* hist) {
+  if (!s || !fun || !vext || !U || !delta || !mu) return TDSLDA_EINVAL;
+  return static_guard("tdslda_static_solve", [&] {
+    require(s->maxit > 0 && s->tol > 0 && s->eF_ref > 0, TDSLDA_EINVAL, "bad iteration parameters");
+    const bool fixed_n = s->a_mu != 0.0;
+    require(!fixed_n || s->N_req > 0, TDSLDA_EINVAL, "fixed-N mode needs N_req > 0");
+    StaticSolver S(*s, *fun, vext);
+    const size_t b = sizeof(double) * S.M;
+    HIPCHK(hipMemcpy(S.U, U, b, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(S.D, delta, b, hipMemcpyHostToDevice));
+    double m = *mu;
+    int done = 0, it = 0;
+    for (it = 1; it <= s->maxit; ++it) {
+      S.map(m);
+      double red[3];
+      HIPCHK(hipMemcpy(red, S.red, sizeof(red), hipMemcpyDeviceToHost));
+      const double r = std::max(red[1], red[2]) / s->eF_ref;
+      const double rn = fixed_n ? std::fabs(red[0] - s->N_req) / s->N_req : 0.0;
+      if (hist) {
+        hist[4 * (it - 1) + 0] = r;
+        hist[4 * (it - 1) + 1] = rn;
+        hist[4 * (it - 1) + 2] = m;
+        hist[4 * (it - 1) + 3] = red[0];
+      }
+      require(std::isfinite(r) && std::isfinite(red[0]), TDSLDA_EUNSTABLE, "non-finite residual");
+      if (r < s->tol && rn < s->tol) {
+        HIPCHK(hipMemcpy(U, S.Uo, b, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(delta, S.Do, b, hipMemcpyDeviceToHost));
+        done = 1;
+        break;
+      }
+      hipLaunchKernelGGL(tdslda::k_st_mix, dim3(tdslda::cdiv(S.M, 256)), dim3(256), 0, 0, S.M, s->mix, S.Uo,
+                         S.Do, S.U, S.D);
+      HIPCHK(hipGetLastError());
+      if (fixed_n) m += s->a_mu / s->N_req * (s->N_req - red[0]);
+    }
+    if (!done) {
+      HIPCHK(hipMemcpy(U, S.U, b, hipMemcpyDeviceToHost));
+      HIPCHK(hipMemcpy(delta, S.D, b, hipMemcpyDeviceToHost));
+      it = s->maxit;
+    }
+    *mu = m;
+    if (iters) *iters = it;
+    if (converged) *converged = done;
+  });
+}
+
+}  // extern "C"

@@ -38,6 +38,12 @@ class Run(C.Structure):
                 ("tol_E", C.c_double), ("hip_stream", C.c_void_p)]
 
 
+class Static(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("dx", C.c_double), ("dy", C.c_double),
+                ("dz", C.c_double), ("ec", C.c_double), ("mix", C.c_double), ("a_mu", C.c_double),
+                ("N_req", C.c_double), ("tol", C.c_double), ("eF_ref", C.c_double), ("maxit", C.c_int)]
+
+
 class TdsldaError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"libtdslda status {status}: {msg}")
@@ -75,6 +81,20 @@ _SIGS = {
     "tdslda_autotune": [C.c_void_p, C.POINTER(C.c_int), C.c_void_p, C.c_void_p],
     "tdslda_q1d_count": [C.POINTER(Lattice), C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
                          C.c_void_p, C.POINTER(C.c_int64)],
+    "tdslda_static_map": [C.POINTER(Static), C.POINTER(Functional), C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
+                          C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double)],
+    "tdslda_static_solve": [C.POINTER(Static), C.POINTER(Functional), C.c_void_p, C.c_void_p, C.c_void_p,
+                            C.POINTER(C.c_double), C.POINTER(C.c_int), C.POINTER(C.c_int), C.c_void_p],
+    "tdslda_nn_nparams": [C.c_int],
+    "tdslda_nn_create": [C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p, C.POINTER(C.c_void_p)],
+    "tdslda_nn_destroy": [C.c_void_p],
+    "tdslda_nn_params": [C.c_void_p, C.c_void_p, C.POINTER(C.c_int64)],
+    "tdslda_nn_set_params": [C.c_void_p, C.c_void_p],
+    "tdslda_nn_forward": [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p],
+    "tdslda_nn_loss_grad": [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_float, C.c_void_p,
+                            C.c_void_p],
+    "tdslda_nn_train_step": [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_float, C.c_float,
+                             C.c_void_p],
     "tdslda_q1d_load_static": [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
                                C.POINTER(C.c_int64)],
 }
@@ -94,7 +114,8 @@ def load_library(path=None):
     for name, args in _SIGS.items():
         f = getattr(lib, name)
         f.argtypes = args
-        f.restype = C.c_char_p if name in ("tdslda_last_error", "tdslda_kernel_name") else C.c_int
+        f.restype = (C.c_char_p if name in ("tdslda_last_error", "tdslda_kernel_name")
+                     else C.c_int64 if name == "tdslda_nn_nparams" else C.c_int)
     _lib = lib
     return lib
 
@@ -315,6 +336,112 @@ def q1d_count(lattice, kperp2, hfield, delta, ecut):
     if st != OK:
         raise TdsldaError(st, "tdslda_q1d_count failed")
     return counts, tot.value
+
+
+def static_params(nx, ny, nz, d=(1.0, 1.0, 1.0), ec=0.5 * np.pi ** 2, mix=0.5, a_mu=0.0, N_req=0.0, tol=1e-8,
+                  eF_ref=0.5, maxit=500):
+    return Static(nx, ny, nz, d[0], d[1], d[2], ec, mix, a_mu, N_req, tol, eF_ref, maxit)
+
+
+def static_map(params, fun, vext, U, delta, mu):
+    """One application of the static map K on the device: (U_out, delta_out,
+    rho, nu, N)."""
+    lib = load_library()
+    shp = np.shape(vext)
+    v, u, d = _f64(vext).ravel(), _f64(U).ravel(), _f64(delta).ravel()
+    Uo, Do, rho, nu = (np.empty(v.size) for _ in range(4))
+    N = C.c_double()
+    st = lib.tdslda_static_map(C.byref(params), C.byref(fun), _p(v), _p(u), _p(d), float(mu), _p(Uo), _p(Do),
+                               _p(rho), _p(nu), C.byref(N))
+    if st != OK:
+        raise TdsldaError(st, "tdslda_static_map failed")
+    return Uo.reshape(shp), Do.reshape(shp), rho.reshape(shp), nu.reshape(shp), N.value
+
+
+def static_solve(params, fun, vext, U, delta, mu):
+    """Self-consistent iteration on the device from (U, delta, mu).  Returns
+    (U, delta, mu, iterations, converged, history[iterations][4])."""
+    lib = load_library()
+    shp = np.shape(vext)
+    v = _f64(vext).ravel()
+    u, d = _f64(U).ravel().copy(), _f64(delta).ravel().copy()
+    m = C.c_double(float(mu))
+    it, ok = C.c_int(), C.c_int()
+    hist = np.zeros((params.maxit, 4))
+    st = lib.tdslda_static_solve(C.byref(params), C.byref(fun), _p(v), _p(u), _p(d), C.byref(m), C.byref(it),
+                                 C.byref(ok), _p(hist))
+    if st != OK:
+        raise TdsldaError(st, "tdslda_static_solve failed")
+    return u.reshape(shp), d.reshape(shp), m.value, it.value, bool(ok.value), hist[:it.value]
+
+
+class Network:
+    """The warm-start network (tdslda_nn_*): float32 host arrays in, out."""
+
+    def __init__(self, H, W, channels, batch_max, theta0):
+        self.lib = load_library()
+        self.H, self.W, self.C, self.batch_max = H, W, channels, batch_max
+        self.P = int(self.lib.tdslda_nn_nparams(channels))
+        th = np.ascontiguousarray(theta0, dtype=np.float32).ravel()
+        if th.size != self.P:
+            raise ValueError(f"theta0 has {th.size} values, the network {self.P}")
+        hp = C.c_void_p()
+        st = self.lib.tdslda_nn_create(H, W, channels, batch_max, th.ctypes.data_as(C.c_void_p), C.byref(hp))
+        if st != OK:
+            raise TdsldaError(st, "tdslda_nn_create failed")
+        self.h = hp
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.tdslda_nn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, st, what):
+        if st != OK:
+            raise TdsldaError(st, what)
+
+    def params(self):
+        out = np.empty(self.P, dtype=np.float32)
+        self._chk(self.lib.tdslda_nn_params(self.h, out.ctypes.data_as(C.c_void_p), None), "tdslda_nn_params")
+        return out
+
+    def set_params(self, theta):
+        th = np.ascontiguousarray(theta, dtype=np.float32).ravel()
+        self._chk(self.lib.tdslda_nn_set_params(self.h, th.ctypes.data_as(C.c_void_p)), "tdslda_nn_set_params")
+
+    def forward(self, x):
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        B = x.shape[0]
+        maps = np.empty((B, 2, self.H, self.W), dtype=np.float32)
+        mu = np.empty(B, dtype=np.float32)
+        self._chk(self.lib.tdslda_nn_forward(self.h, B, x.ctypes.data_as(C.c_void_p), maps.ctypes.data_as(C.c_void_p),
+                                             mu.ctypes.data_as(C.c_void_p)), "tdslda_nn_forward")
+        return maps, mu
+
+    def loss_grad(self, x, Y, ymu, lam_mu=1.0):
+        x, Y, ymu = (np.ascontiguousarray(a, dtype=np.float32) for a in (x, Y, ymu))
+        loss = np.zeros(1, dtype=np.float32)
+        grad = np.empty(self.P, dtype=np.float32)
+        self._chk(self.lib.tdslda_nn_loss_grad(self.h, x.shape[0], x.ctypes.data_as(C.c_void_p),
+                                               Y.ctypes.data_as(C.c_void_p), ymu.ctypes.data_as(C.c_void_p),
+                                               float(lam_mu), loss.ctypes.data_as(C.c_void_p),
+                                               grad.ctypes.data_as(C.c_void_p)), "tdslda_nn_loss_grad")
+        return float(loss[0]), grad
+
+    def train_step(self, x, Y, ymu, lam_mu, lr):
+        x, Y, ymu = (np.ascontiguousarray(a, dtype=np.float32) for a in (x, Y, ymu))
+        loss = np.zeros(1, dtype=np.float32)
+        self._chk(self.lib.tdslda_nn_train_step(self.h, x.shape[0], x.ctypes.data_as(C.c_void_p),
+                                                Y.ctypes.data_as(C.c_void_p), ymu.ctypes.data_as(C.c_void_p),
+                                                float(lam_mu), float(lr), loss.ctypes.data_as(C.c_void_p)),
+                  "tdslda_nn_train_step")
+        return float(loss[0])
 
 
 def lattice_3d(n, d=1.0):

@@ -1,0 +1,174 @@
+"""Learned warm start of the static solve (host-side orchestration only: the
+solves run in libtdslda's device solver, the network in its kernels).
+
+Workload: a quasi-2D trapped gas on an nx x ny x-y lattice with nz plane
+waves along z, V_ext = 1/2 omega^2 (x^2 + y^2) + 1-4 Gaussian obstacles
+(amplitudes U(0.5, 3) eF_ref, widths U(2, 8) sites of a 64-site box scaled
+to the lattice, uniform centres), fixed particle number N_req = N of the
+obstacle-free trap at mu = 1.  The plain start is the uniform state at the
+reference Fermi momentum k_F = 1 (eF_ref = 1/2); the warm start is the
+network's prediction of (U, Delta, mu) from V_ext.  Both are iterated by the
+same linear mixing to r < tol; when the warm start does not converge the
+plain start is used (and counted).
+"""
+import time
+
+import numpy as np
+
+from . import tdslda as T
+
+EF_REF = 0.5
+XI_UFG = 0.4     # mu / eF of the uniform unitary gas (plain start)
+DELTA_UFG = 0.5  # Delta / eF of the uniform unitary gas (plain start)
+
+Q2D = dict(nx=16, ny=16, nz=8, omega=0.24, mix=0.5, a_mu=0.5, tol=1e-8, maxit=400, channels=32)
+
+
+def vext(cfg, seed):
+    import synth
+    nx, ny = cfg["nx"], cfg["ny"]
+    x = np.arange(nx) - nx // 2
+    y = np.arange(ny) - ny // 2
+    X, Y = np.meshgrid(x, y, indexing="ij")
+    v = 0.5 * cfg["omega"] ** 2 * (X ** 2 + Y ** 2)
+    amp, wid, cen = synth.obstacles(seed, float(nx))
+    s = nx / 64.0
+    for a, w, (cx, cy) in zip(amp, wid, cen):
+        v = v + EF_REF * a * np.exp(-((X - cx) ** 2 + (Y - cy) ** 2) / (2.0 * (w * s) ** 2))
+    return v
+
+
+def plain_start(cfg, fun):
+    U = np.full((cfg["nx"], cfg["ny"]), fun.B * EF_REF)
+    D = np.full((cfg["nx"], cfg["ny"]), DELTA_UFG * EF_REF)
+    return U, D, XI_UFG * EF_REF
+
+
+def params(cfg, N_req=0.0, a_mu=None):
+    return T.static_params(cfg["nx"], cfg["ny"], cfg["nz"], ec=0.5 * np.pi ** 2, mix=cfg["mix"],
+                           a_mu=cfg["a_mu"] if a_mu is None else a_mu, N_req=N_req, tol=cfg["tol"],
+                           eF_ref=EF_REF, maxit=cfg["maxit"])
+
+
+def required_n(cfg, fun):
+    """N of the obstacle-free trap at mu = 1 (fixed-mu solve)."""
+    nx, ny = cfg["nx"], cfg["ny"]
+    x = np.arange(nx) - nx // 2
+    y = np.arange(ny) - ny // 2
+    X, Y = np.meshgrid(x, y, indexing="ij")
+    v = 0.5 * cfg["omega"] ** 2 * (X ** 2 + Y ** 2)
+    U0, D0, _ = plain_start(cfg, fun)
+    U, D, mu, it, ok, hist = T.static_solve(params(cfg, a_mu=0.0), fun, v, U0, D0, 1.0)
+    if not ok:
+        raise RuntimeError("reference trap did not converge")
+    _, _, _, _, N = T.static_map(params(cfg), fun, v, U, D, mu)
+    return N
+
+
+def solve(cfg, fun, N_req, v, start):
+    U0, D0, mu0 = start
+    t0 = time.perf_counter()
+    U, D, mu, it, ok, hist = T.static_solve(params(cfg, N_req), fun, v, U0, D0, mu0)
+    return dict(U=U, D=D, mu=mu, iters=it, converged=ok, seconds=time.perf_counter() - t0)
+
+
+class WarmStart:
+    """Normalisation + network; fit() trains on method-generated solves."""
+
+    def __init__(self, cfg, seed=0, batch_max=64):
+        self.cfg = cfg
+        C = cfg["channels"]
+        g = np.random.Generator(np.random.PCG64(seed))
+        parts = []
+        for name, s in _shapes(C):
+            if name.startswith("b"):
+                parts.append(np.zeros(s))
+            else:
+                fan_in = int(np.prod(s[1:])) if len(s) > 1 else s[0]
+                parts.append(g.standard_normal(s) * np.sqrt(2.0 / fan_in))
+        theta0 = np.concatenate([p.ravel() for p in parts]).astype(np.float32)
+        self.net = T.Network(cfg["nx"], cfg["ny"], C, batch_max, theta0)
+        self.batch_max = batch_max
+        self.xs = 1.0
+
+    def _x(self, vs):
+        return (np.asarray(vs)[:, None] / self.xs).astype(np.float32)
+
+    def fit(self, V, U, D, mu, epochs=300, lr=2e-3, lam_mu=1.0, seed=1):
+        V = np.asarray(V)
+        self.xs = float(np.abs(V).max())
+        X = self._x(V)
+        Y = np.stack([np.asarray(U) / EF_REF, np.asarray(D) / EF_REF], axis=1).astype(np.float32)
+        ym = (np.asarray(mu) / EF_REF).astype(np.float32)
+        g = np.random.Generator(np.random.PCG64(seed))
+        n = X.shape[0]
+        B = min(self.batch_max, n)
+        losses = []
+        steps = 0
+        for ep in range(epochs):
+            perm = g.permutation(n)
+            rate = lr * (0.5 * (1 + np.cos(np.pi * ep / epochs)))
+            for b0 in range(0, n - B + 1, B):
+                idx = perm[b0:b0 + B]
+                losses.append(self.net.train_step(X[idx], Y[idx], ym[idx], lam_mu, rate))
+                steps += 1
+        return dict(steps=steps, final_loss=float(np.mean(losses[-10:])), first_loss=float(losses[0]))
+
+    def predict(self, V):
+        maps, mu = self.net.forward(self._x(V))
+        return maps[:, 0].astype(float) * EF_REF, maps[:, 1].astype(float) * EF_REF, mu.astype(float) * EF_REF
+
+    def close(self):
+        self.net.close()
+
+
+def _shapes(C):
+    return [("W1", (C, 1, 3, 3)), ("b1", (C,)), ("W2", (C, C, 3, 3)), ("b2", (C,)),
+            ("W3", (C, C, 3, 3)), ("b3", (C,)), ("Wm", (2, C)), ("bm", (2,)), ("wmu", (C,)), ("bmu", (1,))]
+
+
+def experiment(cfg, train_seeds, test_seeds, epochs=300, log=None):
+    """Train on solves of train_seeds, then compare iterations to r < tol
+    from the plain and the warm start on test_seeds."""
+    fun = T.functional_slda(1.0, 0.5 * np.pi ** 2)
+    N_req = required_n(cfg, fun)
+    t0 = time.perf_counter()
+    V, U, D, MU, it_train = [], [], [], [], []
+    for s in train_seeds:
+        v = vext(cfg, s)
+        r = solve(cfg, fun, N_req, v, plain_start(cfg, fun))
+        if not r["converged"]:
+            continue
+        V.append(v)
+        U.append(r["U"])
+        D.append(r["D"])
+        MU.append(r["mu"])
+        it_train.append(r["iters"])
+    t_data = time.perf_counter() - t0
+    if log:
+        log(f"training set: {len(V)} solves in {t_data:.1f} s, mean {np.mean(it_train):.1f} iterations")
+    ws = WarmStart(cfg)
+    t0 = time.perf_counter()
+    fit = ws.fit(V, U, D, MU, epochs=epochs)
+    t_fit = time.perf_counter() - t0
+    if log:
+        log(f"fit: {fit['steps']} Adam steps in {t_fit:.1f} s, loss {fit['first_loss']:.3g} -> {fit['final_loss']:.3g}")
+    plain_it, warm_it, fallbacks, warm_s, plain_s = [], [], 0, 0.0, 0.0
+    for s in test_seeds:
+        v = vext(cfg, s)
+        p = solve(cfg, fun, N_req, v, plain_start(cfg, fun))
+        Uw, Dw, muw = ws.predict(v[None])
+        w = solve(cfg, fun, N_req, v, (Uw[0], Dw[0], float(muw[0])))
+        plain_s += p["seconds"]
+        warm_s += w["seconds"]
+        if not w["converged"]:
+            fallbacks += 1
+            w = p
+        plain_it.append(p["iters"])
+        warm_it.append(w["iters"] if w is not p else p["iters"] + cfg["maxit"])
+    ws.close()
+    return dict(lattice=[cfg["nx"], cfg["ny"], cfg["nz"]], n_train=len(V), n_test=len(test_seeds),
+                train_data_seconds=t_data, fit_seconds=t_fit, fit=fit,
+                plain_iters_mean=float(np.mean(plain_it)), warm_iters_mean=float(np.mean(warm_it)),
+                plain_iters=plain_it, warm_iters=warm_it, fallbacks=fallbacks,
+                seconds_per_iteration=plain_s / max(1, sum(plain_it)), N_req=N_req)

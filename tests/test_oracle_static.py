@@ -1,0 +1,75 @@
+"""Pins of the oracle's static quasi-2D solver (Alg. MapK + linear mixing +
+Eq. update-mu): the dense BdG matrix against the uniform dispersion, the
+uniform fixed point against the scalar lattice k-sum, and the fixed-N
+solve with an obstacle."""
+import numpy as np
+import pytest
+
+from oracle import lattice as L, functional as F, uniform as UN, static as ST
+import synth
+
+FUN = F.Functional(F.SLDA)
+EC = 0.5 * np.pi ** 2
+
+
+@pytest.mark.parametrize("kz_index", [0, 1, 2])
+def test_q2d_matrix_uniform_dispersion(kz_index):
+    """P2 (quasi-2D): with constant hfield c and Delta d the eigenvalues of
+    the dense matrix are +-sqrt((k_perp^2/2 + k_z^2/2 + c)^2 + d^2) over the
+    x-y lattice momenta (Nyquist kept)."""
+    g = ST.GeometryQ2D(6, 4, 4, 1.0, 1.3, 0.9)
+    c, d = -0.7, 0.45
+    kz = g.kz[kz_index]
+    E = np.linalg.eigvalsh(ST.build_h(g, np.full(g.shape, c), np.full(g.shape, d), kz))
+    kx, ky = L.kgrid(6, 1.0), L.kgrid(4, 1.3)
+    xi = 0.5 * (kx[:, None] ** 2 + ky[None, :] ** 2) + 0.5 * kz * kz + c
+    Ek = np.sqrt(xi ** 2 + d * d).ravel()
+    ref = np.sort(np.concatenate([Ek, -Ek]))
+    assert np.abs(E - ref).max() < 1e-12
+
+
+def test_q2d_multiplicities_cover_the_kz_grid():
+    g = ST.GeometryQ2D(4, 4, 8)
+    kz_all = np.abs(L.kgrid(8, 1.0))
+    for kz, w in zip(g.kz, g.mult):
+        assert np.sum(np.isclose(kz_all, kz)) == w
+
+
+def test_uniform_fixed_point_matches_lattice_k_sum():
+    """P12: without an external potential, at fixed mu, the static solve
+    from a uniform guess converges to a uniform state, and that state is the
+    solution of the scalar k-sum over the N_x x N_y x N_z lattice with the
+    same regulator (oracle.uniform.lattice_uniform) to 1e-9."""
+    g = ST.GeometryQ2D(6, 6, 4)
+    mu = 1.0
+    vext = np.zeros(g.shape)
+    U, D, mu_out, it, ok = ST.solve(g, FUN, vext, np.full(g.shape, -0.2), np.full(g.shape, 0.3), mu, EC,
+                                    mix=0.5, tol=1e-11, maxit=400)
+    assert ok
+    assert np.ptp(U) < 1e-10 and np.ptp(np.real(D)) < 1e-10
+    lam = float(F.lambda_c(np.array(U.mean()), mu, EC))
+    lat = L.Lattice(6, 6, 4)
+    Uk, Dk = UN.lattice_uniform(lat, FUN, mu, lam, delta_guess=float(np.real(D.mean())), U_guess=float(U.mean()))
+    assert abs(Uk - U.mean()) < 1e-9
+    assert abs(Dk - np.real(D.mean())) < 1e-9
+
+
+def test_fixed_n_solve_with_obstacle():
+    """Fixed-N mode with a trap and one Gaussian obstacle: the iteration
+    converges to r < 1e-8, N equals N_req, and the converged potentials are
+    a fixed point of MapK (one more application moves them by < 1e-7)."""
+    g = ST.GeometryQ2D(8, 8, 4)
+    X, Y = g.coords()
+    amp, wid, cen = synth.obstacles(5, 8.0)
+    vext = 0.5 * 0.4 ** 2 * (X ** 2 + Y ** 2) + amp[0] * 0.5 * np.exp(
+        -((X - cen[0, 0] / 4) ** 2 + (Y - cen[0, 1] / 4) ** 2) / (2 * (wid[0] / 4) ** 2))
+    # N_req from the same trap at mu = 1 without the obstacle, a few iterations
+    U0, D0 = np.full(g.shape, -0.2), np.full(g.shape, 0.25)
+    _, _, _, _, N_req = ST.map_k(g, FUN, 0.5 * 0.4 ** 2 * (X ** 2 + Y ** 2), U0, D0, 1.0, EC)
+    hist = []
+    U, D, mu, it, ok = ST.solve(g, FUN, vext, U0, D0, 0.8, EC, mix=0.5, a_mu=0.5, N_req=N_req, tol=1e-8,
+                                maxit=600, history=hist)
+    assert ok, hist[-1]
+    Uo, Do, rho, nu, N = ST.map_k(g, FUN, vext, U, D, mu, EC)
+    assert abs(N - N_req) / N_req < 1e-7
+    assert np.abs(Uo - U).max() < 1e-7 and np.abs(Do - D).max() < 1e-7
