@@ -203,6 +203,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--no-q1d", action="store_true")
+    ap.add_argument("--no-warmstart", action="store_true")
+    ap.add_argument("--warmstart-size", choices=["small", "medium"], default="small",
+                    help="small: 8x8x4 lattice, 48 training / 8 held-out solves (seconds); medium: 16x16x8, "
+                         "200 / 40 (about ten minutes)")
     ap.add_argument("--q1d-steps", type=int, default=200,
                     help="steps of the batched quasi-1D run (one graph launch)")
     ap.add_argument("--copy-calib", action="store_true",
@@ -259,6 +263,17 @@ def main():
         q1d = run_q1d(args.q1d_steps, max(1, args.warmup))
         print(f"# batched q1d: {q1d['value']:.4g} state-steps/s over {q1d['steps']} steps "
               f"({q1d['nst']} states), graph record {q1d['graph_record_ms']:.0f} ms", file=sys.stderr, flush=True)
+    warm = None
+    if not args.no_warmstart:
+        from paper_2602_08982_amd import warmstart as WS
+        if args.warmstart_size == "small":
+            wcfg, ntr, nte, ep = dict(WS.Q2D, nx=8, ny=8, nz=4, omega=0.48, channels=16), 48, 8, 200
+        else:
+            wcfg, ntr, nte, ep = dict(WS.Q2D), 200, 40, 300
+        warm = WS.experiment(wcfg, range(0, ntr), range(10000, 10000 + nte), epochs=ep,
+                             log=lambda m: print("# warm start: " + m, file=sys.stderr, flush=True))
+        print(f"# warm start: {warm['warm_iters_mean']:.1f} vs plain {warm['plain_iters_mean']:.1f} iterations "
+              f"to r < 1e-8 ({warm['n_test']} held-out seeds)", file=sys.stderr, flush=True)
     cpu = None if args.no_cpu else cpu_baseline()
 
     line = {
@@ -298,6 +313,16 @@ def main():
             "setup_seconds": q1d["setup_seconds"], "tuned_workgroups": q1d["tuned"],
             "problems": q1d["problems"], "kernels": q1d["kernels"], "check": q1d["check"],
             "roofline": roofline(dict(q1d, steps=q1d["profile_steps"]), copy_bps) if q1d["kernels"] else None,
+        }
+    if warm is not None:
+        line["learned_warm_start"] = {
+            "workload": f"static quasi-2D solve, {warm['lattice'][0]}x{warm['lattice'][1]} x-y lattice, "
+                        f"{warm['lattice'][2]} k_z modes, trap + 1-4 obstacles, fixed N, linear mixing 0.5",
+            "metric": "mixing iterations to r < 1e-8, mean over held-out seeds",
+            "warm": warm["warm_iters_mean"], "plain": warm["plain_iters_mean"], "fallbacks": warm["fallbacks"],
+            "n_train": warm["n_train"], "n_test": warm["n_test"],
+            "seconds_per_iteration": warm["seconds_per_iteration"],
+            "train_data_seconds": warm["train_data_seconds"], "fit_seconds": warm["fit_seconds"],
         }
     print(json.dumps(line))
 

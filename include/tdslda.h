@@ -200,7 +200,7 @@ tdslda_status tdslda_q1d_count(const tdslda_lattice* lat, int nprob, const doubl
 tdslda_status tdslda_q1d_load_static(tdslda_ctx* ctx, int nprob, const double* kperp2, const double* hfield,
                                      const double* delta, double ecut, int64_t* nloaded);
 
-/* Static self-consistent solve, quasi-2D geometry (Sec. 3.4, Alg. MapK;
+/* Static self-consistent solve, quasi-2D geometry (Sec. 3.2, Alg. MapK;
  * Sec. 3.1 quasi-2D item): an nx x ny periodic x-y lattice (spacings dx, dy)
  * and nz plane-wave momenta along z (spacing dz, L_z = nz dz); the
  * nz/2 + 1 distinct |k_z| are diagonalised once per iteration (real BdG
@@ -239,7 +239,7 @@ tdslda_status tdslda_static_solve(const tdslda_static* s, const tdslda_functiona
                                   double* hist);
 
 /* Warm-start network of the static workflow (learned initial guess for
- * the fixed-point iteration of Alg. MapK; Sec. 4.6 on initial guesses).
+ * the fixed-point iteration of Alg. MapK; Sec. 5.2 on initial guesses).
  * A small convolutional network maps the normalised external potential of
  * an H x W x-y lattice (host float [B][H][W]) to normalised (U, Delta) maps
  * ([B][2][H][W]) and a chemical potential ([B]):

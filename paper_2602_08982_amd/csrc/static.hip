@@ -1,5 +1,5 @@
 // Static self-consistent solve of the quasi-2D problem on the device
-// (Sec. 3.4, Alg. MapK; Sec. 3.1 quasi-2D item): an N_x x N_y lattice in the
+// (Sec. 3.2, Alg. MapK; Sec. 3.1 quasi-2D item): an N_x x N_y lattice in the
 // x-y plane with plane waves along z.  Every iteration builds the real BdG
 // matrices of the N_z/2 + 1 distinct |k_z| (Eq. HpsiEpsi with the exact
 // spectral D2 of Eq. D2 in x and y), diagonalises them in one batched
