@@ -232,17 +232,17 @@ __global__ __launch_bounds__((SlabCfg<NX, NY, NZ>::TB)) void k_dens(
 //   grid = (ceil(M / (TB DS_P)), ceil(nstates / DG)), block = TB
 //   dens_part layout [group][3][M]
 constexpr int DS_TB = 256, DS_P = 2;
-template <typename R, int DG>
+template <typename R, int DG, int PS = DS_P>
 __global__ __launch_bounds__(DS_TB) void k_dens_sum(
     const cpx<R>* __restrict__ X, int64_t nstates, int64_t M, const double* __restrict__ wu,
     const double* __restrict__ wv, const double* __restrict__ scale, double* __restrict__ dens_part) {
   const int tid = threadIdx.x;
-  const int64_t site0 = int64_t(blockIdx.x) * (DS_TB * DS_P) + tid;
+  const int64_t site0 = int64_t(blockIdx.x) * (DS_TB * PS) + tid;
   const int64_t nbeg = int64_t(blockIdx.y) * DG;
   const int nloc = int(nstates - nbeg < DG ? nstates - nbeg : DG);
-  double ar[DS_P], anr[DS_P], ani[DS_P];
+  double ar[PS], anr[PS], ani[PS];
 #pragma unroll
-  for (int i = 0; i < DS_P; ++i) ar[i] = anr[i] = ani[i] = 0.0;
+  for (int i = 0; i < PS; ++i) ar[i] = anr[i] = ani[i] = 0.0;
   const cpx<R>* xb = X + nbeg * 2 * M;
 #pragma unroll 4
   for (int ls = 0; ls < nloc; ++ls) {
@@ -250,7 +250,7 @@ __global__ __launch_bounds__(DS_TB) void k_dens_sum(
     const double s2 = s * s, cu = fu * s2, cv = fv * s2, cw = (fv - fu) * s2;
     const cpx<R>* xs = xb + int64_t(ls) * 2 * M;
 #pragma unroll
-    for (int i = 0; i < DS_P; ++i) {
+    for (int i = 0; i < PS; ++i) {
       const int64_t r = site0 + i * DS_TB;
       if (r < M) {
         const cpx<R> u = xs[r], v = xs[M + r];
@@ -263,7 +263,7 @@ __global__ __launch_bounds__(DS_TB) void k_dens_sum(
   }
   double* out = dens_part + int64_t(blockIdx.y) * 3 * M;
 #pragma unroll
-  for (int i = 0; i < DS_P; ++i) {
+  for (int i = 0; i < PS; ++i) {
     const int64_t r = site0 + i * DS_TB;
     if (r < M) {
       out[r] = ar[i];
@@ -461,8 +461,10 @@ __global__ __launch_bounds__((SlabCfg<NX, NY, NZ>::TB)) void k_lap2(Lap2Args<R> 
     const int p = tid + i * TB;
     if (p < SS) {
       const int o = int(site0 + i * TB) * ES;
-      lds[CFG::lds_index(0, p)] = s * bload<R>(rX, vt, o);
-      lds[CFG::lds_index(1, p)] = s * bload<R>(rX, vt, o + M * ES);
+      const cpx<R> xu = s * bload<R>(rX, vt, o), xv = s * bload<R>(rX, vt, o + M * ES);
+      lds[CFG::lds_index(0, p)] = xu;
+      lds[CFG::lds_index(1, p)] = xv;
+
     }
   }
   __syncthreads();
@@ -522,7 +524,8 @@ __global__ __launch_bounds__((SlabCfg<NX, NY, NZ>::TB)) void k_lap2(Lap2Args<R> 
       const cpx<R> lv = lds[CFG::lds_index(1, p)] + bload<R>(rT, vt, ov);
       const R fa = bload_real<R>(rA, tid * RS, oa);
       const cpx<R> D = bload<R>(rD, vt, ou);
-      // phi is re-read (the block read it a moment ago; it comes from cache)
+      // phi is re-read: holding the thread's sites through the transforms
+      // halves the waves per SIMD in FP64 and measured slower in FP32
       const cpx<R> u = s * bload<R>(rX, vt, ou), v = s * bload<R>(rX, vt, ov);
       // H (u, v) = ( -1/2 lap u + A u + D v ,  D^* u + 1/2 lap v - A v )
       cpx<R> Hu = R(-0.5) * lu + fa * u + D * v;

@@ -69,7 +69,8 @@ __device__ __forceinline__ int q_wavenum(int l, int p_k1) {
 
 // ---------------------------------------------------------------------------
 // dens: rho, nu partials over a group of G states per workgroup and the
-// kinetic part 1/2 (int |d u|^2 - int |d v|^2) of <H>_n (slot 0).
+// kinetic part 1/2 (int |d u|^2 - int |d v|^2) of <H>_n (slot 0) of the
+// stored (unscaled) state; the finalisation multiplies it by scale^2.
 template <typename R, int A, int G, int TB>
 __global__ __launch_bounds__(TB) void q_dens(const cpx<R>* __restrict__ X, int64_t nstates,
                                               const double* __restrict__ wu, const double* __restrict__ wv,
@@ -90,14 +91,15 @@ __global__ __launch_bounds__(TB) void q_dens(const cpx<R>* __restrict__ X, int64
     const int64_t n = nbeg + it * WS + grp;
     const bool live = n < nstates;
     const int64_t nn = live ? n : 0;
-    const R s = live ? R(sc.scale[nn]) : R(0);
-    const double fu = live ? wu[nn] : 0.0, fv = live ? wv[nn] : 0.0;
+    const double s = live ? sc.scale[nn] : 0.0;
+    const double s2 = s * s;
+    const double fu = live ? wu[nn] * s2 : 0.0, fv = live ? wv[nn] * s2 : 0.0;
     const cpx<R>* Xn = X + nn * 2 * N;
     cpx<R> u[A], v[A];
 #pragma unroll
     for (int b = 0; b < A; ++b) {
-      u[b] = s * Xn[a + A * b];
-      v[b] = s * Xn[N + a + A * b];
+      u[b] = Xn[a + A * b];
+      v[b] = Xn[N + a + A * b];
       const double ur = u[b].x, ui = u[b].y, vr = v[b].x, vi = v[b].y;
       ar[b] += fv * (vr * vr + vi * vi) + fu * (ur * ur + ui * ui);
       const double dw = fv - fu;
@@ -203,13 +205,20 @@ __global__ __launch_bounds__(TB) void q_lap1(const cpx<R>* __restrict__ X, int64
 
 // lap2: pointwise H from T and the integrator modes (see k_lap2)
 template <typename R, int A, int TB, int MODE, int NP = 4, int NQ = 5>
-__global__ __launch_bounds__(TB) void q_lap2(Lap2Args<R> P, int64_t nstates, const double* __restrict__ kperp2) {
+__global__ __launch_bounds__(TB) void q_lap2(Lap2Args<R> P, int64_t nstates, const double* __restrict__ kperp2,
+                                             const cpx<R>* __restrict__ tw, double kz2) {
   constexpr int HD = (NP > NQ - 1) ? NP : NQ - 1;
   using CFG = Q1DCfg<R, A, TB>;
   constexpr int N = CFG::N, WS = CFG::WS;
+  // CORR / FULL leave the z kinetic part of <H> of the state they write
+  constexpr bool KIN = MODE == L2_CORR || MODE == L2_FULL;
+  __shared__ cpx<R> lds_all[KIN ? WS : 1][KIN ? A * CFG::PAD : 1];
   const int tid = threadIdx.x, grp = tid / A, a = tid % A;
-  const int64_t n = int64_t(blockIdx.x) * WS + grp;
-  if (n >= nstates) return;  // whole lane groups leave together; no barriers below
+  const int64_t n0 = int64_t(blockIdx.x) * WS + grp;
+  const bool live = n0 < nstates;
+  if (!KIN && !live) return;  // no barriers in these modes
+  const int64_t n = live ? n0 : 0;
+  cpx<R> wu_[KIN ? A : 1], wv_[KIN ? A : 1];
   const R s = P.scale ? R(P.scale[n]) : R(1);
   const R h = P.hshift ? R(P.hshift[n]) : R(0);
   const R hk = R(0.5 * kperp2[n]);
@@ -248,12 +257,16 @@ __global__ __launch_bounds__(TB) void q_lap2(Lap2Args<R> P, int64_t nstates, con
         } else if constexpr (MODE == L2_CORR) {
           const R a0 = R(P.a[0]);
           const cpx<R> nu_ = P.hist[0][iu] + a0 * fu, nv_ = P.hist[0][iv] + a0 * fv;
-          P.Xout[iu] = nu_;
-          P.Xout[iv] = nv_;
+          if (live) {
+            P.Xout[iu] = nu_;
+            P.Xout[iv] = nv_;
+          }
           nacc += norm2(nu_) + norm2(nv_);
+          if constexpr (KIN) {
+            wu_[b] = nu_;
+            wv_[b] = nv_;
+          }
         } else {  // L2_FULL
-          P.out[iu] = fu;
-          P.out[iv] = fv;
           cpx<R> pu = u + R(P.b[0]) * fu, pv = v + R(P.b[0]) * fv;
           cpx<R> cu = u + R(P.a[1]) * fu, cv = v + R(P.a[1]) * fv;
           sfor<1, HD>::run([&](auto jc) {
@@ -268,19 +281,44 @@ __global__ __launch_bounds__(TB) void q_lap2(Lap2Args<R> P, int64_t nstates, con
               cv = cv + R(P.a[j + 1]) * hv;
             }
           });
-          P.Xout[iu] = pu;
-          P.Xout[iv] = pv;
-          P.cout[iu] = cu;
-          P.cout[iv] = cv;
+          if (live) {
+            P.out[iu] = fu;
+            P.out[iv] = fv;
+            P.Xout[iu] = pu;
+            P.Xout[iv] = pv;
+            P.cout[iu] = cu;
+            P.cout[iv] = cv;
+          }
           nacc += norm2(pu) + norm2(pv);
+          if constexpr (KIN) {
+            wu_[b] = pu;
+            wv_[b] = pv;
+          }
         }
       }
     }
   }
+  if constexpr (KIN) {
+    // sum_k k^2 |phi_k|^2 of the written (unscaled) u and v lines
+    cpx<R>* lds = lds_all[grp];
+    q_fwd<R, A>(wu_, a, lds, tw);
+    q_fwd<R, A>(wv_, a, lds, tw);
+    double ku = 0.0, kv = 0.0;
+    sfor<0, A>::run([&](auto pc) {
+      constexpr int p = decltype(pc)::value;
+      const int m = q_wavenum<A>(a, freq_of_pos<A>(p));
+      ku += double(m * m) * norm2(wu_[p]);
+      kv += double(m * m) * norm2(wv_[p]);
+    });
+    double kin = 0.5 * (ku - kv) * kz2 / double(N) * P.dV;
+#pragma unroll
+    for (int o = A / 2; o > 0; o >>= 1) kin += __shfl_xor(kin, o, A);
+    if (live && a == 0) P.h_part[n * P.h_stride + 0] = kin;
+  }
   if (P.nrm_part) {
 #pragma unroll
     for (int o = A / 2; o > 0; o >>= 1) nacc += __shfl_xor(nacc, o, A);
-    if (a == 0) P.nrm_part[n * P.nrm_stride] = nacc;
+    if (live && a == 0) P.nrm_part[n * P.nrm_stride] = nacc;
   }
 }
 
@@ -443,6 +481,17 @@ struct EngineQ1D final : Engine {
     });
     c.nsg_used = int(ng);
   }
+  static constexpr int DGQ = G;  // states per dens_sum group (the partial buffer is sized for G)
+  void dens_sum(Ctx& c, const void* X, const double* scale, int64_t nst) override {
+    dim3 grid(cdiv(N, DS_TB), cdiv(nst, DGQ));
+    c.launch(KC_DENS, [&] {
+      hipLaunchKernelGGL((k_dens_sum<R, DGQ, 1>), grid, dim3(DS_TB), 0, c.stream, (const cpx<R>*)X, nst,
+                         int64_t(N), c.wu, c.wv, scale, c.dens_part);
+    });
+    c.nsg_used = int(cdiv(nst, DGQ));
+  }
+  bool producer_kinetic() const override { return true; }
+  int raw_h_slots() const override { return 1; }
   void reduce_pot(Ctx& c, bool update) override {
     FunParams fp{c.fun.functional, c.fun.B, c.fun.C, c.fun.inv_g_bdg, c.fun.mu, c.ainv};
     c.launch(KC_REDUCE_POT, [&] {
@@ -486,31 +535,36 @@ struct EngineQ1D final : Engine {
     P.tay_re = d.tay_re;
     P.tay_im = d.tay_im;
     P.init_acc = d.init_acc;
+    P.h_part = c.h_part;
+    P.h_stride = c.h_stride;
+    P.dV = c.lat.dz;
+    twiddles(c);
+    const double k2 = kz2(c);
     with_tb(tb[2], [&](auto t) {
       constexpr int TB = decltype(t)::value;
       dim3 grid(cdiv(nst, TB / A)), block(TB);
       switch (d.mode) {
         case L2_H:
-          c.launch(KC_LAP2_H, [&] { hipLaunchKernelGGL((q_lap2<R, A, TB, L2_H>), grid, block, 0, c.stream, P, nst, c.kperp2); });
+          c.launch(KC_LAP2_H, [&] { hipLaunchKernelGGL((q_lap2<R, A, TB, L2_H>), grid, block, 0, c.stream, P, nst, c.kperp2, tw, k2); });
           break;
         case L2_F:
-          c.launch(KC_LAP2_F, [&] { hipLaunchKernelGGL((q_lap2<R, A, TB, L2_F>), grid, block, 0, c.stream, P, nst, c.kperp2); });
+          c.launch(KC_LAP2_F, [&] { hipLaunchKernelGGL((q_lap2<R, A, TB, L2_F>), grid, block, 0, c.stream, P, nst, c.kperp2, tw, k2); });
           break;
         case L2_CORR:
-          c.launch(KC_LAP2_CORR, [&] { hipLaunchKernelGGL((q_lap2<R, A, TB, L2_CORR>), grid, block, 0, c.stream, P, nst, c.kperp2); });
+          c.launch(KC_LAP2_CORR, [&] { hipLaunchKernelGGL((q_lap2<R, A, TB, L2_CORR>), grid, block, 0, c.stream, P, nst, c.kperp2, tw, k2); });
           break;
         case L2_FULL:
           c.launch(KC_LAP2_FULL, [&] {
             if (c.np == 3)
-              hipLaunchKernelGGL((q_lap2<R, A, TB, L2_FULL, 3, 4>), grid, block, 0, c.stream, P, nst, c.kperp2);
+              hipLaunchKernelGGL((q_lap2<R, A, TB, L2_FULL, 3, 4>), grid, block, 0, c.stream, P, nst, c.kperp2, tw, k2);
             else if (c.np == 5)
-              hipLaunchKernelGGL((q_lap2<R, A, TB, L2_FULL, 5, 5>), grid, block, 0, c.stream, P, nst, c.kperp2);
+              hipLaunchKernelGGL((q_lap2<R, A, TB, L2_FULL, 5, 5>), grid, block, 0, c.stream, P, nst, c.kperp2, tw, k2);
             else
-              hipLaunchKernelGGL((q_lap2<R, A, TB, L2_FULL, 4, 5>), grid, block, 0, c.stream, P, nst, c.kperp2);
+              hipLaunchKernelGGL((q_lap2<R, A, TB, L2_FULL, 4, 5>), grid, block, 0, c.stream, P, nst, c.kperp2, tw, k2);
           });
           break;
         default:
-          c.launch(KC_LAP2_TAYLOR, [&] { hipLaunchKernelGGL((q_lap2<R, A, TB, L2_TAYLOR>), grid, block, 0, c.stream, P, nst, c.kperp2); });
+          c.launch(KC_LAP2_TAYLOR, [&] { hipLaunchKernelGGL((q_lap2<R, A, TB, L2_TAYLOR>), grid, block, 0, c.stream, P, nst, c.kperp2, tw, k2); });
       }
     });
   }
