@@ -287,20 +287,11 @@ struct FunParams {
 // Lambda_c (SLDA) or 1/(4 pi a_s) - Lambda_c (BdG), U = B eF(rho_+) -
 // |Delta|^2 / (3 C rho_+^(2/3)) (SLDA, A=1) or 0 (BdG).
 template <typename R>
-__global__ __launch_bounds__(256) void k_reduce_pot(
-    const double* __restrict__ dens_part, int ngroups, int64_t M, FunParams fp,
-    const double* __restrict__ lam, const double* __restrict__ vext, double* __restrict__ rho,
-    double* __restrict__ nu, double* __restrict__ U, double* __restrict__ delta,
-    R* __restrict__ hA, cpx<R>* __restrict__ hD, int update_fields) {
-  const int64_t r = int64_t(blockIdx.x) * 256 + threadIdx.x;
-  if (r >= M) return;
-  double sr = 0.0, snr = 0.0, sni = 0.0;
-  for (int g = 0; g < ngroups; ++g) {
-    const double* p = dens_part + int64_t(g) * 3 * M;
-    sr += p[r];
-    snr += p[M + r];
-    sni += p[2 * M + r];
-  }
+__device__ __forceinline__ void pot_from_sums(int64_t r, double sr, double snr, double sni, const FunParams& fp,
+                                              const double* __restrict__ lam, const double* __restrict__ vext,
+                                              double* __restrict__ rho, double* __restrict__ nu,
+                                              double* __restrict__ U, double* __restrict__ delta,
+                                              R* __restrict__ hA, cpx<R>* __restrict__ hD, int update_fields) {
   sr *= fp.ainv;
   snr *= fp.ainv;
   sni *= fp.ainv;
@@ -328,6 +319,59 @@ __global__ __launch_bounds__(256) void k_reduce_pot(
   delta[2 * r + 1] = di;
   hA[r] = R(u + vext[r] - fp.mu);
   hD[r] = cpx<R>{R(dr), R(di)};
+}
+
+// one thread per site, groups summed in order
+template <typename R>
+__global__ __launch_bounds__(256) void k_reduce_pot(
+    const double* __restrict__ dens_part, int ngroups, int64_t M, FunParams fp,
+    const double* __restrict__ lam, const double* __restrict__ vext, double* __restrict__ rho,
+    double* __restrict__ nu, double* __restrict__ U, double* __restrict__ delta,
+    R* __restrict__ hA, cpx<R>* __restrict__ hD, int update_fields) {
+  const int64_t r = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (r >= M) return;
+  double sr = 0.0, snr = 0.0, sni = 0.0;
+  for (int g = 0; g < ngroups; ++g) {
+    const double* p = dens_part + int64_t(g) * 3 * M;
+    sr += p[r];
+    snr += p[M + r];
+    sni += p[2 * M + r];
+  }
+  pot_from_sums<R>(r, sr, snr, sni, fp, lam, vext, rho, nu, U, delta, hA, hD, update_fields);
+}
+
+// one workgroup per site (few sites, many groups): thread t sums groups
+// t, t + 256, ... in order, then a fixed-order tree over the threads
+template <typename R>
+__global__ __launch_bounds__(256) void k_reduce_pot_wide(
+    const double* __restrict__ dens_part, int ngroups, int64_t M, FunParams fp,
+    const double* __restrict__ lam, const double* __restrict__ vext, double* __restrict__ rho,
+    double* __restrict__ nu, double* __restrict__ U, double* __restrict__ delta,
+    R* __restrict__ hA, cpx<R>* __restrict__ hD, int update_fields) {
+  __shared__ double t3[3][256];
+  const int64_t r = blockIdx.x;
+  const int t = threadIdx.x;
+  double sr = 0.0, snr = 0.0, sni = 0.0;
+  for (int g = t; g < ngroups; g += 256) {
+    const double* p = dens_part + int64_t(g) * 3 * M;
+    sr += p[r];
+    snr += p[M + r];
+    sni += p[2 * M + r];
+  }
+  t3[0][t] = sr;
+  t3[1][t] = snr;
+  t3[2][t] = sni;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (t < k) {
+      t3[0][t] += t3[0][t + k];
+      t3[1][t] += t3[1][t + k];
+      t3[2][t] += t3[2][t + k];
+    }
+    __syncthreads();
+  }
+  if (t == 0) pot_from_sums<R>(r, t3[0][0], t3[1][0], t3[2][0], fp, lam, vext, rho, nu, U, delta, hA, hD,
+                               update_fields);
 }
 
 // Frozen fields (linear mode): hA, hD from given U, Delta.

@@ -495,9 +495,14 @@ struct EngineQ1D final : Engine {
   void reduce_pot(Ctx& c, bool update) override {
     FunParams fp{c.fun.functional, c.fun.B, c.fun.C, c.fun.inv_g_bdg, c.fun.mu, c.ainv};
     c.launch(KC_REDUCE_POT, [&] {
-      hipLaunchKernelGGL((k_reduce_pot<R>), dim3(cdiv(N, 256)), dim3(256), 0, c.stream, c.dens_part, c.nsg_used,
-                         int64_t(N), fp, c.lam, c.vext, c.rho, c.nu, c.U, c.delta, (R*)c.hA, (cpx<R>*)c.hD,
-                         int(update));
+      if (c.nsg_used >= 64)  // few sites, many state groups: one workgroup per site
+        hipLaunchKernelGGL((k_reduce_pot_wide<R>), dim3(N), dim3(256), 0, c.stream, c.dens_part, c.nsg_used,
+                           int64_t(N), fp, c.lam, c.vext, c.rho, c.nu, c.U, c.delta, (R*)c.hA, (cpx<R>*)c.hD,
+                           int(update));
+      else
+        hipLaunchKernelGGL((k_reduce_pot<R>), dim3(cdiv(N, 256)), dim3(256), 0, c.stream, c.dens_part, c.nsg_used,
+                           int64_t(N), fp, c.lam, c.vext, c.rho, c.nu, c.U, c.delta, (R*)c.hA, (cpx<R>*)c.hD,
+                           int(update));
     });
   }
   void lap1(Ctx& c, const void* X, const double* scale, bool hpart, int64_t nst) override {
@@ -613,8 +618,8 @@ struct EngineQ1D final : Engine {
 
   // Time every workgroup size of each kernel class on the loaded states
   // (median of 5 after a warm launch) and keep the fastest.  Only scratch
-  // buffers are written (dens_part, T, h slots, norm slots), all of which the
-  // next evaluation recomputes.
+  // buffers are written (dens_part, T, h slots, norm slots); the caller marks
+  // the h slots stale so the next evaluation recomputes them.
   int autotune(Ctx& c, int32_t* out, double* ms_out) override {
     twiddles(c);
     const int b = c.phi;
@@ -649,12 +654,18 @@ struct EngineQ1D final : Engine {
         } else if (k == 1) {
           ms = timeit([&] { lap1(c, c.sb[b], c.sscale[b], true, c.nst); });
         } else if (k == 2) {
+          // the corrector form (with its kinetic tail), writing into T only:
+          // T serves as input, partial corrector and output; each thread
+          // reads then writes its own sites
           L2Desc d;
-          d.mode = L2_H;
+          d.mode = L2_CORR;
           d.X = c.sb[b];
           d.T = c.T;
+          d.Xout = c.T;
+          d.hist[0] = c.T;
           d.scale = c.sscale[b];
-          d.out = c.T;  // in place over T: each thread reads then writes its own sites
+          d.hshift = c.hshift;
+          d.nrm_part = c.nrm_part;
           ms = timeit([&] { lap2(c, d, c.nst); });
         } else {
           PwDesc d;

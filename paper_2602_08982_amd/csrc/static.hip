@@ -202,6 +202,16 @@ struct StaticSolver {
     return p;
   }
   StaticSolver(const tdslda_static& s_, const tdslda_functional& f_, const double* vext_h) : s(s_), f(f_) {
+    try {
+      setup(vext_h);
+    } catch (...) {
+      (void)hipDeviceSynchronize();
+      for (void* p : owned) (void)hipFree(p);
+      owned.clear();
+      throw;
+    }
+  }
+  void setup(const double* vext_h) {
     require(s.nx > 0 && s.ny > 0 && s.nz > 0 && s.nz % 2 == 0 && s.nx % 2 == 0 && s.ny % 2 == 0, TDSLDA_EINVAL,
             "static lattice sizes must be positive and even");
     require(s.dx > 0 && s.dy > 0 && s.dz > 0 && s.ec > 0 && s.mix > 0 && s.mix <= 1, TDSLDA_EINVAL,

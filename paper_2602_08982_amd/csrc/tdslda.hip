@@ -771,6 +771,10 @@ tdslda_status tdslda_autotune(tdslda_ctx* c, int* nclasses, int32_t choice[4], d
     require(c->loaded, TDSLDA_EORDER, "load states before tuning");
     const int k = c->eng->autotune(*c, choice, ms);
     if (nclasses) *nclasses = k;
+    // the trial launches overwrote the scratch <H> slots: the next
+    // evaluation rebuilds them with the full density pass
+    if (k > 0)
+      for (bool& r : c->kin_ready) r = false;
     HIPCHK(hipStreamSynchronize(c->stream));
   });
 }

@@ -91,3 +91,31 @@ def test_q1d_apply_hbdg():
     out = yd.cpu().numpy().reshape(x.shape)
     assert np.abs(out - ref).max() / np.abs(ref).max() < 1e-12
     ctx.close()
+
+
+def test_q1d_many_states_parity():
+    """2,304 problems of N_z = 16 (36,864 states: more than 64 state groups,
+    so the per-site reduction takes the one-workgroup-per-site path and the
+    graph-free hot path uses the transform-free density pass): densities and
+    states after 5 steps against the oracle to 1e-10 (FP64)."""
+    geom, mu, vext, E, kp2, pid, phi = problem(16, 48, 1.0, None, seed=4)
+    assert len(E) > 64 * 512
+    ecreg = 0.5 * np.pi ** 2
+    lam = F.lambda_c(vext, mu, ecreg)
+    z = L.centered_coords(16, 1.0)
+    v0 = 0.5 * (0.0175 * 16) ** 2 * z ** 2
+    sysm = td.TDSystem(geom, F.Functional(F.SLDA), mu, v0, lam, F.fermi_weight(E), F.fermi_weight(-E))
+    ref = td.evolve(sysm, phi, 0.005, 5)
+    ctx = make_ctx(geom, mu, ecreg, len(E), 0)
+    try:
+        ctx.set_external(v0, freeze_regulator=False)
+        ctx.set_regulator(lam)
+        ctx.load_states(phi, E, kp2)
+        ctx.abm_step(5)
+        d = ctx.densities()
+        r, t_, n, j = geom.full_densities(ref, sysm.wu, sysm.wv)
+        assert rel(d["rho"], r) < 1e-10
+        assert rel(d["nu"], n) < 1e-10
+        assert np.abs(ctx.get_states() - ref).max() < 1e-9
+    finally:
+        ctx.close()
