@@ -409,6 +409,7 @@ __global__ __launch_bounds__(TB1) void k_lap1(
   const bi32x4 rA = make_rsrc(hA, M * RS);
   const bi32x4 rD = make_rsrc(hD, M * ES);
   const int vq = q * ES, vqa = q * RS;
+  constexpr bool SPLIT_POT = sizeof(R) == 8;
   double hsum = 0.0;
   if (act) {
     cpx<R> a[NX];
@@ -418,21 +419,38 @@ __global__ __launch_bounds__(TB1) void k_lap1(
       const double sg = comp ? -1.0 : 1.0;
 #pragma unroll
       for (int x = 0; x < NX; ++x) a[x] = s * bload<R>(rX, vq, int(comp * M + x * NYZ) * ES);
+      // potential part A (|u|^2 - |v|^2) + 2 Re(u^* Delta v), only when <H>_n
+      // is wanted.  FP64: A |u|^2 in the u pass, -A |v|^2 and the cross term
+      // in the v pass, which re-reads u (keeping the u line for the v pass
+      // costs more in occupancy than the half re-read).  FP32: after both
+      // passes, re-reading u and v (fewer live registers, measured faster).
+      if (SPLIT_POT && h_part) {
+#pragma unroll
+        for (int x = 0; x < NX; ++x) {
+          const double fa = double(bload_real<R>(rA, vqa, x * NYZ * RS));
+          if (comp == 0) {
+            pot += fa * norm2(a[x]);
+          } else {
+            const cpx<R> u = s * bload<R>(rX, vq, x * NYZ * ES);
+            const cpx<R> dv = bload<R>(rD, vq, x * NYZ * ES) * a[x];
+            pot += 2.0 * (double(u.x) * double(dv.x) + double(u.y) * double(dv.y)) - fa * norm2(a[x]);
+          }
+        }
+      }
       // sum_x |d_x f|^2 = kx2 * ks / NX (Parseval)
       const double ks = second_derivative<NX>(a, R(kx2));
       kin += sg * kx2 * ks / double(NX);
 #pragma unroll
       for (int x = 0; x < NX; ++x) bstore<R>(a[x], rT, vq, int(comp * M + x * NYZ) * ES);
     }
-    // potential part A (|u|^2 - |v|^2) + 2 Re(u^* Delta v), only when <H>_n
-    // is wanted; phi is re-read (keeping the u line for the v pass costs more
-    // in occupancy than the second read)
+    if (!SPLIT_POT && h_part) {
 #pragma unroll 4
-    for (int x = 0; x < (h_part ? NX : 0); ++x) {
-      const cpx<R> u = s * bload<R>(rX, vq, x * NYZ * ES), v = s * bload<R>(rX, vq, int(M + x * NYZ) * ES);
-      const cpx<R> dv = bload<R>(rD, vq, x * NYZ * ES) * v;
-      pot += double(bload_real<R>(rA, vqa, x * NYZ * RS)) * (norm2(u) - norm2(v));
-      pot += 2.0 * (double(u.x) * double(dv.x) + double(u.y) * double(dv.y));
+      for (int x = 0; x < NX; ++x) {
+        const cpx<R> u = s * bload<R>(rX, vq, x * NYZ * ES), v = s * bload<R>(rX, vq, int(M + x * NYZ) * ES);
+        const cpx<R> dv = bload<R>(rD, vq, x * NYZ * ES) * v;
+        pot += double(bload_real<R>(rA, vqa, x * NYZ * RS)) * (norm2(u) - norm2(v));
+        pot += 2.0 * (double(u.x) * double(dv.x) + double(u.y) * double(dv.y));
+      }
     }
     hsum = (0.5 * kin + pot) * dV;
   }
