@@ -52,12 +52,24 @@ __device__ __forceinline__ double norm2(cpx<R> a) {
 
 // ---------------------------------------------------------------------------
 // compile-time tiling of the slab kernels
+// Tiling knobs (compile-time): lines per slab workgroup target and the
+// largest sites-per-thread count for which the fused pass keeps its sites
+// of phi in registers instead of re-reading them.  Defaults: 64 lines, no
+// stash (one x-slab per workgroup with the stash gains 3% on the full pass
+// but loses 14% on the corrector at 32^3 FP64, 2% per step overall).
+#ifndef TDSLDA_SLAB_LINES
+#define TDSLDA_SLAB_LINES 64
+#endif
+#ifndef TDSLDA_STASH_MAXP
+#define TDSLDA_STASH_MAXP 0
+#endif
+
 template <int NX, int NY, int NZ>
 struct SlabCfg {
   static constexpr int NXv = NX, NYv = NY, NZv = NZ;
   static constexpr int NMAX = NY > NZ ? NY : NZ;
   static constexpr int sx_target() {
-    int t = 64 / NMAX;
+    int t = TDSLDA_SLAB_LINES / NMAX;
     if (t < 1) t = 1;
     while (NX % t) --t;
     return t;
@@ -517,6 +529,8 @@ __global__ __launch_bounds__((SlabCfg<NX, NY, NZ>::TB)) void k_lap2(Lap2Args<R> 
   const uint32_t SB = 2 * M * ES;
   const bi32x4 rX = make_rsrc(A.X + so, SB);
   const int vt = tid * ES;
+  constexpr bool STASH = P <= TDSLDA_STASH_MAXP;
+  cpx<R> xs[2][STASH ? P : 1];
 
 #pragma unroll
   for (int i = 0; i < P; ++i) {
@@ -526,7 +540,10 @@ __global__ __launch_bounds__((SlabCfg<NX, NY, NZ>::TB)) void k_lap2(Lap2Args<R> 
       const cpx<R> xu = s * bload<R>(rX, vt, o), xv = s * bload<R>(rX, vt, o + M * ES);
       lds[CFG::lds_index(0, p)] = xu;
       lds[CFG::lds_index(1, p)] = xv;
-
+      if constexpr (STASH) {
+        xs[0][i] = xu;
+        xs[1][i] = xv;
+      }
     }
   }
   __syncthreads();
@@ -586,9 +603,16 @@ __global__ __launch_bounds__((SlabCfg<NX, NY, NZ>::TB)) void k_lap2(Lap2Args<R> 
       const cpx<R> lv = lds[CFG::lds_index(1, p)] + bload<R>(rT, vt, ov);
       const R fa = bload_real<R>(rA, tid * RS, oa);
       const cpx<R> D = bload<R>(rD, vt, ou);
-      // phi is re-read: holding the thread's sites through the transforms
-      // halves the waves per SIMD in FP64 and measured slower in FP32
-      const cpx<R> u = s * bload<R>(rX, vt, ou), v = s * bload<R>(rX, vt, ov);
+      // phi is re-read unless the tiling keeps it (STASH): holding many sites
+      // through the transforms halves the waves per SIMD
+      cpx<R> u, v;
+      if constexpr (STASH) {
+        u = xs[0][i];
+        v = xs[1][i];
+      } else {
+        u = s * bload<R>(rX, vt, ou);
+        v = s * bload<R>(rX, vt, ov);
+      }
       // H (u, v) = ( -1/2 lap u + A u + D v ,  D^* u + 1/2 lap v - A v )
       cpx<R> Hu = R(-0.5) * lu + fa * u + D * v;
       cpx<R> Hv = conj(D) * u + R(0.5) * lv - fa * v;

@@ -107,7 +107,7 @@ def load_library(path=None):
     global _lib
     if _lib is not None:
         return _lib
-    path = path or LIB_PATH
+    path = path or os.environ.get("TDSLDA_LIBRARY") or LIB_PATH
     if not os.path.exists(path):
         raise ImportError(f"{path} is not built; run python -m paper_2602_08982_amd.build")
     lib = C.CDLL(path)
