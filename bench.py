@@ -21,6 +21,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM = 8.0e12  # MI355X HBM3E, bytes/s
+COUNTERS_MD = os.path.join(ROOT, "profiles", "lap2_full_fp64_32_fp32_48_hbm_counters.md")
 
 
 def algorithmic_bytes(kernel, S, nst, depth):
@@ -147,15 +148,27 @@ def copy_bandwidth():
     return 2 * (1 << 29) * 8 / sorted(ts)[2]
 
 
-def roofline(res, copy_bps=None):
+def roofline(res, copy_bps=None, prec=None, nx=None):
+    """Dominant kernel of the timed steps against the HBM peak.  traffic =
+    HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE summary
+    (copy-calibrated), null when that summary does not cover this kernel or
+    the kernel sources changed since the counters were taken."""
     kern = res["kernels"]
     if not kern:
         return None
     dom = max(kern, key=lambda k: kern[k]["total_ms"])
     g = kern[dom]["gbps"]
+    traffic = None
+    if prec is not None:
+        from paper_2602_08982_amd import profsum
+        traffic = profsum.read_traffic(COUNTERS_MD, prec, nx, dom)
     out = dict(bound="hbm", kernel=dom, achieved=g, peak=PEAK_HBM / 1e9, unit="GB/s",
-               frac=(g * 1e9 / PEAK_HBM) if g else None, traffic=None,
+               frac=(g * 1e9 / PEAK_HBM) if g else None, traffic=traffic,
                share_of_step=kern[dom]["total_ms"] / (res["ms_per_step"] * res["steps"]))
+    if traffic is not None and g:
+        alg = g * 1e9 * kern[dom]["avg_ms"] * 1e-3
+        out["algorithmic_bytes"] = alg
+        out["traffic_over_algorithmic"] = traffic / alg
     if copy_bps:
         out["copy_GBps"] = copy_bps / 1e9
         out["frac_of_copy"] = g * 1e9 / copy_bps if g else None
@@ -292,7 +305,7 @@ def main():
         "config": {"workload": "plain FP64 32^3 trapped gas, one vortex (AB4AM5, dt=0.005)",
                    "lattice": [32, 32, 32], "states_evolved": plain["nst"],
                    "states_represented": 2 * plain["nst"], "integrator": "AB4AM5"},
-        "roofline": roofline(plain, copy_bps),
+        "roofline": roofline(plain, copy_bps, "double", 32),
         "cpu_baseline": cpu,
         "kernels": plain["kernels"],
         "check": plain["check"],
@@ -301,7 +314,7 @@ def main():
         line["fp32_mixed"] = {
             "workload": "FP32-mixed 48^3 elongated trap, vortex pair, 8192 lowest-|E| states",
             "value": mixed["value"], "unit": "state-steps/s", "ms_per_step": mixed["ms_per_step"],
-            "dtype": "f32 states / f64 sums", "roofline": roofline(mixed, copy_bps), "kernels": mixed["kernels"],
+            "dtype": "f32 states / f64 sums", "roofline": roofline(mixed, copy_bps, "float", 48), "kernels": mixed["kernels"],
             "check": mixed["check"], "vs_fp64_same_workload": mixed["vs_fp64"],
         }
     if q1d is not None:

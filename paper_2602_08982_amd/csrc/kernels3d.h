@@ -265,7 +265,7 @@ __global__ __launch_bounds__(DS_TB) void k_dens_sum(
     for (int i = 0; i < PS; ++i) {
       const int64_t r = site0 + i * DS_TB;
       if (r < M) {
-        const cpx<R> u = xs[r], v = xs[M + r];
+        const cpx<R> u = ld_stream(xs + r), v = ld_stream(xs + M + r);
         const double ur = u.x, ui = u.y, vr = v.x, vi = v.y;
         ar[i] += cv * (vr * vr + vi * vi) + cu * (ur * ur + ui * ui);
         anr[i] += cw * (ur * vr + ui * vi);  // u v^*
@@ -429,8 +429,14 @@ __global__ __launch_bounds__(TB1) void k_lap1(
 #pragma unroll 1
     for (int comp = 0; comp < 2; ++comp) {
       const double sg = comp ? -1.0 : 1.0;
+      // lines that the potential part reads again stay cached; the rest stream
+      if (h_part && (comp == 0 || !SPLIT_POT)) {
 #pragma unroll
-      for (int x = 0; x < NX; ++x) a[x] = s * bload<R>(rX, vq, int(comp * M + x * NYZ) * ES);
+        for (int x = 0; x < NX; ++x) a[x] = s * bload<R>(rX, vq, int(comp * M + x * NYZ) * ES);
+      } else {
+#pragma unroll
+        for (int x = 0; x < NX; ++x) a[x] = s * bload_nt<R>(rX, vq, int(comp * M + x * NYZ) * ES);
+      }
       // potential part A (|u|^2 - |v|^2) + 2 Re(u^* Delta v), only when <H>_n
       // is wanted.  FP64: A |u|^2 in the u pass, -A |v|^2 and the cross term
       // in the v pass, which re-reads u (keeping the u line for the v pass
@@ -443,7 +449,7 @@ __global__ __launch_bounds__(TB1) void k_lap1(
           if (comp == 0) {
             pot += fa * norm2(a[x]);
           } else {
-            const cpx<R> u = s * bload<R>(rX, vq, x * NYZ * ES);
+            const cpx<R> u = s * bload_nt<R>(rX, vq, x * NYZ * ES);
             const cpx<R> dv = bload<R>(rD, vq, x * NYZ * ES) * a[x];
             pot += 2.0 * (double(u.x) * double(dv.x) + double(u.y) * double(dv.y)) - fa * norm2(a[x]);
           }
@@ -453,12 +459,12 @@ __global__ __launch_bounds__(TB1) void k_lap1(
       const double ks = second_derivative<NX>(a, R(kx2));
       kin += sg * kx2 * ks / double(NX);
 #pragma unroll
-      for (int x = 0; x < NX; ++x) bstore<R>(a[x], rT, vq, int(comp * M + x * NYZ) * ES);
+      for (int x = 0; x < NX; ++x) bstore_nt<R>(a[x], rT, vq, int(comp * M + x * NYZ) * ES);
     }
     if (!SPLIT_POT && h_part) {
 #pragma unroll 4
       for (int x = 0; x < NX; ++x) {
-        const cpx<R> u = s * bload<R>(rX, vq, x * NYZ * ES), v = s * bload<R>(rX, vq, int(M + x * NYZ) * ES);
+        const cpx<R> u = s * bload_nt<R>(rX, vq, x * NYZ * ES), v = s * bload_nt<R>(rX, vq, int(M + x * NYZ) * ES);
         const cpx<R> dv = bload<R>(rD, vq, x * NYZ * ES) * v;
         pot += double(bload_real<R>(rA, vqa, x * NYZ * RS)) * (norm2(u) - norm2(v));
         pot += 2.0 * (double(u.x) * double(dv.x) + double(u.y) * double(dv.y));
@@ -599,8 +605,8 @@ __global__ __launch_bounds__((SlabCfg<NX, NY, NZ>::TB)) void k_lap2(Lap2Args<R> 
     if (p < SS) {
       const int ou = int(site0 + i * TB) * ES, ov = ou + M * ES;
       const int oa = int(site0 + i * TB) * RS;
-      const cpx<R> lu = lds[CFG::lds_index(0, p)] + bload<R>(rT, vt, ou);
-      const cpx<R> lv = lds[CFG::lds_index(1, p)] + bload<R>(rT, vt, ov);
+      const cpx<R> lu = lds[CFG::lds_index(0, p)] + bload_nt<R>(rT, vt, ou);
+      const cpx<R> lv = lds[CFG::lds_index(1, p)] + bload_nt<R>(rT, vt, ov);
       const R fa = bload_real<R>(rA, tid * RS, oa);
       const cpx<R> D = bload<R>(rD, vt, ou);
       // phi is re-read unless the tiling keeps it (STASH): holding many sites
@@ -610,58 +616,58 @@ __global__ __launch_bounds__((SlabCfg<NX, NY, NZ>::TB)) void k_lap2(Lap2Args<R> 
         u = xs[0][i];
         v = xs[1][i];
       } else {
-        u = s * bload<R>(rX, vt, ou);
-        v = s * bload<R>(rX, vt, ov);
+        u = s * bload_nt<R>(rX, vt, ou);
+        v = s * bload_nt<R>(rX, vt, ov);
       }
       // H (u, v) = ( -1/2 lap u + A u + D v ,  D^* u + 1/2 lap v - A v )
       cpx<R> Hu = R(-0.5) * lu + fa * u + D * v;
       cpx<R> Hv = conj(D) * u + R(0.5) * lv - fa * v;
       if constexpr (MODE == L2_H) {
-        bstore<R>(Hu, rO, vt, ou);
-        bstore<R>(Hv, rO, vt, ov);
+        bstore_nt<R>(Hu, rO, vt, ou);
+        bstore_nt<R>(Hv, rO, vt, ov);
       } else {
         // f = -i (H - h) phi
         const cpx<R> gu = Hu - h * u, gv = Hv - h * v;
         if constexpr (MODE == L2_TAYLOR) {
           const cpx<R> c{R(A.tay_re), R(A.tay_im)};
           const cpx<R> ou_ = c * gu, ov_ = c * gv;
-          bstore<R>(ou_, rO, vt, ou);
-          bstore<R>(ov_, rO, vt, ov);
+          bstore_nt<R>(ou_, rO, vt, ou);
+          bstore_nt<R>(ov_, rO, vt, ov);
           cpx<R> su, sv;
           if (A.init_acc) {
             su = u + ou_;
             sv = v + ov_;
           } else {
-            su = bload<R>(rAcc, vt, ou) + ou_;
-            sv = bload<R>(rAcc, vt, ov) + ov_;
+            su = bload_nt<R>(rAcc, vt, ou) + ou_;
+            sv = bload_nt<R>(rAcc, vt, ov) + ov_;
           }
-          bstore<R>(su, rAcc, vt, ou);
-          bstore<R>(sv, rAcc, vt, ov);
+          bstore_nt<R>(su, rAcc, vt, ou);
+          bstore_nt<R>(sv, rAcc, vt, ov);
           nacc += norm2(su) + norm2(sv);
         } else {
           const cpx<R> fu{gu.y, -gu.x}, fv{gv.y, -gv.x};  // -i g
           if constexpr (MODE == L2_F) {
-            bstore<R>(fu, rO, vt, ou);
-            bstore<R>(fv, rO, vt, ov);
+            bstore_nt<R>(fu, rO, vt, ou);
+            bstore_nt<R>(fv, rO, vt, ov);
           } else if constexpr (MODE == L2_CORR) {
             // phi_new = c + dt a_0 f(p), written over the input
             const R a0 = R(A.a[0]);
-            const cpx<R> nu_ = bload<R>(rH[0], vt, ou) + a0 * fu;
-            const cpx<R> nv_ = bload<R>(rH[0], vt, ov) + a0 * fv;
-            bstore<R>(nu_, rX, vt, ou);
-            bstore<R>(nv_, rX, vt, ov);
+            const cpx<R> nu_ = bload_nt<R>(rH[0], vt, ou) + a0 * fu;
+            const cpx<R> nv_ = bload_nt<R>(rH[0], vt, ov) + a0 * fv;
+            bstore_nt<R>(nu_, rX, vt, ou);
+            bstore_nt<R>(nv_, rX, vt, ov);
             nacc += norm2(nu_) + norm2(nv_);
             // the written state replaces this thread's own LDS sites
             lds[CFG::lds_index(0, p)] = nu_;
             lds[CFG::lds_index(1, p)] = nv_;
           } else {  // L2_FULL: f_k, next predictor p (over the input), partial corrector c
-            bstore<R>(fu, rO, vt, ou);
-            bstore<R>(fv, rO, vt, ov);
+            bstore_nt<R>(fu, rO, vt, ou);
+            bstore_nt<R>(fv, rO, vt, ov);
             cpx<R> pu = u + R(A.b[0]) * fu, pv = v + R(A.b[0]) * fv;
             cpx<R> cu = u + R(A.a[1]) * fu, cv = v + R(A.a[1]) * fv;
             sfor<1, HD>::run([&](auto jc) {
               constexpr int j = decltype(jc)::value;
-              const cpx<R> hu = bload<R>(rH[j], vt, ou), hv = bload<R>(rH[j], vt, ov);
+              const cpx<R> hu = bload_nt<R>(rH[j], vt, ou), hv = bload_nt<R>(rH[j], vt, ov);
               if constexpr (j < NP) {
                 pu = pu + R(A.b[j]) * hu;
                 pv = pv + R(A.b[j]) * hv;
@@ -671,10 +677,10 @@ __global__ __launch_bounds__((SlabCfg<NX, NY, NZ>::TB)) void k_lap2(Lap2Args<R> 
                 cv = cv + R(A.a[j + 1]) * hv;
               }
             });
-            bstore<R>(pu, rX, vt, ou);
-            bstore<R>(pv, rX, vt, ov);
-            bstore<R>(cu, rC, vt, ou);
-            bstore<R>(cv, rC, vt, ov);
+            bstore_nt<R>(pu, rX, vt, ou);
+            bstore_nt<R>(pv, rX, vt, ov);
+            bstore_nt<R>(cu, rC, vt, ou);
+            bstore_nt<R>(cv, rC, vt, ov);
             nacc += norm2(pu) + norm2(pv);
             lds[CFG::lds_index(0, p)] = pu;
             lds[CFG::lds_index(1, p)] = pv;
@@ -747,23 +753,23 @@ __global__ __launch_bounds__((SlabCfg<NX, NY, NZ>::TB)) void k_pointwise(PwArgs<
       for (int c = 0; c < 2; ++c) {
         const int o = int(int64_t(g) * SS + i * TB + c * M) * ES;
         if constexpr (MODE == PW_NORM) {
-          nacc += norm2(bload<R>(rX, vt, o));
+          nacc += norm2(bload_nt<R>(rX, vt, o));
         } else if constexpr (MODE == PW_SCALE) {
           const double s = A.scale[n];
-          const cpx<R> x = bload<R>(rX, vt, o);
+          const cpx<R> x = bload_nt<R>(rX, vt, o);
           A.out64[so + int64_t(g) * SS + c * M + p] = cpx<double>{s * double(x.x), s * double(x.y)};
         } else {  // PW_PRED
           const R s = R(A.scale[n]);
-          const cpx<R> phi = s * bload<R>(rX, vt, o);
+          const cpx<R> phi = s * bload_nt<R>(rX, vt, o);
           cpx<R> pp = phi, cc = phi;
           sfor<0, HD>::run([&](auto jc) {
             constexpr int j = decltype(jc)::value;
-            const cpx<R> f = bload<R>(rH[j], vt, o);
+            const cpx<R> f = bload_nt<R>(rH[j], vt, o);
             if constexpr (j < NP) pp = pp + R(A.b[j]) * f;
             if constexpr (j + 1 < NQ) cc = cc + R(A.a[j + 1]) * f;
           });
-          bstore<R>(pp, rX, vt, o);
-          bstore<R>(cc, rC, vt, o);
+          bstore_nt<R>(pp, rX, vt, o);
+          bstore_nt<R>(cc, rC, vt, o);
           nacc += norm2(pp);
         }
       }

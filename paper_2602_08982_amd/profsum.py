@@ -1,0 +1,173 @@
+"""Summaries of rocprofv3 output as short Markdown text.
+
+    python -m paper_2602_08982_amd.profsum stats  RUN_kernel_stats.csv OUT.md --command "..."
+    python -m paper_2602_08982_amd.profsum counters FETCH.csv WRITE.csv OUT.md --command "..."
+
+`stats` tabulates calls / total / average duration per kernel.  `counters`
+turns the per-dispatch FETCH_SIZE and WRITE_SIZE readings (KiB) into HBM
+bytes per launch: each counter is scaled by the factor that maps its reading
+for the run's 4 GiB device-to-device copy (the largest __amd_rocclr_copyBuffer
+dispatch, 2^32 bytes read and 2^32 bytes written) onto those known sizes.
+The counters summary records a digest of the 3D kernel sources and build
+flags so that a reader (bench.py) can tell whether the figures still describe
+the kernels as built.
+"""
+import argparse
+import collections
+import csv
+import hashlib
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCES = ["csrc/kernels3d.h", "csrc/engine3d.h", "csrc/bufio.h", "csrc/fft.h", "build.py"]
+COPY_BYTES = 1 << 32
+
+LAP2_MODES = {0: "lap2_h", 1: "lap2_f", 2: "lap2_corr", 3: "lap2_full", 4: "lap2_taylor"}
+PW_MODES = {0: "norm", 1: "pred"}
+
+
+def sources_digest():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(HERE, rel), "rb") as f:
+            h.update(rel.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def role(name):
+    """Short role of a 3D-path kernel (the names bench.py reports), else None."""
+    m = re.search(r"k_lap2<(\w+), \d+, \d+, \d+, (\d)", name)
+    if m:
+        return LAP2_MODES[int(m.group(2))]
+    m = re.search(r"k_pointwise<(\w+), \d+, \d+, \d+, (\d)", name)
+    if m:
+        return PW_MODES[int(m.group(2))]
+    for pat, r in (("k_lap1<", "lap1"), ("k_dens_sum<", "dens"), ("k_dens<", "dens_kin"),
+                   ("k_reduce_pot", "reduce_pot"), ("k_finalize", "finalize")):
+        if pat in name:
+            return r
+    return None
+
+
+def precision(name):
+    m = re.search(r"<(double|float)\b", name)
+    return m.group(1) if m else ""
+
+
+def key(name):
+    """precision:lattice-extent:role of a 3D-path kernel (x extent from the
+    template arguments of lap1 / lap2 / pointwise), else None."""
+    rl = role(name)
+    if rl is None:
+        return None
+    m = re.search(r"<(?:double|float), (\d+)", name)
+    nx = m.group(1) if m and rl not in ("dens", "dens_kin", "reduce_pot", "finalize") else "-"
+    return f"{precision(name)}:{nx}:{rl}"
+
+
+def short(name, width=72):
+    n = name.replace("tdslda::", "").replace("void ", "")
+    return n if len(n) <= width else n[:width - 3] + "..."
+
+
+def cmd_stats(args):
+    rows = list(csv.DictReader(open(args.csv)))
+    out = [f"# {args.title}", "", "Command (from the repository root, on one MI355X):", "",
+           "    " + args.command, "", "| kernel | role | calls | total ms | avg ms | % |",
+           "|---|---|---:|---:|---:|---:|"]
+    for r in rows:
+        nm = r["Name"]
+        rl = role(nm)
+        rl = f"{rl} ({precision(nm)})" if rl else ""
+        out.append(f"| `{short(nm)}` | {rl} | {r['Calls']} | {int(r['TotalDurationNs']) / 1e6:.3f} | "
+                   f"{float(r['AverageNs']) / 1e6:.3f} | {r['Percentage']} |")
+    if args.note:
+        out += ["", args.note]
+    with open(args.out, "w") as f:
+        f.write("\n".join(out) + "\n")
+
+
+def _per_kernel(path):
+    agg = collections.defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        agg[r["Kernel_Name"]].append(float(r["Counter_Value"]) * 1024.0)
+    return agg
+
+
+def _copy_factor(agg):
+    copies = [v for k, vals in agg.items() if "copyBuffer" in k for v in vals]
+    if not copies:
+        raise SystemExit("no __amd_rocclr_copyBuffer dispatch in the counter file")
+    return COPY_BYTES / max(copies)
+
+
+def cmd_counters(args):
+    fetch, write = _per_kernel(args.fetch), _per_kernel(args.write)
+    ff, fw = _copy_factor(fetch), _copy_factor(write)
+    out = [f"# {args.title}", "", "Commands (from the repository root, on one MI355X):", ""]
+    out += ["    " + c for c in args.command]
+    out += ["", f"Calibration: the 4 GiB device-to-device copy reads {COPY_BYTES} bytes and writes "
+                f"{COPY_BYTES}; its FETCH_SIZE reading x {ff:.4f} and its WRITE_SIZE reading x {fw:.4f} "
+                "give those sizes, and every kernel's readings are scaled by the same factors.", "",
+            "| kernel | role | dispatches | HBM read GB / launch | HBM written GB / launch |",
+            "|---|---|---:|---:|---:|"]
+    machine = []
+    for nm in sorted(fetch, key=lambda k: -sum(fetch[k]) / len(fetch[k])):
+        rl = role(nm)
+        if rl is None:
+            continue
+        rd = ff * sum(fetch[nm]) / len(fetch[nm])
+        wr = fw * sum(write.get(nm, [0.0])) / max(1, len(write.get(nm, [])))
+        out.append(f"| `{short(nm)}` | {rl} ({precision(nm)}) | {len(fetch[nm])} | {rd / 1e9:.3f} | "
+                   f"{wr / 1e9:.3f} |")
+        machine.append(f"traffic {key(nm)} {rd + wr:.6e}")
+    out += ["", "Machine-readable lines (bytes per launch, read + written; sources digest of the "
+                "3D kernel headers and build flags the counters were taken with):", ""]
+    out += ["    " + m for m in machine]
+    out += [f"    sources {sources_digest()}"]
+    if args.note:
+        out += ["", args.note]
+    with open(args.out, "w") as f:
+        f.write("\n".join(out) + "\n")
+
+
+def read_traffic(md_path, prec, nx, kernel):
+    """Bytes per launch recorded for the kernel (precision "double" / "float",
+    x extent, role), or None when the file is missing or the kernel sources
+    changed since it was written."""
+    if not os.path.exists(md_path):
+        return None
+    val, src = None, None
+    want = f"{prec}:{nx}:{kernel}"
+    for line in open(md_path):
+        p = line.split()
+        if len(p) == 3 and p[0] == "traffic" and p[1] == want:
+            val = float(p[2])
+        if len(p) == 2 and p[0] == "sources":
+            src = p[1]
+    return val if src == sources_digest() else None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("csv")
+    s.add_argument("out")
+    s.add_argument("--command", required=True)
+    s.add_argument("--title", default="Kernel trace")
+    s.add_argument("--note", default="")
+    c = sub.add_parser("counters")
+    c.add_argument("fetch")
+    c.add_argument("write")
+    c.add_argument("out")
+    c.add_argument("--command", action="append", required=True)
+    c.add_argument("--title", default="HBM traffic counters")
+    c.add_argument("--note", default="")
+    a = ap.parse_args()
+    (cmd_stats if a.cmd == "stats" else cmd_counters)(a)
+
+
+if __name__ == "__main__":
+    main()
