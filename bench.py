@@ -24,15 +24,18 @@ PEAK_HBM = 8.0e12  # MI355X HBM3E, bytes/s
 COUNTERS_MD = os.path.join(ROOT, "profiles", "lap2_full_fp64_32_fp32_48_hbm_counters.md")
 
 
-def algorithmic_bytes(kernel, S, nst, depth):
+def algorithmic_bytes(kernel, S, nst, depth, fused=False):
     """Bytes a launch of each kernel must move for nst states of S bytes
-    (its inputs read once and outputs written once)."""
+    (its inputs read once and outputs written once).  fused: the quasi-1D
+    kernel set, whose F / CORR / FULL passes take D2z phi themselves (no T)."""
     table = {
         "dens": 1, "lap1": 2, "lap2_corr": 4, "lap2_f": 3, "lap2_h": 3,
         "lap2_full": 2 + (depth - 1) + 3,   # phi, T, f_{k-1..k-D+1}; f_k, p, c
         "pred": 1 + depth + 2,              # phi, f_{k-1..k-D}; p, c
         "lap2_taylor": 4, "norm": 1,
     }
+    if fused:
+        table.update({"lap2_corr": 3, "lap2_f": 2, "lap2_full": 1 + (depth - 1) + 3})
     return table[kernel] * S * nst if kernel in table else None
 
 
@@ -116,7 +119,7 @@ def run_q1d(steps, warmup, seed=7, profile_steps=2):
         for k, (n, ms) in stats.items():
             if n == 0:
                 continue
-            b = algorithmic_bytes(k, S, nst, 4)
+            b = algorithmic_bytes(k, S, nst, 4, fused=True)
             avg = ms / n
             kern[k] = dict(launches=n, avg_ms=avg, total_ms=ms, gbps=(b / (avg * 1e-3) / 1e9) if b else None)
     st, chk = ctx.check()

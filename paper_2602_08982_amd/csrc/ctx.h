@@ -83,6 +83,10 @@ struct Engine {
   virtual bool producer_kinetic() const { return false; }
   // h slots that hold partials of the unscaled state
   virtual int raw_h_slots() const { return 0; }
+  // true when lap2 in the F / CORR / FULL modes takes <H>_n of its input
+  // itself (the whole state in one workgroup): those evaluations then need
+  // the fields only, no lap1 and no shift
+  virtual bool self_shift() const { return false; }
   // choose launch shapes by timing them on the loaded states; returns the
   // number of kernel classes tuned (0: this kernel set has no choices)
   virtual int autotune(Ctx& c, int32_t* out, double* ms_out) { (void)c; (void)out; (void)ms_out; return 0; }

@@ -203,57 +203,110 @@ __global__ __launch_bounds__(TB) void q_lap1(const cpx<R>* __restrict__ X, int64
   if (live && a == 0 && h_part) h_part[n * h_stride + 1] = t;
 }
 
-// lap2: pointwise H from T and the integrator modes (see k_lap2)
+// lap2: H phi and the integrator modes (see k_lap2).  A state fits one lane
+// group, so F / CORR / FULL take the whole H phi in one pass: D2z of u and v
+// by the four-step DFT, then <H>_n = Re <phi|H phi> dz over the group (the
+// states are normalised by their scale), then f = -i (H - <H>_n) phi and the
+// integrator arithmetic; no intermediate T and no separate <H>_n pass.  H and
+// TAYLOR read D2z phi from T and the given shift (the Taylor terms use the
+// <H>_n of the state the operator was built from, not their own).
 template <typename R, int A, int TB, int MODE, int NP = 4, int NQ = 5>
 __global__ __launch_bounds__(TB) void q_lap2(Lap2Args<R> P, int64_t nstates, const double* __restrict__ kperp2,
                                              const cpx<R>* __restrict__ tw, double kz2) {
   constexpr int HD = (NP > NQ - 1) ? NP : NQ - 1;
   using CFG = Q1DCfg<R, A, TB>;
   constexpr int N = CFG::N, WS = CFG::WS;
-  // CORR / FULL leave the z kinetic part of <H> of the state they write
-  constexpr bool KIN = MODE == L2_CORR || MODE == L2_FULL;
-  __shared__ cpx<R> lds_all[KIN ? WS : 1][KIN ? A * CFG::PAD : 1];
+  constexpr bool SELF = MODE == L2_F || MODE == L2_CORR || MODE == L2_FULL;
+  __shared__ cpx<R> lds_all[SELF ? WS : 1][SELF ? A * CFG::PAD : 1];
   const int tid = threadIdx.x, grp = tid / A, a = tid % A;
   const int64_t n0 = int64_t(blockIdx.x) * WS + grp;
   const bool live = n0 < nstates;
-  if (!KIN && !live) return;  // no barriers in these modes
+  if (!SELF && !live) return;  // no barriers in these modes
   const int64_t n = live ? n0 : 0;
-  cpx<R> wu_[KIN ? A : 1], wv_[KIN ? A : 1];
   const R s = P.scale ? R(P.scale[n]) : R(1);
-  const R h = P.hshift ? R(P.hshift[n]) : R(0);
   const R hk = R(0.5 * kperp2[n]);
   const int64_t so = n * 2 * N;
+  // phi and D2z phi of this lane's sites
+  cpx<R> u[A], v[A], Hu[A], Hv[A];
+#pragma unroll
+  for (int b = 0; b < A; ++b) {
+    const int z = a + A * b;
+    u[b] = s * P.X[so + z];
+    v[b] = s * P.X[so + N + z];
+  }
+  if constexpr (SELF) {
+    const R f = R(-kz2 / double(N));
+    auto d2 = [&](cpx<R>(&w)[A]) {
+      q_fwd<R, A>(w, a, lds_all[grp], tw);
+      sfor<0, A>::run([&](auto pc) {
+        constexpr int p = decltype(pc)::value;
+        const int m = q_wavenum<A>(a, freq_of_pos<A>(p));
+        w[p] = (f * R(m * m)) * w[p];
+      });
+      q_inv<R, A>(w, a, lds_all[grp], tw);
+    };
+#pragma unroll
+    for (int b = 0; b < A; ++b) {
+      Hu[b] = u[b];
+      Hv[b] = v[b];
+    }
+    d2(Hu);
+    d2(Hv);
+  } else {
+#pragma unroll
+    for (int b = 0; b < A; ++b) {
+      Hu[b] = P.T[so + a + A * b];
+      Hv[b] = P.T[so + N + a + A * b];
+    }
+  }
+  double hloc = 0.0;
+#pragma unroll
+  for (int b = 0; b < A; ++b) {
+    const int z = a + A * b;
+    const R fa = P.hA[z] + hk;
+    const cpx<R> D = P.hD[z];
+    const cpx<R> lu = Hu[b], lv = Hv[b];
+    Hu[b] = R(-0.5) * lu + fa * u[b] + D * v[b];
+    Hv[b] = conj(D) * u[b] + R(0.5) * lv - fa * v[b];
+    if constexpr (SELF)
+      hloc += double(u[b].x) * double(Hu[b].x) + double(u[b].y) * double(Hu[b].y) +
+              double(v[b].x) * double(Hv[b].x) + double(v[b].y) * double(Hv[b].y);
+  }
+  R h;
+  if constexpr (SELF) {
+#pragma unroll
+    for (int o = A / 2; o > 0; o >>= 1) hloc += __shfl_xor(hloc, o, A);
+    h = R(__shfl(hloc, 0, A) * P.dV);  // every lane of the group takes lane 0's sum
+  } else {
+    h = P.hshift ? R(P.hshift[n]) : R(0);
+  }
   double nacc = 0.0;
 #pragma unroll
   for (int b = 0; b < A; ++b) {
     const int z = a + A * b;
     const int64_t iu = so + z, iv = so + N + z;
-    const cpx<R> u = s * P.X[iu], v = s * P.X[iv];
-    const cpx<R> lu = P.T[iu], lv = P.T[iv];
-    const R fa = P.hA[z] + hk;
-    const cpx<R> D = P.hD[z];
-    const cpx<R> Hu = R(-0.5) * lu + fa * u + D * v;
-    const cpx<R> Hv = conj(D) * u + R(0.5) * lv - fa * v;
     if constexpr (MODE == L2_H) {
-      P.out[iu] = Hu;
-      P.out[iv] = Hv;
+      P.out[iu] = Hu[b];
+      P.out[iv] = Hv[b];
     } else {
-      const cpx<R> gu = Hu - h * u, gv = Hv - h * v;
+      const cpx<R> gu = Hu[b] - h * u[b], gv = Hv[b] - h * v[b];
       if constexpr (MODE == L2_TAYLOR) {
         const cpx<R> c{R(P.tay_re), R(P.tay_im)};
         const cpx<R> ou = c * gu, ov = c * gv;
         P.out[iu] = ou;
         P.out[iv] = ov;
-        const cpx<R> su = P.init_acc ? u + ou : P.acc[iu] + ou;
-        const cpx<R> sv = P.init_acc ? v + ov : P.acc[iv] + ov;
+        const cpx<R> su = P.init_acc ? u[b] + ou : P.acc[iu] + ou;
+        const cpx<R> sv = P.init_acc ? v[b] + ov : P.acc[iv] + ov;
         P.acc[iu] = su;
         P.acc[iv] = sv;
         nacc += norm2(su) + norm2(sv);
       } else {
         const cpx<R> fu{gu.y, -gu.x}, fv{gv.y, -gv.x};
         if constexpr (MODE == L2_F) {
-          P.out[iu] = fu;
-          P.out[iv] = fv;
+          if (live) {
+            P.out[iu] = fu;
+            P.out[iv] = fv;
+          }
         } else if constexpr (MODE == L2_CORR) {
           const R a0 = R(P.a[0]);
           const cpx<R> nu_ = P.hist[0][iu] + a0 * fu, nv_ = P.hist[0][iv] + a0 * fv;
@@ -262,13 +315,9 @@ __global__ __launch_bounds__(TB) void q_lap2(Lap2Args<R> P, int64_t nstates, con
             P.Xout[iv] = nv_;
           }
           nacc += norm2(nu_) + norm2(nv_);
-          if constexpr (KIN) {
-            wu_[b] = nu_;
-            wv_[b] = nv_;
-          }
         } else {  // L2_FULL
-          cpx<R> pu = u + R(P.b[0]) * fu, pv = v + R(P.b[0]) * fv;
-          cpx<R> cu = u + R(P.a[1]) * fu, cv = v + R(P.a[1]) * fv;
+          cpx<R> pu = u[b] + R(P.b[0]) * fu, pv = v[b] + R(P.b[0]) * fv;
+          cpx<R> cu = u[b] + R(P.a[1]) * fu, cv = v[b] + R(P.a[1]) * fv;
           sfor<1, HD>::run([&](auto jc) {
             constexpr int j = decltype(jc)::value;
             const cpx<R> hu = P.hist[j][iu], hv = P.hist[j][iv];
@@ -290,30 +339,9 @@ __global__ __launch_bounds__(TB) void q_lap2(Lap2Args<R> P, int64_t nstates, con
             P.cout[iv] = cv;
           }
           nacc += norm2(pu) + norm2(pv);
-          if constexpr (KIN) {
-            wu_[b] = pu;
-            wv_[b] = pv;
-          }
         }
       }
     }
-  }
-  if constexpr (KIN) {
-    // sum_k k^2 |phi_k|^2 of the written (unscaled) u and v lines
-    cpx<R>* lds = lds_all[grp];
-    q_fwd<R, A>(wu_, a, lds, tw);
-    q_fwd<R, A>(wv_, a, lds, tw);
-    double ku = 0.0, kv = 0.0;
-    sfor<0, A>::run([&](auto pc) {
-      constexpr int p = decltype(pc)::value;
-      const int m = q_wavenum<A>(a, freq_of_pos<A>(p));
-      ku += double(m * m) * norm2(wu_[p]);
-      kv += double(m * m) * norm2(wv_[p]);
-    });
-    double kin = 0.5 * (ku - kv) * kz2 / double(N) * P.dV;
-#pragma unroll
-    for (int o = A / 2; o > 0; o >>= 1) kin += __shfl_xor(kin, o, A);
-    if (live && a == 0) P.h_part[n * P.h_stride + 0] = kin;
   }
   if (P.nrm_part) {
 #pragma unroll
@@ -490,7 +518,8 @@ struct EngineQ1D final : Engine {
     });
     c.nsg_used = int(cdiv(nst, DGQ));
   }
-  bool producer_kinetic() const override { return true; }
+  bool producer_kinetic() const override { return false; }
+  bool self_shift() const override { return true; }
   int raw_h_slots() const override { return 1; }
   void reduce_pot(Ctx& c, bool update) override {
     FunParams fp{c.fun.functional, c.fun.B, c.fun.C, c.fun.inv_g_bdg, c.fun.mu, c.ainv};
@@ -654,9 +683,9 @@ struct EngineQ1D final : Engine {
         } else if (k == 1) {
           ms = timeit([&] { lap1(c, c.sb[b], c.sscale[b], true, c.nst); });
         } else if (k == 2) {
-          // the corrector form (with its kinetic tail), writing into T only:
-          // T serves as input, partial corrector and output; each thread
-          // reads then writes its own sites
+          // the corrector form (H phi, <H>_n and the corrector in one
+          // pass), writing into T only: T serves as partial corrector and
+          // output; each thread reads then writes its own sites
           L2Desc d;
           d.mode = L2_CORR;
           d.X = c.sb[b];

@@ -6,7 +6,9 @@
 // normalisation scale) and hist[0..D-1] (f_{k-1}, ..., f_{k-D}).  One ABM
 // step is two right-hand-side evaluations, each
 //     dens -> reduce_pot -> lap1 -> finalize(<H>) -> lap2(mode),
-// where lap2 fuses H.psi, the <H>_n shift and the integrator arithmetic
+// (dens -> reduce_pot -> lap2 where a state fits one workgroup and lap2
+// takes <H>_n itself), where lap2 fuses H.psi, the shift and the integrator
+// arithmetic
 // (Alg. AB4AM5: the corrector after the first evaluation, the next step's
 // predictor and partial corrector after the second).
 #include <hip/hip_runtime.h>
@@ -103,6 +105,18 @@ void prepare(Ctx& c, int b) {
   c.eng->reduce_pot(c, !c.frozen);
   c.eng->lap1(c, c.sb[b], c.sscale[b], true, c.nst);
   fin(c, c.nst, c.sscale[b], false, true);
+  c.fields_valid = true;
+}
+
+// what an F / CORR / FULL evaluation of buffer b needs: the fields, and the
+// shift unless the engine's lap2 takes it itself
+void prepare_eval(Ctx& c, int b) {
+  if (!c.eng->self_shift()) {
+    prepare(c, b);
+    return;
+  }
+  c.eng->dens_sum(c, c.sb[b], c.sscale[b], c.nst);
+  c.eng->reduce_pot(c, !c.frozen);
   c.fields_valid = true;
 }
 
@@ -236,7 +250,7 @@ void abm(Ctx& c, int64_t nsteps) {
   }
   for (int64_t s = 0; s < nsteps; ++s) {
     // evaluation at the predicted state; corrector
-    prepare(c, c.phi);
+    prepare_eval(c, c.phi);
     {
       L2Desc d;
       d.mode = L2_CORR;
@@ -258,7 +272,7 @@ void abm(Ctx& c, int64_t nsteps) {
       c.hist[0] = freed;
     }
     // evaluation at the corrected state
-    prepare(c, c.phi);
+    prepare_eval(c, c.phi);
     L2Desc d;
     d.X = c.sb[c.phi];
     d.T = c.T;
