@@ -134,7 +134,9 @@ def experiment(cfg, train_seeds, test_seeds, epochs=300, log=None):
     N_req = required_n(cfg, fun)
     t0 = time.perf_counter()
     V, U, D, MU, it_train = [], [], [], [], []
-    for s in train_seeds:
+    for i, s in enumerate(train_seeds):
+        if log and i and i % 10 == 0:
+            log(f"training solves: {i} of {len(train_seeds)} ({time.perf_counter() - t0:.0f} s)")
         v = vext(cfg, s)
         r = solve(cfg, fun, N_req, v, plain_start(cfg, fun))
         if not r["converged"]:
@@ -154,7 +156,9 @@ def experiment(cfg, train_seeds, test_seeds, epochs=300, log=None):
     if log:
         log(f"fit: {fit['steps']} Adam steps in {t_fit:.1f} s, loss {fit['first_loss']:.3g} -> {fit['final_loss']:.3g}")
     plain_it, warm_it, fallbacks, warm_s, plain_s = [], [], 0, 0.0, 0.0
-    for s in test_seeds:
+    for i, s in enumerate(test_seeds):
+        if log and i and i % 5 == 0:
+            log(f"held-out seeds: {i} of {len(test_seeds)}")
         v = vext(cfg, s)
         p = solve(cfg, fun, N_req, v, plain_start(cfg, fun))
         Uw, Dw, muw = ws.predict(v[None])
