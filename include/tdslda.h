@@ -94,7 +94,9 @@ typedef struct {
  * device buffers: (history depth + 1) state buffers plus one intermediate
  * buffer (the x-derivative of every state), per-state scalars and the FP64
  * fields.  Supported shapes: cubic N^3 with N in {4,6,8,12,16,24,32,48},
- * 8x8x16 (3D); N_z in {16,32,64,128,256} (Q1D).  Errors: EINVAL, ENOMEM. */
+ * 8x8x16 (3D); N_z in {16,64,256} (Q1D: N_z = A^2 with A lanes per state).
+ * The quasi-1D F / CORR / FULL evaluations do not use the intermediate
+ * buffer.  Errors: EINVAL (including an unsupported shape), ENOMEM. */
 tdslda_status tdslda_create(const tdslda_lattice* lat, const tdslda_functional* fun,
                             const tdslda_run* run, int64_t capacity, tdslda_ctx** out);
 tdslda_status tdslda_destroy(tdslda_ctx* ctx);
