@@ -42,9 +42,16 @@ def role(name):
         return LAP2_MODES[int(m.group(2))]
     m = re.search(r"k_pointwise<(\w+), \d+, \d+, \d+, (\d)", name)
     if m:
-        return PW_MODES[int(m.group(2))]
+        return PW_MODES.get(int(m.group(2)), "scale")
+    m = re.search(r"q_lap2<\w+, \d+, \d+, (\d)", name)
+    if m:
+        return "q1d_" + LAP2_MODES[int(m.group(1))]
+    m = re.search(r"q_pointwise<\w+, \d+, \d+, (\d)", name)
+    if m:
+        return "q1d_" + PW_MODES.get(int(m.group(1)), "scale")
     for pat, r in (("k_lap1<", "lap1"), ("k_dens_sum<", "dens"), ("k_dens<", "dens_kin"),
-                   ("k_reduce_pot", "reduce_pot"), ("k_finalize", "finalize")):
+                   ("k_reduce_pot", "reduce_pot"), ("k_finalize", "finalize"), ("q_lap1<", "q1d_lap1"),
+                   ("q_dens<", "q1d_dens_kin")):
         if pat in name:
             return r
     return None
@@ -62,7 +69,7 @@ def key(name):
     if rl is None:
         return None
     m = re.search(r"<(?:double|float), (\d+)", name)
-    nx = m.group(1) if m and rl not in ("dens", "dens_kin", "reduce_pot", "finalize") else "-"
+    nx = m.group(1) if m and rl not in ("dens", "reduce_pot", "finalize") else "-"
     return f"{precision(name)}:{nx}:{rl}"
 
 
@@ -76,12 +83,23 @@ def cmd_stats(args):
     out = [f"# {args.title}", "", "Command (from the repository root, on one MI355X):", "",
            "    " + args.command, "", "| kernel | role | calls | total ms | avg ms | % |",
            "|---|---|---:|---:|---:|---:|"]
+    # every kernel of the path (those with a role), and the others down to
+    # the args.others-th by total time
+    others, skipped, skipped_ms = 0, 0, 0.0
     for r in rows:
         nm = r["Name"]
         rl = role(nm)
+        if rl is None:
+            others += 1
+            if others > args.others:
+                skipped += 1
+                skipped_ms += int(r["TotalDurationNs"]) / 1e6
+                continue
         rl = f"{rl} ({precision(nm)})" if rl else ""
         out.append(f"| `{short(nm)}` | {rl} | {r['Calls']} | {int(r['TotalDurationNs']) / 1e6:.3f} | "
                    f"{float(r['AverageNs']) / 1e6:.3f} | {r['Percentage']} |")
+    if skipped:
+        out += ["", f"{skipped} further kernels outside the path ({skipped_ms:.1f} ms in total) are not listed."]
     if args.note:
         out += ["", args.note]
     with open(args.out, "w") as f:
@@ -158,6 +176,7 @@ def main():
     s.add_argument("--command", required=True)
     s.add_argument("--title", default="Kernel trace")
     s.add_argument("--note", default="")
+    s.add_argument("--others", type=int, default=12, help="kernels outside the path to list")
     c = sub.add_parser("counters")
     c.add_argument("fetch")
     c.add_argument("write")
