@@ -8,7 +8,8 @@ same BdG problem, so the N_z/2 + 1 distinct |k_z| are diagonalised once and
 weighted by their multiplicity (1 for m = 0 and m = -N_z/2, 2 otherwise).
 
 The map K of Alg. MapK (H -> eigenpairs -> densities -> potentials), the
-linear mixing of the potentials, the fixed-N chemical-potential update of
+linear and modified Broyden mixing of the potentials, the fixed-N
+chemical-potential update of
 Eq. update-mu and the convergence test (residual of the potentials and of
 N; readings in the design notes) are written out plainly: dense matrices,
 numpy.linalg.eigh, FP64.
@@ -77,15 +78,62 @@ def map_k(geom, fun, vext, U, delta, mu, ec):
     return Uo, Do, rho, nu, N
 
 
+class Broyden:
+    """Modified Broyden mixing of a real vector p (the Broyden option of
+    Sec. 3.2, which follows the variant for strongly interacting systems of
+    Baran et al., Phys. Rev. C 78, 014318 (2008), built on Johnson's
+    modified method).  With F_i = K[p_i] - p_i and the last m normalised
+    differences dF_k = (F_{k+1} - F_k) / |F_{k+1} - F_k|,
+    dp_k = (p_{k+1} - p_k) / |F_{k+1} - F_k|:
+        a_kl  = w0^2 delta_kl + dF_k . dF_l      (weights w_k = 1)
+        gamma = a^{-1} c,  c_k = dF_k . F_i
+        p_{i+1} = p_i + m_p F_i - sum_l gamma_l (m_p dF_l + dp_l).
+    m = 0 is linear mixing.  With w0 -> 0 and m >= the dimension this is
+    Anderson mixing, which on a linear map reaches the fixed point in at most
+    dim + 1 steps (its iterates are GMRES's)."""
+
+    def __init__(self, m, mix, w0=0.01):
+        self.m, self.mix, self.w0 = int(m), float(mix), float(w0)
+        self.dF, self.dp = [], []
+        self.prev = None
+
+    def step(self, p, Kp):
+        p = np.asarray(p, float)
+        F = np.asarray(Kp, float) - p
+        if self.m > 0 and self.prev is not None:
+            p0, F0 = self.prev
+            dF = F - F0
+            n = np.linalg.norm(dF)
+            self.dF.append(dF / n)
+            self.dp.append((p - p0) / n)
+            if len(self.dF) > self.m:
+                self.dF.pop(0)
+                self.dp.pop(0)
+        self.prev = (p, F)
+        out = p + self.mix * F
+        if self.m > 0 and self.dF:
+            DF = np.array(self.dF)
+            a = self.w0 ** 2 * np.eye(len(self.dF)) + DF @ DF.T
+            gamma = np.linalg.solve(a, DF @ F)
+            for g, dF, dp in zip(gamma, self.dF, self.dp):
+                out = out - g * (self.mix * dF + dp)
+        return out
+
+
 def solve(geom, fun, vext, U, delta, mu, ec, mix=0.5, a_mu=0.5, N_req=None, tol=1e-8, eF_ref=0.5,
-          maxit=500, history=None):
-    """Linear mixing p_{n+1} = m K[p_n] + (1 - m) p_n on p = (U, Delta); in
-    fixed-N mode (N_req given) mu follows Eq. update-mu each iteration.
-    Converged when max(|U_out - U_in|_inf, |Delta_out - Delta_in|_inf) /
-    eF_ref < tol and (fixed N) |N - N_req| / N_req < tol.  Returns
-    (U, Delta, mu, iterations, converged)."""
+          maxit=500, history=None, broyden=0, w0=0.01):
+    """Iterate p = (U, Delta) to the fixed point of K: linear mixing
+    p_{n+1} = m K[p_n] + (1 - m) p_n (broyden = 0) or the modified Broyden
+    mixing above with the last `broyden` differences.  In fixed-N mode
+    (N_req given) Eq. update-mu is a step of K: with linear mixing mu takes
+    its output unmixed; with Broyden mixing mu is a component of p.  Converged when
+    max(|U_out - U_in|_inf, |Delta_out - Delta_in|_inf) / eF_ref < tol and
+    (fixed N) |N - N_req| / N_req < tol.  Returns (U, Delta, mu, iterations,
+    converged)."""
     U = np.array(U, float)
     delta = np.array(delta, complex)
+    mixer = Broyden(broyden, mix, w0)
+    n = U.size
     for it in range(1, maxit + 1):
         Uo, Do, rho, nu, N = map_k(geom, fun, vext, U, delta, mu, ec)
         r = max(np.abs(Uo - U).max(), np.abs(Do - delta).max()) / eF_ref
@@ -94,8 +142,17 @@ def solve(geom, fun, vext, U, delta, mu, ec, mix=0.5, a_mu=0.5, N_req=None, tol=
             history.append((r, rn, mu, N))
         if r < tol and rn < tol:
             return Uo, Do, mu, it, True
-        U = mix * Uo + (1.0 - mix) * U
-        delta = mix * Do + (1.0 - mix) * delta
-        if N_req is not None:
-            mu = mu + a_mu / N_req * (N_req - N)
+        mu_out = mu if N_req is None else mu + a_mu / N_req * (N_req - N)
+        if broyden:
+            # mu is part of p here: Eq. update-mu is the last step of K
+            p = np.concatenate([U.ravel(), delta.real.ravel(), delta.imag.ravel(), [mu]])
+            Kp = np.concatenate([np.ravel(Uo), np.real(Do).ravel(), np.imag(Do).ravel(), [mu_out]])
+            q = mixer.step(p, Kp)
+            U = q[:n].reshape(U.shape)
+            delta = (q[n:2 * n] + 1j * q[2 * n:3 * n]).reshape(U.shape)
+            mu = q[3 * n]
+        else:
+            U = mix * Uo + (1.0 - mix) * U
+            delta = mix * Do + (1.0 - mix) * delta
+            mu = mu_out
     return U, delta, mu, maxit, False

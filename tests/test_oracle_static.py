@@ -73,3 +73,54 @@ def test_fixed_n_solve_with_obstacle():
     Uo, Do, rho, nu, N = ST.map_k(g, FUN, vext, U, D, mu, EC)
     assert abs(N - N_req) / N_req < 1e-7
     assert np.abs(Uo - U).max() < 1e-7 and np.abs(Do - D).max() < 1e-7
+
+
+def test_broyden_terminates_on_linear_maps():
+    """The modified Broyden mixing with w0 -> 0 and a history as long as the
+    dimension is Anderson mixing, whose iterates on a linear map p -> A p + b
+    reach the fixed point in at most dim + 1 steps (they are GMRES's): the
+    error is still > 1e-5 after dim steps and < 1e-9 after dim + 1, for two
+    mixing parameters; linear mixing is far from converged by then.  With no
+    history the step is linear mixing exactly."""
+    rng = np.random.default_rng(0)
+    n = 10
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    A = Q @ np.diag(rng.uniform(-0.9, 0.9, n)) @ Q.T + 0.05 * rng.standard_normal((n, n))
+    b = rng.standard_normal(n)
+    ps = np.linalg.solve(np.eye(n) - A, b)
+    for mix in (0.5, 1.0):
+        B = ST.Broyden(n, mix, w0=1e-10)
+        p = np.zeros(n)
+        errs = []
+        for _ in range(n + 1):
+            p = B.step(p, A @ p + b)
+            errs.append(np.linalg.norm(p - ps) / np.linalg.norm(ps))
+        assert errs[n - 1] > 1e-5 and errs[n] < 1e-9, errs
+        q = np.zeros(n)
+        for _ in range(n + 1):
+            q = q + mix * (A @ q + b - q)
+        assert np.linalg.norm(q - ps) / np.linalg.norm(ps) > 1e-2
+    B0 = ST.Broyden(0, 0.3)
+    p, Kp = rng.standard_normal(n), rng.standard_normal(n)
+    for _ in range(3):
+        assert np.array_equal(B0.step(p, Kp), p + 0.3 * (Kp - p))
+
+
+def test_broyden_solve_reaches_the_linear_mixing_fixed_point():
+    """Fixed-N solve with a trap and an obstacle: modified Broyden mixing
+    (history 8) converges to the same potentials, mu and N as linear mixing
+    (both to r < 1e-10) in fewer iterations."""
+    g = ST.GeometryQ2D(8, 8, 4)
+    X, Y = g.coords()
+    amp, wid, cen = synth.obstacles(5, 8.0)
+    trap = 0.5 * 0.4 ** 2 * (X ** 2 + Y ** 2)
+    vext = trap + amp[0] * 0.5 * np.exp(
+        -((X - cen[0, 0] / 4) ** 2 + (Y - cen[0, 1] / 4) ** 2) / (2 * (wid[0] / 4) ** 2))
+    U0, D0 = np.full(g.shape, -0.2), np.full(g.shape, 0.25)
+    _, _, _, _, N_req = ST.map_k(g, FUN, trap, U0, D0, 1.0, EC)
+    kw = dict(mix=0.5, a_mu=0.5, N_req=N_req, tol=1e-10, maxit=800)
+    Ul, Dl, mul, itl, okl = ST.solve(g, FUN, vext, U0, D0, 0.8, EC, **kw)
+    Ub, Db, mub, itb, okb = ST.solve(g, FUN, vext, U0, D0, 0.8, EC, broyden=8, **kw)
+    assert okl and okb
+    assert itb < itl, (itb, itl)
+    assert np.abs(Ub - Ul).max() < 1e-8 and np.abs(Db - Dl).max() < 1e-8 and abs(mub - mul) < 1e-8
