@@ -294,6 +294,9 @@ def main():
                              log=lambda m: print("# warm start: " + m, file=sys.stderr, flush=True))
         print(f"# warm start: {warm['warm_iters_mean']:.1f} vs plain {warm['plain_iters_mean']:.1f} iterations "
               f"to r < 1e-8 ({warm['n_test']} held-out seeds)", file=sys.stderr, flush=True)
+        if warm.get("broyden"):
+            print(f"# Broyden mixing: warm {warm['warm_broyden_iters_mean']:.1f} vs plain "
+                  f"{warm['plain_broyden_iters_mean']:.1f} iterations", file=sys.stderr, flush=True)
     cpu = None if args.no_cpu else cpu_baseline()
 
     line = {
@@ -338,9 +341,11 @@ def main():
     if warm is not None:
         line["learned_warm_start"] = {
             "workload": f"static quasi-2D solve, {warm['lattice'][0]}x{warm['lattice'][1]} x-y lattice, "
-                        f"{warm['lattice'][2]} k_z modes, trap + 1-4 obstacles, fixed N, linear mixing 0.5",
+                        f"{warm['lattice'][2]} k_z modes, trap + 1-4 obstacles, fixed N, linear mixing 0.5 "
+                        f"(and modified Broyden mixing, history {warm.get('broyden', 0)})",
             "metric": "mixing iterations to r < 1e-8, mean over held-out seeds",
             "warm": warm["warm_iters_mean"], "plain": warm["plain_iters_mean"], "fallbacks": warm["fallbacks"],
+            "warm_broyden": warm.get("warm_broyden_iters_mean"), "plain_broyden": warm.get("plain_broyden_iters_mean"),
             "n_train": warm["n_train"], "n_test": warm["n_test"],
             "seconds_per_iteration": warm["seconds_per_iteration"],
             "train_data_seconds": warm["train_data_seconds"], "fit_seconds": warm["fit_seconds"],

@@ -209,11 +209,19 @@ tdslda_status tdslda_q1d_load_static(tdslda_ctx* ctx, int nprob, const double* k
  * matrices of order 2 nx ny, one batched rocSOLVER call) with multiplicity
  * weights.  T = 0: every E > 0 eigenpair is occupied.  The map K returns the
  * potentials of the SLDA (A = 1) or BdG functional with the regulator
- * Lambda_c(V_+ = V_ext + U_in, mu, ec).  Iteration: linear mixing of (U,
- * Delta) with parameter mix; fixed-N mode when a_mu != 0 (Eq. update-mu with
- * N = int rho_+ d^3r); converged when max(|U_out - U_in|_inf,
- * |Delta_out - Delta_in|_inf) / eF_ref < tol and |N - N_req| / N_req < tol.
- * Delta is real.  All arrays are host FP64 [nx*ny], flat index ix*ny + iy. */
+ * Lambda_c(V_+ = V_ext + U_in, mu, ec).  Fixed-N mode when a_mu != 0
+ * (Eq. update-mu, with N = int rho_+ d^3r, is the last step of K).
+ * Iteration (Sec. 3.2, the two mixing methods):
+ *   broyden = 0: linear mixing of (U, Delta) with parameter mix; mu takes
+ *     the update-mu output unmixed;
+ *   broyden = m > 0: modified Broyden mixing (the variant the paper cites,
+ *     Baran et al., Phys. Rev. C 78, 014318) of p = (U, Delta, mu) with the
+ *     last m normalised differences of p and of F = K[p] - p, weights 1 and
+ *     w0:  a = w0^2 I + dF dF^T,  gamma = a^-1 (dF . F),
+ *     p_new = p + mix F - sum_l gamma_l (mix dF_l + dp_l);  m <= 8.
+ * Converged when max(|U_out - U_in|_inf, |Delta_out - Delta_in|_inf) /
+ * eF_ref < tol and |N - N_req| / N_req < tol.  Delta is real.  All arrays
+ * are host FP64 [nx*ny], flat index ix*ny + iy. */
 typedef struct {
   int nx, ny, nz;
   double dx, dy, dz;
@@ -224,6 +232,8 @@ typedef struct {
   double tol;    /* residual threshold */
   double eF_ref; /* Fermi energy of the reference uniform system */
   int maxit;
+  int broyden;   /* history length of the Broyden mixing (0..8); 0 = linear mixing */
+  double w0;     /* Broyden regularisation weight (e.g. 0.01) */
 } tdslda_static;
 
 /* One application of K at (U, delta, mu): U_out, delta_out, rho (per spin),

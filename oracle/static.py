@@ -104,8 +104,9 @@ class Broyden:
             p0, F0 = self.prev
             dF = F - F0
             n = np.linalg.norm(dF)
-            self.dF.append(dF / n)
-            self.dp.append((p - p0) / n)
+            inv = 1.0 / n if n > 0 else 0.0  # an unchanged residual: a zero row (gamma 0)
+            self.dF.append(dF * inv)
+            self.dp.append((p - p0) * inv)
             if len(self.dF) > self.m:
                 self.dF.pop(0)
                 self.dp.pop(0)

@@ -167,6 +167,147 @@ __global__ void k_st_mix(int M, double m, const double* __restrict__ Uo, const d
 }
 namespace {
 
+// Modified Broyden mixing step (one workgroup) on p = (U, Delta, mu) of
+// length L = 2 M + 1, F = K[p] - p with K[p] = (U_out, Delta_out, mu_out).
+// History: rows dF[k], dp[k] (k < nh, ring order) of normalised differences;
+// when have_prev the difference to (pprev, Fprev) is written to row `slot`
+// first (a zero row when |F - Fprev| = 0).  Then
+//   a = w0^2 I + dF dF^T,  c = dF F,  gamma = a^-1 c (Cholesky, thread 0),
+//   p_new = p + mix F - sum_l gamma_l (mix dF_l + dp_l),
+// written over U, Delta; mu_new to out_mu.  Sums run in a fixed order.
+constexpr int kBroydenMax = 8;
+constexpr int kBTB = 1024;
+__global__ __launch_bounds__(kBTB) void k_st_broyden(int M, double* __restrict__ U, double* __restrict__ D,
+                                                     const double* __restrict__ Uo, const double* __restrict__ Do,
+                                                     double mu, double mu_out, double mix, double w0, int have_prev,
+                                                     int slot, int nh, double* __restrict__ pprev,
+                                                     double* __restrict__ Fprev, double* __restrict__ dF,
+                                                     double* __restrict__ dp, double* __restrict__ out_mu) {
+  constexpr int NS = kBroydenMax * (kBroydenMax + 1) / 2 + kBroydenMax;  // a (upper) and c
+  constexpr int NW = kBTB / 64;
+  __shared__ double red[NW][NS];
+  __shared__ double tot[NS];
+  __shared__ double gam[kBroydenMax];
+  const int t = threadIdx.x, L = 2 * M + 1;
+  auto pval = [&](int i) { return i < M ? U[i] : (i < 2 * M ? D[i - M] : mu); };
+  auto kval = [&](int i) { return i < M ? Uo[i] : (i < 2 * M ? Do[i - M] : mu_out); };
+  // block sum of one value per thread (fixed order), result in tot[0]
+  auto block_sum1 = [&](double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (t % 64 == 0) red[t / 64][0] = v;
+    __syncthreads();
+    if (t == 0) {
+      double s = 0.0;
+      for (int w = 0; w < NW; ++w) s += red[w][0];
+      tot[0] = s;
+    }
+    __syncthreads();
+    return tot[0];
+  };
+  if (have_prev) {
+    double n2 = 0.0;
+    for (int i = t; i < L; i += kBTB) {
+      const double p = pval(i), F = kval(i) - p;
+      const double df = F - Fprev[i];
+      dF[int64_t(slot) * L + i] = df;
+      dp[int64_t(slot) * L + i] = p - pprev[i];
+      n2 += df * df;
+    }
+    // an unchanged residual gives a zero row, which takes no part in the
+    // mixing (its gamma is 0)
+    const double nrm = sqrt(block_sum1(n2));
+    const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+    for (int i = t; i < L; i += kBTB) {
+      dF[int64_t(slot) * L + i] *= inv;
+      dp[int64_t(slot) * L + i] *= inv;
+    }
+    __syncthreads();
+  }
+  const int nk = nh;  // rows in use (ring order)
+  for (int i = t; i < L; i += kBTB) {
+    const double p = pval(i);
+    pprev[i] = p;
+    Fprev[i] = kval(i) - p;
+  }
+  __syncthreads();
+  double acc[NS];
+#pragma unroll
+  for (int q = 0; q < NS; ++q) acc[q] = 0.0;
+  for (int i = t; i < L; i += kBTB) {
+    const double F = Fprev[i];
+    double f[kBroydenMax];
+#pragma unroll
+    for (int k = 0; k < kBroydenMax; ++k) f[k] = k < nk ? dF[int64_t(k) * L + i] : 0.0;
+    int q = 0;
+#pragma unroll
+    for (int k = 0; k < kBroydenMax; ++k) {
+#pragma unroll
+      for (int l = k; l < kBroydenMax; ++l) acc[q++] += f[k] * f[l];
+      acc[kBroydenMax * (kBroydenMax + 1) / 2 + k] += f[k] * F;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NS; ++q) {
+    double v = acc[q];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (t % 64 == 0) red[t / 64][q] = v;
+  }
+  __syncthreads();
+  if (t < NS) {
+    double s = 0.0;
+    for (int w = 0; w < NW; ++w) s += red[w][t];
+    tot[t] = s;
+  }
+  __syncthreads();
+  if (t == 0) {
+    // a = w0^2 I + G (upper triangle packed row by row), Cholesky a = R^T R
+    double a[kBroydenMax][kBroydenMax], c[kBroydenMax];
+    int q = 0;
+    for (int k = 0; k < kBroydenMax; ++k)
+      for (int l = k; l < kBroydenMax; ++l) {
+        a[k][l] = a[l][k] = tot[q] + (k == l ? w0 * w0 : 0.0);
+        ++q;
+      }
+    for (int k = 0; k < kBroydenMax; ++k) c[k] = tot[kBroydenMax * (kBroydenMax + 1) / 2 + k];
+    for (int j = 0; j < nk; ++j) {
+      double d = a[j][j];
+      for (int k = 0; k < j; ++k) d -= a[k][j] * a[k][j];
+      d = sqrt(d);
+      a[j][j] = d;
+      for (int l = j + 1; l < nk; ++l) {
+        double v = a[j][l];
+        for (int k = 0; k < j; ++k) v -= a[k][j] * a[k][l];
+        a[j][l] = v / d;
+      }
+    }
+    double y[kBroydenMax];
+    for (int j = 0; j < nk; ++j) {  // R^T y = c
+      double v = c[j];
+      for (int k = 0; k < j; ++k) v -= a[k][j] * y[k];
+      y[j] = v / a[j][j];
+    }
+    for (int j = nk - 1; j >= 0; --j) {  // R gamma = y
+      double v = y[j];
+      for (int k = j + 1; k < nk; ++k) v -= a[j][k] * gam[k];
+      gam[j] = v / a[j][j];
+    }
+  }
+  __syncthreads();
+  for (int i = t; i < L; i += kBTB) {
+    const double F = Fprev[i];
+    double v = pprev[i] + mix * F;
+    for (int l = 0; l < nk; ++l) v -= gam[l] * (mix * dF[int64_t(l) * L + i] + dp[int64_t(l) * L + i]);
+    if (i < M)
+      U[i] = v;
+    else if (i < 2 * M)
+      D[i - M] = v;
+    else
+      *out_mu = v;
+  }
+}
+
 struct Handle {
   rocblas_handle h = nullptr;
   Handle() {
@@ -188,6 +329,8 @@ struct StaticSolver {
   double *H = nullptr, *Ev = nullptr, *Ew = nullptr, *kz2 = nullptr, *wc = nullptr, *d2x = nullptr, *d2y = nullptr;
   double *vext = nullptr, *U = nullptr, *D = nullptr, *Uo = nullptr, *Do = nullptr, *hf = nullptr;
   double *rho = nullptr, *nu = nullptr, *red = nullptr;
+  // Broyden mixing: previous p and F, history rows, new mu
+  double *pprev = nullptr, *Fprev = nullptr, *bdF = nullptr, *bdp = nullptr, *bmu = nullptr;
   int* bad = nullptr;
   rocblas_int* info = nullptr;
   Handle rb;
@@ -217,6 +360,8 @@ struct StaticSolver {
     require(s.dx > 0 && s.dy > 0 && s.dz > 0 && s.ec > 0 && s.mix > 0 && s.mix <= 1, TDSLDA_EINVAL,
             "bad static solver parameters");
     require(f.functional == TDSLDA_FUNC_SLDA || f.functional == TDSLDA_FUNC_BDG, TDSLDA_EINVAL, "unknown functional");
+    require(s.broyden >= 0 && s.broyden <= kBroydenMax && (s.broyden == 0 || s.w0 > 0), TDSLDA_EINVAL,
+            "Broyden history must be in [0, 8] with w0 > 0");
     M = s.nx * s.ny;
     N2 = 2 * M;
     nclass = s.nz / 2 + 1;
@@ -231,6 +376,14 @@ struct StaticSolver {
     for (double** p : {&vext, &U, &D, &Uo, &Do, &hf, &rho, &nu}) *p = (double*)alloc(sizeof(double) * M);
     red = (double*)alloc(sizeof(double) * 4);
     bad = (int*)alloc(sizeof(int));
+    if (s.broyden > 0) {
+      const size_t L = size_t(2 * M + 1);
+      pprev = (double*)alloc(sizeof(double) * L);
+      Fprev = (double*)alloc(sizeof(double) * L);
+      bdF = (double*)alloc(sizeof(double) * L * s.broyden);
+      bdp = (double*)alloc(sizeof(double) * L * s.broyden);
+      bmu = (double*)alloc(sizeof(double));
+    }
     std::vector<double> k2(nclass), w(nclass);
     for (int m = 0; m < nclass; ++m) {
       const double k = 2.0 * kPi * m / (s.nz * s.dz);
@@ -357,10 +510,24 @@ tdslda_status tdslda_static_solve(const tdslda_static* s, const tdslda_functiona
         done = 1;
         break;
       }
-      hipLaunchKernelGGL(tdslda::k_st_mix, dim3(tdslda::cdiv(S.M, 256)), dim3(256), 0, 0, S.M, s->mix, S.Uo,
-                         S.Do, S.U, S.D);
-      HIPCHK(hipGetLastError());
-      if (fixed_n) m += s->a_mu / s->N_req * (s->N_req - red[0]);
+      const double mu_out = fixed_n ? m + s->a_mu / s->N_req * (s->N_req - red[0]) : m;
+      if (s->broyden > 0) {
+        // p = (U, Delta, mu); the difference to the previous iterate goes to
+        // ring row (it - 2) mod m from the second iteration on
+        const int have_prev = it > 1 ? 1 : 0;
+        const int stored = it - 1;  // differences after this step
+        const int slot = have_prev ? (stored - 1) % s->broyden : 0;
+        const int nh = std::min(stored, s->broyden);
+        hipLaunchKernelGGL(tdslda::k_st_broyden, dim3(1), dim3(tdslda::kBTB), 0, 0, S.M, S.U, S.D, S.Uo, S.Do, m,
+                           mu_out, s->mix, s->w0, have_prev, slot, nh, S.pprev, S.Fprev, S.bdF, S.bdp, S.bmu);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpy(&m, S.bmu, sizeof(double), hipMemcpyDeviceToHost));
+      } else {
+        hipLaunchKernelGGL(tdslda::k_st_mix, dim3(tdslda::cdiv(S.M, 256)), dim3(256), 0, 0, S.M, s->mix, S.Uo,
+                           S.Do, S.U, S.D);
+        HIPCHK(hipGetLastError());
+        m = mu_out;
+      }
     }
     if (!done) {
       HIPCHK(hipMemcpy(U, S.U, b, hipMemcpyDeviceToHost));

@@ -8,8 +8,9 @@ to the lattice, uniform centres), fixed particle number N_req = N of the
 obstacle-free trap at mu = 1.  The plain start is the uniform state at the
 reference Fermi momentum k_F = 1 (eF_ref = 1/2); the warm start is the
 network's prediction of (U, Delta, mu) from V_ext.  Both are iterated by the
-same linear mixing to r < tol; when the warm start does not converge the
-plain start is used (and counted).
+same mixing to r < tol (linear mixing, and the modified Broyden mixing as
+the non-learned accelerator to compare with); when the warm start does not
+converge the plain start is used (and counted).
 """
 import time
 
@@ -21,7 +22,8 @@ EF_REF = 0.5
 XI_UFG = 0.4     # mu / eF of the uniform unitary gas (plain start)
 DELTA_UFG = 0.5  # Delta / eF of the uniform unitary gas (plain start)
 
-Q2D = dict(nx=16, ny=16, nz=8, omega=0.24, mix=0.5, a_mu=0.5, tol=1e-8, maxit=400, channels=32)
+Q2D = dict(nx=16, ny=16, nz=8, omega=0.24, mix=0.5, a_mu=0.5, tol=1e-8, maxit=400, channels=32, broyden=8,
+           w0=0.01)
 
 
 def vext(cfg, seed):
@@ -44,10 +46,10 @@ def plain_start(cfg, fun):
     return U, D, XI_UFG * EF_REF
 
 
-def params(cfg, N_req=0.0, a_mu=None):
+def params(cfg, N_req=0.0, a_mu=None, broyden=0):
     return T.static_params(cfg["nx"], cfg["ny"], cfg["nz"], ec=0.5 * np.pi ** 2, mix=cfg["mix"],
                            a_mu=cfg["a_mu"] if a_mu is None else a_mu, N_req=N_req, tol=cfg["tol"],
-                           eF_ref=EF_REF, maxit=cfg["maxit"])
+                           eF_ref=EF_REF, maxit=cfg["maxit"], broyden=broyden, w0=cfg.get("w0", 0.01))
 
 
 def required_n(cfg, fun):
@@ -65,10 +67,10 @@ def required_n(cfg, fun):
     return N
 
 
-def solve(cfg, fun, N_req, v, start):
+def solve(cfg, fun, N_req, v, start, broyden=0):
     U0, D0, mu0 = start
     t0 = time.perf_counter()
-    U, D, mu, it, ok, hist = T.static_solve(params(cfg, N_req), fun, v, U0, D0, mu0)
+    U, D, mu, it, ok, hist = T.static_solve(params(cfg, N_req, broyden=broyden), fun, v, U0, D0, mu0)
     return dict(U=U, D=D, mu=mu, iters=it, converged=ok, seconds=time.perf_counter() - t0)
 
 
@@ -134,11 +136,14 @@ def experiment(cfg, train_seeds, test_seeds, epochs=300, log=None):
     N_req = required_n(cfg, fun)
     t0 = time.perf_counter()
     V, U, D, MU, it_train = [], [], [], [], []
+    nb = cfg.get("broyden", 0)
     for i, s in enumerate(train_seeds):
         if log and i and i % 10 == 0:
             log(f"training solves: {i} of {len(train_seeds)} ({time.perf_counter() - t0:.0f} s)")
         v = vext(cfg, s)
-        r = solve(cfg, fun, N_req, v, plain_start(cfg, fun))
+        # the training targets are fixed points of K; the Broyden iteration
+        # reaches the same ones in fewer maps
+        r = solve(cfg, fun, N_req, v, plain_start(cfg, fun), broyden=nb)
         if not r["converged"]:
             continue
         V.append(v)
@@ -155,24 +160,38 @@ def experiment(cfg, train_seeds, test_seeds, epochs=300, log=None):
     t_fit = time.perf_counter() - t0
     if log:
         log(f"fit: {fit['steps']} Adam steps in {t_fit:.1f} s, loss {fit['first_loss']:.3g} -> {fit['final_loss']:.3g}")
-    plain_it, warm_it, fallbacks, warm_s, plain_s = [], [], 0, 0.0, 0.0
+    # iterations to r < tol from the plain and the warm start, with linear
+    # mixing and (nb > 0) with Broyden mixing; a warm start that does not
+    # converge falls back to the plain start and is charged maxit extra
+    its = {k: [] for k in ("plain", "warm", "plain_broyden", "warm_broyden")}
+    fallbacks, plain_s = 0, 0.0
     for i, s in enumerate(test_seeds):
         if log and i and i % 5 == 0:
             log(f"held-out seeds: {i} of {len(test_seeds)}")
         v = vext(cfg, s)
-        p = solve(cfg, fun, N_req, v, plain_start(cfg, fun))
         Uw, Dw, muw = ws.predict(v[None])
-        w = solve(cfg, fun, N_req, v, (Uw[0], Dw[0], float(muw[0])))
-        plain_s += p["seconds"]
-        warm_s += w["seconds"]
-        if not w["converged"]:
-            fallbacks += 1
-            w = p
-        plain_it.append(p["iters"])
-        warm_it.append(w["iters"] if w is not p else p["iters"] + cfg["maxit"])
+        warm = (Uw[0], Dw[0], float(muw[0]))
+        for suffix, b in (("", 0), ("_broyden", nb)):
+            if suffix and not nb:
+                continue
+            p = solve(cfg, fun, N_req, v, plain_start(cfg, fun), broyden=b)
+            w = solve(cfg, fun, N_req, v, warm, broyden=b)
+            if not suffix:
+                plain_s += p["seconds"]
+            its["plain" + suffix].append(p["iters"])
+            if w["converged"]:
+                its["warm" + suffix].append(w["iters"])
+            else:
+                fallbacks += 1
+                its["warm" + suffix].append(p["iters"] + cfg["maxit"])
     ws.close()
-    return dict(lattice=[cfg["nx"], cfg["ny"], cfg["nz"]], n_train=len(V), n_test=len(test_seeds),
-                train_data_seconds=t_data, fit_seconds=t_fit, fit=fit,
-                plain_iters_mean=float(np.mean(plain_it)), warm_iters_mean=float(np.mean(warm_it)),
-                plain_iters=plain_it, warm_iters=warm_it, fallbacks=fallbacks,
-                seconds_per_iteration=plain_s / max(1, sum(plain_it)), N_req=N_req)
+    out = dict(lattice=[cfg["nx"], cfg["ny"], cfg["nz"]], n_train=len(V), n_test=len(test_seeds),
+               train_data_seconds=t_data, fit_seconds=t_fit, fit=fit, fallbacks=fallbacks,
+               plain_iters_mean=float(np.mean(its["plain"])), warm_iters_mean=float(np.mean(its["warm"])),
+               plain_iters=its["plain"], warm_iters=its["warm"],
+               seconds_per_iteration=plain_s / max(1, sum(its["plain"])), N_req=N_req, broyden=nb)
+    if nb:
+        out.update(plain_broyden_iters_mean=float(np.mean(its["plain_broyden"])),
+                   warm_broyden_iters_mean=float(np.mean(its["warm_broyden"])),
+                   plain_broyden_iters=its["plain_broyden"], warm_broyden_iters=its["warm_broyden"])
+    return out

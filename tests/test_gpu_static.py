@@ -84,3 +84,42 @@ def test_static_solve_matches_oracle():
     assert abs(mug - muo) < 1e-9
     ho = np.array(hist)
     assert np.abs(hg[:, 0] - ho[:, 0]).max() < 1e-8
+
+
+@pytest.mark.parametrize("m", [3, 8])
+def test_static_broyden_matches_oracle(m):
+    """Fixed-N modified Broyden mixing (history 3 and 8, w0 = 0.01, mix 0.5;
+    mu a component of p) to r < 1e-8: the device iteration follows the
+    oracle's residual history, takes its iteration count (within one: the
+    Broyden step amplifies rounding differences late in the run) and ends
+    on the same fields and mu."""
+    t = T()
+    g, vext = case()
+    fo = F.Functional(F.SLDA)
+    U0, D0, mu0 = np.full(g.shape, -0.2), np.full(g.shape, 0.25), 0.8
+    X, Y = g.coords()
+    _, _, _, _, N_req = ST.map_k(g, fo, 0.5 * 0.4 ** 2 * (X ** 2 + Y ** 2), U0, D0, 1.0, EC)
+    hist = []
+    Uo, Do, muo, ito, ok = ST.solve(g, fo, vext, U0, D0, mu0, EC, mix=0.5, a_mu=0.5, N_req=N_req, tol=1e-8,
+                                    maxit=300, history=hist, broyden=m, w0=0.01)
+    assert ok
+    p = t.static_params(g.nx, g.ny, g.nz, ec=EC, mix=0.5, a_mu=0.5, N_req=N_req, tol=1e-8, maxit=300, broyden=m,
+                        w0=0.01)
+    Ug, Dg, mug, itg, okg, hg = t.static_solve(p, t.functional_slda(mu0, EC), vext, U0, D0, mu0)
+    assert okg
+    assert abs(itg - ito) <= 1
+    assert np.abs(Ug - Uo).max() < 1e-8
+    assert np.abs(Dg - np.real(Do)).max() < 1e-8
+    assert abs(mug - muo) < 1e-8
+    ho = np.array(hist)
+    k = min(len(ho), len(hg), 10)
+    assert np.abs(hg[:k, 0] - ho[:k, 0]).max() < 1e-9 * max(1.0, np.abs(ho[:k, 0]).max())
+
+
+def test_static_broyden_rejects_long_history():
+    t = T()
+    g, vext = case()
+    p = t.static_params(g.nx, g.ny, g.nz, ec=EC, broyden=9)
+    with pytest.raises(t.TdsldaError) as ei:
+        t.static_solve(p, t.functional_slda(0.8, EC), vext, np.zeros(g.shape), np.full(g.shape, 0.2), 0.8)
+    assert ei.value.status == t.EINVAL
