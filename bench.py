@@ -287,7 +287,7 @@ def main():
     if not args.no_warmstart:
         from paper_2602_08982_amd import warmstart as WS
         if args.warmstart_size == "small":
-            wcfg, ntr, nte, ep = dict(WS.Q2D, nx=8, ny=8, nz=4, omega=0.48, channels=16), 48, 8, 200
+            wcfg, ntr, nte, ep = dict(WS.Q2D, nx=8, ny=8, nz=4, omega=0.48, channels=16, coarse=6), 48, 8, 200
         else:
             wcfg, ntr, nte, ep = dict(WS.Q2D), 200, 40, 300
         warm = WS.experiment(wcfg, range(0, ntr), range(10000, 10000 + nte), epochs=ep,
@@ -297,6 +297,13 @@ def main():
         if warm.get("broyden"):
             print(f"# Broyden mixing: warm {warm['warm_broyden_iters_mean']:.1f} vs plain "
                   f"{warm['plain_broyden_iters_mean']:.1f} iterations", file=sys.stderr, flush=True)
+        if warm.get("coarse_start"):
+            cs = warm["coarse_start"]
+            for k in ("linear", "broyden"):
+                if k in cs:
+                    print(f"# coarse-lattice start ({k} mixing): {cs[k]['coarse_iters_mean']:.1f} coarse + "
+                          f"{cs[k]['fine_iters_mean']:.1f} target iterations = {cs[k]['target_equivalent']:.1f} "
+                          f"target-equivalent (cost ratio {cs['cost_ratio']:.3f})", file=sys.stderr, flush=True)
     cpu = None if args.no_cpu else cpu_baseline()
 
     line = {
@@ -349,6 +356,7 @@ def main():
             "n_train": warm["n_train"], "n_test": warm["n_test"],
             "seconds_per_iteration": warm["seconds_per_iteration"],
             "train_data_seconds": warm["train_data_seconds"], "fit_seconds": warm["fit_seconds"],
+            "coarse_lattice_start": warm.get("coarse_start"),
         }
     print(json.dumps(line))
 

@@ -250,6 +250,20 @@ tdslda_status tdslda_static_solve(const tdslda_static* s, const tdslda_functiona
                                   double* U, double* delta, double* mu, int* iters, int* converged,
                                   double* hist);
 
+/* Fourier interpolation of a real field between two lattices of one
+ * periodic x-y box (Sec. 5.2, refining lattice resolution: a solution on a
+ * coarse lattice is interpolated onto the target lattice as its initial
+ * guess).  f: host FP64 [nx*ny] (index ix*ny + iy) with spacings dx, dy;
+ * out: host FP64 [nx2*ny2] with spacings dx2, dy2; nx dx = nx2 dx2 and
+ * ny dy = ny2 dy2.  out = Re 1/(L_x L_y) sum_lm f~_lm exp[i (k_l x + k_m y)]
+ * with f~ the lattice Fourier coefficients of f (k grid of Sec. 3.1,
+ * Nyquist at -pi/d) and positions measured from the shared box corner, so
+ * points shared by the two lattices keep their values.  Direct sums on the
+ * device (coefficients, then one thread per target site).  Errors: EINVAL
+ * (sizes, odd source sizes, spacings, box mismatch), ENOMEM. */
+tdslda_status tdslda_interp2d(int nx, int ny, double dx, double dy, const double* f, int nx2, int ny2, double dx2,
+                              double dy2, double* out);
+
 /* Warm-start network of the static workflow (learned initial guess for
  * the fixed-point iteration of Alg. MapK; Sec. 5.2 on initial guesses).
  * A small convolutional network maps the normalised external potential of

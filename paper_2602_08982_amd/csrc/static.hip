@@ -308,6 +308,58 @@ __global__ __launch_bounds__(kBTB) void k_st_broyden(int M, double* __restrict__
   }
 }
 
+// Fourier interpolation between two lattices of one periodic x-y box
+// (Sec. 5.2, refining lattice resolution).  Positions are measured from the
+// shared box corner (site i at i d); k grid of Sec. 3.1 (Nyquist at -pi/d).
+__device__ __forceinline__ double kgrid_at(int l, int n, double d) {
+  return 2.0 * kPi / (n * d) * double(l < n / 2 ? l : l - n);
+}
+
+// f~_lm = dx dy sum_ij f_ij exp[-2 pi i (l i / nx + m j / ny)], one thread
+// per (l, m); the phase index is reduced modulo n in integers
+__global__ void k_interp_coef(int nx, int ny, double dx, double dy, const double* __restrict__ f,
+                              double* __restrict__ ft) {
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  if (q >= nx * ny) return;
+  const int l = q / ny, m = q - l * ny;
+  double re = 0.0, im = 0.0;
+  for (int i = 0; i < nx; ++i) {
+    const int pi_ = int((int64_t(l) * i) % nx);
+    for (int j = 0; j < ny; ++j) {
+      const int pj = int((int64_t(m) * j) % ny);
+      const double ang = -2.0 * kPi * (double(pi_) / nx + double(pj) / ny);
+      double sn, cs;
+      sincos(ang, &sn, &cs);
+      const double v = f[i * ny + j];
+      re += v * cs;
+      im += v * sn;
+    }
+  }
+  ft[2 * q] = dx * dy * re;
+  ft[2 * q + 1] = dx * dy * im;
+}
+
+// out_ab = Re 1/(Lx Ly) sum_lm f~_lm exp[i (k_l x_a + k_m y_b)], one thread per
+// target site
+__global__ void k_interp_eval(int nx, int ny, double dx, double dy, const double* __restrict__ ft, int nx2,
+                              int ny2, double dx2, double dy2, double* __restrict__ out) {
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  if (q >= nx2 * ny2) return;
+  const int a = q / ny2, b = q - a * ny2;
+  const double x = a * dx2, y = b * dy2;
+  double acc = 0.0;
+  for (int l = 0; l < nx; ++l) {
+    const double kx = kgrid_at(l, nx, dx);
+    for (int m = 0; m < ny; ++m) {
+      double sn, cs;
+      sincos(kx * x + kgrid_at(m, ny, dy) * y, &sn, &cs);
+      const int c = l * ny + m;
+      acc += ft[2 * c] * cs - ft[2 * c + 1] * sn;
+    }
+  }
+  out[q] = acc / (nx * dx * ny * dy);
+}
+
 struct Handle {
   rocblas_handle h = nullptr;
   Handle() {
@@ -537,6 +589,49 @@ tdslda_status tdslda_static_solve(const tdslda_static* s, const tdslda_functiona
     *mu = m;
     if (iters) *iters = it;
     if (converged) *converged = done;
+  });
+}
+
+tdslda_status tdslda_interp2d(int nx, int ny, double dx, double dy, const double* f, int nx2, int ny2, double dx2,
+                              double dy2, double* out) {
+  if (!f || !out) return TDSLDA_EINVAL;
+  return static_guard("tdslda_interp2d", [&] {
+    require(nx > 0 && ny > 0 && nx2 > 0 && ny2 > 0 && nx % 2 == 0 && ny % 2 == 0, TDSLDA_EINVAL,
+            "lattice sizes must be positive (source sizes even)");
+    require(nx <= 4096 && ny <= 4096 && int64_t(nx2) * ny2 <= (int64_t(1) << 28), TDSLDA_EINVAL,
+            "lattice too large for the direct sums");
+    require(dx > 0 && dy > 0 && dx2 > 0 && dy2 > 0, TDSLDA_EINVAL, "spacings must be positive");
+    const double Lx = nx * dx, Ly = ny * dy;
+    require(std::fabs(nx2 * dx2 - Lx) <= 1e-12 * Lx && std::fabs(ny2 * dy2 - Ly) <= 1e-12 * Ly, TDSLDA_EINVAL,
+            "the two lattices must span the same box");
+    const size_t n1 = size_t(nx) * ny, n2 = size_t(nx2) * ny2;
+    double *df = nullptr, *dft = nullptr, *dout = nullptr;
+    auto release = [&] {
+      if (df) (void)hipFree(df);
+      if (dft) (void)hipFree(dft);
+      if (dout) (void)hipFree(dout);
+    };
+    if (hipMalloc(&df, n1 * sizeof(double)) != hipSuccess || hipMalloc(&dft, 2 * n1 * sizeof(double)) != hipSuccess ||
+        hipMalloc(&dout, n2 * sizeof(double)) != hipSuccess) {
+      (void)hipGetLastError();
+      release();
+      throw Fail{TDSLDA_ENOMEM, "hipMalloc failed (interp2d)"};
+    }
+    try {
+      HIPCHK(hipMemcpy(df, f, n1 * sizeof(double), hipMemcpyHostToDevice));
+      hipLaunchKernelGGL(tdslda::k_interp_coef, dim3(tdslda::cdiv(int64_t(n1), 256)), dim3(256), 0, 0, nx, ny, dx,
+                         dy, df, dft);
+      HIPCHK(hipGetLastError());
+      hipLaunchKernelGGL(tdslda::k_interp_eval, dim3(tdslda::cdiv(int64_t(n2), 256)), dim3(256), 0, 0, nx, ny, dx,
+                         dy, dft, nx2, ny2, dx2, dy2, dout);
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipMemcpy(out, dout, n2 * sizeof(double), hipMemcpyDeviceToHost));
+    } catch (...) {
+      (void)hipDeviceSynchronize();
+      release();
+      throw;
+    }
+    release();
   });
 }
 

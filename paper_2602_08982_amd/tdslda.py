@@ -86,6 +86,8 @@ _SIGS = {
                           C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double)],
     "tdslda_static_solve": [C.POINTER(Static), C.POINTER(Functional), C.c_void_p, C.c_void_p, C.c_void_p,
                             C.POINTER(C.c_double), C.POINTER(C.c_int), C.POINTER(C.c_int), C.c_void_p],
+    "tdslda_interp2d": [C.c_int, C.c_int, C.c_double, C.c_double, C.c_void_p, C.c_int, C.c_int, C.c_double,
+                        C.c_double, C.c_void_p],
     "tdslda_nn_nparams": [C.c_int],
     "tdslda_nn_create": [C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p, C.POINTER(C.c_void_p)],
     "tdslda_nn_destroy": [C.c_void_p],
@@ -374,6 +376,21 @@ def static_solve(params, fun, vext, U, delta, mu):
     if st != OK:
         raise TdsldaError(st, "tdslda_static_solve failed")
     return u.reshape(shp), d.reshape(shp), m.value, it.value, bool(ok.value), hist[:it.value]
+
+
+def interp2d(f, d, shape2, d2):
+    """Fourier interpolation of a real x-y field onto another lattice of the
+    same box (tdslda_interp2d); d, d2 = (dx, dy) spacings."""
+    lib = load_library()
+    f = _f64(f)
+    nx, ny = f.shape
+    nx2, ny2 = shape2
+    out = np.empty(nx2 * ny2)
+    st = lib.tdslda_interp2d(nx, ny, float(d[0]), float(d[1]), _p(f.ravel()), nx2, ny2, float(d2[0]), float(d2[1]),
+                             _p(out))
+    if st != OK:
+        raise TdsldaError(st, "tdslda_interp2d failed")
+    return out.reshape(nx2, ny2)
 
 
 class Network:

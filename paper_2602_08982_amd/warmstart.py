@@ -23,18 +23,23 @@ XI_UFG = 0.4     # mu / eF of the uniform unitary gas (plain start)
 DELTA_UFG = 0.5  # Delta / eF of the uniform unitary gas (plain start)
 
 Q2D = dict(nx=16, ny=16, nz=8, omega=0.24, mix=0.5, a_mu=0.5, tol=1e-8, maxit=400, channels=32, broyden=8,
-           w0=0.01)
+           w0=0.01, coarse=12)
 
 
-def vext(cfg, seed):
+def vext(cfg, seed, nx=None, ny=None):
+    """V_ext on the nx x ny lattice of the target box (default: the target
+    lattice itself, spacing 1; a coarser lattice has spacing L / nx), at the
+    centred coordinates x = (i - nx/2) d."""
     import synth
-    nx, ny = cfg["nx"], cfg["ny"]
-    x = np.arange(nx) - nx // 2
-    y = np.arange(ny) - ny // 2
+    L_x, L_y = cfg["nx"], cfg["ny"]
+    nx = L_x if nx is None else nx
+    ny = L_y if ny is None else ny
+    x = (np.arange(nx) - nx // 2) * (L_x / nx)
+    y = (np.arange(ny) - ny // 2) * (L_y / ny)
     X, Y = np.meshgrid(x, y, indexing="ij")
     v = 0.5 * cfg["omega"] ** 2 * (X ** 2 + Y ** 2)
-    amp, wid, cen = synth.obstacles(seed, float(nx))
-    s = nx / 64.0
+    amp, wid, cen = synth.obstacles(seed, float(L_x))
+    s = L_x / 64.0
     for a, w, (cx, cy) in zip(amp, wid, cen):
         v = v + EF_REF * a * np.exp(-((X - cx) ** 2 + (Y - cy) ** 2) / (2.0 * (w * s) ** 2))
     return v
@@ -47,7 +52,12 @@ def plain_start(cfg, fun):
 
 
 def params(cfg, N_req=0.0, a_mu=None, broyden=0):
-    return T.static_params(cfg["nx"], cfg["ny"], cfg["nz"], ec=0.5 * np.pi ** 2, mix=cfg["mix"],
+    """Solver parameters.  A coarse lattice (spacing cfg["d"] > 1) keeps the
+    target lattice's regulator cut-off (pi^2/2): the coarse solve is a guess
+    for the target problem, and its own lattice cut-off would leave the
+    regulator undefined where V_ext - mu exceeds it."""
+    d = cfg.get("d", 1.0)
+    return T.static_params(cfg["nx"], cfg["ny"], cfg["nz"], d=(d, d, 1.0), ec=0.5 * np.pi ** 2, mix=cfg["mix"],
                            a_mu=cfg["a_mu"] if a_mu is None else a_mu, N_req=N_req, tol=cfg["tol"],
                            eF_ref=EF_REF, maxit=cfg["maxit"], broyden=broyden, w0=cfg.get("w0", 0.01))
 
@@ -72,6 +82,24 @@ def solve(cfg, fun, N_req, v, start, broyden=0):
     t0 = time.perf_counter()
     U, D, mu, it, ok, hist = T.static_solve(params(cfg, N_req, broyden=broyden), fun, v, U0, D0, mu0)
     return dict(U=U, D=D, mu=mu, iters=it, converged=ok, seconds=time.perf_counter() - t0)
+
+
+def coarse_start(cfg, fun, N_req, seed, nxc, broyden=0):
+    """Sec. 5.2, refining lattice resolution: solve on an nxc x nxc lattice of
+    the same box (spacing nx / nxc), then interpolate (U, Delta) onto the
+    target lattice (tdslda_interp2d); mu carries over.  Returns (start,
+    coarse result)."""
+    d = cfg["nx"] / nxc
+    cc = dict(cfg, nx=nxc, ny=nxc, d=d)
+    vc = vext(cfg, seed, nxc, nxc)
+    U0, D0, mu0 = plain_start(cc, fun)
+    t0 = time.perf_counter()
+    U, D, mu, it, ok, hist = T.static_solve(params(cc, N_req, broyden=broyden), fun, vc, U0, D0, mu0)
+    res = dict(iters=it, converged=ok, seconds=time.perf_counter() - t0)
+    shape = (cfg["nx"], cfg["ny"])
+    Uf = T.interp2d(U, (d, d), shape, (1.0, 1.0))
+    Df = T.interp2d(D, (d, d), shape, (1.0, 1.0))
+    return (Uf, Df, mu), res
 
 
 class WarmStart:
@@ -165,6 +193,8 @@ def experiment(cfg, train_seeds, test_seeds, epochs=300, log=None):
     # converge falls back to the plain start and is charged maxit extra
     its = {k: [] for k in ("plain", "warm", "plain_broyden", "warm_broyden")}
     fallbacks, plain_s = 0, 0.0
+    coarse = {k: [] for k in ("coarse", "fine", "coarse_broyden", "fine_broyden")}
+    coarse.update(fallbacks=0, coarse_s=0.0, coarse_it=0)
     for i, s in enumerate(test_seeds):
         if log and i and i % 5 == 0:
             log(f"held-out seeds: {i} of {len(test_seeds)}")
@@ -184,12 +214,33 @@ def experiment(cfg, train_seeds, test_seeds, epochs=300, log=None):
             else:
                 fallbacks += 1
                 its["warm" + suffix].append(p["iters"] + cfg["maxit"])
+        nxc = cfg.get("coarse", 0)
+        for suffix, b in (("", 0), ("_broyden", nb)):
+            if not nxc or (suffix and not nb):
+                continue
+            start, cres = coarse_start(cfg, fun, N_req, s, nxc, broyden=b)
+            f = solve(cfg, fun, N_req, v, start, broyden=b)
+            coarse["coarse" + suffix].append(cres["iters"])
+            coarse["fine" + suffix].append(f["iters"] if f["converged"] else f["iters"] + cfg["maxit"])
+            coarse["fallbacks"] += 0 if (f["converged"] and cres["converged"]) else 1
+            coarse["coarse_s"] += cres["seconds"]
+            coarse["coarse_it"] += cres["iters"]
     ws.close()
     out = dict(lattice=[cfg["nx"], cfg["ny"], cfg["nz"]], n_train=len(V), n_test=len(test_seeds),
                train_data_seconds=t_data, fit_seconds=t_fit, fit=fit, fallbacks=fallbacks,
                plain_iters_mean=float(np.mean(its["plain"])), warm_iters_mean=float(np.mean(its["warm"])),
                plain_iters=its["plain"], warm_iters=its["warm"],
                seconds_per_iteration=plain_s / max(1, sum(its["plain"])), N_req=N_req, broyden=nb)
+    if coarse["coarse"]:
+        # cost of a coarse iteration in target-lattice iterations, measured
+        ratio = (coarse["coarse_s"] / max(1, coarse["coarse_it"])) / out["seconds_per_iteration"]
+        cres = dict(lattice=[cfg["coarse"], cfg["coarse"], cfg["nz"]], cost_ratio=ratio, fallbacks=coarse["fallbacks"])
+        for suffix in ("", "_broyden"):
+            if coarse["coarse" + suffix]:
+                c, f = np.mean(coarse["coarse" + suffix]), np.mean(coarse["fine" + suffix])
+                cres["linear" if not suffix else "broyden"] = dict(coarse_iters_mean=float(c), fine_iters_mean=float(f),
+                                                                   target_equivalent=float(c * ratio + f))
+        out["coarse_start"] = cres
     if nb:
         out.update(plain_broyden_iters_mean=float(np.mean(its["plain_broyden"])),
                    warm_broyden_iters_mean=float(np.mean(its["warm_broyden"])),

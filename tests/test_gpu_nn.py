@@ -72,10 +72,12 @@ def test_learned_warm_start_saves_iterations():
     seeds; Broyden mixing (history 8) from the plain start also beats linear
     mixing (both are reported, with the warm start under Broyden mixing)."""
     from paper_2602_08982_amd import warmstart as WS
-    cfg = dict(WS.Q2D, nx=8, ny=8, nz=4, omega=0.48, channels=16, maxit=400)
+    cfg = dict(WS.Q2D, nx=8, ny=8, nz=4, omega=0.48, channels=16, maxit=400, coarse=6)
     res = WS.experiment(cfg, range(0, 48), range(10000, 10008), epochs=200)
     assert res["n_train"] >= 40
     assert res["fallbacks"] == 0
     assert res["warm_iters_mean"] < res["plain_iters_mean"], res
     # the non-learned accelerator the network is compared with
     assert res["plain_broyden_iters_mean"] < res["plain_iters_mean"], res
+    # the coarse-lattice route (6x6 solve interpolated onto 8x8) converges
+    assert res["coarse_start"]["fallbacks"] == 0, res["coarse_start"]

@@ -123,3 +123,25 @@ def test_static_broyden_rejects_long_history():
     with pytest.raises(t.TdsldaError) as ei:
         t.static_solve(p, t.functional_slda(0.8, EC), vext, np.zeros(g.shape), np.full(g.shape, 0.2), 0.8)
     assert ei.value.status == t.EINVAL
+
+
+@pytest.mark.parametrize("src,dst", [((6, 8, 2.0, 1.5), (12, 16, 1.0, 0.75)), ((12, 12, 1.0, 1.0), (16, 10, 0.75, 1.2)),
+                                     ((8, 8, 1.0, 1.0), (8, 8, 1.0, 1.0))])
+def test_interp2d_matches_oracle(src, dst):
+    """Fourier interpolation on the device against the oracle's direct sum
+    (coarse to fine, to an unrelated lattice of the same box, identity)."""
+    from oracle import interp as I
+    t = T()
+    nx, ny, dx, dy = src
+    nx2, ny2, dx2, dy2 = dst
+    f = synth.uniform_field(9, (nx, ny), -1.0, 1.0)
+    ref = I.to_lattice(f, dx, dy, nx2, ny2, dx2, dy2)
+    got = t.interp2d(f, (dx, dy), (nx2, ny2), (dx2, dy2))
+    assert np.abs(got - ref).max() < 1e-12
+
+
+def test_interp2d_rejects_a_different_box():
+    t = T()
+    with pytest.raises(t.TdsldaError) as ei:
+        t.interp2d(np.zeros((6, 6)), (1.0, 1.0), (8, 8), (1.0, 1.0))
+    assert ei.value.status == t.EINVAL
