@@ -151,7 +151,7 @@ def copy_bandwidth():
     return 2 * (1 << 29) * 8 / sorted(ts)[2]
 
 
-def roofline(res, copy_bps=None, prec=None, nx=None):
+def roofline(res, copy_bps=None, prec=None, nx=None, role_prefix=""):
     """Dominant kernel of the timed steps against the HBM peak.  traffic =
     HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE summary
     (copy-calibrated), null when that summary does not cover this kernel or
@@ -164,7 +164,7 @@ def roofline(res, copy_bps=None, prec=None, nx=None):
     traffic = None
     if prec is not None:
         from paper_2602_08982_amd import profsum
-        traffic = profsum.read_traffic(COUNTERS_MD, prec, nx, dom)
+        traffic = profsum.read_traffic(COUNTERS_MD, prec, nx, role_prefix + dom)
     out = dict(bound="hbm", kernel=dom, achieved=g, peak=PEAK_HBM / 1e9, unit="GB/s",
                frac=(g * 1e9 / PEAK_HBM) if g else None, traffic=traffic,
                share_of_step=kern[dom]["total_ms"] / (res["ms_per_step"] * res["steps"]))
@@ -343,7 +343,8 @@ def main():
             "states_evolved": q1d["nst"], "graph_record_ms": q1d["graph_record_ms"],
             "setup_seconds": q1d["setup_seconds"], "tuned_workgroups": q1d["tuned"],
             "problems": q1d["problems"], "kernels": q1d["kernels"], "check": q1d["check"],
-            "roofline": roofline(dict(q1d, steps=q1d["profile_steps"]), copy_bps) if q1d["kernels"] else None,
+            "roofline": roofline(dict(q1d, steps=q1d["profile_steps"]), copy_bps, "float", 16, "q1d_")
+            if q1d["kernels"] else None,
         }
     if warm is not None:
         line["learned_warm_start"] = {

@@ -63,13 +63,14 @@ def precision(name):
 
 
 def key(name):
-    """precision:lattice-extent:role of a 3D-path kernel (x extent from the
-    template arguments of lap1 / lap2 / pointwise), else None."""
+    """precision:extent:role of a path kernel (extent = the first integer
+    template argument: x extent of the 3D kernels, A of the quasi-1D ones,
+    the state-group size of the density-sum pass), else None."""
     rl = role(name)
     if rl is None:
         return None
     m = re.search(r"<(?:double|float), (\d+)", name)
-    nx = m.group(1) if m and rl not in ("dens", "reduce_pot", "finalize") else "-"
+    nx = m.group(1) if m and rl not in ("reduce_pot", "finalize") else "-"
     return f"{precision(name)}:{nx}:{rl}"
 
 
@@ -141,7 +142,7 @@ def cmd_counters(args):
                    f"{wr / 1e9:.3f} |")
         machine.append(f"traffic {key(nm)} {rd + wr:.6e}")
     out += ["", "Machine-readable lines (bytes per launch, read + written; sources digest of the "
-                "3D kernel headers and build flags the counters were taken with):", ""]
+                "kernel sources and build flags the counters were taken with):", ""]
     out += ["    " + m for m in machine]
     out += [f"    sources {sources_digest()}"]
     if args.note:
