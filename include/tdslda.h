@@ -178,7 +178,8 @@ tdslda_status tdslda_abm_graph(tdslda_ctx* ctx, int64_t nsteps, double graph_ms[
 /* Launch-shape tuner: times each candidate workgroup size of every tunable
  * kernel class on the loaded states and keeps the fastest for the rest of
  * the context's life.  Quasi-1D kernel sets tune 4 classes (density pass,
- * z-derivative pass, fused H.psi/integrator pass, pointwise pass) over
+ * z-derivative pass, fused H.psi/integrator passes (timed as one step's
+ * corrector and full pass), pointwise pass) over
  * 64/128/256 threads; full-3D sets have fixed shapes (nclasses = 0).  Only
  * scratch buffers are written.  choice[4], ms[4] (host, may be NULL): chosen
  * workgroup size and its median time per class.  Errors: EORDER before a load. */

@@ -683,9 +683,10 @@ struct EngineQ1D final : Engine {
         } else if (k == 1) {
           ms = timeit([&] { lap1(c, c.sb[b], c.sscale[b], true, c.nst); });
         } else if (k == 2) {
-          // the corrector form (H phi, <H>_n and the corrector in one
-          // pass), writing into T only: T serves as partial corrector and
-          // output; each thread reads then writes its own sites
+          // one step's two fused passes, the corrector form and the full
+          // form (H phi, <H>_n and the integrator in one pass each), writing
+          // into T only: T serves as every history input and every output;
+          // each thread reads then writes its own sites
           L2Desc d;
           d.mode = L2_CORR;
           d.X = c.sb[b];
@@ -695,7 +696,15 @@ struct EngineQ1D final : Engine {
           d.scale = c.sscale[b];
           d.hshift = c.hshift;
           d.nrm_part = c.nrm_part;
-          ms = timeit([&] { lap2(c, d, c.nst); });
+          L2Desc e = d;
+          e.mode = L2_FULL;
+          e.out = c.T;
+          e.cout = c.T;
+          for (int j = 1; j < 5; ++j) e.hist[j] = c.T;
+          ms = timeit([&] {
+            lap2(c, d, c.nst);
+            lap2(c, e, c.nst);
+          });
         } else {
           PwDesc d;
           d.mode = PW_NORM;
