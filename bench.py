@@ -93,6 +93,37 @@ def run_workload(cfg, steps, warmup, seed_vortex, profile=True, precision=None, 
                 vortices=vort, obs=obs)
 
 
+def track_precision(steps, every, warmup, seed_vortex=4):
+    """The FP32-mixed 48^3 workload and its FP64 run side by side in time
+    (one after the other on the device): rho, nu and E of both every
+    `every` steps after the warm-up; returns the relative errors of the
+    FP32-mixed run at each checkpoint (not timed)."""
+    from paper_2602_08982_amd import tdslda as T
+    from paper_2602_08982_amd import workloads as W
+    import synth
+    (x1, y1), (x2, y2) = synth.vortex_pair(seed_vortex)
+    vort = [(x1, y1, 1.0), (x2, y2, -1.0)]
+    runs = {}
+    for prec in (T.FP32_MIXED, T.FP64):
+        ctx, _ = W.setup(W.MIXED, vort, precision=prec)
+        ctx.abm_step(warmup)
+        obs = []
+        for done in range(every, steps + 1, every):
+            ctx.abm_step(every)
+            d = ctx.densities()
+            obs.append((done, d["rho"], d["nu"], ctx.energy()))
+        ctx.close()
+        runs[prec] = obs
+        print(f"# precision track: {'fp32-mixed' if prec == T.FP32_MIXED else 'fp64'} run done", file=sys.stderr,
+              flush=True)
+    out = []
+    for (k, r32, n32, e32), (_, r64, n64, e64) in zip(runs[T.FP32_MIXED], runs[T.FP64]):
+        out.append(dict(step=k, rho_rel_err=float(np.abs(r32 - r64).max() / np.abs(r64).max()),
+                        nu_rel_err=float(np.abs(n32 - n64).max() / np.abs(n64).max()),
+                        energy_rel_err=float(abs(e32["total"] - e64["total"]) / abs(e64["EFG"]))))
+    return out
+
+
 def run_q1d(steps, warmup, seed=7, profile_steps=2):
     """Batched quasi-1D workload: set-up (device eigensolver), start-up and
     warm-up steps, launch-shape tuning, then `steps` steps recorded as one
@@ -220,14 +251,17 @@ def main():
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--no-q1d", action="store_true")
     ap.add_argument("--no-warmstart", action="store_true")
-    ap.add_argument("--warmstart-size", choices=["small", "medium"], default="small",
+    ap.add_argument("--warmstart-size", choices=["small", "medium", "large"], default="small",
                     help="small: 8x8x4 lattice, 48 training / 8 held-out solves (seconds); medium: 16x16x8, "
-                         "200 / 40 (about ten minutes)")
+                         "200 / 40 (about ten minutes); large: 24x24x8, 100 / 20, Broyden mixing only")
     ap.add_argument("--q1d-steps", type=int, default=2000,
                     help="steps of the batched quasi-1D run (one graph launch)")
     ap.add_argument("--mixed-steps", type=int, default=None,
                     help="steps of the FP32-mixed run and of its FP64 reference (default: --steps); the "
                          "errors of rho, nu and E are taken after them")
+    ap.add_argument("--precision-track", type=int, default=0, metavar="STEPS",
+                    help="also run the FP32-mixed 48^3 workload and its FP64 run for STEPS steps and report the "
+                         "FP32-mixed errors of rho, nu and E every 50 steps (not timed)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a device-to-device copy of 4 GiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -278,6 +312,7 @@ def main():
             rho_rel_err=float(np.abs(o["rho"] - r["rho"]).max() / np.abs(r["rho"]).max()),
             nu_rel_err=float(np.abs(o["nu"] - r["nu"]).max() / np.abs(r["nu"]).max()),
             energy_rel_err=float(abs(o["energy"]["total"] - r["energy"]["total"]) / abs(r["energy"]["EFG"])))
+    track = track_precision(args.precision_track, 50, args.warmup) if args.precision_track else None
     q1d = None
     if not args.no_q1d:
         q1d = run_q1d(args.q1d_steps, max(1, args.warmup))
@@ -288,13 +323,16 @@ def main():
         from paper_2602_08982_amd import warmstart as WS
         if args.warmstart_size == "small":
             wcfg, ntr, nte, ep = dict(WS.Q2D, nx=8, ny=8, nz=4, omega=0.48, channels=16, coarse=6), 48, 8, 200
-        else:
+        elif args.warmstart_size == "medium":
             wcfg, ntr, nte, ep = dict(WS.Q2D), 200, 40, 300
+        else:
+            wcfg, ntr, nte, ep = dict(WS.Q2D, nx=24, ny=24, omega=0.16, coarse=18, linear=False), 100, 20, 300
         warm = WS.experiment(wcfg, range(0, ntr), range(10000, 10000 + nte), epochs=ep,
                              log=lambda m: print("# warm start: " + m, file=sys.stderr, flush=True))
-        print(f"# warm start: {warm['warm_iters_mean']:.1f} vs plain {warm['plain_iters_mean']:.1f} iterations "
-              f"to r < 1e-8 ({warm['n_test']} held-out seeds)", file=sys.stderr, flush=True)
-        if warm.get("broyden"):
+        if "warm_iters_mean" in warm:
+            print(f"# warm start: {warm['warm_iters_mean']:.1f} vs plain {warm['plain_iters_mean']:.1f} iterations "
+                  f"to r < 1e-8 ({warm['n_test']} held-out seeds)", file=sys.stderr, flush=True)
+        if "warm_broyden_iters_mean" in warm:
             print(f"# Broyden mixing: warm {warm['warm_broyden_iters_mean']:.1f} vs plain "
                   f"{warm['plain_broyden_iters_mean']:.1f} iterations", file=sys.stderr, flush=True)
         if warm.get("coarse_start"):
@@ -335,6 +373,8 @@ def main():
             "dtype": "f32 states / f64 sums", "roofline": roofline(mixed, copy_bps, "float", 48), "kernels": mixed["kernels"],
             "check": mixed["check"], "vs_fp64_same_workload": mixed["vs_fp64"],
         }
+    if track is not None:
+        line["fp32_mixed_error_track"] = track
     if q1d is not None:
         line["batched_q1d"] = {
             "workload": "2,304 quasi-1D problems (48x48 k_perp), N_z=256, |E|<12, FP32 states / FP64 sums, "
@@ -352,7 +392,7 @@ def main():
                         f"{warm['lattice'][2]} k_z modes, trap + 1-4 obstacles, fixed N, linear mixing 0.5 "
                         f"(and modified Broyden mixing, history {warm.get('broyden', 0)})",
             "metric": "mixing iterations to r < 1e-8, mean over held-out seeds",
-            "warm": warm["warm_iters_mean"], "plain": warm["plain_iters_mean"], "fallbacks": warm["fallbacks"],
+            "warm": warm.get("warm_iters_mean"), "plain": warm.get("plain_iters_mean"), "fallbacks": warm["fallbacks"],
             "warm_broyden": warm.get("warm_broyden_iters_mean"), "plain_broyden": warm.get("plain_broyden_iters_mean"),
             "n_train": warm["n_train"], "n_test": warm["n_test"],
             "seconds_per_iteration": warm["seconds_per_iteration"],

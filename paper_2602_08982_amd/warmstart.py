@@ -192,7 +192,9 @@ def experiment(cfg, train_seeds, test_seeds, epochs=300, log=None):
     # mixing and (nb > 0) with Broyden mixing; a warm start that does not
     # converge falls back to the plain start and is charged maxit extra
     its = {k: [] for k in ("plain", "warm", "plain_broyden", "warm_broyden")}
-    fallbacks, plain_s = 0, 0.0
+    fallbacks, plain_s, plain_it = 0, 0.0, 0
+    # the mixings compared: linear (unless cfg["linear"] is False) and Broyden
+    mixings = ([("", 0)] if cfg.get("linear", True) else []) + ([("_broyden", nb)] if nb else [])
     coarse = {k: [] for k in ("coarse", "fine", "coarse_broyden", "fine_broyden")}
     coarse.update(fallbacks=0, coarse_s=0.0, coarse_it=0)
     for i, s in enumerate(test_seeds):
@@ -201,13 +203,11 @@ def experiment(cfg, train_seeds, test_seeds, epochs=300, log=None):
         v = vext(cfg, s)
         Uw, Dw, muw = ws.predict(v[None])
         warm = (Uw[0], Dw[0], float(muw[0]))
-        for suffix, b in (("", 0), ("_broyden", nb)):
-            if suffix and not nb:
-                continue
+        for suffix, b in mixings:
             p = solve(cfg, fun, N_req, v, plain_start(cfg, fun), broyden=b)
             w = solve(cfg, fun, N_req, v, warm, broyden=b)
-            if not suffix:
-                plain_s += p["seconds"]
+            plain_s += p["seconds"]
+            plain_it += p["iters"]
             its["plain" + suffix].append(p["iters"])
             if w["converged"]:
                 its["warm" + suffix].append(w["iters"])
@@ -215,9 +215,7 @@ def experiment(cfg, train_seeds, test_seeds, epochs=300, log=None):
                 fallbacks += 1
                 its["warm" + suffix].append(p["iters"] + cfg["maxit"])
         nxc = cfg.get("coarse", 0)
-        for suffix, b in (("", 0), ("_broyden", nb)):
-            if not nxc or (suffix and not nb):
-                continue
+        for suffix, b in (mixings if nxc else ()):
             start, cres = coarse_start(cfg, fun, N_req, s, nxc, broyden=b)
             f = solve(cfg, fun, N_req, v, start, broyden=b)
             coarse["coarse" + suffix].append(cres["iters"])
@@ -228,9 +226,10 @@ def experiment(cfg, train_seeds, test_seeds, epochs=300, log=None):
     ws.close()
     out = dict(lattice=[cfg["nx"], cfg["ny"], cfg["nz"]], n_train=len(V), n_test=len(test_seeds),
                train_data_seconds=t_data, fit_seconds=t_fit, fit=fit, fallbacks=fallbacks,
-               plain_iters_mean=float(np.mean(its["plain"])), warm_iters_mean=float(np.mean(its["warm"])),
-               plain_iters=its["plain"], warm_iters=its["warm"],
-               seconds_per_iteration=plain_s / max(1, sum(its["plain"])), N_req=N_req, broyden=nb)
+               seconds_per_iteration=plain_s / max(1, plain_it), N_req=N_req, broyden=nb)
+    if its["plain"]:
+        out.update(plain_iters_mean=float(np.mean(its["plain"])), warm_iters_mean=float(np.mean(its["warm"])),
+                   plain_iters=its["plain"], warm_iters=its["warm"])
     if coarse["coarse"]:
         # cost of a coarse iteration in target-lattice iterations, measured
         ratio = (coarse["coarse_s"] / max(1, coarse["coarse_it"])) / out["seconds_per_iteration"]
@@ -241,7 +240,7 @@ def experiment(cfg, train_seeds, test_seeds, epochs=300, log=None):
                 cres["linear" if not suffix else "broyden"] = dict(coarse_iters_mean=float(c), fine_iters_mean=float(f),
                                                                    target_equivalent=float(c * ratio + f))
         out["coarse_start"] = cres
-    if nb:
+    if its["plain_broyden"]:
         out.update(plain_broyden_iters_mean=float(np.mean(its["plain_broyden"])),
                    warm_broyden_iters_mean=float(np.mean(its["warm_broyden"])),
                    plain_broyden_iters=its["plain_broyden"], warm_broyden_iters=its["warm_broyden"])
