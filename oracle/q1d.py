@@ -75,6 +75,27 @@ class GeometryQ1D:
         return rho, tau, nu, [zero, zero.copy(), jz]
 
 
+    def friction_sources(self, phi, wu, wv):
+        """What the dissipative fields of the quantum-friction evolution
+        need (Sec. 5.2, correcting the initial state by a time-dependent
+        approach), in this geometry (fields depend on z only):
+          div j = d_z j_z (D1 with the Nyquist mode zeroed, as j itself),
+          B'    = -1/2 sum_n (f_v - f_u) [u grad^2 v^* + v^* grad^2 u] / (L_x L_y)
+                  with grad^2 = D2z - k_perp^2 and the weights of nu,
+          N     = int rho_+ d^3r.
+        Returns (div_j, B', N)."""
+        rho, _, _, j = self.full_densities(phi, wu, wv)
+        div_j = np.real(L.spectral_derivative(j[2], self.kz, 0, 1))
+        u, v = phi[:, 0], phi[:, 1]
+        kp = self.kperp2[:, None]
+        lu = self._lap(u) - kp * u
+        lv = self._lap(v) - kp * v
+        w = (np.asarray(wv, float) - np.asarray(wu, float))[:, None]
+        Bp = -0.5 * np.sum(w * (u * np.conj(lv) + np.conj(v) * lu), axis=0) / self.area
+        N = self.dV_energy * np.sum(2.0 * rho)
+        return div_j, Bp, N
+
+
 def dense_h_1d(hfield, delta, nz, dz, kperp2):
     """2N_z x 2N_z BdG matrix of one problem (Eq. D2 along z)."""
     K = -0.5 * L.d2_matrix(nz, dz)

@@ -58,6 +58,28 @@ class Geometry3D:
         return D.spin_symmetric(phi, wu, wv, self.lat)
 
 
+class Friction:
+    """Dissipative mean fields (quantum friction) of Sec. 5.2, correcting
+    the initial state by a time-dependent approach, added to U and Delta at
+    every field build:
+        U_diss     = -(alpha / rho0) div j,
+        Delta_diss = Delta [beta sin(theta_nu - theta_B') + i gamma~],
+        gamma~     = gamma (N - N_req) / N_req   (0 without N_req),
+    theta_nu = arg nu, theta_B' = arg B' with B' from the geometry's
+    friction_sources.  rho0 is a reference density (a parameter here)."""
+
+    def __init__(self, alpha=0.0, beta=0.0, gamma=0.0, rho0=1.0, N_req=None):
+        self.alpha, self.beta, self.gamma = float(alpha), float(beta), float(gamma)
+        self.rho0, self.N_req = float(rho0), N_req
+
+    def terms(self, geom, phi, wu, wv, nu, delta):
+        div_j, Bp, N = geom.friction_sources(phi, wu, wv)
+        Ud = -self.alpha / self.rho0 * div_j
+        gt = 0.0 if self.N_req is None else self.gamma * (N - self.N_req) / self.N_req
+        Dd = delta * (self.beta * np.sin(np.angle(nu) - np.angle(Bp)) + 1j * gt)
+        return Ud, Dd
+
+
 class TDSystem:
     """Everything the right-hand side f needs besides the states.
 
@@ -65,10 +87,12 @@ class TDSystem:
     after t=0); lam: frozen regulator Lambda_c(r) (reading: computed once,
     never refreshed, so that U is the exact derivative of the energy);
     wu, wv: frozen thermal weights f(E_n), f(-E_n) (Sec. 2.5).
-    frozen=(hfield, delta) switches to linear mode (fields not rebuilt)."""
+    frozen=(hfield, delta) switches to linear mode (fields not rebuilt);
+    friction (a Friction) adds the dissipative fields."""
 
-    def __init__(self, geom, fun, mu, vext, lam, wu, wv, frozen=None):
+    def __init__(self, geom, fun, mu, vext, lam, wu, wv, frozen=None, friction=None):
         self.geom, self.fun, self.mu = geom, fun, float(mu)
+        self.friction = friction
         self.vext = np.asarray(vext, float)
         self.lam = np.asarray(lam, float)
         self.wu = np.asarray(wu, float)
@@ -82,6 +106,9 @@ class TDSystem:
             return self.frozen
         rho, nu = self.geom.rho_nu(phi, self.wu, self.wv)
         U, delta, _ = F.potentials(rho, nu, self.lam, self.fun)
+        if self.friction is not None:
+            Ud, Dd = self.friction.terms(self.geom, phi, self.wu, self.wv, nu, delta)
+            return U + Ud + self.vext - self.mu, delta + Dd
         return U + self.vext - self.mu, delta
 
     def expect(self, phi, hphi):
