@@ -124,10 +124,12 @@ def track_precision(steps, every, warmup, seed_vortex=4):
     return out
 
 
-def run_q1d(steps, warmup, seed=7, profile_steps=2):
+def run_q1d(steps, warmup, seed=7, profile_steps=2, friction=False):
     """Batched quasi-1D workload: set-up (device eigensolver), start-up and
     warm-up steps, launch-shape tuning, then `steps` steps recorded as one
-    HIP graph and launched once (timed from launch to completion)."""
+    HIP graph and launched once (timed from launch to completion).
+    friction: the same with the quantum-friction terms on (alpha = beta = 5,
+    gamma = 0.1, rho0 = the initial maximum density, N_req = the initial N)."""
     import torch
     from paper_2602_08982_amd import tdslda as T
     from paper_2602_08982_amd import workloads as W
@@ -135,6 +137,9 @@ def run_q1d(steps, warmup, seed=7, profile_steps=2):
     ctx, info = W.setup_q1d(W.Q1D, seed, stream=torch.cuda.current_stream().cuda_stream)
     t_setup = time.perf_counter() - t0
     nst = info["states"]
+    if friction:
+        rho0 = float(ctx.densities()["rho"].max())
+        ctx.set_friction(alpha=5.0, beta=5.0, gamma=0.1, rho0=rho0, N_req=ctx.energy()["N"])
     ctx.abm_step(warmup)
     tuned = ctx.autotune()
     torch.cuda.synchronize()
@@ -256,6 +261,8 @@ def main():
                          "200 / 40 (about ten minutes); large: 24x24x8, 100 / 20, Broyden mixing only")
     ap.add_argument("--q1d-steps", type=int, default=2000,
                     help="steps of the batched quasi-1D run (one graph launch)")
+    ap.add_argument("--q1d-friction", action="store_true",
+                    help="also time the batched quasi-1D run with the quantum-friction terms on")
     ap.add_argument("--mixed-steps", type=int, default=None,
                     help="steps of the FP32-mixed run and of its FP64 reference (default: --steps); the "
                          "errors of rho, nu and E are taken after them")
@@ -313,6 +320,10 @@ def main():
             nu_rel_err=float(np.abs(o["nu"] - r["nu"]).max() / np.abs(r["nu"]).max()),
             energy_rel_err=float(abs(o["energy"]["total"] - r["energy"]["total"]) / abs(r["energy"]["EFG"])))
     track = track_precision(args.precision_track, 50, args.warmup) if args.precision_track else None
+    q1d_fric = None
+    if args.q1d_friction:
+        q1d_fric = run_q1d(args.q1d_steps, max(1, args.warmup), friction=True)
+        print(f"# batched q1d with friction: {q1d_fric['value']:.4g} state-steps/s", file=sys.stderr, flush=True)
     q1d = None
     if not args.no_q1d:
         q1d = run_q1d(args.q1d_steps, max(1, args.warmup))
@@ -375,6 +386,12 @@ def main():
         }
     if track is not None:
         line["fp32_mixed_error_track"] = track
+    if q1d_fric is not None:
+        line["batched_q1d_friction"] = {
+            "workload": "the batched quasi-1D run with the quantum-friction terms on (alpha = beta = 5, gamma = 0.1)",
+            "value": q1d_fric["value"], "unit": "state-steps/s", "ms_per_step": q1d_fric["ms_per_step"],
+            "kernels": q1d_fric["kernels"], "check": q1d_fric["check"],
+        }
     if q1d is not None:
         line["batched_q1d"] = {
             "workload": "2,304 quasi-1D problems (48x48 k_perp), N_z=256, |E|<12, FP32 states / FP64 sums, "

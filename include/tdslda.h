@@ -160,6 +160,22 @@ tdslda_status tdslda_get_fields(tdslda_ctx* ctx, double* U, double* delta_reim);
  * states with the same index is used. */
 tdslda_status tdslda_apply_hbdg(tdslda_ctx* ctx, const void* in_dev, void* out_dev, int64_t n);
 
+/* Quantum friction (Sec. 5.2, correcting the initial state by a
+ * time-dependent approach): from the next field build on, the evolution
+ * adds the dissipative fields
+ *   U_diss     = -(alpha / rho0) d_z j_z,
+ *   Delta_diss = Delta [beta sin(theta_nu - theta_B') + i gamma (N - N_req) / N_req],
+ * theta_nu = arg nu, theta_B' = arg B', B' = -1/2 sum_n (f_v - f_u)
+ * [u lap v^* + v^* lap u] (lap = D2z - k_perp^2, normalised states,
+ * 1/(L_x L_y)), j_z with D1z (Nyquist zeroed), N = int rho_+ d^3r.  The
+ * gamma term is off when N_req <= 0; all of alpha, beta and the gamma term
+ * zero switch friction off.  Each field build then takes one more pass over
+ * the states (the derivatives by four-step DFTs).  Quasi-1D contexts only;
+ * not stored by tdslda_save.  Errors: EINVAL (3D context, non-finite
+ * parameters, rho0 <= 0), ENOMEM. */
+tdslda_status tdslda_set_friction(tdslda_ctx* ctx, double alpha, double beta, double gamma, double rho0,
+                                  double N_req);
+
 /* Advance the loaded states by nsteps steps of the selected ABM integrator.
  * The first call after a load runs the start-up (selfstart), which is not
  * counted in nsteps.  Errors: EORDER before any load. */

@@ -19,11 +19,11 @@ namespace tdslda {
 enum KClass {
   KC_DENS = 0, KC_REDUCE_POT, KC_LAP1, KC_FINALIZE, KC_LAP2_CORR, KC_LAP2_FULL, KC_LAP2_F,
   KC_LAP2_H, KC_LAP2_TAYLOR, KC_PRED, KC_NORM, KC_GRAD, KC_ENERGY, KC_SETUP, KC_Q1D_FUSED,
-  KC_DENS_KIN, KC_COUNT
+  KC_DENS_KIN, KC_FRICTION, KC_COUNT
 };
 inline const char* const kKernelNames[KC_COUNT] = {
     "dens", "reduce_pot", "lap1", "finalize", "lap2_corr", "lap2_full", "lap2_f", "lap2_h",
-    "lap2_taylor", "pred", "norm", "grad", "energy", "setup", "q1d_fused", "dens_kin"};
+    "lap2_taylor", "pred", "norm", "grad", "energy", "setup", "q1d_fused", "dens_kin", "friction"};
 
 struct Fail {
   tdslda_status st;
@@ -95,6 +95,12 @@ struct Engine {
   virtual void lap2(Ctx& c, const L2Desc& d, int64_t nst) = 0;
   virtual void pointwise(Ctx& c, const PwDesc& d, int64_t nst) = 0;
   virtual void grad(Ctx& c, const void* X, const double* scale, int64_t n0, int64_t nchunk) = 0;
+  // quantum friction: add the dissipative terms to the fields just built
+  // from the states X (only the quasi-1D kernel set has it)
+  virtual void friction(Ctx& c, const void* X, const double* scale, int64_t nst) {
+    (void)c, (void)X, (void)scale, (void)nst;
+    throw Fail{TDSLDA_EINVAL, "quantum friction is built for the quasi-1D kernel set"};
+  }
   virtual size_t elem_size() const = 0;
 };
 
@@ -134,6 +140,11 @@ struct tdslda_ctx {
   int* dflag = nullptr;
   int32_t* kidx_dev = nullptr;
   int64_t kidx_cap = 0;
+  // quantum friction (quasi-1D): parameters, group partials [group][3][M]
+  // (j_z, Re B', Im B'), summed fields j[M], B'[M][2]
+  bool fric = false;
+  double f_alpha = 0, f_beta = 0, f_gamma = 0, f_rho0 = 1, f_Nreq = 0;
+  double *fric_part = nullptr, *fric_j = nullptr, *fric_bp = nullptr;
 
   // integrator state
   bool kin_ready[6] = {false, false, false, false, false, false};  // h slots hold this buffer's partials

@@ -461,6 +461,201 @@ __global__ __launch_bounds__(256) void q_grad(const cpx<R>* __restrict__ X, int6
   }
 }
 
+// ---------------------------------------------------------------------------
+// Quantum friction (the dissipative fields of Sec. 5.2, correcting the
+// initial state by a time-dependent approach).  q_fric: per state the
+// derivatives D1z (Nyquist zeroed) and D2z of u and v by the four-step DFT,
+// and the group partials of
+//   j_z = sum_n [f_v Im(v (D1 v)^*) - f_u Im(u (D1 u)^*)],
+//   B'  = -1/2 sum_n (f_v - f_u) [u (lap v)^* + v^* lap u],  lap = D2z - k_perp^2,
+// on the normalised states (the 1/(L_x L_y) factor is applied later).
+//   grid = ceil(nstates / G) workgroups, block = TB; part layout [group][3][N]
+template <typename R, int A, int G, int TB>
+__global__ __launch_bounds__(TB) void q_fric(const cpx<R>* __restrict__ X, int64_t nstates,
+                                              const double* __restrict__ wu, const double* __restrict__ wv,
+                                              const double* __restrict__ scale, const double* __restrict__ kperp2,
+                                              double* __restrict__ part, const cpx<R>* __restrict__ tw,
+                                              double kz) {
+  using CFG = Q1DCfg<R, A, TB>;
+  constexpr int N = CFG::N, WS = CFG::WS;
+  constexpr int NW = CFG::TB / kWave;
+  __shared__ cpx<R> lds_all[WS][A * CFG::PAD];
+  __shared__ double red[NW][3 * N];
+  const int tid = threadIdx.x, grp = tid / A, a = tid % A;
+  cpx<R>* lds = lds_all[grp];
+  double aj[A], abr[A], abi[A];
+#pragma unroll
+  for (int b = 0; b < A; ++b) aj[b] = abr[b] = abi[b] = 0.0;
+  const R inv_n = R(1.0 / N);
+  const int64_t nbeg = int64_t(blockIdx.x) * G;
+  for (int it = 0; it < G / WS; ++it) {
+    const int64_t n = nbeg + it * WS + grp;
+    const bool live = n < nstates;
+    const int64_t nn = live ? n : 0;
+    const R s = R(scale[nn]);
+    const double fu = live ? wu[nn] : 0.0, fv = live ? wv[nn] : 0.0, fw = fv - fu;
+    const R kp = R(kperp2[nn]);
+    const cpx<R>* Xn = X + nn * 2 * N;
+    cpx<R> u[A], v[A], t[A], d[A];
+#pragma unroll
+    for (int b = 0; b < A; ++b) {
+      u[b] = s * Xn[a + A * b];
+      v[b] = s * Xn[N + a + A * b];
+    }
+    // one component: spectrum in t; D1 -> j term, D2 -> lap in d
+    auto derivs = [&](cpx<R>(&x)[A], double wgt) {
+#pragma unroll
+      for (int b = 0; b < A; ++b) t[b] = x[b];
+      q_fwd<R, A>(t, a, lds, tw);
+      sfor<0, A>::run([&](auto pc) {
+        constexpr int p = decltype(pc)::value;
+        const int m = q_wavenum<A>(a, freq_of_pos<A>(p));
+        const R k = m == -N / 2 ? R(0) : R(kz * m);
+        d[p] = cpx<R>{-k * t[p].y, k * t[p].x};  // i k x~
+      });
+      q_inv<R, A>(d, a, lds, tw);
+#pragma unroll
+      for (int b = 0; b < A; ++b) {
+        const cpx<R> g = inv_n * d[b];
+        aj[b] += wgt * (double(x[b].y) * double(g.x) - double(x[b].x) * double(g.y));  // Im(x g^*)
+      }
+      sfor<0, A>::run([&](auto pc) {
+        constexpr int p = decltype(pc)::value;
+        const int m = q_wavenum<A>(a, freq_of_pos<A>(p));
+        const R k2 = R(kz * kz * double(m) * double(m));
+        d[p] = -k2 * t[p];
+      });
+      q_inv<R, A>(d, a, lds, tw);
+#pragma unroll
+      for (int b = 0; b < A; ++b) d[b] = inv_n * d[b] - kp * x[b];
+    };
+    derivs(u, -fu);  // d = lap u
+#pragma unroll
+    for (int b = 0; b < A; ++b) {  // v^* lap u
+      abr[b] += -0.5 * fw * (double(v[b].x) * double(d[b].x) + double(v[b].y) * double(d[b].y));
+      abi[b] += -0.5 * fw * (double(v[b].x) * double(d[b].y) - double(v[b].y) * double(d[b].x));
+    }
+    derivs(v, fv);  // d = lap v
+#pragma unroll
+    for (int b = 0; b < A; ++b) {  // u (lap v)^*
+      abr[b] += -0.5 * fw * (double(u[b].x) * double(d[b].x) + double(u[b].y) * double(d[b].y));
+      abi[b] += -0.5 * fw * (double(u[b].y) * double(d[b].x) - double(u[b].x) * double(d[b].y));
+    }
+  }
+  // sum the lane groups (as q_dens): shuffles within a wave, then the waves
+#pragma unroll
+  for (int b = 0; b < A; ++b) {
+#pragma unroll
+    for (int o = A; o < kWave; o <<= 1) {
+      aj[b] += __shfl_xor(aj[b], o, kWave);
+      abr[b] += __shfl_xor(abr[b], o, kWave);
+      abi[b] += __shfl_xor(abi[b], o, kWave);
+    }
+  }
+  const int w = tid / kWave, lw = tid % kWave;
+  if (lw < A) {
+#pragma unroll
+    for (int b = 0; b < A; ++b) {
+      red[w][a + A * b] = aj[b];
+      red[w][N + a + A * b] = abr[b];
+      red[w][2 * N + a + A * b] = abi[b];
+    }
+  }
+  __syncthreads();
+  double* out = part + int64_t(blockIdx.x) * 3 * N;
+  for (int i = tid; i < 3 * N; i += CFG::TB) {
+    double acc = 0.0;
+#pragma unroll
+    for (int w2 = 0; w2 < NW; ++w2) acc += red[w2][i];
+    out[i] = acc;
+  }
+}
+
+// one workgroup per site: the group partials summed in a fixed order,
+// times 1/(L_x L_y)
+__global__ __launch_bounds__(256) void q_fric_reduce(const double* __restrict__ part, int ngroups, int N,
+                                                     double ainv, double* __restrict__ jz, double* __restrict__ bp) {
+  __shared__ double t3[3][256];
+  const int r = blockIdx.x, t = threadIdx.x;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  for (int g = t; g < ngroups; g += 256) {
+    const double* p = part + int64_t(g) * 3 * N;
+    a0 += p[r];
+    a1 += p[N + r];
+    a2 += p[2 * N + r];
+  }
+  t3[0][t] = a0;
+  t3[1][t] = a1;
+  t3[2][t] = a2;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (t < k) {
+      t3[0][t] += t3[0][t + k];
+      t3[1][t] += t3[1][t + k];
+      t3[2][t] += t3[2][t + k];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    jz[r] = ainv * t3[0][0];
+    bp[2 * r] = ainv * t3[1][0];
+    bp[2 * r + 1] = ainv * t3[2][0];
+  }
+}
+
+// one workgroup (N <= 256 sites): N = dVe sum 2 rho, div j = D1z j (direct
+// DFT, Nyquist zeroed), then the fields with the dissipative terms:
+//   hA = U + V_ext - mu - (alpha / rho0) div j,
+//   hD = Delta [1 + beta sin(theta_nu - theta_B') + i gamma (N - N_req) / N_req]
+template <typename R>
+__global__ __launch_bounds__(256) void q_fric_fields(int N, double dz, double dVe, const double* __restrict__ rho,
+                                                     const double* __restrict__ jz, const double* __restrict__ bp,
+                                                     const double* __restrict__ nu, const double* __restrict__ U,
+                                                     const double* __restrict__ delta, const double* __restrict__ vext,
+                                                     double mu, double alpha, double beta, double gamma,
+                                                     double rho0, double N_req, R* __restrict__ hA,
+                                                     cpx<R>* __restrict__ hD) {
+  __shared__ double sn[256];
+  __shared__ double jr[256], ji[256];
+  const int t = threadIdx.x;
+  sn[t] = t < N ? 2.0 * rho[t] : 0.0;
+  if (t < N) {  // j~_k = sum_z j_z exp(-2 pi i k z / N)
+    double re = 0.0, im = 0.0;
+    for (int z = 0; z < N; ++z) {
+      double s_, c_;
+      sincos(-2.0 * kPi * double((int64_t(t) * z) % N) / N, &s_, &c_);
+      re += jz[z] * c_;
+      im += jz[z] * s_;
+    }
+    jr[t] = re;
+    ji[t] = im;
+  }
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (t < k) sn[t] += sn[t + k];
+    __syncthreads();
+  }
+  const double Ntot = dVe * sn[0];
+  const double gt = N_req > 0.0 ? gamma * (Ntot - N_req) / N_req : 0.0;
+  if (t >= N) return;
+  double dj = 0.0;  // Re 1/N sum_k (i k) j~_k exp(2 pi i k z / N)
+  for (int k = 0; k < N; ++k) {
+    if (k == N / 2) continue;
+    const double km = 2.0 * kPi / (N * dz) * double(k < N / 2 ? k : k - N);
+    double s_, c_;
+    sincos(2.0 * kPi * double((int64_t(k) * t) % N) / N, &s_, &c_);
+    // (i km)(jr + i ji)(c + i s), real part
+    dj += -km * (ji[k] * c_ + jr[k] * s_);
+  }
+  dj /= N;
+  const double th_nu = atan2(nu[2 * t + 1], nu[2 * t]);
+  const double th_b = atan2(bp[2 * t + 1], bp[2 * t]);
+  const double fr = 1.0 + beta * sin(th_nu - th_b), fi = gt;
+  const double dr = delta[2 * t], di = delta[2 * t + 1];
+  hA[t] = R(U[t] + vext[t] - mu - alpha / rho0 * dj);
+  hD[t] = cpx<R>{R(dr * fr - di * fi), R(dr * fi + di * fr)};
+}
+
 // workgroup sizes the tuner chooses from (states per workgroup = TB / A)
 template <class F>
 void with_tb(int tb, F&& f) {
@@ -633,6 +828,23 @@ struct EngineQ1D final : Engine {
         });
       else
         c.launch(KC_SETUP, [&] { hipLaunchKernelGGL((q_pointwise<R, A, TB, PW_SCALE>), grid, block, 0, c.stream, P, nst); });
+    });
+  }
+  void friction(Ctx& c, const void* X, const double* scale, int64_t nst) override {
+    twiddles(c);
+    const unsigned ng = cdiv(nst, G);
+    const double kz = 2 * kPi / (N * c.lat.dz);
+    c.launch(KC_FRICTION, [&] {
+      with_tb(tb[0], [&](auto t) {
+        constexpr int TB = decltype(t)::value;
+        hipLaunchKernelGGL((q_fric<R, A, G, TB>), dim3(ng), dim3(TB), 0, c.stream, (const cpx<R>*)X, nst, c.wu,
+                           c.wv, scale, c.kperp2, c.fric_part, tw, kz);
+      });
+      hipLaunchKernelGGL(q_fric_reduce, dim3(N), dim3(256), 0, c.stream, c.fric_part, int(ng), N, c.ainv, c.fric_j,
+                         c.fric_bp);
+      hipLaunchKernelGGL((q_fric_fields<R>), dim3(1), dim3(256), 0, c.stream, N, c.lat.dz, c.dVe, c.rho, c.fric_j,
+                         c.fric_bp, c.nu, c.U, c.delta, c.vext, c.fun.mu, c.f_alpha, c.f_beta, c.f_gamma, c.f_rho0,
+                         c.f_Nreq, (R*)c.hA, (cpx<R>*)c.hD);
     });
   }
   void grad(Ctx& c, const void* X, const double* scale, int64_t n0, int64_t nchunk) override {

@@ -103,6 +103,7 @@ void prepare(Ctx& c, int b) {
   else
     c.eng->dens(c, c.sb[b], c.sscale[b], c.nst);
   c.eng->reduce_pot(c, !c.frozen);
+  if (c.fric && !c.frozen) c.eng->friction(c, c.sb[b], c.sscale[b], c.nst);
   c.eng->lap1(c, c.sb[b], c.sscale[b], true, c.nst);
   fin(c, c.nst, c.sscale[b], false, true);
   c.fields_valid = true;
@@ -117,6 +118,7 @@ void prepare_eval(Ctx& c, int b) {
   }
   c.eng->dens_sum(c, c.sb[b], c.sscale[b], c.nst);
   c.eng->reduce_pot(c, !c.frozen);
+  if (c.fric && !c.frozen) c.eng->friction(c, c.sb[b], c.sscale[b], c.nst);
   c.fields_valid = true;
 }
 
@@ -723,6 +725,28 @@ tdslda_status tdslda_apply_hbdg(tdslda_ctx* c, const void* in_dev, void* out_dev
     d.out = out_dev;
     c->eng->lap2(*c, d, n);
     HIPCHK(hipStreamSynchronize(c->stream));
+  });
+}
+
+tdslda_status tdslda_set_friction(tdslda_ctx* c, double alpha, double beta, double gamma, double rho0,
+                                  double N_req) {
+  return guard(c, [&] {
+    require(c->q1d, TDSLDA_EINVAL, "quantum friction is built for the quasi-1D kernel set");
+    require(std::isfinite(alpha) && std::isfinite(beta) && std::isfinite(gamma) && std::isfinite(N_req) &&
+                std::isfinite(rho0) && rho0 > 0.0,
+            TDSLDA_EINVAL, "friction parameters must be finite, rho0 > 0");
+    c->f_alpha = alpha;
+    c->f_beta = beta;
+    c->f_gamma = gamma;
+    c->f_rho0 = rho0;
+    c->f_Nreq = N_req > 0.0 ? N_req : 0.0;
+    c->fric = alpha != 0.0 || beta != 0.0 || (gamma != 0.0 && N_req > 0.0);
+    if (c->fric && !c->fric_part) {
+      const int64_t ng = cdiv(c->cap, c->eng->group());
+      c->fric_part = (double*)c->dalloc(sizeof(double) * 3 * size_t(ng) * c->M);
+      c->fric_j = (double*)c->dalloc(sizeof(double) * c->M);
+      c->fric_bp = (double*)c->dalloc(sizeof(double) * 2 * c->M);
+    }
   });
 }
 

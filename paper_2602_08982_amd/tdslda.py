@@ -86,6 +86,7 @@ _SIGS = {
                           C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double)],
     "tdslda_static_solve": [C.POINTER(Static), C.POINTER(Functional), C.c_void_p, C.c_void_p, C.c_void_p,
                             C.POINTER(C.c_double), C.POINTER(C.c_int), C.POINTER(C.c_int), C.c_void_p],
+    "tdslda_set_friction": [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double],
     "tdslda_interp2d": [C.c_int, C.c_int, C.c_double, C.c_double, C.c_void_p, C.c_int, C.c_int, C.c_double,
                         C.c_double, C.c_void_p],
     "tdslda_nn_nparams": [C.c_int],
@@ -253,6 +254,11 @@ class Context:
 
     def apply_hbdg(self, x_dev, y_dev, n):
         self._chk(self.lib.tdslda_apply_hbdg(self.h, _dev_ptr(x_dev), _dev_ptr(y_dev), int(n)))
+
+    def set_friction(self, alpha=0.0, beta=0.0, gamma=0.0, rho0=1.0, N_req=0.0):
+        """Quantum-friction terms of the quasi-1D evolution (tdslda_set_friction)."""
+        self._chk(self.lib.tdslda_set_friction(self.h, float(alpha), float(beta), float(gamma), float(rho0),
+                                               float(N_req)))
 
     def abm_step(self, nsteps=1):
         self._chk(self.lib.tdslda_abm_step(self.h, int(nsteps)))

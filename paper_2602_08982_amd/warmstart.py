@@ -230,7 +230,7 @@ def experiment(cfg, train_seeds, test_seeds, epochs=300, log=None):
     if its["plain"]:
         out.update(plain_iters_mean=float(np.mean(its["plain"])), warm_iters_mean=float(np.mean(its["warm"])),
                    plain_iters=its["plain"], warm_iters=its["warm"])
-    if coarse["coarse"]:
+    if coarse["coarse"] or coarse["coarse_broyden"]:
         # cost of a coarse iteration in target-lattice iterations, measured
         ratio = (coarse["coarse_s"] / max(1, coarse["coarse_it"])) / out["seconds_per_iteration"]
         cres = dict(lattice=[cfg["coarse"], cfg["coarse"], cfg["nz"]], cost_ratio=ratio, fallbacks=coarse["fallbacks"])
