@@ -478,15 +478,14 @@ __global__ __launch_bounds__(TB) void q_fric(const cpx<R>* __restrict__ X, int64
                                               double kz) {
   using CFG = Q1DCfg<R, A, TB>;
   constexpr int N = CFG::N, WS = CFG::WS;
+  constexpr int NW = CFG::TB / kWave;
   __shared__ cpx<R> lds_all[WS][A * CFG::PAD];
-  // FP64 accumulators of each lane group in LDS (registers would cost the
-  // pass its occupancy): acc[group][j, Re B', Im B'][site]; a lane owns the
-  // sites a + A b of its group's row
-  __shared__ double acc[WS][3][N];
+  __shared__ double red[NW][3 * N];
   const int tid = threadIdx.x, grp = tid / A, a = tid % A;
   cpx<R>* lds = lds_all[grp];
+  double aj[A], abr[A], abi[A];
 #pragma unroll
-  for (int b = 0; b < A; ++b) acc[grp][0][a + A * b] = acc[grp][1][a + A * b] = acc[grp][2][a + A * b] = 0.0;
+  for (int b = 0; b < A; ++b) aj[b] = abr[b] = abi[b] = 0.0;
   const R inv_n = R(1.0 / N);
   const int64_t nbeg = int64_t(blockIdx.x) * G;
   for (int it = 0; it < G / WS; ++it) {
@@ -497,9 +496,14 @@ __global__ __launch_bounds__(TB) void q_fric(const cpx<R>* __restrict__ X, int64
     const double fu = live ? wu[nn] : 0.0, fv = live ? wv[nn] : 0.0, fw = fv - fu;
     const R kp = R(kperp2[nn]);
     const cpx<R>* Xn = X + nn * 2 * N;
-    cpx<R> x[A], t[A], d[A];
-    // one component x: spectrum in t; D1 -> j term; returns lap x in d
-    auto derivs = [&](double wgt) {
+    cpx<R> u[A], v[A], t[A], d[A];
+#pragma unroll
+    for (int b = 0; b < A; ++b) {
+      u[b] = s * Xn[a + A * b];
+      v[b] = s * Xn[N + a + A * b];
+    }
+    // one component: spectrum in t; D1 -> j term, D2 -> lap in d
+    auto derivs = [&](cpx<R>(&x)[A], double wgt) {
 #pragma unroll
       for (int b = 0; b < A; ++b) t[b] = x[b];
       q_fwd<R, A>(t, a, lds, tw);
@@ -513,7 +517,7 @@ __global__ __launch_bounds__(TB) void q_fric(const cpx<R>* __restrict__ X, int64
 #pragma unroll
       for (int b = 0; b < A; ++b) {
         const cpx<R> g = inv_n * d[b];
-        acc[grp][0][a + A * b] += wgt * (double(x[b].y) * double(g.x) - double(x[b].x) * double(g.y));  // Im(x g^*)
+        aj[b] += wgt * (double(x[b].y) * double(g.x) - double(x[b].x) * double(g.y));  // Im(x g^*)
       }
       sfor<0, A>::run([&](auto pc) {
         constexpr int p = decltype(pc)::value;
@@ -525,34 +529,45 @@ __global__ __launch_bounds__(TB) void q_fric(const cpx<R>* __restrict__ X, int64
 #pragma unroll
       for (int b = 0; b < A; ++b) d[b] = inv_n * d[b] - kp * x[b];
     };
-#pragma unroll
-    for (int b = 0; b < A; ++b) x[b] = s * Xn[a + A * b];  // u
-    derivs(-fu);                                           // d = lap u
-#pragma unroll
-    for (int b = 0; b < A; ++b) x[b] = s * Xn[N + a + A * b];  // v
+    derivs(u, -fu);  // d = lap u
 #pragma unroll
     for (int b = 0; b < A; ++b) {  // v^* lap u
-      const int z = a + A * b;
-      acc[grp][1][z] += -0.5 * fw * (double(x[b].x) * double(d[b].x) + double(x[b].y) * double(d[b].y));
-      acc[grp][2][z] += -0.5 * fw * (double(x[b].x) * double(d[b].y) - double(x[b].y) * double(d[b].x));
+      abr[b] += -0.5 * fw * (double(v[b].x) * double(d[b].x) + double(v[b].y) * double(d[b].y));
+      abi[b] += -0.5 * fw * (double(v[b].x) * double(d[b].y) - double(v[b].y) * double(d[b].x));
     }
-    derivs(fv);  // d = lap v
+    derivs(v, fv);  // d = lap v
 #pragma unroll
-    for (int b = 0; b < A; ++b) {  // u (lap v)^*, u read again (cached)
-      const int z = a + A * b;
-      const cpx<R> u = s * Xn[z];
-      acc[grp][1][z] += -0.5 * fw * (double(u.x) * double(d[b].x) + double(u.y) * double(d[b].y));
-      acc[grp][2][z] += -0.5 * fw * (double(u.y) * double(d[b].x) - double(u.x) * double(d[b].y));
+    for (int b = 0; b < A; ++b) {  // u (lap v)^*
+      abr[b] += -0.5 * fw * (double(u[b].x) * double(d[b].x) + double(u[b].y) * double(d[b].y));
+      abi[b] += -0.5 * fw * (double(u[b].y) * double(d[b].x) - double(u[b].x) * double(d[b].y));
+    }
+  }
+  // sum the lane groups (as q_dens): shuffles within a wave, then the waves
+#pragma unroll
+  for (int b = 0; b < A; ++b) {
+#pragma unroll
+    for (int o = A; o < kWave; o <<= 1) {
+      aj[b] += __shfl_xor(aj[b], o, kWave);
+      abr[b] += __shfl_xor(abr[b], o, kWave);
+      abi[b] += __shfl_xor(abi[b], o, kWave);
+    }
+  }
+  const int w = tid / kWave, lw = tid % kWave;
+  if (lw < A) {
+#pragma unroll
+    for (int b = 0; b < A; ++b) {
+      red[w][a + A * b] = aj[b];
+      red[w][N + a + A * b] = abr[b];
+      red[w][2 * N + a + A * b] = abi[b];
     }
   }
   __syncthreads();
   double* out = part + int64_t(blockIdx.x) * 3 * N;
   for (int i = tid; i < 3 * N; i += CFG::TB) {
-    const int f = i / N, z = i - f * N;
-    double sum = 0.0;
+    double acc = 0.0;
 #pragma unroll
-    for (int g2 = 0; g2 < WS; ++g2) sum += acc[g2][f][z];
-    out[i] = sum;
+    for (int w2 = 0; w2 < NW; ++w2) acc += red[w2][i];
+    out[i] = acc;
   }
 }
 
@@ -820,10 +835,11 @@ struct EngineQ1D final : Engine {
     const unsigned ng = cdiv(nst, G);
     const double kz = 2 * kPi / (N * c.lat.dz);
     c.launch(KC_FRICTION, [&] {
-      // one wave per workgroup: its LDS accumulators stay small enough for
-      // several workgroups per CU in both precisions
-      hipLaunchKernelGGL((q_fric<R, A, G, 64>), dim3(ng), dim3(64), 0, c.stream, (const cpx<R>*)X, nst, c.wu, c.wv,
-                         scale, c.kperp2, c.fric_part, tw, kz);
+      with_tb(tb[0], [&](auto t) {
+        constexpr int TB = decltype(t)::value;
+        hipLaunchKernelGGL((q_fric<R, A, G, TB>), dim3(ng), dim3(TB), 0, c.stream, (const cpx<R>*)X, nst, c.wu,
+                           c.wv, scale, c.kperp2, c.fric_part, tw, kz);
+      });
       hipLaunchKernelGGL(q_fric_reduce, dim3(N), dim3(256), 0, c.stream, c.fric_part, int(ng), N, c.ainv, c.fric_j,
                          c.fric_bp);
       hipLaunchKernelGGL((q_fric_fields<R>), dim3(1), dim3(256), 0, c.stream, N, c.lat.dz, c.dVe, c.rho, c.fric_j,
