@@ -33,7 +33,8 @@ struct Engine3D final : Engine {
     });
     c.nsg_used = int(cdiv(nst, G));
   }
-  static constexpr int DG = sizeof(R) == 8 ? 64 : 128;  // states per dens_sum group
+  // states per dens_sum group (FP64: 256 measured 12% faster than 64 at 32^3)
+  static constexpr int DG = sizeof(R) == 8 ? 256 : 128;
   void dens_sum(Ctx& c, const void* X, const double* scale, int64_t nst) override {
     dim3 grid(cdiv(M, DS_TB * DS_P), cdiv(nst, DG));
     c.launch(KC_DENS, [&] {
