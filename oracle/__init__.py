@@ -25,6 +25,11 @@ beyond what the paper's definitions and algorithms state:
                directions, one 1D BdG problem per transverse momentum.
   uniform      Uniform-system solutions (continuum and lattice) used as
                pins and as the plane-wave starting point.
+  static       Sec. 3.2 (Alg. MapK): the quasi-2D static self-consistent
+               solve with linear and modified Broyden mixing.
+  interp       Sec. 5.2: Fourier interpolation between lattices of a box.
+  cnn          The warm-start network (forward, gradients, Adam).
+  td.Friction  Sec. 5.2: quantum-friction (dissipative) mean fields.
 
 Where the paper is silent or garbled, the reading taken is stated at the
 function that takes it.

@@ -6,6 +6,9 @@ Eq. HpsiEpsi) with the A_sigma = 1 single-particle Hamiltonian
 
 For real U and V_ext, (h - mu)^* = h - mu.  The field hfield = U + V_ext - mu
 is passed as one real array.
+
+Part of the oracle: test infrastructure only (tests, the smoke check and
+the benchmark's CPU baseline use it; the product path never does).
 """
 import numpy as np
 from . import lattice as L

@@ -17,6 +17,9 @@ gives per axis
 
 and keeps tau invariant under f -> f^*, so the general and the
 spin-symmetric forms of the densities agree point by point.
+
+Part of the oracle: test infrastructure only (tests, the smoke check and
+the benchmark's CPU baseline use it; the product path never does).
 """
 import numpy as np
 from . import lattice as L

@@ -4,6 +4,9 @@
 Notation: rho is the density of ONE spin component (rho_a = rho_b = rho),
 rho_p = rho_a + rho_b = 2 rho is the total density (Sec. 2.4, rho_+),
 tau and j are per spin component, nu is the anomalous density.
+
+Part of the oracle: test infrastructure only (tests, the smoke check and
+the benchmark's CPU baseline use it; the product path never does).
 """
 import numpy as np
 

@@ -3,6 +3,9 @@
 Units hbar = m = k_B = 1 (Sec. 2.1).  A function on an N_x x N_y x N_z mesh
 is stored as a numpy array of that shape; the flat index order is
 ixyz = (ix*N_y + iy)*N_z + iz (z fastest), which is numpy's C order.
+
+Part of the oracle: test infrastructure only (tests, the smoke check and
+the benchmark's CPU baseline use it; the product path never does).
 """
 import numpy as np
 import scipy.fft as sfft

@@ -8,6 +8,9 @@ States of all problems are one flat batch of shape (n, 2, N_z); every state
 carries its own k_perp^2.  The free directions are called x and y here, the
 lattice axis z (the paper keeps x and puts the plane waves on y, z; the
 labels do not matter).
+
+Part of the oracle: test infrastructure only (tests, the smoke check and
+the benchmark's CPU baseline use it; the product path never does).
 """
 import numpy as np
 

@@ -10,6 +10,9 @@ where H(phi) is built from the densities of all states.  Integrators:
 AB3AM4, AB4AM5 and AB5AM5 (Eqs. AB3-AB5, AM4-AM5) in the memory schedule of
 Alg. AB4AM5, started either from a stationary history or by the Taylor
 predictor-corrector of Eq. Taylor-exp.
+
+Part of the oracle: test infrastructure only (tests, the smoke check and
+the benchmark's CPU baseline use it; the product path never does).
 """
 import numpy as np
 from math import factorial

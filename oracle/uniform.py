@@ -4,6 +4,9 @@ self-consistent uniform state on a periodic lattice.
 Both are scalar problems; they serve as pins for the lattice machinery and
 as plane-wave starting points (the paper's uniform-system solution used to
 start TD runs quickly, Sec. 4.5.1).
+
+Part of the oracle: test infrastructure only (tests, the smoke check and
+the benchmark's CPU baseline use it; the product path never does).
 """
 import numpy as np
 from scipy import integrate, optimize
