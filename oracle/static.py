@@ -10,9 +10,9 @@ weighted by their multiplicity (1 for m = 0 and m = -N_z/2, 2 otherwise).
 The map K of Alg. MapK (H -> eigenpairs -> densities -> potentials), the
 linear and modified Broyden mixing of the potentials, the fixed-N
 chemical-potential update of
-Eq. update-mu and the convergence test (residual of the potentials and of
-N; readings in the design notes) are written out plainly: dense matrices,
-numpy.linalg.eigh, FP64.
+Eq. update-mu and the convergence test (the largest change of the
+potentials relative to eF_ref, and of N relative to N_req) are written out
+plainly: dense matrices, numpy.linalg.eigh, FP64.
 """
 import numpy as np
 

@@ -29,7 +29,8 @@ SOURCES = [
 
 FLAGS = [
     "-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
-    # no packed-FP32 VALU instructions (see the design notes)
+    # no packed-FP32 VALU instructions: some of their forms have given wrong
+    # results on this hardware without any error
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
 
