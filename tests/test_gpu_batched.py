@@ -192,3 +192,22 @@ def test_batched_q1d_fullsize():
         assert np.isfinite(e1["total"])
     finally:
         ctx.close()
+
+
+def test_graph_advance_with_friction_equals_eager():
+    """The recorded advance includes the quantum-friction passes: abm_graph
+    and abm_step give bit-identical states with all three terms on."""
+    t = T()
+    a, b = _q1d_ctx(t, 0), _q1d_ctx(t, 0)
+    try:
+        for c in (a, b):
+            N0 = c.energy()["N"]
+            c.set_friction(alpha=5.0, beta=5.0, gamma=0.1, rho0=0.05, N_req=1.01 * N0)
+            c.abm_step(0)
+        for k in (3, 4):
+            a.abm_step(k)
+            b.abm_graph(k)
+            assert np.array_equal(a.get_states(), b.get_states())
+    finally:
+        a.close()
+        b.close()
