@@ -350,6 +350,77 @@ __global__ __launch_bounds__(TB) void q_lap2(Lap2Args<R> P, int64_t nstates, con
   }
 }
 
+// The corrector in a split layout: a state is owned by 2A lanes, the first
+// A hold u and the others v (sites z = a + A b each), so every lane
+// transforms one component and H couples the components site by site
+// through one lane exchange; <H>_n = Re <phi|H phi> dz over the 2A lanes.
+// Half the arrays per lane of the one-group form (more waves per SIMD),
+// which pays for the corrector; for F and FULL the one-group form measured
+// faster.
+template <typename R, int A, int TB>
+__global__ __launch_bounds__(TB) void q_corr_split(Lap2Args<R> P, int64_t nstates, const double* __restrict__ kperp2,
+                                                   const cpx<R>* __restrict__ tw, double kz2) {
+  constexpr int N = A * A, L = 2 * A, WS = TB / L, PAD = A + 1;
+  static_assert(TB % L == 0 && kWave % L == 0, "a state's lanes must sit in one wave");
+  __shared__ cpx<R> lds_all[2 * WS][A * PAD];
+  const int tid = threadIdx.x, grp = tid / L, l = tid % L, comp = l / A, a = l % A;
+  const int64_t n0 = int64_t(blockIdx.x) * WS + grp;
+  const bool live = n0 < nstates;  // dead groups still take part in the barriers
+  const int64_t n = live ? n0 : 0;
+  const R s = P.scale ? R(P.scale[n]) : R(1);
+  const R hk = R(0.5 * kperp2[n]);
+  const int64_t base = n * 2 * N + int64_t(comp) * N;
+  cpx<R> x[A], hx[A];
+#pragma unroll
+  for (int b = 0; b < A; ++b) {
+    x[b] = s * P.X[base + a + A * b];
+    hx[b] = x[b];
+  }
+  {
+    cpx<R>* lds = lds_all[2 * grp + comp];
+    const R f = R(-kz2 / double(N));
+    q_fwd<R, A>(hx, a, lds, tw);
+    sfor<0, A>::run([&](auto pc) {
+      constexpr int p = decltype(pc)::value;
+      const int m = q_wavenum<A>(a, freq_of_pos<A>(p));
+      hx[p] = (f * R(m * m)) * hx[p];
+    });
+    q_inv<R, A>(hx, a, lds, tw);
+  }
+  // u rows: -1/2 D2 u + fa u + D v;  v rows: -(-1/2 D2 v + fa v) + D^* u
+  const R sg = comp ? R(-1) : R(1);
+  double hloc = 0.0;
+#pragma unroll
+  for (int b = 0; b < A; ++b) {
+    const int z = a + A * b;
+    const cpx<R> y{__shfl_xor(x[b].x, A, L), __shfl_xor(x[b].y, A, L)};  // other component at z
+    const R fa = P.hA[z] + hk;
+    const cpx<R> D = P.hD[z];
+    const cpx<R> Dc = comp ? conj(D) : D;
+    hx[b] = sg * (R(-0.5) * hx[b] + fa * x[b]) + Dc * y;
+    hloc += double(x[b].x) * double(hx[b].x) + double(x[b].y) * double(hx[b].y);
+  }
+#pragma unroll
+  for (int o = A; o > 0; o >>= 1) hloc += __shfl_xor(hloc, o, L);
+  const R h = R(__shfl(hloc, 0, L) * P.dV);  // every lane takes the group's first sum
+  const R a0 = R(P.a[0]);
+  double nacc = 0.0;
+#pragma unroll
+  for (int b = 0; b < A; ++b) {
+    const int64_t ix = base + a + A * b;
+    const cpx<R> g = hx[b] - h * x[b];
+    const cpx<R> fv{g.y, -g.x};  // -i g
+    const cpx<R> nw = P.hist[0][ix] + a0 * fv;
+    if (live) P.Xout[ix] = nw;
+    nacc += norm2(nw);
+  }
+  if (P.nrm_part) {
+#pragma unroll
+    for (int o = A; o > 0; o >>= 1) nacc += __shfl_xor(nacc, o, L);
+    if (live && l == 0) P.nrm_part[n * P.nrm_stride] = nacc;
+  }
+}
+
 template <typename R, int A, int TB, int MODE, int NP = 4, int NQ = 5>
 __global__ __launch_bounds__(TB) void q_pointwise(PwArgs<R> P, int64_t nstates) {
   constexpr int HD = (NP > NQ - 1) ? NP : NQ - 1;
@@ -780,7 +851,10 @@ struct EngineQ1D final : Engine {
           c.launch(KC_LAP2_F, [&] { hipLaunchKernelGGL((q_lap2<R, A, TB, L2_F>), grid, block, 0, c.stream, P, nst, c.kperp2, tw, k2); });
           break;
         case L2_CORR:
-          c.launch(KC_LAP2_CORR, [&] { hipLaunchKernelGGL((q_lap2<R, A, TB, L2_CORR>), grid, block, 0, c.stream, P, nst, c.kperp2, tw, k2); });
+          c.launch(KC_LAP2_CORR, [&] {
+            hipLaunchKernelGGL((q_corr_split<R, A, TB>), dim3(cdiv(nst, TB / (2 * A))), block, 0, c.stream, P, nst,
+                               c.kperp2, tw, k2);
+          });
           break;
         case L2_FULL:
           c.launch(KC_LAP2_FULL, [&] {
