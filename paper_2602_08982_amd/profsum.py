@@ -51,7 +51,7 @@ def role(name):
         return "q1d_" + PW_MODES.get(int(m.group(1)), "scale")
     for pat, r in (("k_lap1<", "lap1"), ("k_dens_sum<", "dens"), ("k_dens<", "dens_kin"),
                    ("k_reduce_pot", "reduce_pot"), ("k_finalize", "finalize"), ("q_lap1<", "q1d_lap1"),
-                   ("q_dens<", "q1d_dens_kin")):
+                   ("q_dens<", "q1d_dens_kin"), ("q_corr_split<", "q1d_lap2_corr"), ("q_fric<", "q1d_friction")):
         if pat in name:
             return r
     return None
