@@ -136,10 +136,12 @@ def energy_density(rho, tau, jsq, nu, lam, fun):
     return kin + pot + pair + cm
 
 
-def energy_terms(rho, tau, j, nu, lam, vext, fun, dV):
+def energy_terms(rho, tau, j, nu, lam, vext, fun, dV, dext=None):
     """Energy contributions of Sec. 3.2 (spin-symmetric, j = (jx, jy, jz)
-    per spin): E_kin, E_pot, E_pair, E_curr, E_pot.ext and their sum.
-    E_pair = -int Delta^* nu, which equals int g_eff |nu|^2."""
+    per spin): E_kin, E_pot, E_pair, E_curr, E_pot.ext, the external
+    pairing energy E_pair.ext = -int (Delta_ext nu^* + c.c.) (zero without
+    dext) and their sum.  E_pair = -int Delta^* nu, which equals
+    int g_eff |nu|^2."""
     U, delta, g = potentials(rho, nu, lam, fun)
     jsq = sum(np.abs(c) ** 2 for c in j)
     rho_s = np.maximum(rho, RHO_FLOOR / 2)
@@ -148,8 +150,9 @@ def energy_terms(rho, tau, j, nu, lam, vext, fun, dV):
     e_pair = -dV * np.sum(np.real(np.conj(delta) * nu))
     e_curr = dV * np.sum(2.0 * jsq / (2.0 * rho_s))
     e_ext = dV * np.sum(vext * 2.0 * rho)
-    tot = e_kin + e_pot + e_pair + e_curr + e_ext
-    return dict(kin=e_kin, pot=e_pot, pair=e_pair, curr=e_curr, potext=e_ext, total=tot)
+    e_pext = 0.0 if dext is None else -2.0 * dV * np.sum(np.real(dext * np.conj(nu)))
+    tot = e_kin + e_pot + e_pair + e_curr + e_ext + e_pext
+    return dict(kin=e_kin, pot=e_pot, pair=e_pair, curr=e_curr, potext=e_ext, pairext=e_pext, total=tot)
 
 
 def fermi_weight(E, T=0.0):

@@ -91,11 +91,15 @@ class TDSystem:
     never refreshed, so that U is the exact derivative of the energy);
     wu, wv: frozen thermal weights f(E_n), f(-E_n) (Sec. 2.5).
     frozen=(hfield, delta) switches to linear mode (fields not rebuilt);
-    friction (a Friction) adds the dissipative fields."""
+    friction (a Friction) adds the dissipative fields.
+    dext: external pairing potential Delta_ext(r) (Sec. 2.2, Eq. E_tot; None
+    = 0).  The off-diagonal of H is Delta + Delta_ext (Eq. HpsiEpsi and its
+    time-dependent form), in linear mode too; Delta itself stays -g nu."""
 
-    def __init__(self, geom, fun, mu, vext, lam, wu, wv, frozen=None, friction=None):
+    def __init__(self, geom, fun, mu, vext, lam, wu, wv, frozen=None, friction=None, dext=None):
         self.geom, self.fun, self.mu = geom, fun, float(mu)
         self.friction = friction
+        self.dext = None if dext is None else np.asarray(dext, complex)
         self.vext = np.asarray(vext, float)
         self.lam = np.asarray(lam, float)
         self.wu = np.asarray(wu, float)
@@ -104,14 +108,18 @@ class TDSystem:
         self.n_f_evals = 0
 
     def fields(self, phi):
-        """Densities -> potentials -> (hfield = U + V_ext - mu, Delta)."""
+        """Densities -> potentials -> (hfield = U + V_ext - mu, the
+        off-diagonal field Delta + Delta_ext)."""
         if self.frozen is not None:
-            return self.frozen
+            hf, de = self.frozen
+            return hf, de if self.dext is None else de + self.dext
         rho, nu = self.geom.rho_nu(phi, self.wu, self.wv)
         U, delta, _ = F.potentials(rho, nu, self.lam, self.fun)
         if self.friction is not None:
             Ud, Dd = self.friction.terms(self.geom, phi, self.wu, self.wv, nu, delta)
-            return U + Ud + self.vext - self.mu, delta + Dd
+            U, delta = U + Ud, delta + Dd
+        if self.dext is not None:
+            delta = delta + self.dext
         return U + self.vext - self.mu, delta
 
     def expect(self, phi, hphi):
@@ -215,12 +223,12 @@ def evolve(sys, phi0, dt, nsteps, scheme="AB4AM5", selfstart=1, r=5, callback=No
 
 
 def observables(sys, phi):
-    """Energy terms of Sec. 3.2, particle number N = int rho_+ dV and the
-    free-gas normalisation E_FG = 3/5 N eF of the uniform system with the
-    same mean density."""
+    """Energy terms of Sec. 3.2 (the external pairing energy included),
+    particle number N = int rho_+ dV and the free-gas normalisation
+    E_FG = 3/5 N eF of the uniform system with the same mean density."""
     g = sys.geom
     rho, tau, nu, j = g.full_densities(phi, sys.wu, sys.wv)
-    terms = F.energy_terms(rho, tau, j, nu, sys.lam, sys.vext, sys.fun, g.dV_energy)
+    terms = F.energy_terms(rho, tau, j, nu, sys.lam, sys.vext, sys.fun, g.dV_energy, dext=sys.dext)
     N = g.dV_energy * np.sum(2.0 * rho)
     vol = g.dV_energy * np.prod(rho.shape)
     terms["N"] = N
