@@ -24,19 +24,34 @@ PEAK_HBM = 8.0e12  # MI355X HBM3E, bytes/s
 COUNTERS_MD = os.path.join(ROOT, "profiles", "lap2_full_fp64_32_fp32_48_hbm_counters.md")
 
 
-def algorithmic_bytes(kernel, S, nst, depth, fused=False):
-    """Bytes a launch of each kernel must move for nst states of S bytes
-    (its inputs read once and outputs written once).  fused: the quasi-1D
-    kernel set, whose F / CORR / FULL passes take D2z phi themselves (no T)."""
-    table = {
-        "dens": 1, "lap1": 2, "lap2_corr": 4, "lap2_f": 3, "lap2_h": 3,
-        "lap2_full": 2 + (depth - 1) + 3,   # phi, T, f_{k-1..k-D+1}; f_k, p, c
-        "pred": 1 + depth + 2,              # phi, f_{k-1..k-D}; p, c
-        "lap2_taylor": 4, "norm": 1,
+def algorithmic_bytes(kernel, S, nst, depth, fused=False, design=False):
+    """Bytes a launch of each kernel moves for nst states of S bytes.
+
+    Method bytes (default): what the step of Alg. AB4AM5 must move with the
+    state on chip, 12 S per step: a density pass reads phi (1 S); the
+    corrector pass reads phi and the partial corrector c and writes phi_new
+    (3 S); the full pass reads phi and f_{k-1..k-D+1} and writes f_k, the
+    next predictor p and partial corrector c (1 + (D - 1) + 3 = 7 S at
+    D = 4).  The x-line pass of the split 3D Laplacian and the T = D2x phi
+    read of the slab passes are this design's own traffic: 0 method bytes.
+    design=True: the bytes the 3D kernels actually read and write once
+    (T included: lap1 2 S, corrector 4 S, full pass 8 S).  The quasi-1D
+    kernel set (fused=True) keeps each state in one lane group, so its
+    design bytes are the method bytes."""
+    method = {
+        "dens": 1, "lap1": 0, "lap2_corr": 3, "lap2_f": 2, "lap2_h": 2,
+        "lap2_full": 1 + (depth - 1) + 3,
+        "pred": 1 + depth + 2,
+        "lap2_taylor": 3, "norm": 1,
     }
-    if fused:
-        table.update({"lap2_corr": 3, "lap2_f": 2, "lap2_full": 1 + (depth - 1) + 3})
+    split = dict(method, lap1=2, lap2_corr=4, lap2_f=3, lap2_h=3, lap2_full=2 + (depth - 1) + 3, lap2_taylor=4)
+    table = split if (design and not fused) else method
     return table[kernel] * S * nst if kernel in table else None
+
+
+def step_roofline(S):
+    """Roofline state-steps/s of the method: 12 S per state-step at 8 TB/s."""
+    return PEAK_HBM / (12.0 * S)
 
 
 def run_workload(cfg, steps, warmup, seed_vortex, profile=True, precision=None, observe=False):
@@ -83,9 +98,11 @@ def run_workload(cfg, steps, warmup, seed_vortex, profile=True, precision=None, 
         if n == 0:
             continue
         b = algorithmic_bytes(k, S, nst, depth)
+        bd = algorithmic_bytes(k, S, nst, depth, design=True)
         avg = ms / n
         kern[k] = dict(launches=n, avg_ms=avg, total_ms=ms,
-                       gbps=(b / (avg * 1e-3) / 1e9) if b else None)
+                       gbps=(b / (avg * 1e-3) / 1e9) if b else None,
+                       design_gbps=(bd / (avg * 1e-3) / 1e9) if bd else None)
     ctx.close()
     del ctx
     return dict(nst=nst, seconds=dt, warm_seconds=t_warm, value=nst * steps / dt,
@@ -124,19 +141,22 @@ def track_precision(steps, every, warmup, seed_vortex=4):
     return out
 
 
-def run_q1d(steps, warmup, seed=7, profile_steps=2, friction=False):
+def run_q1d(steps, warmup, seed=7, profile_steps=2, friction=False, precision=None):
     """Batched quasi-1D workload: set-up (device eigensolver), start-up and
     warm-up steps, launch-shape tuning, then `steps` steps recorded as one
     HIP graph and launched once (timed from launch to completion).
     friction: the same with the quantum-friction terms on (alpha = beta = 5,
-    gamma = 0.1, rho0 = the initial maximum density, N_req = the initial N)."""
+    gamma = 0.1, rho0 = the initial maximum density, N_req = the initial N).
+    precision: the context precision (default: the workload's FP32-mixed)."""
     import torch
     from paper_2602_08982_amd import tdslda as T
     from paper_2602_08982_amd import workloads as W
     t0 = time.perf_counter()
-    ctx, info = W.setup_q1d(W.Q1D, seed, stream=torch.cuda.current_stream().cuda_stream)
+    ctx, info = W.setup_q1d(W.Q1D, seed, stream=torch.cuda.current_stream().cuda_stream, precision=precision)
     t_setup = time.perf_counter() - t0
     nst = info["states"]
+    prec = W.Q1D["precision"] if precision is None else precision
+    S = 2 * W.Q1D["nz"] * (16 if prec == T.FP64 else 8)
     if friction:
         rho0 = float(ctx.densities()["rho"].max())
         ctx.set_friction(alpha=5.0, beta=5.0, gamma=0.1, rho0=rho0, N_req=ctx.energy()["N"])
@@ -151,7 +171,6 @@ def run_q1d(steps, warmup, seed=7, profile_steps=2, friction=False):
         ctx.abm_step(profile_steps)
         stats = ctx.kernel_stats()
         ctx.set_profiling(False)
-        S = 2 * W.Q1D["nz"] * 8
         for k, (n, ms) in stats.items():
             if n == 0:
                 continue
@@ -163,62 +182,84 @@ def run_q1d(steps, warmup, seed=7, profile_steps=2, friction=False):
     info = {k: v for k, v in info.items() if k not in ("kperp2", "counts")}
     return dict(nst=nst, steps=steps, seconds=dt, value=nst * steps / dt, ms_per_step=1e3 * dt / steps,
                 graph_record_ms=rec_ms, setup_seconds=t_setup, tuned=tuned, kernels=kern,
-                profile_steps=profile_steps,
+                profile_steps=profile_steps, S=S,
                 check=dict(status=st, **chk), problems=info)
 
 
 def copy_bandwidth():
-    """Bytes moved per second by a plain device-to-device copy of 4 GiB
-    (read + write), median of 5: the practical HBM ceiling on this device."""
+    """Bytes moved per second (read + write) by the library's streaming copy
+    kernel (tdslda_device_copy) over 4 GiB, median of 5, timed with HIP
+    events on the stream it is launched on: the plain read-once / write-once
+    reference on this device."""
     import torch
-    a = torch.ones(1 << 29, dtype=torch.float64, device="cuda")
+    from paper_2602_08982_amd import tdslda as T
+    n = 1 << 29
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
-    b.copy_(a)
+    st = torch.cuda.current_stream()
+    T.device_copy(b, a, 8 * n, st.cuda_stream)
     ts = []
     for _ in range(5):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        b.copy_(a)
-        e1.record()
+        e0.record(st)
+        T.device_copy(b, a, 8 * n, st.cuda_stream)
+        e1.record(st)
         torch.cuda.synchronize()
         ts.append(e0.elapsed_time(e1) * 1e-3)
+    ok = bool(torch.equal(a, b))
     del a, b
     torch.cuda.empty_cache()
-    return 2 * (1 << 29) * 8 / sorted(ts)[2]
+    if not ok:
+        raise RuntimeError("device copy produced wrong data")
+    return 2 * n * 8 / sorted(ts)[2]
 
 
 def roofline(res, copy_bps=None, prec=None, nx=None, role_prefix=""):
-    """Dominant kernel of the timed steps against the HBM peak.  traffic =
-    HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE summary
-    (copy-calibrated), null when that summary does not cover this kernel or
-    the kernel sources changed since the counters were taken."""
+    """Dominant kernel of the timed steps against the HBM peak.
+    achieved = method bytes per launch (algorithmic_bytes) / mean launch
+    time; the kernel's own read-once / write-once bytes (the split-Laplacian
+    intermediate included) are reported beside it as design_*.
+    step_frac = state-steps/s / the method's roofline rate 8 TB/s / (12 S).
+    traffic = HBM bytes per launch from the committed FETCH_SIZE /
+    WRITE_SIZE summary (copy-calibrated), null when that summary does not
+    cover this kernel or the kernel sources changed since the counters
+    were taken."""
     kern = res["kernels"]
     if not kern:
         return None
     dom = max(kern, key=lambda k: kern[k]["total_ms"])
     g = kern[dom]["gbps"]
+    gd = kern[dom].get("design_gbps")
+    avg_s = kern[dom]["avg_ms"] * 1e-3
     traffic = None
     if prec is not None:
         from paper_2602_08982_amd import profsum
         traffic = profsum.read_traffic(COUNTERS_MD, prec, nx, role_prefix + dom)
     out = dict(bound="hbm", kernel=dom, achieved=g, peak=PEAK_HBM / 1e9, unit="GB/s",
                frac=(g * 1e9 / PEAK_HBM) if g else None, traffic=traffic,
-               share_of_step=kern[dom]["total_ms"] / (res["ms_per_step"] * res["steps"]))
-    if traffic is not None and g:
-        alg = g * 1e9 * kern[dom]["avg_ms"] * 1e-3
-        out["algorithmic_bytes"] = alg
-        out["traffic_over_algorithmic"] = traffic / alg
+               method_bytes_per_launch=(g * 1e9 * avg_s) if g else None,
+               share_of_step=kern[dom]["total_ms"] / (res["ms_per_step"] * res["steps"]),
+               step_frac=res["value"] / step_roofline(res["S"]))
+    if gd is not None:
+        out["design_bytes_per_launch"] = gd * 1e9 * avg_s
+        out["design_achieved"] = gd
+        out["design_frac"] = gd * 1e9 / PEAK_HBM
+    if traffic is not None:
+        out["traffic_GBps"] = traffic / avg_s / 1e9
+        if g:
+            out["traffic_over_method_bytes"] = traffic / (g * 1e9 * avg_s)
     if copy_bps:
         out["copy_GBps"] = copy_bps / 1e9
         out["frac_of_copy"] = g * 1e9 / copy_bps if g else None
     return out
 
 
-def cpu_baseline(nsample=1024, steps=3):
+def cpu_baseline(nsample=1024, steps=3, workers=-1):
     """The FP64 oracle on a bounded sample of the same workload: nsample
     plane-wave states of the 32^3 trapped gas (trap + vortex), stationary
     start (one f evaluation), then `steps` AB4AM5 steps; the rate is
-    nsample * steps / time of those steps."""
+    nsample * steps / time of those steps.  workers: scipy.fft threads of
+    the oracle (-1 = every host core, 1 = a single core)."""
     from oracle import lattice as L, bdg, functional as F, td
     from paper_2602_08982_amd import workloads as W
     import synth
@@ -234,16 +275,21 @@ def cpu_baseline(nsample=1024, steps=3):
     lam = F.lambda_c(vext, cfg["mu"], 0.5 * np.pi ** 2)
     sysm = td.TDSystem(td.Geometry3D(lat), F.Functional(F.SLDA), cfg["mu"], vext, lam,
                        F.fermi_weight(E), F.fermi_weight(-E))
-    p, hist, _ = td.start(sysm, phi, cfg["dt"], "AB4AM5", selfstart=0)
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        p, hist = td.abm_step(sysm, p, hist, cfg["dt"])
-    dt = time.perf_counter() - t0
-    cores = os.cpu_count()
+    saved = L._WORKERS
+    L._WORKERS = workers
+    try:
+        p, hist, _ = td.start(sysm, phi, cfg["dt"], "AB4AM5", selfstart=0)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            p, hist = td.abm_step(sysm, p, hist, cfg["dt"])
+        dt = time.perf_counter() - t0
+    finally:
+        L._WORKERS = saved
+    cores = os.cpu_count() if workers == -1 else workers
     return dict(value=nsample * steps / dt, unit="state-steps/s", cores=cores, kind="oracle",
                 sample=f"{nsample} of the 32768 states of the 32^3 FP64 workload (seeded choice), "
                        f"{steps} AB4AM5 steps after a stationary start, timed steps only; "
-                       f"scipy.fft with workers=-1 ({cores} host threads)", seconds=dt)
+                       f"scipy.fft with workers={workers} ({cores} host threads)", seconds=dt)
 
 
 def main():
@@ -261,6 +307,8 @@ def main():
                          "200 / 40 (about ten minutes); large: 24x24x8, 100 / 20, Broyden mixing only")
     ap.add_argument("--q1d-steps", type=int, default=2000,
                     help="steps of the batched quasi-1D run (one graph launch)")
+    ap.add_argument("--q1d-fp64-steps", type=int, default=500,
+                    help="steps of the FP64 run of the batched quasi-1D workload (one graph launch; 0 = skip)")
     ap.add_argument("--q1d-friction", action="store_true",
                     help="also time the batched quasi-1D run with the quantum-friction terms on")
     ap.add_argument("--mixed-steps", type=int, default=None,
@@ -329,6 +377,11 @@ def main():
         q1d = run_q1d(args.q1d_steps, max(1, args.warmup))
         print(f"# batched q1d: {q1d['value']:.4g} state-steps/s over {q1d['steps']} steps "
               f"({q1d['nst']} states), graph record {q1d['graph_record_ms']:.0f} ms", file=sys.stderr, flush=True)
+    q1d64 = None
+    if not args.no_q1d and args.q1d_fp64_steps > 0:
+        q1d64 = run_q1d(args.q1d_fp64_steps, max(1, args.warmup), precision=T.FP64, profile_steps=0)
+        print(f"# batched q1d FP64: {q1d64['value']:.4g} state-steps/s over {q1d64['steps']} steps",
+              file=sys.stderr, flush=True)
     warm = None
     if not args.no_warmstart:
         from paper_2602_08982_amd import warmstart as WS
@@ -353,7 +406,12 @@ def main():
                     print(f"# coarse-lattice start ({k} mixing): {cs[k]['coarse_iters_mean']:.1f} coarse + "
                           f"{cs[k]['fine_iters_mean']:.1f} target iterations = {cs[k]['target_equivalent']:.1f} "
                           f"target-equivalent (cost ratio {cs['cost_ratio']:.3f})", file=sys.stderr, flush=True)
-    cpu = None if args.no_cpu else cpu_baseline()
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline()
+        cpu["single_core"] = cpu_baseline(nsample=128, steps=2, workers=1)
+        print(f"# cpu oracle: {cpu['value']:.4g} state-steps/s ({cpu['cores']} threads), "
+              f"{cpu['single_core']['value']:.4g} on one core", file=sys.stderr, flush=True)
 
     line = {
         "metric": "TDSLDA quasiparticle state-steps/s + %HBM roofline, FP32-mixed vs FP64",
@@ -403,6 +461,10 @@ def main():
             "roofline": roofline(dict(q1d, steps=q1d["profile_steps"]), copy_bps, "float", 16, "q1d_")
             if q1d["kernels"] else None,
         }
+        if q1d64 is not None:
+            line["batched_q1d"]["vs_fp64_same_workload"] = dict(
+                fp64_value=q1d64["value"], fp64_ms_per_step=q1d64["ms_per_step"], fp64_steps=q1d64["steps"],
+                speedup=q1d["value"] / q1d64["value"], fp64_check=q1d64["check"])
     if warm is not None:
         line["learned_warm_start"] = {
             "workload": f"static quasi-2D solve, {warm['lattice'][0]}x{warm['lattice'][1]} x-y lattice, "

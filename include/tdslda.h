@@ -107,11 +107,20 @@ const char* tdslda_last_error(const tdslda_ctx* ctx);
 tdslda_status tdslda_memory_plan(const tdslda_lattice* lat, const tdslda_run* run,
                                  int64_t nstates, int64_t* bytes_out);
 
-/* External potential V_ext[M] (host, FP64), switched on from now on.  If
- * freeze_regulator != 0 the regulator Lambda_c(r) of Eq. Creg is (re)computed
- * from it with V_+ = V_ext and then kept frozen (the regulator is never
- * refreshed during TD). */
-tdslda_status tdslda_set_external(tdslda_ctx* ctx, const double* vext, int freeze_regulator);
+/* External fields (Sec. 2.2, Eq. E_tot), switched on from now on:
+ * V_ext[M] (host, FP64) and the external pairing potential
+ * Delta_ext[M][2] (host, FP64 re|im; NULL = 0).  H then carries U + V_ext -
+ * mu on the diagonal and Delta + Delta_ext off the diagonal (Eq. HpsiEpsi
+ * and its time-dependent form), in linear mode too; Delta itself stays
+ * -g_eff nu, and tdslda_energy adds E_pair.ext = -int (Delta_ext nu^* +
+ * c.c.).  With a non-zero Delta_ext the particle number is not conserved
+ * and tdslda_check checks E - mu N only.  If freeze_regulator != 0 the
+ * regulator Lambda_c(r) of Eq. Creg is (re)computed from V_ext with V_+ =
+ * V_ext and then kept frozen (the regulator is never refreshed during TD).
+ * Errors: EINVAL (vext NULL, non-finite Delta_ext, E_c below the local band
+ * bottom). */
+tdslda_status tdslda_set_external(tdslda_ctx* ctx, const double* vext, const double* dext_reim,
+                                  int freeze_regulator);
 /* Set the frozen regulator Lambda_c[M] directly (host, FP64). */
 tdslda_status tdslda_set_regulator(tdslda_ctx* ctx, const double* lam);
 
@@ -187,8 +196,11 @@ tdslda_status tdslda_abm_step(tdslda_ctx* ctx, int64_t nsteps);
  * grid-wide synchronisation point (density reductions included).  Requires
  * a started integrator (one tdslda_abm_step call, nsteps >= 0, after the
  * load) and profiling off.  graph_ms (may be NULL) = {record + instantiate
- * time, launch-to-completion time} in milliseconds.
- * Errors: EORDER before the start-up or with profiling on. */
+ * time, launch-to-completion time} in milliseconds.  If recording or
+ * instantiation fails, nothing has run and the context is left as before
+ * the call; if the launch itself fails, the context drops its states (a
+ * later call needs a new load, EORDER until then).
+ * Errors: EORDER before the start-up or with profiling on; EDEVICE. */
 tdslda_status tdslda_abm_graph(tdslda_ctx* ctx, int64_t nsteps, double graph_ms[2]);
 
 /* Launch-shape tuner: times each candidate workgroup size of every tunable
@@ -309,16 +321,19 @@ tdslda_status tdslda_nn_loss_grad(tdslda_nn* nn, int B, const float* x, const fl
 tdslda_status tdslda_nn_train_step(tdslda_nn* nn, int B, const float* x, const float* Y, const float* y_mu,
                                    float lam_mu, float lr, float* loss);
 
-/* Energy terms of Sec. 3.2 for the current states, host out[8]:
- * {E_kin, E_pot, E_pair, E_curr, E_pot.ext, E_total, N, E_FG} with
- * N = int rho_+ dV and E_FG = 3/5 N eF of the uniform gas of the same mean
- * density.  Quasi-1D integrals include the transverse area. */
-tdslda_status tdslda_energy(tdslda_ctx* ctx, double terms_out[8]);
+/* Energy terms of Sec. 3.2 for the current states, host out[9]:
+ * {E_kin, E_pot, E_pair, E_curr, E_pot.ext, E_total, N, E_FG, E_pair.ext}
+ * with E_total the sum of the five terms and E_pair.ext, N = int rho_+ dV
+ * and E_FG = 3/5 N eF of the uniform gas of the same mean density.
+ * Quasi-1D integrals include the transverse area. */
+tdslda_status tdslda_energy(tdslda_ctx* ctx, double terms_out[9]);
 
 /* Conservation check of Sec. 4.5.1 against the values at the first call
- * after a load: returns EUNSTABLE if |N-N0|/N0 > tol_N, |E-E0|/E_FG > tol_E,
- * or a state norm is not finite.  out[3] (may be NULL) = {dN/N0, dE/E_FG,
- * max |norm - 1|}. */
+ * after a load (or after tdslda_set_external): returns EUNSTABLE if
+ * |N-N0|/N0 > tol_N, |Omega-Omega0|/E_FG > tol_E with Omega = E_total - mu N
+ * (the quantity of Eq. E_tot, conserved at fixed mu), or a state norm is not
+ * finite.  The N check is skipped while Delta_ext is non-zero.  out[3] (may
+ * be NULL) = {dN/N0, dOmega/E_FG, max |norm - 1|}. */
 tdslda_status tdslda_check(tdslda_ctx* ctx, double out[3]);
 
 /* Copy the current normalised states to the host ([n][2][M][2] FP64). */
@@ -332,6 +347,16 @@ tdslda_status tdslda_info(tdslda_ctx* ctx, int64_t* nstates, int64_t* steps, dou
  * precision, integrator and capacity >= the saved state count. */
 tdslda_status tdslda_save(tdslda_ctx* ctx, const char* path);
 tdslda_status tdslda_load(tdslda_ctx* ctx, const char* path);
+
+/* Streaming device-to-device copy of `bytes` bytes on hip_stream (a
+ * hipStream_t; NULL = the null stream), asynchronous: 128-bit non-temporal
+ * loads and stores, consecutive lanes on consecutive words.  The HBM
+ * reference of the measurement (a plain read-once / write-once kernel of
+ * known traffic); also used by the stationary start-up to replicate the
+ * history.  dst and src are device pointers, 16-byte aligned, not
+ * overlapping; bytes >= 0 is a multiple of 16.  Errors: EINVAL (alignment,
+ * size, overlap), EDEVICE (launch failure). */
+tdslda_status tdslda_device_copy(void* dst, const void* src, int64_t bytes, void* hip_stream);
 
 /* Kernel timing.  With profiling on, every kernel launch is bracketed by HIP
  * events on the context stream; tdslda_kernel_stats returns, for kernel class

@@ -133,6 +133,8 @@ struct tdslda_ctx {
   int nsg_max = 1, nsg_used = 1;
   double *rho = nullptr, *nu = nullptr, *tau = nullptr, *jc = nullptr;
   double *U = nullptr, *delta = nullptr, *vext = nullptr, *lam = nullptr, *theta = nullptr;
+  double* dext = nullptr;  // external pairing potential [M][2] (zero unless set)
+  bool dext_on = false;
   void *hA = nullptr, *hD = nullptr;
   double* gscratch = nullptr;  // [gchunk][4][M] doubles (tau_s, j_s); also FP64 staging
   int64_t gchunk = 1;

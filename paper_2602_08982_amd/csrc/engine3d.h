@@ -46,7 +46,7 @@ struct Engine3D final : Engine {
   bool producer_kinetic() const override { return true; }
   int raw_h_slots() const override { return CFG::NGX; }
   void reduce_pot(Ctx& c, bool update) override {
-    FunParams fp{c.fun.functional, c.fun.B, c.fun.C, c.fun.inv_g_bdg, c.fun.mu, c.ainv};
+    FunParams fp{c.fun.functional, c.fun.B, c.fun.C, c.fun.inv_g_bdg, c.fun.mu, c.ainv, c.dext};
     c.launch(KC_REDUCE_POT, [&] {
       hipLaunchKernelGGL((k_reduce_pot<R>), dim3(cdiv(M, 256)), dim3(256), 0, c.stream, c.dens_part,
                          c.nsg_used, int64_t(M), fp, c.lam, c.vext, c.rho, c.nu, c.U, c.delta, (R*)c.hA,

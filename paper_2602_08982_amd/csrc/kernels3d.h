@@ -292,12 +292,14 @@ struct FunParams {
   double B, C, inv_g;  // constants
   double mu;
   double ainv;         // 1 in 3D, 1/(L_x L_y) in quasi-1D
+  const double* dext;  // external pairing potential [M][2] (added to Delta in H)
 };
 
 // reduce_pot: sum the state-group partials (fixed order) and build the
 // potentials pointwise: Delta = -g_eff nu with 1/g_eff = rho_+^(1/3)/C -
 // Lambda_c (SLDA) or 1/(4 pi a_s) - Lambda_c (BdG), U = B eF(rho_+) -
-// |Delta|^2 / (3 C rho_+^(2/3)) (SLDA, A=1) or 0 (BdG).
+// |Delta|^2 / (3 C rho_+^(2/3)) (SLDA, A=1) or 0 (BdG).  The off-diagonal
+// field of H is Delta + Delta_ext (Eq. HpsiEpsi).
 template <typename R>
 __device__ __forceinline__ void pot_from_sums(int64_t r, double sr, double snr, double sni, const FunParams& fp,
                                               const double* __restrict__ lam, const double* __restrict__ vext,
@@ -330,7 +332,7 @@ __device__ __forceinline__ void pot_from_sums(int64_t r, double sr, double snr, 
   delta[2 * r] = dr;
   delta[2 * r + 1] = di;
   hA[r] = R(u + vext[r] - fp.mu);
-  hD[r] = cpx<R>{R(dr), R(di)};
+  hD[r] = cpx<R>{R(dr + fp.dext[2 * r]), R(di + fp.dext[2 * r + 1])};
 }
 
 // one thread per site, groups summed in order
@@ -386,15 +388,16 @@ __global__ __launch_bounds__(256) void k_reduce_pot_wide(
                                update_fields);
 }
 
-// Frozen fields (linear mode): hA, hD from given U, Delta.
+// Frozen fields (linear mode): hA, hD from given U, Delta (hD = Delta +
+// Delta_ext).
 template <typename R>
 __global__ void k_set_fields(int64_t M, const double* __restrict__ U, const double* __restrict__ delta,
-                             const double* __restrict__ vext, double mu, R* __restrict__ hA,
-                             cpx<R>* __restrict__ hD) {
+                             const double* __restrict__ vext, const double* __restrict__ dext, double mu,
+                             R* __restrict__ hA, cpx<R>* __restrict__ hD) {
   const int64_t r = int64_t(blockIdx.x) * 256 + threadIdx.x;
   if (r >= M) return;
   hA[r] = R(U[r] + vext[r] - mu);
-  hD[r] = cpx<R>{R(delta[2 * r]), R(delta[2 * r + 1])};
+  hD[r] = cpx<R>{R(delta[2 * r] + dext[2 * r]), R(delta[2 * r + 1] + dext[2 * r + 1])};
 }
 
 // ---------------------------------------------------------------------------

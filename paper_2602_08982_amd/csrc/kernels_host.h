@@ -56,16 +56,18 @@ __global__ void k_grad_reduce(int64_t nchunk, int64_t M, double ainv, const doub
 
 // ---------------------------------------------------------------------------
 // Energy terms of Sec. 3.2 (A = 1, spin-symmetric) reduced in one block:
-// out = {E_kin, E_pot, E_pair, E_curr, E_ext, N}
+// out = {E_kin, E_pot, E_pair, E_curr, E_ext, N, E_pair.ext}
+// with E_pair.ext = -int (Delta_ext nu^* + c.c.)
 __global__ __launch_bounds__(1024) void k_energy(int64_t M, const double* __restrict__ rho,
                                                  const double* __restrict__ tau,
                                                  const double* __restrict__ nu,
                                                  const double* __restrict__ j,
                                                  const double* __restrict__ delta,
-                                                 const double* __restrict__ vext, double B,
+                                                 const double* __restrict__ vext,
+                                                 const double* __restrict__ dext, double B,
                                                  int slda, double dVe, double* __restrict__ out) {
   __shared__ double red[1024 / kWave];
-  double ek = 0, ep = 0, epa = 0, ec = 0, ee = 0, nn = 0;
+  double ek = 0, ep = 0, epa = 0, ec = 0, ee = 0, nn = 0, epx = 0;
   for (int64_t r = threadIdx.x; r < M; r += 1024) {
     const double rs = fmax(rho[r], 0.5e-14);
     const double jsq = j[r] * j[r] + j[M + r] * j[M + r] + j[2 * M + r] * j[2 * M + r];
@@ -75,11 +77,33 @@ __global__ __launch_bounds__(1024) void k_energy(int64_t M, const double* __rest
     ec += jsq / rs;
     ee += vext[r] * 2.0 * rho[r];
     nn += 2.0 * rho[r];
+    epx -= 2.0 * (dext[2 * r] * nu[2 * r] + dext[2 * r + 1] * nu[2 * r + 1]);
   }
-  double v[6] = {ek, ep, epa, ec, ee, nn};
-  for (int k = 0; k < 6; ++k) {
+  double v[7] = {ek, ep, epa, ec, ee, nn, epx};
+  for (int k = 0; k < 7; ++k) {
     const double t = block_sum<1024>(v[k], red);
     if (threadIdx.x == 0) out[k] = t * dVe;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Streaming copy: each thread moves CP_U 16-byte words with non-temporal
+// 128-bit loads and stores; consecutive lanes touch consecutive words.
+constexpr int CP_TB = 256, CP_U = 4;
+typedef int cp_v4i __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(CP_TB) void k_stream_copy(const cp_v4i* __restrict__ src, cp_v4i* __restrict__ dst,
+                                                       int64_t n16) {
+  const int64_t base = int64_t(blockIdx.x) * (CP_TB * CP_U) + threadIdx.x;
+  cp_v4i v[CP_U];
+#pragma unroll
+  for (int k = 0; k < CP_U; ++k) {
+    const int64_t i = base + int64_t(k) * CP_TB;
+    if (i < n16) v[k] = __builtin_nontemporal_load(src + i);
+  }
+#pragma unroll
+  for (int k = 0; k < CP_U; ++k) {
+    const int64_t i = base + int64_t(k) * CP_TB;
+    if (i < n16) __builtin_nontemporal_store(v[k], dst + i);
   }
 }
 

@@ -678,11 +678,13 @@ __global__ __launch_bounds__(256) void q_fric_reduce(const double* __restrict__ 
 // DFT, Nyquist zeroed), then the fields with the dissipative terms:
 //   hA = U + V_ext - mu - (alpha / rho0) div j,
 //   hD = Delta [1 + beta sin(theta_nu - theta_B') + i gamma (N - N_req) / N_req]
+//        + Delta_ext
 template <typename R>
 __global__ __launch_bounds__(256) void q_fric_fields(int N, double dz, double dVe, const double* __restrict__ rho,
                                                      const double* __restrict__ jz, const double* __restrict__ bp,
                                                      const double* __restrict__ nu, const double* __restrict__ U,
                                                      const double* __restrict__ delta, const double* __restrict__ vext,
+                                                     const double* __restrict__ dext,
                                                      double mu, double alpha, double beta, double gamma,
                                                      double rho0, double N_req, R* __restrict__ hA,
                                                      cpx<R>* __restrict__ hD) {
@@ -724,7 +726,7 @@ __global__ __launch_bounds__(256) void q_fric_fields(int N, double dz, double dV
   const double fr = 1.0 + beta * sin(th_nu - th_b), fi = gt;
   const double dr = delta[2 * t], di = delta[2 * t + 1];
   hA[t] = R(U[t] + vext[t] - mu - alpha / rho0 * dj);
-  hD[t] = cpx<R>{R(dr * fr - di * fi), R(dr * fi + di * fr)};
+  hD[t] = cpx<R>{R(dr * fr - di * fi + dext[2 * t]), R(dr * fi + di * fr + dext[2 * t + 1])};
 }
 
 // workgroup sizes the tuner chooses from (states per workgroup = TB / A)
@@ -788,7 +790,7 @@ struct EngineQ1D final : Engine {
   bool self_shift() const override { return true; }
   int raw_h_slots() const override { return 1; }
   void reduce_pot(Ctx& c, bool update) override {
-    FunParams fp{c.fun.functional, c.fun.B, c.fun.C, c.fun.inv_g_bdg, c.fun.mu, c.ainv};
+    FunParams fp{c.fun.functional, c.fun.B, c.fun.C, c.fun.inv_g_bdg, c.fun.mu, c.ainv, c.dext};
     c.launch(KC_REDUCE_POT, [&] {
       if (c.nsg_used >= 64)  // few sites, many state groups: one workgroup per site
         hipLaunchKernelGGL((k_reduce_pot_wide<R>), dim3(N), dim3(256), 0, c.stream, c.dens_part, c.nsg_used,
@@ -917,7 +919,7 @@ struct EngineQ1D final : Engine {
       hipLaunchKernelGGL(q_fric_reduce, dim3(N), dim3(256), 0, c.stream, c.fric_part, int(ng), N, c.ainv, c.fric_j,
                          c.fric_bp);
       hipLaunchKernelGGL((q_fric_fields<R>), dim3(1), dim3(256), 0, c.stream, N, c.lat.dz, c.dVe, c.rho, c.fric_j,
-                         c.fric_bp, c.nu, c.U, c.delta, c.vext, c.fun.mu, c.f_alpha, c.f_beta, c.f_gamma, c.f_rho0,
+                         c.fric_bp, c.nu, c.U, c.delta, c.vext, c.dext, c.fun.mu, c.f_alpha, c.f_beta, c.f_gamma, c.f_rho0,
                          c.f_Nreq, (R*)c.hA, (cpx<R>*)c.hD);
     });
   }

@@ -93,6 +93,15 @@ void fin(Ctx& c, int64_t nst, double* scale, bool do_scale, bool do_h) {
   });
 }
 
+// streaming device copy (bytes a multiple of 16, both ends 16-byte aligned)
+void device_copy(void* dst, const void* src, int64_t bytes, hipStream_t st) {
+  const int64_t n16 = bytes / 16;
+  if (n16 == 0) return;
+  hipLaunchKernelGGL(k_stream_copy, dim3(cdiv(n16, CP_TB * CP_U)), dim3(CP_TB), 0, st, (const cp_v4i*)src,
+                     (cp_v4i*)dst, n16);
+  HIPCHK(hipGetLastError());
+}
+
 // buffer b was rewritten by a kernel that leaves no kinetic partials
 inline void touched(Ctx& c, int b) { c.kin_ready[b] = false; }
 
@@ -202,7 +211,7 @@ void start(Ctx& c) {
     while ((int)hl.size() < D) {
       int b = freeb.back();
       freeb.pop_back();
-      HIPCHK(hipMemcpyAsync(c.sb[b], c.sb[f0], size_t(c.nst) * 2 * c.M * c.esz, hipMemcpyDeviceToDevice, c.stream));
+      device_copy(c.sb[b], c.sb[f0], int64_t(c.nst) * 2 * c.M * int64_t(c.esz), c.stream);
       touched(c, b);
       hl.push_back(b);
     }
@@ -318,13 +327,13 @@ void full_densities(Ctx& c) {
   }
 }
 
-void energy(Ctx& c, double* out8) {
+void energy(Ctx& c, double* out8) {  // out8[9]
   full_densities(c);
   c.launch(KC_ENERGY, [&] {
     hipLaunchKernelGGL(k_energy, dim3(1), dim3(1024), 0, c.stream, c.M, c.rho, c.tau, c.nu, c.jc, c.delta,
-                       c.vext, c.fun.B, int(c.fun.functional == TDSLDA_FUNC_SLDA), c.dVe, c.eout);
+                       c.vext, c.dext, c.fun.B, int(c.fun.functional == TDSLDA_FUNC_SLDA), c.dVe, c.eout);
   });
-  double h[6];
+  double h[7];
   HIPCHK(hipMemcpyAsync(h, c.eout, sizeof(h), hipMemcpyDeviceToHost, c.stream));
   HIPCHK(hipStreamSynchronize(c.stream));
   const double N = h[5];
@@ -334,9 +343,22 @@ void energy(Ctx& c, double* out8) {
   out8[2] = h[2];
   out8[3] = h[3];
   out8[4] = h[4];
-  out8[5] = h[0] + h[1] + h[2] + h[3] + h[4];
+  out8[5] = h[0] + h[1] + h[2] + h[3] + h[4] + h[6];
   out8[6] = N;
   out8[7] = 0.6 * N * ef;
+  out8[8] = h[6];
+}
+
+// frozen (linear-mode) fields: hA = U + V_ext - mu, hD = Delta + Delta_ext
+void set_frozen_fields(Ctx& c) {
+  c.launch(KC_SETUP, [&] {
+    if (c.esz == 16)
+      hipLaunchKernelGGL((k_set_fields<double>), dim3(cdiv(c.M, 256)), dim3(256), 0, c.stream, c.M, c.U, c.delta,
+                         c.vext, c.dext, c.fun.mu, (double*)c.hA, (cpx<double>*)c.hD);
+    else
+      hipLaunchKernelGGL((k_set_fields<float>), dim3(cdiv(c.M, 256)), dim3(256), 0, c.stream, c.M, c.U, c.delta,
+                         c.vext, c.dext, c.fun.mu, (float*)c.hA, (cpx<float>*)c.hD);
+  });
 }
 
 void after_load(Ctx& c) {
@@ -402,6 +424,19 @@ void check_lattice(const tdslda_lattice& lat) {
 extern "C" {
 
 const char* tdslda_kernel_name(int k) { return (k >= 0 && k < KC_COUNT) ? kKernelNames[k] : nullptr; }
+
+tdslda_status tdslda_device_copy(void* dst, const void* src, int64_t bytes, void* hip_stream) {
+  if (!dst || !src || bytes < 0 || bytes % 16 || (uintptr_t(dst) | uintptr_t(src)) % 16) return TDSLDA_EINVAL;
+  const uintptr_t d = uintptr_t(dst), s = uintptr_t(src);
+  if (d < s + uint64_t(bytes) && s < d + uint64_t(bytes) && bytes > 0) return TDSLDA_EINVAL;
+  if (bytes / 16 > int64_t(0x7fffffff) * CP_TB * CP_U) return TDSLDA_EINVAL;
+  try {
+    device_copy(dst, src, bytes, (hipStream_t)hip_stream);
+    return TDSLDA_OK;
+  } catch (const Fail& e) {
+    return e.st;
+  }
+}
 
 const char* tdslda_last_error(const tdslda_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
@@ -488,6 +523,8 @@ tdslda_status tdslda_create(const tdslda_lattice* lat, const tdslda_functional* 
     c->vext = (double*)c->dalloc(8 * M);
     c->lam = (double*)c->dalloc(8 * M);
     c->theta = (double*)c->dalloc(8 * M);
+    c->dext = (double*)c->dalloc(16 * M);
+    HIPCHK(hipMemsetAsync(c->dext, 0, 16 * M, c->stream));
     c->hA = c->dalloc(M * c->esz / 2);
     c->hD = c->dalloc(M * c->esz);
     HIPCHK(hipMemsetAsync(c->vext, 0, 8 * M, c->stream));
@@ -515,10 +552,22 @@ tdslda_status tdslda_destroy(tdslda_ctx* ctx) {
   return TDSLDA_OK;
 }
 
-tdslda_status tdslda_set_external(tdslda_ctx* c, const double* vext, int freeze_regulator) {
+tdslda_status tdslda_set_external(tdslda_ctx* c, const double* vext, const double* dext_reim,
+                                  int freeze_regulator) {
   return guard(c, [&] {
     require(vext != nullptr, TDSLDA_EINVAL, "vext is NULL");
+    if (dext_reim)
+      for (int64_t i = 0; i < 2 * c->M; ++i)
+        require(std::isfinite(dext_reim[i]), TDSLDA_EINVAL, "Delta_ext is not finite");
     HIPCHK(hipMemcpyAsync(c->vext, vext, 8 * c->M, hipMemcpyHostToDevice, c->stream));
+    c->dext_on = false;
+    if (dext_reim) {
+      HIPCHK(hipMemcpyAsync(c->dext, dext_reim, 16 * c->M, hipMemcpyHostToDevice, c->stream));
+      for (int64_t i = 0; i < 2 * c->M; ++i) c->dext_on = c->dext_on || dext_reim[i] != 0.0;
+    } else {
+      HIPCHK(hipMemsetAsync(c->dext, 0, 16 * c->M, c->stream));
+    }
+    c->have_ref = false;
     if (freeze_regulator) {
       HIPCHK(hipMemsetAsync(c->dflag, 0, 4, c->stream));
       c->launch(KC_SETUP, [&] {
@@ -534,6 +583,7 @@ tdslda_status tdslda_set_external(tdslda_ctx* c, const double* vext, int freeze_
       c->eng->dens(*c, c->sb[c->phi], c->sscale[c->phi], c->nst);
       c->eng->reduce_pot(*c, true);
     }
+    if (c->frozen) set_frozen_fields(*c);
     HIPCHK(hipStreamSynchronize(c->stream));
   });
 }
@@ -677,14 +727,7 @@ tdslda_status tdslda_set_fields(tdslda_ctx* c, const double* U, const double* de
     require(U && delta_reim, TDSLDA_EINVAL, "give both U and Delta, or neither");
     HIPCHK(hipMemcpyAsync(c->U, U, 8 * c->M, hipMemcpyHostToDevice, c->stream));
     HIPCHK(hipMemcpyAsync(c->delta, delta_reim, 16 * c->M, hipMemcpyHostToDevice, c->stream));
-    c->launch(KC_SETUP, [&] {
-      if (c->esz == 16)
-        hipLaunchKernelGGL((k_set_fields<double>), dim3(cdiv(c->M, 256)), dim3(256), 0, c->stream, c->M, c->U,
-                           c->delta, c->vext, c->fun.mu, (double*)c->hA, (cpx<double>*)c->hD);
-      else
-        hipLaunchKernelGGL((k_set_fields<float>), dim3(cdiv(c->M, 256)), dim3(256), 0, c->stream, c->M, c->U,
-                           c->delta, c->vext, c->fun.mu, (float*)c->hA, (cpx<float>*)c->hD);
-    });
+    set_frozen_fields(*c);
     c->frozen = true;
     c->fields_valid = true;
     HIPCHK(hipStreamSynchronize(c->stream));
@@ -771,6 +814,19 @@ tdslda_status tdslda_abm_graph(tdslda_ctx* c, int64_t nsteps, double graph_ms[2]
     c->stream = cs;
     hipGraph_t g = nullptr;
     hipGraphExec_t ge = nullptr;
+    // recording runs abm() on the host, which advances the integrator's
+    // bookkeeping (buffer roles, kinetic-partial flags, step count, time)
+    // without touching device memory: keep a copy to restore if the graph
+    // never runs
+    const int phi0 = c->phi;
+    int hist0[5];
+    bool kin0[6];
+    std::copy(c->hist, c->hist + 5, hist0);
+    std::copy(c->kin_ready, c->kin_ready + 6, kin0);
+    const int64_t steps0 = c->steps;
+    const double time0 = c->time;
+    const bool fv0 = c->fields_valid;
+    bool launched = false;
     auto cleanup = [&] {
       if (ge) (void)hipGraphExecDestroy(ge);
       if (g) (void)hipGraphDestroy(g);
@@ -789,6 +845,7 @@ tdslda_status tdslda_abm_graph(tdslda_ctx* c, int64_t nsteps, double graph_ms[2]
       HIPCHK(hipStreamEndCapture(cs, &g));
       HIPCHK(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
       const auto t1 = std::chrono::steady_clock::now();
+      launched = true;
       HIPCHK(hipGraphLaunch(ge, cs));
       HIPCHK(hipStreamSynchronize(cs));
       const auto t2 = std::chrono::steady_clock::now();
@@ -798,6 +855,20 @@ tdslda_status tdslda_abm_graph(tdslda_ctx* c, int64_t nsteps, double graph_ms[2]
       }
     } catch (...) {
       cleanup();
+      if (!launched) {
+        // nothing ran on the device: the context is as before the call
+        c->phi = phi0;
+        std::copy(hist0, hist0 + 5, c->hist);
+        std::copy(kin0, kin0 + 6, c->kin_ready);
+        c->steps = steps0;
+        c->time = time0;
+        c->fields_valid = fv0;
+      } else {
+        // the launch failed part-way: the buffers no longer match any
+        // bookkeeping, so the states must be loaded again
+        c->loaded = false;
+        c->started = false;
+      }
       throw;
     }
     cleanup();
@@ -850,7 +921,7 @@ tdslda_status tdslda_q1d_load_static(tdslda_ctx* c, int nprob, const double* kpe
   });
 }
 
-tdslda_status tdslda_energy(tdslda_ctx* c, double terms_out[8]) {
+tdslda_status tdslda_energy(tdslda_ctx* c, double terms_out[9]) {
   return guard(c, [&] {
     require(c->loaded, TDSLDA_EORDER, "load states first");
     require(terms_out != nullptr, TDSLDA_EINVAL, "terms_out is NULL");
@@ -862,7 +933,7 @@ tdslda_status tdslda_check(tdslda_ctx* c, double out[3]) {
   tdslda_status extra = TDSLDA_OK;
   tdslda_status st = guard(c, [&] {
     require(c->loaded, TDSLDA_EORDER, "load states first");
-    double e[8];
+    double e[9];
     energy(*c, e);
     // norms of the stored state: 1/scale^2 must be 1 for a normalised state
     std::vector<double> sc(c->nst);
@@ -881,10 +952,12 @@ tdslda_status tdslda_check(tdslda_ctx* c, double out[3]) {
     if (!c->have_ref) {
       c->have_ref = true;
       c->N0 = e[6];
-      c->E0 = e[5];
+      c->E0 = e[5] - c->fun.mu * e[6];
     }
-    const double dn = std::fabs(e[6] - c->N0) / std::fabs(c->N0);
-    const double de = std::fabs(e[5] - c->E0) / std::fabs(e[7]);
+    // conserved at fixed mu: Omega = E - mu N (Eq. E_tot); N itself is not
+    // conserved when a pairing source Delta_ext acts
+    const double dn = c->dext_on ? 0.0 : std::fabs(e[6] - c->N0) / std::fabs(c->N0);
+    const double de = std::fabs(e[5] - c->fun.mu * e[6] - c->E0) / std::fabs(e[7]);
     if (out) {
       out[0] = dn;
       out[1] = de;
@@ -960,6 +1033,7 @@ tdslda_status tdslda_save(tdslda_ctx* c, const char* path) {
     dump(c->lam, 8 * c->M);
     dump(c->U, 8 * c->M);
     dump(c->delta, 16 * c->M);
+    dump(c->dext, 16 * c->M);
     // kinetic <H> partials left by the last producer kernel, so a resumed
     // run continues with exactly the arithmetic of an uninterrupted one
     int kin[6];
@@ -1009,6 +1083,13 @@ tdslda_status tdslda_load(tdslda_ctx* c, const char* path) {
     undump(c->lam, 8 * c->M);
     undump(c->U, 8 * c->M);
     undump(c->delta, 16 * c->M);
+    {
+      std::vector<double> dx(2 * c->M);
+      ok = ok && std::fread(dx.data(), 8, dx.size(), f) == dx.size();
+      if (ok) HIPCHK(hipMemcpy(c->dext, dx.data(), 16 * c->M, hipMemcpyHostToDevice));
+      c->dext_on = false;
+      for (double v : dx) c->dext_on = c->dext_on || v != 0.0;
+    }
     int kin[6] = {0, 0, 0, 0, 0, 0};
     ok = ok && std::fread(kin, sizeof(kin), 1, f) == 1;
     std::vector<double> hp(size_t(n) * c->h_stride);
@@ -1025,14 +1106,7 @@ tdslda_status tdslda_load(tdslda_ctx* c, const char* path) {
     c->loaded = true;
     c->have_ref = false;
     if (hdr[7]) {
-      c->launch(KC_SETUP, [&] {
-        if (c->esz == 16)
-          hipLaunchKernelGGL((k_set_fields<double>), dim3(cdiv(c->M, 256)), dim3(256), 0, c->stream, c->M, c->U,
-                             c->delta, c->vext, c->fun.mu, (double*)c->hA, (cpx<double>*)c->hD);
-        else
-          hipLaunchKernelGGL((k_set_fields<float>), dim3(cdiv(c->M, 256)), dim3(256), 0, c->stream, c->M, c->U,
-                             c->delta, c->vext, c->fun.mu, (float*)c->hA, (cpx<float>*)c->hD);
-      });
+      set_frozen_fields(*c);
       c->frozen = true;
     } else {
       c->frozen = false;

@@ -58,7 +58,7 @@ _SIGS = {
     "tdslda_destroy": [C.c_void_p],
     "tdslda_last_error": [C.c_void_p],
     "tdslda_memory_plan": [C.POINTER(Lattice), C.POINTER(Run), C.c_int64, C.POINTER(C.c_int64)],
-    "tdslda_set_external": [C.c_void_p, C.c_void_p, C.c_int],
+    "tdslda_set_external": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int],
     "tdslda_set_regulator": [C.c_void_p, C.c_void_p],
     "tdslda_load_states": [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p],
     "tdslda_load_states_device": [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p],
@@ -78,6 +78,7 @@ _SIGS = {
     "tdslda_set_profiling": [C.c_void_p, C.c_int],
     "tdslda_kernel_stats": [C.c_void_p, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_double)],
     "tdslda_kernel_name": [C.c_int],
+    "tdslda_device_copy": [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p],
     "tdslda_abm_graph": [C.c_void_p, C.c_int64, C.c_void_p],
     "tdslda_autotune": [C.c_void_p, C.POINTER(C.c_int), C.c_void_p, C.c_void_p],
     "tdslda_q1d_count": [C.POINTER(Lattice), C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
@@ -143,6 +144,15 @@ def _dev_ptr(t):
     return C.c_void_p(t.data_ptr())
 
 
+def device_copy(dst, src, nbytes, stream=None):
+    """tdslda_device_copy: streaming copy between device tensors (or raw
+    device pointers) on a HIP stream (an integer handle; None = null)."""
+    lib = load_library()
+    st = lib.tdslda_device_copy(_dev_ptr(dst), _dev_ptr(src), int(nbytes), C.c_void_p(stream or 0))
+    if st != OK:
+        raise TdsldaError(st, "device_copy rejected the arguments")
+
+
 def kernel_names():
     lib = load_library()
     out, k = [], 0
@@ -198,9 +208,12 @@ class Context:
             pass
 
     # --- set-up -----------------------------------------------------------
-    def set_external(self, vext, freeze_regulator=True):
+    def set_external(self, vext, freeze_regulator=True, dext=None):
+        """V_ext (real) and optionally the external pairing potential
+        Delta_ext (complex) on the lattice."""
         v = _f64(vext).ravel()
-        self._chk(self.lib.tdslda_set_external(self.h, _p(v), int(freeze_regulator)))
+        d = None if dext is None else _c128_as_f64(np.asarray(dext).ravel())
+        self._chk(self.lib.tdslda_set_external(self.h, _p(v), _p(d), int(freeze_regulator)))
 
     def set_regulator(self, lam):
         v = _f64(lam).ravel()
@@ -264,9 +277,9 @@ class Context:
         self._chk(self.lib.tdslda_abm_step(self.h, int(nsteps)))
 
     def energy(self):
-        out = np.empty(8)
+        out = np.empty(9)
         self._chk(self.lib.tdslda_energy(self.h, _p(out)))
-        keys = ("kin", "pot", "pair", "curr", "potext", "total", "N", "EFG")
+        keys = ("kin", "pot", "pair", "curr", "potext", "total", "N", "EFG", "pairext")
         return dict(zip(keys, out.tolist()))
 
     def check(self):
