@@ -293,6 +293,25 @@ tdslda_status tdslda_static_solve(const tdslda_static* s, const tdslda_functiona
 tdslda_status tdslda_interp2d(int nx, int ny, double dx, double dy, const double* f, int nx2, int ny2, double dx2,
                               double dy2, double* out);
 
+/* Allocation-free variant of tdslda_interp2d, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same operation and result as
+ * tdslda_interp2d, but f_dev (FP64 [nx*ny]) and out_dev (FP64 [nx2*ny2])
+ * are caller-owned device arrays, the two kernels are queued on hip_stream
+ * (a hipStream_t; NULL = the null stream) and the call returns without
+ * waiting.  The Fourier coefficients go to a fixed device array of the
+ * library (1 MiB per GPU, held until the process ends) instead of a
+ * per-call allocation, which limits the source lattice to nx * ny <= 65536;
+ * the call performs no hipMalloc, hipFree or other allocation.  Every call
+ * on one GPU shares that array: calls that overlap in time on the same GPU
+ * (different streams, or threads) race and must be serialised by the
+ * caller.  Nothing in the array needs clearing (each call writes every
+ * coefficient it reads).  Errors: EINVAL (NULL pointers, sizes, source
+ * lattice beyond the limit, spacings, box mismatch), EDEVICE (launch
+ * failure, no device). */
+tdslda_status tdslda_interp2d_noalloc(int nx, int ny, double dx, double dy, const double* f_dev, int nx2, int ny2,
+                                      double dx2, double dy2, double* out_dev, void* hip_stream);
+
 /* Warm-start network of the static workflow (learned initial guess for
  * the fixed-point iteration of Alg. MapK; Sec. 5.2 on initial guesses).
  * A small convolutional network maps the normalised external potential of

@@ -15,6 +15,7 @@
 #include <cmath>
 #include <cstdio>
 #include <functional>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -489,6 +490,41 @@ struct StaticSolver {
 }  // namespace tdslda
 
 // ============================================================================
+// Allocation-free interpolation: the Fourier coefficients live in a fixed
+// device array instead of a per-call allocation.  Each GPU the library runs
+// on holds its own copy (2 x kInterpScratchPoints doubles, 1 MiB) until the
+// process ends; its address is looked up once per device and only that
+// address is handed to kernels (the array's name is a host-side stand-in).
+constexpr int64_t kInterpScratchPoints = 65536;  // largest source lattice nx*ny
+static __device__ __align__(256) double scratch[2 * kInterpScratchPoints];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// device address of this device's scratch array (looked up on first use)
+double* scratch_on_current_device() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    (void)hipGetLastError();
+    throw tdslda::Fail{TDSLDA_EDEVICE, "no current HIP device"};
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      throw tdslda::Fail{TDSLDA_EDEVICE, std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e)};
+    }
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  return g_scratch_ptr[dev];
+}
+}  // namespace
+
+// ============================================================================
 // C ABI
 using tdslda::Fail;
 using tdslda::StaticSolver;
@@ -632,6 +668,31 @@ tdslda_status tdslda_interp2d(int nx, int ny, double dx, double dy, const double
       throw;
     }
     release();
+  });
+}
+
+tdslda_status tdslda_interp2d_noalloc(int nx, int ny, double dx, double dy, const double* f_dev, int nx2, int ny2,
+                                      double dx2, double dy2, double* out_dev, void* hip_stream) {
+  if (!f_dev || !out_dev) return TDSLDA_EINVAL;
+  return static_guard("tdslda_interp2d_noalloc", [&] {
+    require(nx > 0 && ny > 0 && nx2 > 0 && ny2 > 0 && nx % 2 == 0 && ny % 2 == 0, TDSLDA_EINVAL,
+            "lattice sizes must be positive (source sizes even)");
+    require(int64_t(nx) * ny <= kInterpScratchPoints, TDSLDA_EINVAL,
+            "source lattice larger than the fixed coefficient array (nx * ny <= 65536)");
+    require(int64_t(nx2) * ny2 <= (int64_t(1) << 28), TDSLDA_EINVAL, "target lattice too large for the direct sums");
+    require(dx > 0 && dy > 0 && dx2 > 0 && dy2 > 0, TDSLDA_EINVAL, "spacings must be positive");
+    const double Lx = nx * dx, Ly = ny * dy;
+    require(std::fabs(nx2 * dx2 - Lx) <= 1e-12 * Lx && std::fabs(ny2 * dy2 - Ly) <= 1e-12 * Ly, TDSLDA_EINVAL,
+            "the two lattices must span the same box");
+    double* ft = scratch_on_current_device();
+    const hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    const int64_t n1 = int64_t(nx) * ny, n2 = int64_t(nx2) * ny2;
+    hipLaunchKernelGGL(tdslda::k_interp_coef, dim3(tdslda::cdiv(n1, 256)), dim3(256), 0, st, nx, ny, dx, dy, f_dev,
+                       ft);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(tdslda::k_interp_eval, dim3(tdslda::cdiv(n2, 256)), dim3(256), 0, st, nx, ny, dx, dy, ft, nx2,
+                       ny2, dx2, dy2, out_dev);
+    HIPCHK(hipGetLastError());
   });
 }
 

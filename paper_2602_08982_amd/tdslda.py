@@ -90,6 +90,8 @@ _SIGS = {
     "tdslda_set_friction": [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double],
     "tdslda_interp2d": [C.c_int, C.c_int, C.c_double, C.c_double, C.c_void_p, C.c_int, C.c_int, C.c_double,
                         C.c_double, C.c_void_p],
+    "tdslda_interp2d_noalloc": [C.c_int, C.c_int, C.c_double, C.c_double, C.c_void_p, C.c_int, C.c_int,
+                                C.c_double, C.c_double, C.c_void_p, C.c_void_p],
     "tdslda_nn_nparams": [C.c_int],
     "tdslda_nn_create": [C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p, C.POINTER(C.c_void_p)],
     "tdslda_nn_destroy": [C.c_void_p],
@@ -410,6 +412,23 @@ def interp2d(f, d, shape2, d2):
     if st != OK:
         raise TdsldaError(st, "tdslda_interp2d failed")
     return out.reshape(nx2, ny2)
+
+
+def interp2d_noalloc(f_dev, d, out_dev, d2, stream=None):
+    """tdslda_interp2d_noalloc: the same interpolation between device
+    tensors (FP64, shapes (nx, ny) and (nx2, ny2)), queued on `stream`
+    (a hipStream_t handle, None = null stream); no device allocation."""
+    lib = load_library()
+    for t in (f_dev, out_dev):
+        if t.dim() != 2 or not t.is_cuda or t.dtype.itemsize != 8 or not t.is_floating_point() or \
+                not t.is_contiguous():
+            raise ValueError("interp2d_noalloc takes contiguous 2D float64 device tensors")
+    nx, ny = f_dev.shape
+    nx2, ny2 = out_dev.shape
+    st = lib.tdslda_interp2d_noalloc(nx, ny, float(d[0]), float(d[1]), _dev_ptr(f_dev), nx2, ny2, float(d2[0]),
+                                     float(d2[1]), _dev_ptr(out_dev), C.c_void_p(stream or 0))
+    if st != OK:
+        raise TdsldaError(st, "tdslda_interp2d_noalloc failed")
 
 
 class Network:
