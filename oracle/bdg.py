@@ -83,9 +83,16 @@ def vortex_phase(lat, vortices):
 
 
 def imprint_phase(phi, theta):
-    """u_n <- exp(i theta) u_n for every state, v unchanged.  Reading of the
-    vortex imprint: Delta is derived from the states in TD, so the phase is
-    put on u, which multiplies nu and hence Delta by exp(i theta)."""
+    """Vortex imprint (a phase e^{i theta} on Delta): Delta is derived
+    from the states in TD, so the phase goes onto the states as the local
+    gauge rotation of both fermion fields by theta/2: u_n <- e^{i theta/2} u_n,
+    v_n <- e^{-i theta/2} v_n for every state.  This multiplies nu = sum u v^*
+    (and hence Delta) by e^{i theta}, leaves rho unchanged, and commutes with
+    the partner map (u, v) -> (v^*, -u^*) of the spin-symmetric reduction
+    (Sec. 2.3), so the imprinted E > 0 states still stand for a complete set
+    closed under that map.  (e^{i theta/2} changes sign across a branch line
+    of theta; the imprinted states carry that sign change.)"""
     out = phi.copy()
-    out[:, 0] = np.exp(1j * theta) * phi[:, 0]
+    out[:, 0] = np.exp(0.5j * theta) * phi[:, 0]
+    out[:, 1] = np.exp(-0.5j * theta) * phi[:, 1]
     return out

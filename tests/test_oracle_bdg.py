@@ -56,25 +56,25 @@ def test_dense_matvec_equals_spectral_apply():
 def test_general_equals_spin_symmetric(T, gauge):
     """P7: densities of all 2M states with both branches explicit
     (Eqs. na3D-jb3D) equal the spin-symmetric form over E>0 states only
-    (Eqs. nab3D-jab3D).  With the gauge, u -> exp(i theta) u is put on the
-    E>0 states and the E<0 half is rebuilt from them by the partner map
-    (u, v) -> (v^*, -u^*) of the spin-symmetric case, so the check covers
-    states whose phases wind."""
+    (Eqs. nab3D-jab3D).  With the gauge, the vortex imprint is applied to
+    the whole eigenbasis (both signs of E): the imprinted E>0 states must
+    still reproduce the densities of the imprinted complete set, tau and j
+    included, which holds only if the imprint commutes with the partner map
+    (u, v) -> (v^*, -u^*) of the spin-symmetric case (a phase on u alone
+    fails here: tau_a != tau_b)."""
     lat = L.Lattice(4, 4, 4)
     hf = synth.uniform_field(31, lat.shape) - 0.8
     de = synth.complex_normal(32, lat.shape, 0.4)
     E, phi = bdg.eigenstates(hf, de, lat)
     pos = E > 0
     Ep, php = E[pos], phi[pos]
+    # the E<0 half of the spectrum is the partner set, up to phases
+    assert np.allclose(np.sort(-E[~pos]), np.sort(Ep), atol=1e-12)
+    phi_all, E_all = phi, E
     if gauge:
-        php = bdg.imprint_phase(php, bdg.vortex_phase(lat, [(0.3, -0.2, 1)]))
-        partners = np.stack([np.conj(php[:, 1]), -np.conj(php[:, 0])], axis=1)
-        phi_all = np.concatenate([php, partners])
-        E_all = np.concatenate([Ep, -Ep])
-    else:
-        phi_all, E_all = phi, E
-        # the E<0 half of the spectrum is the partner set, up to phases
-        assert np.allclose(np.sort(-E[~pos]), np.sort(Ep), atol=1e-12)
+        theta = bdg.vortex_phase(lat, [(0.3, -0.2, 1)])
+        phi_all = bdg.imprint_phase(phi, theta)
+        php = bdg.imprint_phase(php, theta)
     g = D.general(phi_all, F.fermi_weight(E_all, T), F.fermi_weight(-E_all, T), lat)
     rho, tau, nu, j = D.spin_symmetric(php, F.fermi_weight(Ep, T), F.fermi_weight(-Ep, T), lat)
     tol = 1e-13
@@ -83,6 +83,27 @@ def test_general_equals_spin_symmetric(T, gauge):
     assert np.abs(g["nu"] - nu).max() < tol
     for c in range(3):
         assert np.abs(g["j_a"][c] - j[c]).max() < tol and np.abs(g["j_b"][c] - j[c]).max() < tol
+
+
+def test_imprint_commutes_with_partner_map():
+    """The vortex imprint maps the partner (v^*, -u^*) of a state to the
+    partner of the imprinted state, keeps states orthonormal and multiplies
+    nu by e^{i theta} while leaving rho unchanged."""
+    lat = L.Lattice(6, 6, 2)
+    phi = D.normalize(synth.complex_normal(35, (4, 2) + lat.shape), lat.dV)
+    theta = bdg.vortex_phase(lat, [(0.4, 0.1, 1), (-1.3, 0.7, -1)])
+    partner = lambda p: np.stack([np.conj(p[:, 1]), -np.conj(p[:, 0])], axis=1)
+    a = bdg.imprint_phase(partner(phi), theta)
+    b = partner(bdg.imprint_phase(phi, theta))
+    assert np.abs(a - b).max() < 1e-15
+    G0 = np.einsum("aclmn,bclmn->ab", np.conj(phi), phi)
+    G1 = np.einsum("aclmn,bclmn->ab", np.conj(bdg.imprint_phase(phi, theta)), bdg.imprint_phase(phi, theta))
+    assert np.abs(G1 - G0).max() < 1e-13
+    w = np.linspace(0.1, 0.9, 4)
+    r0, _, n0, _ = D.spin_symmetric(phi, w, 1 - w, lat)
+    r1, _, n1, _ = D.spin_symmetric(bdg.imprint_phase(phi, theta), w, 1 - w, lat)
+    assert np.abs(r1 - r0).max() < 1e-15 * np.abs(r0).max() * 10
+    assert np.abs(n1 - np.exp(1j * theta) * n0).max() < 1e-14 * np.abs(n0).max()
 
 
 def test_kinetic_density_integrates_to_laplacian_expectation():

@@ -144,6 +144,35 @@ def test_config1_conservation():
     assert abs(o0["N"] - oi["N"]) / oi["N"] < 1e-6
 
 
+def test_vortex_imprint_conserves_energy():
+    """P10 with a vortex: the complete set of the uniform 6^3 state with the
+    vortex imprint (gauge rotation by theta/2 of both components) evolves
+    with N and the energy conserved to the integrator's accuracy: the drift
+    over t = 0.1 is small and falls with dt at the integrator's order.  (A
+    phase put on u alone breaks the partner closure of the E>0 set and the
+    energy then drifts by a few percent independently of dt.)"""
+    lat = L.Lattice(6, 6, 6)
+    mu = 1.0
+    E, phi = bdg.eigenstates(np.full(lat.shape, -mu), np.full(lat.shape, 0.5 + 0j), lat)
+    pos = E > 0
+    E, phi = E[pos], phi[pos]
+    phi = bdg.imprint_phase(phi, bdg.vortex_phase(lat, [(0.3, -0.2, 1.0)]))
+    lam = F.lambda_c(np.zeros(lat.shape), mu, 0.5 * np.pi ** 2)
+    sys_ = td.TDSystem(td.Geometry3D(lat), F.Functional(F.SLDA), mu, np.zeros(lat.shape), lam,
+                       F.fermi_weight(E), F.fermi_weight(-E))
+    drift = []
+    for dt in (0.01, 0.005):
+        p, hist, _ = td.start(sys_, phi, dt, "AB4AM5", 1)
+        o0 = td.observables(sys_, p)
+        for _ in range(int(round(0.1 / dt))):
+            p, hist = td.abm_step(sys_, p, hist, dt, "AB4AM5")
+        o1 = td.observables(sys_, p)
+        assert abs(o1["N"] - o0["N"]) / o0["N"] < 1e-7
+        drift.append(abs(o1["total"] - o0["total"]) / o0["EFG"])
+    assert drift[1] < 1e-7
+    assert drift[0] / drift[1] > 16  # order >= 4
+
+
 def test_time_reversibility():
     """P14: evolving forward n steps and then n steps with dt -> -dt returns
     to the initial densities within the integrator error."""
