@@ -49,6 +49,25 @@ def algorithmic_bytes(kernel, S, nst, depth, fused=False, design=False):
     return table[kernel] * S * nst if kernel in table else None
 
 
+def design_rw(kernel, depth, fused=False):
+    """(reads, writes) in units of S of one launch's design bytes (the
+    bytes the kernel reads and writes once; see algorithmic_bytes)."""
+    if fused:
+        t = {"dens": (1, 0), "lap2_corr": (2, 1), "lap2_full": (1 + depth - 1, 3), "lap2_f": (1, 1),
+             "pred": (1 + depth, 2)}
+    else:
+        t = {"dens": (1, 0), "lap1": (1, 1), "lap2_corr": (3, 1), "lap2_full": (2 + depth - 1, 3),
+             "lap2_f": (2, 1), "lap2_h": (2, 1), "pred": (1 + depth, 2)}
+    return t.get(kernel)
+
+
+def stream_ceiling(reads, writes, read_bps, write_bps):
+    """Rate (bytes/s) of a stream that reads `reads` and writes `writes`
+    units when reads move at read_bps and writes at write_bps, one after the
+    other per byte: (R + W) / (R / read_bps + W / write_bps)."""
+    return (reads + writes) / (reads / read_bps + writes / write_bps)
+
+
 def step_roofline(S):
     """Roofline state-steps/s of the method: 12 S per state-step at 8 TB/s."""
     return PEAK_HBM / (12.0 * S)
@@ -186,35 +205,45 @@ def run_q1d(steps, warmup, seed=7, profile_steps=2, friction=False, precision=No
                 check=dict(status=st, **chk), problems=info)
 
 
-def copy_bandwidth():
-    """Bytes moved per second (read + write) by the library's streaming copy
-    kernel (tdslda_device_copy) over 4 GiB, median of 5, timed with HIP
-    events on the stream it is launched on: the plain read-once / write-once
-    reference on this device."""
+def stream_rates():
+    """This device's HBM stream rates from the library's own streaming
+    kernels over 4 GiB (median of 5, HIP events on the launch stream):
+    read = tdslda_device_read, copy = tdslda_device_copy (read + write
+    bytes); the write rate follows from the two: a copy of B bytes takes
+    (B/2)/read + (B/2)/write."""
     import torch
     from paper_2602_08982_amd import tdslda as T
     n = 1 << 29
     a = torch.ones(n, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
+    sink = torch.zeros(2, dtype=torch.float64, device="cuda")
     st = torch.cuda.current_stream()
-    T.device_copy(b, a, 8 * n, st.cuda_stream)
-    ts = []
-    for _ in range(5):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(st)
-        T.device_copy(b, a, 8 * n, st.cuda_stream)
-        e1.record(st)
-        torch.cuda.synchronize()
-        ts.append(e0.elapsed_time(e1) * 1e-3)
+
+    def med(fn):
+        fn()
+        ts = []
+        for _ in range(5):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            fn()
+            e1.record(st)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1) * 1e-3)
+        return sorted(ts)[2]
+    t_copy = med(lambda: T.device_copy(b, a, 8 * n, st.cuda_stream))
+    t_read = med(lambda: T.device_read(a, 8 * n, sink, st.cuda_stream))
     ok = bool(torch.equal(a, b))
-    del a, b
+    del a, b, sink
     torch.cuda.empty_cache()
     if not ok:
         raise RuntimeError("device copy produced wrong data")
-    return 2 * n * 8 / sorted(ts)[2]
+    read = 8 * n / t_read
+    copy = 2 * 8 * n / t_copy
+    write = 0.5 / (1.0 / copy - 0.5 / read)
+    return dict(read=read, copy=copy, write=write)
 
 
-def roofline(res, copy_bps=None, prec=None, nx=None, role_prefix=""):
+def roofline(res, rates=None, prec=None, nx=None, role_prefix="", fused=False):
     """Dominant kernel of the timed steps against the HBM peak.
     achieved = method bytes per launch (algorithmic_bytes) / mean launch
     time; the kernel's own read-once / write-once bytes (the split-Laplacian
@@ -223,7 +252,9 @@ def roofline(res, copy_bps=None, prec=None, nx=None, role_prefix=""):
     traffic = HBM bytes per launch from the committed FETCH_SIZE /
     WRITE_SIZE summary (copy-calibrated), null when that summary does not
     cover this kernel or the kernel sources changed since the counters
-    were taken."""
+    were taken.  stream_ceiling = the rate this device's streaming kernels
+    reach for the kernel's read / write mix (stream_rates, stream_ceiling),
+    the measured ceiling its design bytes are compared with."""
     kern = res["kernels"]
     if not kern:
         return None
@@ -248,9 +279,17 @@ def roofline(res, copy_bps=None, prec=None, nx=None, role_prefix=""):
         out["traffic_GBps"] = traffic / avg_s / 1e9
         if g:
             out["traffic_over_method_bytes"] = traffic / (g * 1e9 * avg_s)
-    if copy_bps:
-        out["copy_GBps"] = copy_bps / 1e9
-        out["frac_of_copy"] = g * 1e9 / copy_bps if g else None
+    if rates:
+        out["stream_read_GBps"] = rates["read"] / 1e9
+        out["stream_copy_GBps"] = rates["copy"] / 1e9
+        out["stream_write_GBps"] = rates["write"] / 1e9
+        rw = design_rw(dom, 4, fused)
+        if rw:
+            ceil = stream_ceiling(rw[0], rw[1], rates["read"], rates["write"])
+            out["design_reads_writes_S"] = list(rw)
+            out["stream_ceiling_GBps"] = ceil / 1e9
+            ach = gd if gd is not None else g
+            out["frac_of_stream_ceiling"] = ach * 1e9 / ceil if ach else None
     return out
 
 
@@ -344,7 +383,7 @@ def main():
     from paper_2602_08982_amd import workloads as W
     T.load_library()
 
-    copy_bps = copy_bandwidth()
+    rates = stream_rates()
     plain = run_workload(W.PLAIN, args.steps, args.warmup, args.seed)
     plain["steps"] = args.steps
     print(f"# plain fp64 32^3: {plain['value']:.4g} state-steps/s, {plain['ms_per_step']:.2f} ms/step",
@@ -429,7 +468,7 @@ def main():
         "config": {"workload": "plain FP64 32^3 trapped gas, one vortex (AB4AM5, dt=0.005)",
                    "lattice": [32, 32, 32], "states_evolved": plain["nst"],
                    "states_represented": 2 * plain["nst"], "integrator": "AB4AM5"},
-        "roofline": roofline(plain, copy_bps, "double", 32),
+        "roofline": roofline(plain, rates, "double", 32),
         "cpu_baseline": cpu,
         "kernels": plain["kernels"],
         "check": plain["check"],
@@ -439,7 +478,7 @@ def main():
             "workload": "FP32-mixed 48^3 elongated trap, vortex pair, 8192 lowest-|E| states",
             "value": mixed["value"], "unit": "state-steps/s", "ms_per_step": mixed["ms_per_step"],
             "steps": mixed["steps"],
-            "dtype": "f32 states / f64 sums", "roofline": roofline(mixed, copy_bps, "float", 48), "kernels": mixed["kernels"],
+            "dtype": "f32 states / f64 sums", "roofline": roofline(mixed, rates, "float", 48), "kernels": mixed["kernels"],
             "check": mixed["check"], "vs_fp64_same_workload": mixed["vs_fp64"],
         }
     if track is not None:
@@ -458,7 +497,7 @@ def main():
             "states_evolved": q1d["nst"], "graph_record_ms": q1d["graph_record_ms"],
             "setup_seconds": q1d["setup_seconds"], "tuned_workgroups": q1d["tuned"],
             "problems": q1d["problems"], "kernels": q1d["kernels"], "check": q1d["check"],
-            "roofline": roofline(dict(q1d, steps=q1d["profile_steps"]), copy_bps, "float", 16, "q1d_")
+            "roofline": roofline(dict(q1d, steps=q1d["profile_steps"]), rates, "float", 16, "q1d_", fused=True)
             if q1d["kernels"] else None,
         }
         if q1d64 is not None:

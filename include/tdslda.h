@@ -143,9 +143,15 @@ tdslda_status tdslda_load_states_device(tdslda_ctx* ctx, int64_t n, const void* 
  * times exp(i k.r)/sqrt(V).  E_n of each state sets its frozen weights. */
 tdslda_status tdslda_init_plane_waves(tdslda_ctx* ctx, int64_t n, const int32_t* kidx,
                                       double u0, double delta0);
-/* Vortex imprint on every loaded state: u_n <- exp(i theta(r)) u_n with
- * theta = sum_j q_j atan2(y - y_j, x - x_j) (straight lines along z, centred
- * coordinates).  xyq: [nv][3] host array of (x_j, y_j, q_j).  3D only. */
+/* Vortex imprint on every loaded state (a phase e^{i theta} on Delta; Delta
+ * is derived from the states in TD, so the phase goes onto the states as
+ * the local gauge rotation of both fermion fields by theta/2): u_n <- e^{i theta/2} u_n, v_n <- e^{-i theta/2} v_n, which
+ * multiplies nu and Delta by e^{i theta}, keeps rho and the orthonormality
+ * of the states, and commutes with the partner map (u, v) -> (v^*, -u^*) of
+ * the spin-symmetric reduction (Sec. 2.3), so the evolved E > 0 states keep
+ * standing for a complete set.  theta = sum_j q_j atan2(y - y_j, x - x_j)
+ * (straight lines along z, centred coordinates).  xyq: [nv][3] host array
+ * of (x_j, y_j, q_j).  3D only. */
 tdslda_status tdslda_imprint_vortices(tdslda_ctx* ctx, int nv, const double* xyq);
 
 /* Freeze the mean fields (linear mode): U[M] and Delta[M][2] (host FP64) are
@@ -376,6 +382,15 @@ tdslda_status tdslda_load(tdslda_ctx* ctx, const char* path);
  * overlapping; bytes >= 0 is a multiple of 16.  Errors: EINVAL (alignment,
  * size, overlap), EDEVICE (launch failure). */
 tdslda_status tdslda_device_copy(void* dst, const void* src, int64_t bytes, void* hip_stream);
+
+/* Streaming read of `bytes` bytes of src on hip_stream (NULL = the null
+ * stream), asynchronous: 128-bit non-temporal loads, consecutive lanes on
+ * consecutive words, nothing written (sink16, a 16-byte device buffer, is
+ * written only for one particular data pattern, to keep the loads).  The
+ * read-only HBM reference of the measurement, beside tdslda_device_copy.
+ * src and sink16 16-byte aligned device pointers; bytes a multiple of 16.
+ * Errors: EINVAL (alignment, size), EDEVICE (launch failure). */
+tdslda_status tdslda_device_read(const void* src, int64_t bytes, void* sink16, void* hip_stream);
 
 /* Kernel timing.  With profiling on, every kernel launch is bracketed by HIP
  * events on the context stream; tdslda_kernel_stats returns, for kernel class

@@ -867,6 +867,10 @@ __global__ void k_plane_waves(int64_t M, int nx, int ny, int nz, const int32_t* 
   X[n * 2 * M + M + r] = cpx<R>{R(vk * cs * invsqrtV), R(vk * sn * invsqrtV)};
 }
 
+// vortex imprint: gauge rotation of both components by theta/2,
+// u <- e^{i theta/2} u, v <- e^{-i theta/2} v (nu, hence Delta, gains
+// e^{i theta}; the partner map of the spin-symmetric reduction commutes
+// with it)
 template <typename R>
 __global__ void k_imprint(int64_t M, int64_t nstates, const double* __restrict__ theta,
                           cpx<R>* __restrict__ X) {
@@ -874,10 +878,11 @@ __global__ void k_imprint(int64_t M, int64_t nstates, const double* __restrict__
   const int64_t n = blockIdx.y;
   if (r >= M || n >= nstates) return;
   double sn, cs;
-  sincos(theta[r], &sn, &cs);
-  const cpx<R> u = X[n * 2 * M + r];
-  const double ur = u.x, ui = u.y;
+  sincos(0.5 * theta[r], &sn, &cs);
+  const cpx<R> u = X[n * 2 * M + r], v = X[n * 2 * M + M + r];
+  const double ur = u.x, ui = u.y, vr = v.x, vi = v.y;
   X[n * 2 * M + r] = cpx<R>{R(ur * cs - ui * sn), R(ur * sn + ui * cs)};
+  X[n * 2 * M + M + r] = cpx<R>{R(vr * cs + vi * sn), R(vi * cs - vr * sn)};
 }
 
 // host FP64 states -> context precision (and back)

@@ -438,6 +438,17 @@ tdslda_status tdslda_device_copy(void* dst, const void* src, int64_t bytes, void
   }
 }
 
+tdslda_status tdslda_device_read(const void* src, int64_t bytes, void* sink16, void* hip_stream) {
+  if (!src || !sink16 || bytes < 0 || bytes % 16 || (uintptr_t(src) | uintptr_t(sink16)) % 16) return TDSLDA_EINVAL;
+  if (bytes / 16 > int64_t(0x7fffffff) * RD_TB * RD_U) return TDSLDA_EINVAL;
+  const int64_t n16 = bytes / 16;
+  if (n16 == 0) return TDSLDA_OK;
+  hipLaunchKernelGGL(k_stream_read, dim3(cdiv(n16, RD_TB * RD_U)), dim3(RD_TB), 0, (hipStream_t)hip_stream,
+                     (const cp_v4i*)src, (cp_v4i*)sink16, n16);
+  if (hipGetLastError() != hipSuccess) return TDSLDA_EDEVICE;
+  return TDSLDA_OK;
+}
+
 const char* tdslda_last_error(const tdslda_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
 tdslda_status tdslda_memory_plan(const tdslda_lattice* lat, const tdslda_run* run, int64_t nstates,

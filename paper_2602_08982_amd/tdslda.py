@@ -79,6 +79,7 @@ _SIGS = {
     "tdslda_kernel_stats": [C.c_void_p, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_double)],
     "tdslda_kernel_name": [C.c_int],
     "tdslda_device_copy": [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p],
+    "tdslda_device_read": [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p],
     "tdslda_abm_graph": [C.c_void_p, C.c_int64, C.c_void_p],
     "tdslda_autotune": [C.c_void_p, C.POINTER(C.c_int), C.c_void_p, C.c_void_p],
     "tdslda_q1d_count": [C.POINTER(Lattice), C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
@@ -144,6 +145,15 @@ def _dev_ptr(t):
     if isinstance(t, int):
         return C.c_void_p(t)
     return C.c_void_p(t.data_ptr())
+
+
+def device_read(src, nbytes, sink, stream=None):
+    """tdslda_device_read: streaming read of a device tensor (sink: a
+    16-byte device tensor) on a HIP stream (integer handle; None = null)."""
+    lib = load_library()
+    st = lib.tdslda_device_read(_dev_ptr(src), int(nbytes), _dev_ptr(sink), C.c_void_p(stream or 0))
+    if st != OK:
+        raise TdsldaError(st, "device_read rejected the arguments")
 
 
 def device_copy(dst, src, nbytes, stream=None):

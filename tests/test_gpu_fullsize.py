@@ -65,16 +65,16 @@ def test_fullsize_start_and_steps(which):
         ctx.close()
 
 
-def test_fullsize_energy_conservation():
-    """Energy conservation at full size (32^3 FP64, all 32,768 states, trap,
-    no vortex).  A phase imprinted on the u components alone leaves the
-    evolved set without its particle-hole partners' completeness, and the
-    energy functional then drifts even as dt -> 0 (the oracle shows the
-    same); without the imprint the evolution conserves it to the
-    integrator's accuracy."""
+@pytest.mark.parametrize("vortex", [False, True])
+def test_fullsize_energy_conservation(vortex):
+    """Energy conservation at full size (32^3 FP64, all 32,768 states, trap),
+    with and without the vortex: the imprint (gauge rotation of u and v by
+    theta/2) keeps the evolved E > 0 set closed under the partner map, so
+    the energy is conserved to the integrator's accuracy in both cases."""
     from paper_2602_08982_amd import workloads as W
     cfg = W.PLAIN
-    ctx, kidx = W.setup(cfg, [])
+    vort = [(*synth.vortex_offset(2), 1.0)] if vortex else []
+    ctx, kidx = W.setup(cfg, vort)
     try:
         ctx.abm_step(2)
         e1 = ctx.energy()
