@@ -25,6 +25,78 @@ def apply_h(phi, hfield, delta, lat):
     return np.stack([hu, hv], axis=1)
 
 
+def kinetic_alpha(f, alpha, lat):
+    """-1/2 div(alpha grad f) in the symmetrised form of Eq. kinop-alpha,
+    summed over the three axes: -1/4 [lap(alpha f) + alpha lap f - f lap alpha],
+    every Laplacian spectral with the full -k^2 (Eq. D2)."""
+    return -0.25 * (L.laplacian(alpha * f, lat) + alpha * L.laplacian(f, lat) - f * L.laplacian(alpha, lat))
+
+
+def current_term(f, avec, lat):
+    """-(i/2) {A, grad} f = -(i/2) sum_d [A_d d_d f + d_d (A_d f)] (the
+    current-potential term of Eq. h_sigma), each first derivative the
+    spectral D1 with the Nyquist mode zeroed (Sec. 3.1; matrix forms of
+    Eqs. Ad_dx and d_dxA)."""
+    out = np.zeros(f.shape, complex)
+    for d in range(3):
+        axis = f.ndim - 3 + d
+        out += avec[d] * L.spectral_derivative(f, lat.k[d], axis, 1)
+        out += L.spectral_derivative(avec[d] * f, lat.k[d], axis, 1)
+    return -0.5j * out
+
+
+def apply_h_general(phi, hfield, delta, alpha, avec, lat):
+    """H of Eq. HpsiEpsi with the general single-particle Hamiltonian of
+    Eq. h_sigma (spin-symmetric: one alpha, one current potential A):
+
+        h = -1/2 div(alpha grad) + hfield - (i/2) {A, grad},
+        H (u, v) = ( h u + Delta v,  Delta^* u - h^* v ),
+        -h^* v = 1/2 div(alpha grad) v - hfield v - (i/2) {A, grad} v
+
+    (the kinetic and current parts are real operators, hence the same sign
+    of the current term in both rows).  alpha: scalar or field; avec: three
+    real fields (or None)."""
+    alpha = np.broadcast_to(np.asarray(alpha, float), lat.shape)
+    u, v = phi[:, 0], phi[:, 1]
+    ku, kv = kinetic_alpha(u, alpha, lat), kinetic_alpha(v, alpha, lat)
+    hu = ku + hfield * u + delta * v
+    hv = np.conj(delta) * u - (kv + hfield * v)
+    if avec is not None:
+        hu = hu + current_term(u, avec, lat)
+        hv = hv + current_term(v, avec, lat)
+    return np.stack([hu, hv], axis=1)
+
+
+def dense_h_general(hfield, delta, alpha, avec, lat):
+    """2M x 2M matrix of apply_h_general from the dense matrices of Eqs. D1
+    and D2 (Kronecker products per axis): the kinetic part as
+    1/2 [D2 diag(alpha) + diag(alpha) D2 - diag(D2 alpha)] per axis (Eq.
+    kinop-alpha), the current part as diag(A_d) D1_d + D1_d diag(A_d) (Eqs.
+    Ad_dx, d_dxA)."""
+    n = lat.n
+    eye = [np.eye(m) for m in n]
+
+    def axis_op(Dm, d):
+        mats = [eye[0], eye[1], eye[2]]
+        mats[d] = Dm
+        return np.kron(np.kron(mats[0], mats[1]), mats[2])
+    a = np.ravel(np.broadcast_to(np.asarray(alpha, float), lat.shape))
+    A = np.diag(a)
+    K = np.zeros((lat.M, lat.M))
+    for d in range(3):
+        D2 = axis_op(L.d2_matrix(n[d], lat.d[d]), d)
+        K += -0.25 * (D2 @ A + A @ D2 - np.diag(D2 @ a))
+    C = np.zeros((lat.M, lat.M), complex)
+    if avec is not None:
+        for d in range(3):
+            D1 = axis_op(L.d1_matrix(n[d], lat.d[d]), d)
+            Ad = np.diag(np.ravel(avec[d]))
+            C += -0.5j * (Ad @ D1 + D1 @ Ad)
+    h = K + np.diag(np.ravel(hfield))
+    dm = np.diag(np.ravel(delta))
+    return np.block([[h + C, dm], [np.conj(dm), -h + C]])
+
+
 def dense_h(hfield, delta, lat):
     """2M x 2M matrix of H in the ordering (u, v), built from the dense
     derivative matrices of Eq. D2 and diagonal matrices for the local

@@ -118,6 +118,28 @@ def potentials(rho, nu, lam, fun):
     return U, delta, g
 
 
+def potentials_general(rho, nu, j, lam, fun):
+    """Potentials of the SLDA-type functional with A != 1 (Sec. 2.3, the
+    functional derivatives of Eq. h_sigma) in the spin-symmetric case, per
+    spin component:
+        alpha = 2 dE/dtau_sigma = A,
+        A_vec = dE/dj_sigma     = (1 - A) j / rho,
+        U     = dE/drho_sigma   = B eF(rho_+) - |Delta|^2 / (3 C rho_+^(2/3))
+                                  - (1 - A) |j|^2 / (2 rho^2),
+        Delta = -g_eff nu,
+    from the intrinsic part (A/2)(tau - j^2/rho) and the centre-of-mass part
+    j^2/(2 rho) of the energy density (Eqs. sldae-functional,
+    sldae-functional-CM).  j: three arrays (per spin).  Returns (U, Delta,
+    alpha, A_vec)."""
+    U, delta, _ = potentials(rho, nu, lam, fun)
+    rho_s = np.maximum(rho, RHO_FLOOR / 2)
+    jsq = sum(np.abs(c) ** 2 for c in j)
+    c = 1.0 - fun.A
+    U = U - c * jsq / (2.0 * rho_s ** 2)
+    avec = [c * jc / rho_s for jc in j]
+    return U, delta, fun.A, avec
+
+
 def energy_density(rho, tau, jsq, nu, lam, fun):
     """SLDA-type energy density (Eqs. sldae-functional-generic, -CM, and the
     intrinsic part) for the spin-symmetric case, with the regularised

@@ -46,12 +46,41 @@ class GeometryQ1D:
     def _lap(self, f):
         return L.spectral_derivative(f, self.kz, f.ndim - 1, 2)
 
-    def apply_h(self, phi, hfield, delta):
+    def apply_h(self, phi, hfield, delta, alpha=None, avec=None):
+        """H of every problem.  With alpha / avec (the A != 1 functional,
+        Eq. h_sigma) the z kinetic part takes the symmetrised form of Eq.
+        kinop-alpha, the transverse plane waves add 1/2 alpha k_perp^2 (the
+        paper's mu -> mu - 1/2 alpha k_perp^2 of the quasi-1D item), and the
+        current term is -(i/2) {A_z, d_z} with D1 (Nyquist zeroed); the
+        transverse components of A vanish (j_perp cancels between +k_perp and
+        -k_perp)."""
         u, v = phi[:, 0], phi[:, 1]
-        off = 0.5 * self.kperp2[:, None]
-        hu = -0.5 * self._lap(u) + (hfield + off) * u + delta * v
-        hv = np.conj(delta) * u - (-0.5 * self._lap(v) + (hfield + off) * v)
+        if alpha is None and avec is None:
+            off = 0.5 * self.kperp2[:, None]
+            hu = -0.5 * self._lap(u) + (hfield + off) * u + delta * v
+            hv = np.conj(delta) * u - (-0.5 * self._lap(v) + (hfield + off) * v)
+            return np.stack([hu, hv], axis=1)
+        al = np.broadcast_to(np.asarray(1.0 if alpha is None else alpha, float), self.shape)
+        off = 0.5 * al[None, :] * self.kperp2[:, None]
+        lap_a = self._lap(al.astype(complex))
+
+        def kin(f):
+            return -0.25 * (self._lap(al * f) + al * self._lap(f) - f * lap_a) + off * f
+
+        def cur(f):
+            if avec is None:
+                return 0.0
+            az = avec[2]
+            d1 = L.spectral_derivative(f, self.kz, f.ndim - 1, 1)
+            d1a = L.spectral_derivative(az * f, self.kz, f.ndim - 1, 1)
+            return -0.5j * (az * d1 + d1a)
+        hu = kin(u) + hfield * u + cur(u) + delta * v
+        hv = np.conj(delta) * u - (kin(v) + hfield * v) + cur(v)
         return np.stack([hu, hv], axis=1)
+
+    def rho_nu_j(self, phi, wu, wv):
+        rho, _, nu, j = self.full_densities(phi, wu, wv)
+        return rho, nu, j
 
     def _gsq(self, f, dzf):
         """|d_z f|^2 in the symmetric-Nyquist convention of the 3D densities."""

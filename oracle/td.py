@@ -51,11 +51,17 @@ class Geometry3D:
         self.dV_energy = lat.dV   # measure of energy / particle-number integrals
         self.shape = lat.shape
 
-    def apply_h(self, phi, hfield, delta):
-        return bdg.apply_h(phi, hfield, delta, self.lat)
+    def apply_h(self, phi, hfield, delta, alpha=None, avec=None):
+        if alpha is None and avec is None:
+            return bdg.apply_h(phi, hfield, delta, self.lat)
+        return bdg.apply_h_general(phi, hfield, delta, 1.0 if alpha is None else alpha, avec, self.lat)
 
     def rho_nu(self, phi, wu, wv):
         return D.local_densities(phi, wu, wv)
+
+    def rho_nu_j(self, phi, wu, wv):
+        rho, _, nu, j = D.spin_symmetric(phi, wu, wv, self.lat)
+        return rho, nu, j
 
     def full_densities(self, phi, wu, wv):
         return D.spin_symmetric(phi, wu, wv, self.lat)
@@ -109,18 +115,31 @@ class TDSystem:
 
     def fields(self, phi):
         """Densities -> potentials -> (hfield = U + V_ext - mu, the
-        off-diagonal field Delta + Delta_ext)."""
+        off-diagonal field Delta + Delta_ext, alpha, A_vec).  alpha and
+        A_vec are None for the A = 1 functional (Eq. h_sigma_A1); with
+        A != 1 the current j enters every field build (alpha = A, A_vec =
+        (1 - A) j / rho and the current term of U).  frozen = (hfield,
+        Delta) or (hfield, Delta, alpha, A_vec)."""
         if self.frozen is not None:
-            hf, de = self.frozen
-            return hf, de if self.dext is None else de + self.dext
-        rho, nu = self.geom.rho_nu(phi, self.wu, self.wv)
-        U, delta, _ = F.potentials(rho, nu, self.lam, self.fun)
+            hf, de = self.frozen[0], self.frozen[1]
+            al = self.frozen[2] if len(self.frozen) > 2 else None
+            av = self.frozen[3] if len(self.frozen) > 3 else None
+            return hf, (de if self.dext is None else de + self.dext), al, av
+        al = av = None
+        if self.fun.A != 1.0:
+            if self.friction is not None:
+                raise NotImplementedError("quantum friction is written for the A = 1 functional")
+            rho, nu, j = self.geom.rho_nu_j(phi, self.wu, self.wv)
+            U, delta, al, av = F.potentials_general(rho, nu, j, self.lam, self.fun)
+        else:
+            rho, nu = self.geom.rho_nu(phi, self.wu, self.wv)
+            U, delta, _ = F.potentials(rho, nu, self.lam, self.fun)
         if self.friction is not None:
             Ud, Dd = self.friction.terms(self.geom, phi, self.wu, self.wv, nu, delta)
             U, delta = U + Ud, delta + Dd
         if self.dext is not None:
             delta = delta + self.dext
-        return U + self.vext - self.mu, delta
+        return U + self.vext - self.mu, delta, al, av
 
     def expect(self, phi, hphi):
         ax = tuple(range(1, phi.ndim))
@@ -129,8 +148,7 @@ class TDSystem:
     def f(self, phi):
         """f(phi) of Eq. ABM-f for normalised phi."""
         self.n_f_evals += 1
-        hf, de = self.fields(phi)
-        hphi = self.geom.apply_h(phi, hf, de)
+        hphi = self.geom.apply_h(phi, *self.fields(phi))
         e = self.expect(phi, hphi)
         return -1j * (hphi - _bc(e, phi) * phi)
 
@@ -164,12 +182,12 @@ def abm_step(sys, phi, hist, dt, scheme="AB4AM5"):
 
 
 def taylor_apply(sys, phi, fields, shift, tau, r):
-    """sum_{k=0}^{r} (-i tau)^k / k! (H - shift)^k phi with H fixed by fields."""
-    hf, de = fields
+    """sum_{k=0}^{r} (-i tau)^k / k! (H - shift)^k phi with H fixed by fields
+    (the tuple TDSystem.fields returns)."""
     term = phi
     out = phi.copy()
     for k in range(1, r + 1):
-        hterm = sys.geom.apply_h(term, hf, de) - _bc(shift, phi) * term
+        hterm = sys.geom.apply_h(term, *fields) - _bc(shift, phi) * term
         term = (-1j * tau / k) * hterm
         out = out + term
     return out

@@ -27,7 +27,7 @@ def test_uniform_dispersion_with_dext():
     sys_ = td.TDSystem(td.Geometry3D(lat), None, mu, np.zeros(lat.shape), np.zeros(lat.shape),
                        np.zeros(nst), np.ones(nst), frozen=(np.full(lat.shape, U0 - mu), np.full(lat.shape, d0 + 0j)),
                        dext=np.full(lat.shape, dext))
-    hf, de = sys_.fields(None)
+    hf, de = sys_.fields(None)[:2]
     E = np.linalg.eigvalsh(bdg.dense_h(hf, de, lat))
     xi = 0.5 * lat.k2.ravel() + U0 - mu
     ek = np.sqrt(xi ** 2 + abs(d0 + dext) ** 2)
@@ -57,7 +57,7 @@ def test_offdiagonal_field_is_energy_derivative():
     sys_ = td.TDSystem(td.Geometry3D(lat), fun, mu, np.zeros(lat.shape), lam, F.fermi_weight(E),
                        F.fermi_weight(-E), dext=dext)
     rho, tau, nu, j = D.spin_symmetric(D.normalize(phi, lat.dV), sys_.wu, sys_.wv, lat)
-    _, off = sys_.fields(D.normalize(phi, lat.dV))
+    off = sys_.fields(D.normalize(phi, lat.dV))[1]
     tot = lambda x: F.energy_terms(rho, tau, j, x, lam, np.zeros(lat.shape), fun, lat.dV, dext=dext)["total"]
     h = 1e-7
     for site in [(0, 0, 0), (1, 2, 3), (3, 1, 0)]:
@@ -74,8 +74,8 @@ class _FlippedDext(td.TDSystem):
     E_pair.ext as defined."""
 
     def fields(self, phi):
-        hf, de = super().fields(phi)
-        return hf, de - 2.0 * self.dext
+        hf, de, al, av = super().fields(phi)
+        return hf, de - 2.0 * self.dext, al, av
 
 
 def _drift(sys_, phi0, steps=20, dt=0.005):
