@@ -136,6 +136,11 @@ struct tdslda_ctx {
   double* dext = nullptr;  // external pairing potential [M][2] (zero unless set)
   bool dext_on = false;
   void *hA = nullptr, *hD = nullptr;
+  // general functional (A != 1, Eq. h_sigma; quasi-1D kernel set): inverse
+  // effective mass alpha, its D2, and the current potential A_z, [M] in the
+  // context precision; gen = the general operator is in use
+  void *hAl = nullptr, *hLa = nullptr, *hAz = nullptr;
+  bool gen = false;
   double* gscratch = nullptr;  // [gchunk][4][M] doubles (tau_s, j_s); also FP64 staging
   int64_t gchunk = 1;
   double* eout = nullptr;

@@ -64,14 +64,14 @@ __global__ __launch_bounds__(1024) void k_energy(int64_t M, const double* __rest
                                                  const double* __restrict__ j,
                                                  const double* __restrict__ delta,
                                                  const double* __restrict__ vext,
-                                                 const double* __restrict__ dext, double B,
+                                                 const double* __restrict__ dext, double B, double A,
                                                  int slda, double dVe, double* __restrict__ out) {
   __shared__ double red[1024 / kWave];
   double ek = 0, ep = 0, epa = 0, ec = 0, ee = 0, nn = 0, epx = 0;
   for (int64_t r = threadIdx.x; r < M; r += 1024) {
     const double rs = fmax(rho[r], 0.5e-14);
     const double jsq = j[r] * j[r] + j[M + r] * j[M + r] + j[2 * M + r] * j[2 * M + r];
-    ek += (tau[r] - jsq / rs);
+    ek += A * (tau[r] - jsq / rs);
     if (slda) ep += 0.6 * B * (2.0 * rho[r]) * 0.5 * pow(3.0 * kPi * kPi * (2.0 * rho[r]), 2.0 / 3.0);
     epa -= delta[2 * r] * nu[2 * r] + delta[2 * r + 1] * nu[2 * r + 1];
     ec += jsq / rs;
@@ -128,12 +128,12 @@ __global__ __launch_bounds__(RD_TB) void k_stream_read(const cp_v4i* __restrict_
 // set-up kernels
 // Lambda_c of Eq. Creg with V_+ = vext (A = 1); k_0^2 < 0 continued
 // analytically (k_0 = i kappa).
-__global__ void k_lambda(int64_t M, const double* __restrict__ vext, double mu, double ec,
+__global__ void k_lambda(int64_t M, const double* __restrict__ vext, double mu, double ec, double A,
                          double* __restrict__ lam, int* __restrict__ bad) {
   const int64_t r = int64_t(blockIdx.x) * 256 + threadIdx.x;
   if (r >= M) return;
-  const double k0sq = 2.0 * (mu - vext[r]);
-  const double kcsq = 2.0 * (ec + mu - vext[r]);
+  const double k0sq = 2.0 * (mu - vext[r]) / A;
+  const double kcsq = 2.0 * (ec + mu - vext[r]) / A;
   if (kcsq <= 0.0) {
     bad[0] = 1;
     lam[r] = 0.0;
@@ -148,7 +148,53 @@ __global__ void k_lambda(int64_t M, const double* __restrict__ vext, double mu, 
     const double ka = sqrt(-k0sq);
     br = 1.0 + ka / kc * atan(ka / kc);
   }
-  lam[r] = kc / (2.0 * kPi * kPi) * br;
+  lam[r] = kc / (2.0 * kPi * kPi * A) * br;
+}
+
+// FP64 -> context precision, real field
+template <typename R>
+__global__ void k_convert_real(int64_t M, const double* __restrict__ in, R* __restrict__ out) {
+  const int64_t r = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (r < M) out[r] = R(in[r]);
+}
+
+// out[r] = value (the constant inverse effective mass of the functional)
+template <typename R>
+__global__ void k_fill_real(int64_t M, double value, R* __restrict__ out) {
+  const int64_t r = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (r < M) out[r] = R(value);
+}
+
+// D2 of a real field on an N-point periodic axis (N <= 256, one workgroup):
+// out = Re 1/N sum_k (-k^2) f~_k exp(2 pi i k z / N), f~ by direct sums,
+// the Nyquist mode kept (Eq. D2); f also converted to the context precision.
+template <typename R>
+__global__ __launch_bounds__(256) void k_field_d2(int N, double dz, const double* __restrict__ f,
+                                                  R* __restrict__ fout, R* __restrict__ out) {
+  __shared__ double fr[256], fi[256];
+  const int t = threadIdx.x;
+  if (t < N) {
+    double re = 0.0, im = 0.0;
+    for (int z = 0; z < N; ++z) {
+      double s_, c_;
+      sincos(-2.0 * kPi * double((int64_t(t) * z) % N) / N, &s_, &c_);
+      re += f[z] * c_;
+      im += f[z] * s_;
+    }
+    fr[t] = re;
+    fi[t] = im;
+  }
+  __syncthreads();
+  if (t >= N) return;
+  double acc = 0.0;
+  for (int k = 0; k < N; ++k) {
+    const double km = 2.0 * kPi / (N * dz) * double(k < N / 2 ? k : k - N);
+    double s_, c_;
+    sincos(2.0 * kPi * double((int64_t(k) * t) % N) / N, &s_, &c_);
+    acc += -km * km * (fr[k] * c_ - fi[k] * s_);
+  }
+  out[t] = R(acc / N);
+  fout[t] = R(f[t]);
 }
 
 // theta(x, y) of straight vortex lines along z (centred coordinates)

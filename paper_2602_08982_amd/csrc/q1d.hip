@@ -729,6 +729,329 @@ __global__ __launch_bounds__(256) void q_fric_fields(int N, double dz, double dV
   hD[t] = cpx<R>{R(dr * fr - di * fi + dext[2 * t]), R(dr * fi + di * fr + dext[2 * t + 1])};
 }
 
+// ---------------------------------------------------------------------------
+// General functional (A != 1; Sec. 2.3, Eq. h_sigma): the single-particle
+// Hamiltonian carries an inverse effective mass alpha(z) and a current
+// potential A_z(z):
+//   h = -1/2 d_z alpha d_z + 1/2 alpha k_perp^2 + hfield - (i/2) {A_z, d_z},
+// with the kinetic part in the symmetrised form of Eq. kinop-alpha,
+//   d_z alpha d_z x = 1/2 [D2(alpha x) + alpha D2 x - x D2 alpha],
+// and the current part as A_z D1 x + D1(A_z x) (Eqs. Ad_dx, d_dxA; D1 with
+// the Nyquist mode zeroed, D2 with the full k^2).  Self-consistent fields
+// (SLDA at p = 0): alpha = A, A_z = (1 - A) j_z / rho, and U gains
+// -(1 - A) j_z^2 / (2 rho^2); j_z is rebuilt with rho and nu at every field
+// build.
+
+// q_densj: rho, nu and j_z group partials of the normalised states,
+//   j_z = sum_n [f_v Im(v (D1 v)^*) - f_u Im(u (D1 u)^*)],
+// part layout [group][4][N] (rho, Re nu, Im nu, j_z).
+template <typename R, int A, int G, int TB>
+__global__ __launch_bounds__(TB) void q_densj(const cpx<R>* __restrict__ X, int64_t nstates,
+                                               const double* __restrict__ wu, const double* __restrict__ wv,
+                                               const double* __restrict__ scale, double* __restrict__ part,
+                                               const cpx<R>* __restrict__ tw, double kz) {
+  using CFG = Q1DCfg<R, A, TB>;
+  constexpr int N = CFG::N, WS = CFG::WS;
+  constexpr int NW = CFG::TB / kWave;
+  __shared__ cpx<R> lds_all[WS][A * CFG::PAD];
+  __shared__ double red[NW][4 * N];
+  const int tid = threadIdx.x, grp = tid / A, a = tid % A;
+  cpx<R>* lds = lds_all[grp];
+  double ar[A], anr[A], ani[A], aj[A];
+#pragma unroll
+  for (int b = 0; b < A; ++b) ar[b] = anr[b] = ani[b] = aj[b] = 0.0;
+  const R inv_n = R(1.0 / N);
+  const int64_t nbeg = int64_t(blockIdx.x) * G;
+  for (int it = 0; it < G / WS; ++it) {
+    const int64_t n = nbeg + it * WS + grp;
+    const bool live = n < nstates;
+    const int64_t nn = live ? n : 0;
+    const R s = R(scale[nn]);
+    const double fu = live ? wu[nn] : 0.0, fv = live ? wv[nn] : 0.0;
+    const cpx<R>* Xn = X + nn * 2 * N;
+    cpx<R> x[A], d[A];
+#pragma unroll 1
+    for (int comp = 0; comp < 2; ++comp) {
+      const double wgt = comp ? fv : -fu;
+#pragma unroll
+      for (int b = 0; b < A; ++b) {
+        x[b] = s * Xn[comp * N + a + A * b];
+        d[b] = x[b];
+      }
+      if (comp == 0) {
+        // u: rho and nu need v at the same sites, read it here as well
+#pragma unroll
+        for (int b = 0; b < A; ++b) {
+          const cpx<R> v = s * Xn[N + a + A * b];
+          const double ur = x[b].x, ui = x[b].y, vr = v.x, vi = v.y;
+          ar[b] += fv * (vr * vr + vi * vi) + fu * (ur * ur + ui * ui);
+          anr[b] += (fv - fu) * (ur * vr + ui * vi);
+          ani[b] += (fv - fu) * (ui * vr - ur * vi);
+        }
+      }
+      q_fwd<R, A>(d, a, lds, tw);
+      sfor<0, A>::run([&](auto pc) {
+        constexpr int p = decltype(pc)::value;
+        const int m = q_wavenum<A>(a, freq_of_pos<A>(p));
+        const R k = m == -N / 2 ? R(0) : R(kz * m);
+        d[p] = cpx<R>{-k * d[p].y, k * d[p].x};  // i k x~
+      });
+      q_inv<R, A>(d, a, lds, tw);
+#pragma unroll
+      for (int b = 0; b < A; ++b) {
+        const cpx<R> g = inv_n * d[b];
+        aj[b] += wgt * (double(x[b].y) * double(g.x) - double(x[b].x) * double(g.y));  // Im(x g^*)
+      }
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < A; ++b) {
+#pragma unroll
+    for (int o = A; o < kWave; o <<= 1) {
+      ar[b] += __shfl_xor(ar[b], o, kWave);
+      anr[b] += __shfl_xor(anr[b], o, kWave);
+      ani[b] += __shfl_xor(ani[b], o, kWave);
+      aj[b] += __shfl_xor(aj[b], o, kWave);
+    }
+  }
+  const int w = tid / kWave, lw = tid % kWave;
+  if (lw < A) {
+#pragma unroll
+    for (int b = 0; b < A; ++b) {
+      red[w][a + A * b] = ar[b];
+      red[w][N + a + A * b] = anr[b];
+      red[w][2 * N + a + A * b] = ani[b];
+      red[w][3 * N + a + A * b] = aj[b];
+    }
+  }
+  __syncthreads();
+  double* out = part + int64_t(blockIdx.x) * 4 * N;
+  for (int i = tid; i < 4 * N; i += CFG::TB) {
+    double t = 0.0;
+#pragma unroll
+    for (int w2 = 0; w2 < NW; ++w2) t += red[w2][i];
+    out[i] = t;
+  }
+}
+
+// one workgroup per site: the four group partials summed in a fixed order
+// (times 1/(L_x L_y)), then the SLDA potentials at A != 1 (see above):
+//   Delta = -g_eff nu,  U = B eF - |Delta|^2 / (3 C rho_+^(2/3))
+//   - (1 - A) j^2 / (2 rho^2),  A_z = (1 - A) j / rho  (rho per spin).
+template <typename R>
+__global__ __launch_bounds__(256) void q_reduce_gen(const double* __restrict__ part, int ngroups, int N,
+                                                    FunParams fp, double Aconst, const double* __restrict__ lam,
+                                                    const double* __restrict__ vext, double* __restrict__ rho,
+                                                    double* __restrict__ nu, double* __restrict__ jc,
+                                                    double* __restrict__ U, double* __restrict__ delta,
+                                                    R* __restrict__ hA, cpx<R>* __restrict__ hD,
+                                                    R* __restrict__ hAz, int update_fields) {
+  __shared__ double t4[4][256];
+  const int r = blockIdx.x, t = threadIdx.x;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  for (int g = t; g < ngroups; g += 256) {
+    const double* p = part + int64_t(g) * 4 * N;
+    a0 += p[r];
+    a1 += p[N + r];
+    a2 += p[2 * N + r];
+    a3 += p[3 * N + r];
+  }
+  t4[0][t] = a0;
+  t4[1][t] = a1;
+  t4[2][t] = a2;
+  t4[3][t] = a3;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (t < k) {
+      t4[0][t] += t4[0][t + k];
+      t4[1][t] += t4[1][t + k];
+      t4[2][t] += t4[2][t + k];
+      t4[3][t] += t4[3][t + k];
+    }
+    __syncthreads();
+  }
+  if (t != 0) return;
+  const double sr = fp.ainv * t4[0][0], snr = fp.ainv * t4[1][0], sni = fp.ainv * t4[2][0];
+  const double sj = fp.ainv * t4[3][0];
+  rho[r] = sr;
+  nu[2 * r] = snr;
+  nu[2 * r + 1] = sni;
+  jc[r] = 0.0;
+  jc[N + r] = 0.0;
+  jc[2 * N + r] = sj;
+  if (!update_fields) return;
+  const double rp = fmax(2.0 * sr, 1e-14);
+  const double gg = 1.0 / (cbrt(rp) / fp.C - lam[r]);
+  const double dr = -gg * snr, di = -gg * sni;
+  const double ef = 0.5 * pow(3.0 * kPi * kPi * (2.0 * sr), 2.0 / 3.0);
+  const double c23 = cbrt(rp);
+  const double rs = fmax(sr, 0.5e-14), cA = 1.0 - Aconst;
+  const double u = fp.B * ef - (dr * dr + di * di) / (3.0 * fp.C * c23 * c23) - cA * sj * sj / (2.0 * rs * rs);
+  U[r] = u;
+  delta[2 * r] = dr;
+  delta[2 * r + 1] = di;
+  hA[r] = R(u + vext[r] - fp.mu);
+  hD[r] = cpx<R>{R(dr + fp.dext[2 * r]), R(di + fp.dext[2 * r + 1])};
+  hAz[r] = R(cA * sj / rs);
+}
+
+// the general operator in the split layout (as q_corr_split: 2A lanes per
+// state, u on the first A, v on the others), every mode:
+//   H / TAYLOR: the operator of the prepared fields with the given shift,
+//   F / CORR / FULL: <H>_n = Re <phi|H phi> dz over the 2A lanes, then the
+//     integrator arithmetic of k_lap2,
+//   L2_EXPECT: <H>_n only, into h slot 1 (slot 0 cleared): the shift of a
+//     prepared state for the start-up.
+// Per component 7 transforms: x forward, D2 x and D1 x back, alpha x
+// forward and D2 back, A_z x forward and D1 back.
+constexpr int L2_EXPECT = 5;
+template <typename R, int A, int TB, int MODE, int NP = 4, int NQ = 5>
+__global__ __launch_bounds__(TB) void q_gen(Lap2Args<R> P, int64_t nstates, const double* __restrict__ kperp2,
+                                            const R* __restrict__ hAl, const R* __restrict__ hAz,
+                                            const R* __restrict__ hLa, const cpx<R>* __restrict__ tw, double kz) {
+  constexpr int HD = (NP > NQ - 1) ? NP : NQ - 1;
+  constexpr int N = A * A, L = 2 * A, WS = TB / L, PAD = A + 1;
+  static_assert(TB % L == 0 && kWave % L == 0, "a state's lanes must sit in one wave");
+  constexpr bool OWN_H = MODE == L2_F || MODE == L2_CORR || MODE == L2_FULL || MODE == L2_EXPECT;
+  __shared__ cpx<R> lds_all[2 * WS][A * PAD];
+  const int tid = threadIdx.x, grp = tid / L, l = tid % L, comp = l / A, a = l % A;
+  const int64_t n0 = int64_t(blockIdx.x) * WS + grp;
+  const bool live = n0 < nstates;  // dead groups still take part in the barriers
+  const int64_t n = live ? n0 : 0;
+  const R s = P.scale ? R(P.scale[n]) : R(1);
+  const R hk = R(0.5 * kperp2[n]);
+  const int64_t base = n * 2 * N + int64_t(comp) * N;
+  cpx<R>* lds = lds_all[2 * grp + comp];
+  const R inv_n = R(1.0 / N);
+  cpx<R> x[A], t[A], d1[A], kx[A];
+#pragma unroll
+  for (int b = 0; b < A; ++b) {
+    x[b] = s * P.X[base + a + A * b];
+    t[b] = x[b];
+  }
+  // D2 x and D1 x from one forward transform
+  q_fwd<R, A>(t, a, lds, tw);
+  sfor<0, A>::run([&](auto pc) {
+    constexpr int p = decltype(pc)::value;
+    const int m = q_wavenum<A>(a, freq_of_pos<A>(p));
+    const R k = R(kz * m);
+    const cpx<R> y = inv_n * t[p];
+    d1[p] = m == -N / 2 ? cpx<R>{R(0), R(0)} : cpx<R>{-k * y.y, k * y.x};
+    t[p] = (-k * k) * y;
+  });
+  q_inv<R, A>(t, a, lds, tw);
+  q_inv<R, A>(d1, a, lds, tw);
+  // kinetic part without D2(alpha x); current part without D1(A_z x)
+#pragma unroll
+  for (int b = 0; b < A; ++b) {
+    const int z = a + A * b;
+    const R al = hAl[z];
+    kx[b] = R(-0.25) * (al * t[b] - hLa[z] * x[b]) + (al * hk) * x[b];
+    d1[b] = hAz[z] * d1[b];
+    t[b] = al * x[b];
+  }
+  q_fwd<R, A>(t, a, lds, tw);
+  sfor<0, A>::run([&](auto pc) {
+    constexpr int p = decltype(pc)::value;
+    const int m = q_wavenum<A>(a, freq_of_pos<A>(p));
+    const R k = R(kz * m);
+    t[p] = (-k * k * inv_n) * t[p];
+  });
+  q_inv<R, A>(t, a, lds, tw);
+#pragma unroll
+  for (int b = 0; b < A; ++b) {
+    kx[b] = kx[b] + R(-0.25) * t[b];
+    t[b] = hAz[a + A * b] * x[b];
+  }
+  q_fwd<R, A>(t, a, lds, tw);
+  sfor<0, A>::run([&](auto pc) {
+    constexpr int p = decltype(pc)::value;
+    const int m = q_wavenum<A>(a, freq_of_pos<A>(p));
+    const R k = R(kz * m);
+    const cpx<R> y = inv_n * t[p];
+    t[p] = m == -N / 2 ? cpx<R>{R(0), R(0)} : cpx<R>{-k * y.y, k * y.x};
+  });
+  q_inv<R, A>(t, a, lds, tw);
+  // u rows: K u + fa u + C u + D v;  v rows: -(K v + fa v) + C v + D^* u,
+  // C x = -(i/2) [A_z D1 x + D1(A_z x)]
+  const R sg = comp ? R(-1) : R(1);
+  double hloc = 0.0;
+#pragma unroll
+  for (int b = 0; b < A; ++b) {
+    const int z = a + A * b;
+    const cpx<R> y{__shfl_xor(x[b].x, A, L), __shfl_xor(x[b].y, A, L)};  // other component at z
+    const cpx<R> D = P.hD[z];
+    const cpx<R> Dc = comp ? conj(D) : D;
+    const cpx<R> c = d1[b] + t[b];
+    kx[b] = sg * (kx[b] + P.hA[z] * x[b]) + cpx<R>{R(0.5) * c.y, R(-0.5) * c.x} + Dc * y;
+    hloc += double(x[b].x) * double(kx[b].x) + double(x[b].y) * double(kx[b].y);
+  }
+  R h;
+  if constexpr (OWN_H) {
+#pragma unroll
+    for (int o = A; o > 0; o >>= 1) hloc += __shfl_xor(hloc, o, L);
+    const double hs = __shfl(hloc, 0, L) * P.dV;  // every lane takes the group's first sum
+    h = R(hs);
+    if constexpr (MODE == L2_EXPECT) {
+      if (live && l == 0) {
+        P.h_part[n * P.h_stride + 0] = 0.0;
+        P.h_part[n * P.h_stride + 1] = hs;
+      }
+      return;
+    }
+  } else {
+    h = P.hshift ? R(P.hshift[n]) : R(0);
+  }
+  double nacc = 0.0;
+#pragma unroll
+  for (int b = 0; b < A; ++b) {
+    const int64_t ix = base + a + A * b;
+    if constexpr (MODE == L2_H) {
+      if (live) P.out[ix] = kx[b];
+    } else {
+      const cpx<R> g = kx[b] - h * x[b];
+      if constexpr (MODE == L2_TAYLOR) {
+        const cpx<R> c{R(P.tay_re), R(P.tay_im)};
+        const cpx<R> o = c * g;
+        const cpx<R> sm = P.init_acc ? x[b] + o : P.acc[ix] + o;
+        if (live) {
+          P.out[ix] = o;
+          P.acc[ix] = sm;
+        }
+        nacc += norm2(sm);
+      } else {
+        const cpx<R> f{g.y, -g.x};  // -i g
+        if constexpr (MODE == L2_F) {
+          if (live) P.out[ix] = f;
+        } else if constexpr (MODE == L2_CORR) {
+          const cpx<R> nw = P.hist[0][ix] + R(P.a[0]) * f;
+          if (live) P.Xout[ix] = nw;
+          nacc += norm2(nw);
+        } else {  // L2_FULL
+          cpx<R> pp = x[b] + R(P.b[0]) * f, cc = x[b] + R(P.a[1]) * f;
+          sfor<1, HD>::run([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            const cpx<R> hj = P.hist[j][ix];
+            if constexpr (j < NP) pp = pp + R(P.b[j]) * hj;
+            if constexpr (j + 1 < NQ) cc = cc + R(P.a[j + 1]) * hj;
+          });
+          if (live) {
+            P.out[ix] = f;
+            P.Xout[ix] = pp;
+            P.cout[ix] = cc;
+          }
+          nacc += norm2(pp);
+        }
+      }
+    }
+  }
+  if (P.nrm_part && MODE != L2_H && MODE != L2_F) {
+#pragma unroll
+    for (int o = A; o > 0; o >>= 1) nacc += __shfl_xor(nacc, o, L);
+    if (live && l == 0) P.nrm_part[n * P.nrm_stride] = nacc;
+  }
+}
+
 // workgroup sizes the tuner chooses from (states per workgroup = TB / A)
 template <class F>
 void with_tb(int tb, F&& f) {
@@ -768,6 +1091,18 @@ struct EngineQ1D final : Engine {
   void dens(Ctx& c, const void* X, const double* scale, int64_t nst) override {
     twiddles(c);
     const unsigned ng = cdiv(nst, G);
+    if (c.gen) {  // general functional: rho, nu and j_z
+      const double kz = 2 * kPi / (N * c.lat.dz);
+      with_tb(tb[0], [&](auto t) {
+        constexpr int TB = decltype(t)::value;
+        c.launch(KC_DENS, [&] {
+          hipLaunchKernelGGL((q_densj<R, A, G, TB>), dim3(ng), dim3(TB), 0, c.stream, (const cpx<R>*)X, nst, c.wu,
+                             c.wv, scale, c.dens_part, tw, kz);
+        });
+      });
+      c.nsg_used = int(ng);
+      return;
+    }
     with_tb(tb[0], [&](auto t) {
       constexpr int TB = decltype(t)::value;
       c.launch(KC_DENS, [&] {
@@ -779,6 +1114,10 @@ struct EngineQ1D final : Engine {
   }
   static constexpr int DGQ = G;  // states per dens_sum group (the partial buffer is sized for G)
   void dens_sum(Ctx& c, const void* X, const double* scale, int64_t nst) override {
+    if (c.gen) {
+      dens(c, X, scale, nst);
+      return;
+    }
     dim3 grid(cdiv(N, DS_TB), cdiv(nst, DGQ));
     c.launch(KC_DENS, [&] {
       hipLaunchKernelGGL((k_dens_sum<R, DGQ, 1>), grid, dim3(DS_TB), 0, c.stream, (const cpx<R>*)X, nst,
@@ -791,6 +1130,14 @@ struct EngineQ1D final : Engine {
   int raw_h_slots() const override { return 1; }
   void reduce_pot(Ctx& c, bool update) override {
     FunParams fp{c.fun.functional, c.fun.B, c.fun.C, c.fun.inv_g_bdg, c.fun.mu, c.ainv, c.dext};
+    if (c.gen) {
+      c.launch(KC_REDUCE_POT, [&] {
+        hipLaunchKernelGGL((q_reduce_gen<R>), dim3(N), dim3(256), 0, c.stream, c.dens_part, c.nsg_used, N, fp,
+                           c.fun.A, c.lam, c.vext, c.rho, c.nu, c.jc, c.U, c.delta, (R*)c.hA, (cpx<R>*)c.hD,
+                           (R*)c.hAz, int(update && c.fun.functional == TDSLDA_FUNC_SLDA));
+      });
+      return;
+    }
     c.launch(KC_REDUCE_POT, [&] {
       if (c.nsg_used >= 64)  // few sites, many state groups: one workgroup per site
         hipLaunchKernelGGL((k_reduce_pot_wide<R>), dim3(N), dim3(256), 0, c.stream, c.dens_part, c.nsg_used,
@@ -802,7 +1149,60 @@ struct EngineQ1D final : Engine {
                            int(update));
     });
   }
+  // the general operator (q_gen) in any mode, one launch over the batch
+  void gen(Ctx& c, int mode, const Lap2Args<R>& P, int64_t nst) {
+    twiddles(c);
+    const double kz = 2 * kPi / (N * c.lat.dz);
+    const R* al = (const R*)c.hAl;
+    const R* az = (const R*)c.hAz;
+    const R* la = (const R*)c.hLa;
+    with_tb(mode == L2_EXPECT ? tb[1] : tb[2], [&](auto t) {
+      constexpr int TB = decltype(t)::value;
+      dim3 grid(cdiv(nst, TB / (2 * A))), block(TB);
+      const int kc = mode == L2_EXPECT ? KC_LAP1 : mode == L2_H ? KC_LAP2_H : mode == L2_F ? KC_LAP2_F
+                     : mode == L2_CORR ? KC_LAP2_CORR : mode == L2_FULL ? KC_LAP2_FULL : KC_LAP2_TAYLOR;
+      c.launch(kc, [&] {
+        switch (mode) {
+          case L2_EXPECT:
+            hipLaunchKernelGGL((q_gen<R, A, TB, L2_EXPECT>), grid, block, 0, c.stream, P, nst, c.kperp2, al, az, la, tw, kz);
+            break;
+          case L2_H:
+            hipLaunchKernelGGL((q_gen<R, A, TB, L2_H>), grid, block, 0, c.stream, P, nst, c.kperp2, al, az, la, tw, kz);
+            break;
+          case L2_F:
+            hipLaunchKernelGGL((q_gen<R, A, TB, L2_F>), grid, block, 0, c.stream, P, nst, c.kperp2, al, az, la, tw, kz);
+            break;
+          case L2_CORR:
+            hipLaunchKernelGGL((q_gen<R, A, TB, L2_CORR>), grid, block, 0, c.stream, P, nst, c.kperp2, al, az, la, tw, kz);
+            break;
+          case L2_FULL:
+            if (c.np == 3)
+              hipLaunchKernelGGL((q_gen<R, A, TB, L2_FULL, 3, 4>), grid, block, 0, c.stream, P, nst, c.kperp2, al, az, la, tw, kz);
+            else if (c.np == 5)
+              hipLaunchKernelGGL((q_gen<R, A, TB, L2_FULL, 5, 5>), grid, block, 0, c.stream, P, nst, c.kperp2, al, az, la, tw, kz);
+            else
+              hipLaunchKernelGGL((q_gen<R, A, TB, L2_FULL, 4, 5>), grid, block, 0, c.stream, P, nst, c.kperp2, al, az, la, tw, kz);
+            break;
+          default:
+            hipLaunchKernelGGL((q_gen<R, A, TB, L2_TAYLOR>), grid, block, 0, c.stream, P, nst, c.kperp2, al, az, la, tw, kz);
+        }
+      });
+    });
+  }
   void lap1(Ctx& c, const void* X, const double* scale, bool hpart, int64_t nst) override {
+    if (c.gen) {  // the general operator needs no intermediate; only the shift
+      if (!hpart) return;
+      Lap2Args<R> P{};
+      P.X = (const cpx<R>*)X;
+      P.hA = (const R*)c.hA;
+      P.hD = (const cpx<R>*)c.hD;
+      P.scale = scale;
+      P.h_part = c.h_part;
+      P.h_stride = c.h_stride;
+      P.dV = c.lat.dz;
+      gen(c, L2_EXPECT, P, nst);
+      return;
+    }
     twiddles(c);
     with_tb(tb[1], [&](auto t) {
       constexpr int TB = decltype(t)::value;
@@ -840,6 +1240,10 @@ struct EngineQ1D final : Engine {
     P.h_part = c.h_part;
     P.h_stride = c.h_stride;
     P.dV = c.lat.dz;
+    if (c.gen) {
+      gen(c, d.mode, P, nst);
+      return;
+    }
     twiddles(c);
     const double k2 = kz2(c);
     with_tb(tb[2], [&](auto t) {

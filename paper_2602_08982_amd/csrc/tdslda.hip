@@ -331,7 +331,8 @@ void energy(Ctx& c, double* out8) {  // out8[9]
   full_densities(c);
   c.launch(KC_ENERGY, [&] {
     hipLaunchKernelGGL(k_energy, dim3(1), dim3(1024), 0, c.stream, c.M, c.rho, c.tau, c.nu, c.jc, c.delta,
-                       c.vext, c.dext, c.fun.B, int(c.fun.functional == TDSLDA_FUNC_SLDA), c.dVe, c.eout);
+                       c.vext, c.dext, c.fun.B, c.fun.functional == TDSLDA_FUNC_SLDA ? c.fun.A : 1.0,
+                       int(c.fun.functional == TDSLDA_FUNC_SLDA), c.dVe, c.eout);
   });
   double h[7];
   HIPCHK(hipMemcpyAsync(h, c.eout, sizeof(h), hipMemcpyDeviceToHost, c.stream));
@@ -359,6 +360,21 @@ void set_frozen_fields(Ctx& c) {
       hipLaunchKernelGGL((k_set_fields<float>), dim3(cdiv(c.M, 256)), dim3(256), 0, c.stream, c.M, c.U, c.delta,
                          c.vext, c.dext, c.fun.mu, (float*)c.hA, (cpx<float>*)c.hD);
   });
+}
+
+// the functional's own alpha (A; 1 for BdG), D2 alpha = 0, A_z = 0; the
+// general operator is in use when the functional has A != 1
+void reset_current_fields(Ctx& c) {
+  const double a = c.fun.functional == TDSLDA_FUNC_SLDA ? c.fun.A : 1.0;
+  c.launch(KC_SETUP, [&] {
+    if (c.esz == 16)
+      hipLaunchKernelGGL((k_fill_real<double>), dim3(cdiv(c.M, 256)), dim3(256), 0, c.stream, c.M, a, (double*)c.hAl);
+    else
+      hipLaunchKernelGGL((k_fill_real<float>), dim3(cdiv(c.M, 256)), dim3(256), 0, c.stream, c.M, a, (float*)c.hAl);
+  });
+  HIPCHK(hipMemsetAsync(c.hLa, 0, c.M * c.esz / 2, c.stream));
+  HIPCHK(hipMemsetAsync(c.hAz, 0, c.M * c.esz / 2, c.stream));
+  c.gen = a != 1.0;
 }
 
 void after_load(Ctx& c) {
@@ -482,8 +498,11 @@ tdslda_status tdslda_create(const tdslda_lattice* lat, const tdslda_functional* 
             "unknown precision");
     require(fun->functional == TDSLDA_FUNC_SLDA || fun->functional == TDSLDA_FUNC_BDG, TDSLDA_EINVAL,
             "unknown functional");
-    require(fun->functional != TDSLDA_FUNC_SLDA || std::fabs(fun->A - 1.0) < 1e-15, TDSLDA_EINVAL,
-            "the TD path implements A_sigma = 1 only");
+    require(fun->functional != TDSLDA_FUNC_SLDA || std::fabs(fun->A - 1.0) < 1e-15 ||
+                lat->mode == TDSLDA_MODE_Q1D,
+            TDSLDA_EINVAL, "A_sigma != 1 (the general functional) is built for the quasi-1D kernel set only");
+    require(fun->functional != TDSLDA_FUNC_SLDA || (std::isfinite(fun->A) && fun->A > 0), TDSLDA_EINVAL,
+            "A must be positive");
     require(std::isfinite(run->dt) && run->dt != 0.0, TDSLDA_EINVAL, "dt must be finite and non-zero");
     c->lat = *lat;
     c->fun = *fun;
@@ -524,7 +543,7 @@ tdslda_status tdslda_create(const tdslda_lattice* lat, const tdslda_functional* 
     c->nrm_part = (double*)c->dalloc(8 * capacity * c->nrm_stride);
     c->h_part = (double*)c->dalloc(8 * capacity * c->h_stride);
     c->nsg_max = int(cdiv(capacity, c->eng->group()));
-    c->dens_part = (double*)c->dalloc(size_t(c->nsg_max) * 3 * M * 8);
+    c->dens_part = (double*)c->dalloc(size_t(c->nsg_max) * (c->q1d ? 4 : 3) * M * 8);
     c->rho = (double*)c->dalloc(8 * M);
     c->nu = (double*)c->dalloc(16 * M);
     c->tau = (double*)c->dalloc(8 * M);
@@ -538,6 +557,10 @@ tdslda_status tdslda_create(const tdslda_lattice* lat, const tdslda_functional* 
     HIPCHK(hipMemsetAsync(c->dext, 0, 16 * M, c->stream));
     c->hA = c->dalloc(M * c->esz / 2);
     c->hD = c->dalloc(M * c->esz);
+    c->hAl = c->dalloc(M * c->esz / 2);
+    c->hLa = c->dalloc(M * c->esz / 2);
+    c->hAz = c->dalloc(M * c->esz / 2);
+    reset_current_fields(*c);
     HIPCHK(hipMemsetAsync(c->vext, 0, 8 * M, c->stream));
     HIPCHK(hipMemsetAsync(c->lam, 0, 8 * M, c->stream));
     c->gchunk = std::min<int64_t>(capacity, 64);
@@ -583,7 +606,8 @@ tdslda_status tdslda_set_external(tdslda_ctx* c, const double* vext, const doubl
       HIPCHK(hipMemsetAsync(c->dflag, 0, 4, c->stream));
       c->launch(KC_SETUP, [&] {
         hipLaunchKernelGGL(k_lambda, dim3(cdiv(c->M, 256)), dim3(256), 0, c->stream, c->M, c->vext, c->fun.mu,
-                           c->fun.ec_reg, c->lam, c->dflag);
+                           c->fun.ec_reg, c->fun.functional == TDSLDA_FUNC_SLDA ? c->fun.A : 1.0, c->lam,
+                           c->dflag);
       });
       int bad = 0;
       HIPCHK(hipMemcpyAsync(&bad, c->dflag, 4, hipMemcpyDeviceToHost, c->stream));
@@ -727,6 +751,7 @@ tdslda_status tdslda_set_fields(tdslda_ctx* c, const double* U, const double* de
     if (!U && !delta_reim) {
       c->frozen = false;
       c->fields_valid = false;
+      reset_current_fields(*c);
       if (c->loaded) {
         c->eng->dens(*c, c->sb[c->phi], c->sscale[c->phi], c->nst);
         c->eng->reduce_pot(*c, true);
@@ -782,10 +807,53 @@ tdslda_status tdslda_apply_hbdg(tdslda_ctx* c, const void* in_dev, void* out_dev
   });
 }
 
+tdslda_status tdslda_set_current_fields(tdslda_ctx* c, const double* alpha, const double* az) {
+  return guard(c, [&] {
+    require(c->q1d, TDSLDA_EINVAL, "the general operator is built for the quasi-1D kernel set");
+    if (!alpha && !az) {
+      reset_current_fields(*c);
+      HIPCHK(hipStreamSynchronize(c->stream));
+      return;
+    }
+    require(c->frozen, TDSLDA_EORDER, "freeze the fields (tdslda_set_fields) first");
+    for (int64_t i = 0; i < c->M; ++i) {
+      require(!alpha || (std::isfinite(alpha[i]) && alpha[i] > 0.0), TDSLDA_EINVAL, "alpha must be finite, > 0");
+      require(!az || std::isfinite(az[i]), TDSLDA_EINVAL, "A_z must be finite");
+    }
+    reset_current_fields(*c);
+    // staging in the gradient scratch (>= 2 M doubles): alpha, A_z
+    if (alpha) {
+      HIPCHK(hipMemcpyAsync(c->gscratch, alpha, 8 * c->M, hipMemcpyHostToDevice, c->stream));
+      c->launch(KC_SETUP, [&] {
+        if (c->esz == 16)
+          hipLaunchKernelGGL((k_field_d2<double>), dim3(1), dim3(256), 0, c->stream, int(c->M), c->lat.dz, c->gscratch,
+                             (double*)c->hAl, (double*)c->hLa);
+        else
+          hipLaunchKernelGGL((k_field_d2<float>), dim3(1), dim3(256), 0, c->stream, int(c->M), c->lat.dz, c->gscratch,
+                             (float*)c->hAl, (float*)c->hLa);
+      });
+    }
+    if (az) {
+      HIPCHK(hipMemcpyAsync(c->gscratch + c->M, az, 8 * c->M, hipMemcpyHostToDevice, c->stream));
+      c->launch(KC_SETUP, [&] {
+        if (c->esz == 16)
+          hipLaunchKernelGGL((k_convert_real<double>), dim3(cdiv(c->M, 256)), dim3(256), 0, c->stream, c->M,
+                             c->gscratch + c->M, (double*)c->hAz);
+        else
+          hipLaunchKernelGGL((k_convert_real<float>), dim3(cdiv(c->M, 256)), dim3(256), 0, c->stream, c->M,
+                             c->gscratch + c->M, (float*)c->hAz);
+      });
+    }
+    c->gen = true;
+    HIPCHK(hipStreamSynchronize(c->stream));
+  });
+}
+
 tdslda_status tdslda_set_friction(tdslda_ctx* c, double alpha, double beta, double gamma, double rho0,
                                   double N_req) {
   return guard(c, [&] {
     require(c->q1d, TDSLDA_EINVAL, "quantum friction is built for the quasi-1D kernel set");
+    require(!c->gen, TDSLDA_EINVAL, "quantum friction is built for the A = 1 operator");
     require(std::isfinite(alpha) && std::isfinite(beta) && std::isfinite(gamma) && std::isfinite(N_req) &&
                 std::isfinite(rho0) && rho0 > 0.0,
             TDSLDA_EINVAL, "friction parameters must be finite, rho0 > 0");

@@ -65,6 +65,7 @@ _SIGS = {
     "tdslda_init_plane_waves": [C.c_void_p, C.c_int64, C.c_void_p, C.c_double, C.c_double],
     "tdslda_imprint_vortices": [C.c_void_p, C.c_int, C.c_void_p],
     "tdslda_set_fields": [C.c_void_p, C.c_void_p, C.c_void_p],
+    "tdslda_set_current_fields": [C.c_void_p, C.c_void_p, C.c_void_p],
     "tdslda_densities": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
     "tdslda_get_fields": [C.c_void_p, C.c_void_p, C.c_void_p],
     "tdslda_apply_hbdg": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64],
@@ -259,6 +260,13 @@ class Context:
         u = _f64(U).ravel()
         d = _c128_as_f64(np.asarray(delta).ravel())
         self._chk(self.lib.tdslda_set_fields(self.h, _p(u), _p(d)))
+
+    def set_current_fields(self, alpha=None, az=None):
+        """tdslda_set_current_fields: linear-mode alpha(z) and A_z(z) of the
+        general operator (None keeps the functional's value)."""
+        a = None if alpha is None else _f64(alpha).ravel()
+        z = None if az is None else _f64(az).ravel()
+        self._chk(self.lib.tdslda_set_current_fields(self.h, _p(a), _p(z)))
 
     # --- evaluation ---------------------------------------------------------
     def densities(self):
@@ -520,9 +528,13 @@ def lattice_q1d(nz, dz, lx, ly):
     return Lattice(MODE_Q1D, 1, 1, nz, 1.0, 1.0, dz, lx, ly)
 
 
-def functional_slda(mu, ec_reg, B=-0.4332978244473528, C_=-11.11, temperature=0.0):
-    """Unitary-gas SLDA with A = 1 (B recomputed from the ASLDA formula at p=0)."""
-    return Functional(FUNC_SLDA, 1.0, B, C_, 0.0, ec_reg, mu, temperature)
+def functional_slda(mu, ec_reg, A=1.0, B=None, C_=-11.11, temperature=0.0):
+    """Unitary-gas SLDA at p = 0: A = 1 (the A_sigma = 1 option) or the
+    general functional with A = 1.094; B defaults to the ASLDA formula
+    evaluated with A_a = A_b = A, B = 2^(2/3) 0.357 - A."""
+    if B is None:
+        B = 2.0 ** (2.0 / 3.0) * 0.357 - A
+    return Functional(FUNC_SLDA, A, B, C_, 0.0, ec_reg, mu, temperature)
 
 
 def functional_bdg(mu, ec_reg, a_s, temperature=0.0):
