@@ -160,18 +160,22 @@ def track_precision(steps, every, warmup, seed_vortex=4):
     return out
 
 
-def run_q1d(steps, warmup, seed=7, profile_steps=2, friction=False, precision=None):
+def run_q1d(steps, warmup, seed=7, profile_steps=2, friction=False, precision=None, A=1.0, eager=False):
     """Batched quasi-1D workload: set-up (device eigensolver), start-up and
     warm-up steps, launch-shape tuning, then `steps` steps recorded as one
     HIP graph and launched once (timed from launch to completion).
     friction: the same with the quantum-friction terms on (alpha = beta = 5,
     gamma = 0.1, rho0 = the initial maximum density, N_req = the initial N).
-    precision: the context precision (default: the workload's FP32-mixed)."""
+    precision: the context precision (default: the workload's FP32-mixed).
+    A: the functional's A (1.094 = the general functional of Eq. h_sigma,
+    evolving the same initial states).
+    eager: time `steps` steps of tdslda_abm_step (one launch per kernel, no
+    graph in the process) instead of the graph launch."""
     import torch
     from paper_2602_08982_amd import tdslda as T
     from paper_2602_08982_amd import workloads as W
     t0 = time.perf_counter()
-    ctx, info = W.setup_q1d(W.Q1D, seed, stream=torch.cuda.current_stream().cuda_stream, precision=precision)
+    ctx, info = W.setup_q1d(W.Q1D, seed, stream=torch.cuda.current_stream().cuda_stream, precision=precision, A=A)
     t_setup = time.perf_counter() - t0
     nst = info["states"]
     prec = W.Q1D["precision"] if precision is None else precision
@@ -182,8 +186,15 @@ def run_q1d(steps, warmup, seed=7, profile_steps=2, friction=False, precision=No
     ctx.abm_step(warmup)
     tuned = ctx.autotune()
     torch.cuda.synchronize()
-    rec_ms, run_ms = ctx.abm_graph(steps)
-    dt = run_ms * 1e-3
+    if eager:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.abm_step(steps)
+        torch.cuda.synchronize()
+        rec_ms, dt = 0.0, time.perf_counter() - t0
+    else:
+        rec_ms, run_ms = ctx.abm_graph(steps)
+        dt = run_ms * 1e-3
     kern = {}
     if profile_steps:
         ctx.set_profiling(True)
@@ -341,13 +352,19 @@ def main():
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--no-q1d", action="store_true")
     ap.add_argument("--no-warmstart", action="store_true")
-    ap.add_argument("--warmstart-size", choices=["small", "medium", "large"], default="small",
+    ap.add_argument("--warmstart-size", choices=["small", "medium", "default", "large"], default="default",
                     help="small: 8x8x4 lattice, 48 training / 8 held-out solves (seconds); medium: 16x16x8, "
-                         "200 / 40 (about ten minutes); large: 24x24x8, 100 / 20, Broyden mixing only")
+                         "200 / 40 (about ten minutes); default: 24x24x8, 48 / 20, Broyden mixing only (about "
+                         "four minutes); large: 24x24x8, 100 / 20, Broyden mixing only")
     ap.add_argument("--q1d-steps", type=int, default=2000,
                     help="steps of the batched quasi-1D run (one graph launch)")
     ap.add_argument("--q1d-fp64-steps", type=int, default=500,
                     help="steps of the FP64 run of the batched quasi-1D workload (one graph launch; 0 = skip)")
+    ap.add_argument("--q1d-eager", action="store_true",
+                    help="run the batched quasi-1D steps eagerly (tdslda_abm_step) instead of one graph launch")
+    ap.add_argument("--q1d-general-steps", type=int, default=500,
+                    help="steps of the batched quasi-1D run with the general functional (A = 1.094; one graph "
+                         "launch; 0 = skip)")
     ap.add_argument("--q1d-friction", action="store_true",
                     help="also time the batched quasi-1D run with the quantum-friction terms on")
     ap.add_argument("--mixed-steps", type=int, default=None,
@@ -413,14 +430,20 @@ def main():
         print(f"# batched q1d with friction: {q1d_fric['value']:.4g} state-steps/s", file=sys.stderr, flush=True)
     q1d = None
     if not args.no_q1d:
-        q1d = run_q1d(args.q1d_steps, max(1, args.warmup))
+        q1d = run_q1d(args.q1d_steps, max(1, args.warmup), eager=args.q1d_eager)
         print(f"# batched q1d: {q1d['value']:.4g} state-steps/s over {q1d['steps']} steps "
               f"({q1d['nst']} states), graph record {q1d['graph_record_ms']:.0f} ms", file=sys.stderr, flush=True)
     q1d64 = None
     if not args.no_q1d and args.q1d_fp64_steps > 0:
-        q1d64 = run_q1d(args.q1d_fp64_steps, max(1, args.warmup), precision=T.FP64, profile_steps=0)
+        q1d64 = run_q1d(args.q1d_fp64_steps, max(1, args.warmup), precision=T.FP64, profile_steps=0,
+                        eager=args.q1d_eager)
         print(f"# batched q1d FP64: {q1d64['value']:.4g} state-steps/s over {q1d64['steps']} steps",
               file=sys.stderr, flush=True)
+    q1dgen = None
+    if not args.no_q1d and args.q1d_general_steps > 0:
+        q1dgen = run_q1d(args.q1d_general_steps, max(1, args.warmup), A=1.094, eager=args.q1d_eager)
+        print(f"# batched q1d, general functional A = 1.094: {q1dgen['value']:.4g} state-steps/s over "
+              f"{q1dgen['steps']} steps", file=sys.stderr, flush=True)
     warm = None
     if not args.no_warmstart:
         from paper_2602_08982_amd import warmstart as WS
@@ -429,7 +452,8 @@ def main():
         elif args.warmstart_size == "medium":
             wcfg, ntr, nte, ep = dict(WS.Q2D), 200, 40, 300
         else:
-            wcfg, ntr, nte, ep = dict(WS.Q2D, nx=24, ny=24, omega=0.16, coarse=18, linear=False), 100, 20, 300
+            ntr = 100 if args.warmstart_size == "large" else 48
+            wcfg, nte, ep = dict(WS.Q2D, nx=24, ny=24, omega=0.16, coarse=18, linear=False), 20, 300
         warm = WS.experiment(wcfg, range(0, ntr), range(10000, 10000 + nte), epochs=ep,
                              log=lambda m: print("# warm start: " + m, file=sys.stderr, flush=True))
         if "warm_iters_mean" in warm:
@@ -438,6 +462,13 @@ def main():
         if "warm_broyden_iters_mean" in warm:
             print(f"# Broyden mixing: warm {warm['warm_broyden_iters_mean']:.1f} vs plain "
                   f"{warm['plain_broyden_iters_mean']:.1f} iterations", file=sys.stderr, flush=True)
+        if warm.get("symmetry_release_start"):
+            rs = warm["symmetry_release_start"]
+            for k in ("linear", "broyden"):
+                if k in rs:
+                    print(f"# symmetry-release start ({k} mixing): {rs[k]['q1d_iters']} quasi-1D + "
+                          f"{rs[k]['q2d_iters_mean']:.1f} quasi-2D iterations = {rs[k]['target_equivalent']:.1f} "
+                          f"target-equivalent (cost ratio {rs['cost_ratio']:.4f})", file=sys.stderr, flush=True)
         if warm.get("coarse_start"):
             cs = warm["coarse_start"]
             for k in ("linear", "broyden"):
@@ -492,7 +523,7 @@ def main():
     if q1d is not None:
         line["batched_q1d"] = {
             "workload": "2,304 quasi-1D problems (48x48 k_perp), N_z=256, |E|<12, FP32 states / FP64 sums, "
-                        f"{q1d['steps']} AB4AM5 steps in one HIP-graph launch",
+                        f"{q1d['steps']} AB4AM5 steps " + ("eagerly" if args.q1d_eager else "in one HIP-graph launch"),
             "value": q1d["value"], "unit": "state-steps/s", "ms_per_step": q1d["ms_per_step"],
             "states_evolved": q1d["nst"], "graph_record_ms": q1d["graph_record_ms"],
             "setup_seconds": q1d["setup_seconds"], "tuned_workgroups": q1d["tuned"],
@@ -504,6 +535,18 @@ def main():
             line["batched_q1d"]["vs_fp64_same_workload"] = dict(
                 fp64_value=q1d64["value"], fp64_ms_per_step=q1d64["ms_per_step"], fp64_steps=q1d64["steps"],
                 speedup=q1d["value"] / q1d64["value"], fp64_check=q1d64["check"])
+    if q1dgen is not None:
+        line["batched_q1d_general_functional"] = {
+            "workload": "the batched quasi-1D workload (same initial states) evolved with the general functional "
+                        "A = 1.094 (alpha = A, current potential (1 - A) j / rho; Eq. h_sigma with Eq. "
+                        f"kinop-alpha, 7 transforms per component), {q1dgen['steps']} steps "
+                        + ("eagerly" if args.q1d_eager else "in one HIP-graph launch"),
+            "value": q1dgen["value"], "unit": "state-steps/s", "ms_per_step": q1dgen["ms_per_step"],
+            "cost_vs_A1": (q1dgen["ms_per_step"] / q1d["ms_per_step"]) if q1d else None,
+            "kernels": q1dgen["kernels"], "check": q1dgen["check"],
+            "roofline": roofline(dict(q1dgen, steps=q1dgen["profile_steps"]), rates, "float", 16, "q1dgen_",
+                                 fused=True) if q1dgen["kernels"] else None,
+        }
     if warm is not None:
         line["learned_warm_start"] = {
             "workload": f"static quasi-2D solve, {warm['lattice'][0]}x{warm['lattice'][1]} x-y lattice, "
@@ -516,6 +559,7 @@ def main():
             "seconds_per_iteration": warm["seconds_per_iteration"],
             "train_data_seconds": warm["train_data_seconds"], "fit_seconds": warm["fit_seconds"],
             "coarse_lattice_start": warm.get("coarse_start"),
+            "symmetry_release_start": warm.get("symmetry_release_start"),
         }
     print(json.dumps(line))
 

@@ -215,9 +215,11 @@ tdslda_status tdslda_set_friction(tdslda_ctx* ctx, double alpha, double beta, do
 tdslda_status tdslda_abm_step(tdslda_ctx* ctx, int64_t nsteps);
 
 /* The same advance as tdslda_abm_step, recorded once as a HIP graph on the
- * context's stream (a private stream when the context uses the null stream)
- * and submitted as one launch: every kernel boundary of the recording is a
- * grid-wide synchronisation point (density reductions included).  Requires
+ * context's stream (a private stream, created once per context, when the
+ * context uses the null stream) and submitted as one launch: every kernel
+ * boundary of the recording is a grid-wide synchronisation point (density
+ * reductions included).  The call returns after the launch has completed;
+ * the executed graph is released at the next call or by tdslda_destroy.  Requires
  * a started integrator (one tdslda_abm_step call, nsteps >= 0, after the
  * load) and profiling off.  graph_ms (may be NULL) = {record + instantiate
  * time, launch-to-completion time} in milliseconds.  If recording or
@@ -287,6 +289,11 @@ typedef struct {
   int maxit;
   int broyden;   /* history length of the Broyden mixing (0..8); 0 = linear mixing */
   double w0;     /* Broyden regularisation weight (e.g. 0.01) */
+  int q1d;       /* 1: quasi-1D geometry (Sec. 3.1, quasi-1D item; the first stage of releasing
+                    symmetry constraints, Sec. 5.2): an nx-site x lattice with ny plane waves
+                    along y (spacing dy, L_y = ny dy) and nz along z; the distinct (|k_y|, |k_z|)
+                    pairs are diagonalised (order 2 nx) with multiplicities, densities carry
+                    1/(L_y L_z) and fields are [nx].  0: the quasi-2D geometry above */
 } tdslda_static;
 
 /* One application of K at (U, delta, mu): U_out, delta_out, rho (per spin),

@@ -35,11 +35,44 @@ class GeometryQ2D:
         m = np.arange(0, self.nz // 2 + 1)
         self.kz = 2.0 * np.pi * m / (self.nz * self.dz)
         self.mult = np.where((m == 0) | (m == self.nz // 2), 1.0, 2.0)
+        self.Lperp = self.Lz  # length of the plane-wave directions (densities carry 1/Lperp)
 
     def coords(self):
         x = (np.arange(self.nx) - self.nx // 2) * self.dx
         y = (np.arange(self.ny) - self.ny // 2) * self.dy
         return np.meshgrid(x, y, indexing="ij")
+
+
+class GeometryQ1DStatic:
+    """Quasi-1D static geometry (Sec. 3.1, quasi-1D item): an N_x-site
+    periodic lattice along x and plane waves exp(i (k_y y + k_z z)) /
+    sqrt(L_y L_z) in y and z, N_y and N_z lattice momenta (spacings dy, dz).
+    Problems depend on k_perp^2 = k_y^2 + k_z^2 only; the distinct (|k_y|,
+    |k_z|) pairs are diagonalised once with multiplicity w_y w_z (1 for the
+    zero and Nyquist momenta, 2 otherwise), and the densities carry
+    1 / (L_y L_z).  The first stage of releasing symmetry constraints
+    (Sec. 5.2): a problem with translational symmetry in y and z."""
+
+    def __init__(self, nx, ny, nz, dx=1.0, dy=1.0, dz=1.0):
+        self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        self.dx, self.dy, self.dz = float(dx), float(dy), float(dz)
+        self.M = self.nx
+        self.shape = (self.nx,)
+        self.dA = self.dx
+        self.Lperp = self.ny * self.dy * self.nz * self.dz
+        self.K = -0.5 * L.d2_matrix(self.nx, self.dx)
+        my = np.arange(0, self.ny // 2 + 1)
+        mz = np.arange(0, self.nz // 2 + 1)
+        wy = np.where((my == 0) | (my == self.ny // 2), 1.0, 2.0)
+        wz = np.where((mz == 0) | (mz == self.nz // 2), 1.0, 2.0)
+        ky = 2.0 * np.pi * my / (self.ny * self.dy)
+        kz = 2.0 * np.pi * mz / (self.nz * self.dz)
+        # build_h adds k^2/2 of the class momentum: k = |k_perp|
+        self.kz = np.sqrt(ky[:, None] ** 2 + kz[None, :] ** 2).ravel()
+        self.mult = (wy[:, None] * wz[None, :]).ravel()
+
+    def coords(self):
+        return ((np.arange(self.nx) - self.nx // 2) * self.dx,)
 
 
 def build_h(geom, hfield, delta, kz):
@@ -52,9 +85,10 @@ def build_h(geom, hfield, delta, kz):
 
 def densities(geom, hfield, delta):
     """rho (per spin) and nu of the T = 0 state: every E > 0 eigenpair of
-    every k_z, v occupied (f(-E) = 1, f(E) = 0), states normalised in the
-    x-y plane (eigenvectors / sqrt(dx dy)), and the 1 / L_z of the plane
-    waves along z."""
+    every plane-wave class, v occupied (f(-E) = 1, f(E) = 0), states
+    normalised on the lattice (eigenvectors / sqrt(dx dy), quasi-1D
+    / sqrt(dx)), and the 1 / L_z (quasi-1D 1 / (L_y L_z)) of the plane
+    waves."""
     rho = np.zeros(geom.M)
     nu = np.zeros(geom.M, dtype=complex)
     for kz, w in zip(geom.kz, geom.mult):
@@ -64,17 +98,18 @@ def densities(geom, hfield, delta):
         v = W[geom.M:, sel] / np.sqrt(geom.dA)
         rho += w * np.sum(np.abs(v) ** 2, axis=1)
         nu += w * np.sum(u * np.conj(v), axis=1)
-    return (rho / geom.Lz).reshape(geom.shape), (nu / geom.Lz).reshape(geom.shape)
+    return (rho / geom.Lperp).reshape(geom.shape), (nu / geom.Lperp).reshape(geom.shape)
 
 
 def map_k(geom, fun, vext, U, delta, mu, ec):
     """One application of Alg. MapK.  The regulator uses V_+ = V_ext + U_in
     (the static iteration order).  Returns (U_out, Delta_out, rho, nu, N)
-    with N = int rho_+ d^3r = L_z sum 2 rho dx dy."""
+    with N = int rho_+ d^3r = L_z sum 2 rho dx dy (quasi-1D:
+    L_y L_z sum 2 rho dx)."""
     lam = F.lambda_c(vext + U, mu, ec)
     rho, nu = densities(geom, vext + U - mu, delta)
     Uo, Do, _ = F.potentials(rho, nu, lam, fun)
-    N = geom.Lz * geom.dA * np.sum(2.0 * rho)
+    N = geom.Lperp * geom.dA * np.sum(2.0 * rho)
     return Uo, Do, rho, nu, N
 
 

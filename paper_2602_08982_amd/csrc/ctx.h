@@ -238,7 +238,23 @@ struct tdslda_ctx {
     s.hshift = hshift;
     return s;
   }
+  // abm_graph: the private capture stream (when the context uses the null
+  // stream) and the last executable graph, kept until the next abm_graph
+  // call or the context's destruction instead of being released right after
+  // the launch
+  hipStream_t graph_stream = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  hipGraph_t graph = nullptr;
+  void release_graph() {
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    graph_exec = nullptr;
+    graph = nullptr;
+  }
   ~tdslda_ctx() {
+    if (graph_exec || graph_stream) (void)hipDeviceSynchronize();
+    release_graph();
+    if (graph_stream) (void)hipStreamDestroy(graph_stream);
     for (auto& e : events) {
       (void)hipEventDestroy(e.a);
       (void)hipEventDestroy(e.b);

@@ -377,7 +377,8 @@ struct Handle {
 struct StaticSolver {
   const tdslda_static s;
   const tdslda_functional f;
-  int M = 0, N2 = 0, nclass = 0;
+  int M = 0, N2 = 0, nclass = 0, nyl = 1;
+  double vol_factor = 1.0;
   std::vector<void*> owned;
   double *H = nullptr, *Ev = nullptr, *Ew = nullptr, *kz2 = nullptr, *wc = nullptr, *d2x = nullptr, *d2y = nullptr;
   double *vext = nullptr, *U = nullptr, *D = nullptr, *Uo = nullptr, *Do = nullptr, *hf = nullptr;
@@ -415,9 +416,14 @@ struct StaticSolver {
     require(f.functional == TDSLDA_FUNC_SLDA || f.functional == TDSLDA_FUNC_BDG, TDSLDA_EINVAL, "unknown functional");
     require(s.broyden >= 0 && s.broyden <= kBroydenMax && (s.broyden == 0 || s.w0 > 0), TDSLDA_EINVAL,
             "Broyden history must be in [0, 8] with w0 > 0");
-    M = s.nx * s.ny;
+    require(s.q1d == 0 || s.q1d == 1, TDSLDA_EINVAL, "q1d must be 0 or 1");
+    // quasi-1D: the y lattice is one site; y carries plane waves instead
+    nyl = s.q1d ? 1 : s.ny;
+    M = s.nx * nyl;
     N2 = 2 * M;
-    nclass = s.nz / 2 + 1;
+    nclass = s.q1d ? (s.ny / 2 + 1) * (s.nz / 2 + 1) : s.nz / 2 + 1;
+    // measure of a lattice site times the length of the plane-wave directions
+    vol_factor = s.q1d ? s.dx * (s.ny * s.dy) * (s.nz * s.dz) : s.nz * s.dz * s.dx * s.dy;
     H = (double*)alloc(sizeof(double) * size_t(N2) * N2 * nclass);
     Ev = (double*)alloc(sizeof(double) * size_t(N2) * nclass);
     Ew = (double*)alloc(sizeof(double) * size_t(N2) * nclass);
@@ -425,7 +431,7 @@ struct StaticSolver {
     kz2 = (double*)alloc(sizeof(double) * nclass);
     wc = (double*)alloc(sizeof(double) * nclass);
     d2x = (double*)alloc(sizeof(double) * s.nx);
-    d2y = (double*)alloc(sizeof(double) * s.ny);
+    d2y = (double*)alloc(sizeof(double) * nyl);
     for (double** p : {&vext, &U, &D, &Uo, &Do, &hf, &rho, &nu}) *p = (double*)alloc(sizeof(double) * M);
     red = (double*)alloc(sizeof(double) * 4);
     bad = (int*)alloc(sizeof(int));
@@ -438,16 +444,28 @@ struct StaticSolver {
       bmu = (double*)alloc(sizeof(double));
     }
     std::vector<double> k2(nclass), w(nclass);
-    for (int m = 0; m < nclass; ++m) {
-      const double k = 2.0 * kPi * m / (s.nz * s.dz);
-      k2[m] = k * k;
-      w[m] = (m == 0 || m == s.nz / 2) ? 1.0 : 2.0;
+    auto mult = [](int m, int n) { return (m == 0 || m == n / 2) ? 1.0 : 2.0; };
+    if (s.q1d) {  // classes (|k_y|, |k_z|), k_perp^2 = k_y^2 + k_z^2, multiplicity w_y w_z
+      const int ncz = s.nz / 2 + 1;
+      for (int my = 0; my <= s.ny / 2; ++my)
+        for (int mz = 0; mz <= s.nz / 2; ++mz) {
+          const double ky = 2.0 * kPi * my / (s.ny * s.dy), kz = 2.0 * kPi * mz / (s.nz * s.dz);
+          k2[my * ncz + mz] = ky * ky + kz * kz;
+          w[my * ncz + mz] = mult(my, s.ny) * mult(mz, s.nz);
+        }
+    } else {
+      for (int m = 0; m < nclass; ++m) {
+        const double k = 2.0 * kPi * m / (s.nz * s.dz);
+        k2[m] = k * k;
+        w[m] = mult(m, s.nz);
+      }
     }
-    const auto cx = spectral_d2_circulant(s.nx, s.dx), cy = spectral_d2_circulant(s.ny, s.dy);
+    const auto cx = spectral_d2_circulant(s.nx, s.dx);
+    const auto cy = s.q1d ? std::vector<double>(1, 0.0) : spectral_d2_circulant(s.ny, s.dy);
     HIPCHK(hipMemcpy(kz2, k2.data(), sizeof(double) * nclass, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(wc, w.data(), sizeof(double) * nclass, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(d2x, cx.data(), sizeof(double) * s.nx, hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(d2y, cy.data(), sizeof(double) * s.ny, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(d2y, cy.data(), sizeof(double) * nyl, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(vext, vext_h, sizeof(double) * M, hipMemcpyHostToDevice));
   }
   ~StaticSolver() {
@@ -462,21 +480,20 @@ struct StaticSolver {
     hipLaunchKernelGGL(k_add_shift, dim3(gb), dim3(256), 0, 0, M, vext, U, -mu, hf);
     HIPCHK(hipGetLastError());
     const int64_t per = int64_t(N2) * N2;
-    hipLaunchKernelGGL(k_st_build, dim3(cdiv(per * nclass, 256)), dim3(256), 0, 0, H, nclass, s.nx, s.ny, kz2, hf,
+    hipLaunchKernelGGL(k_st_build, dim3(cdiv(per * nclass, 256)), dim3(256), 0, 0, H, nclass, s.nx, nyl, kz2, hf,
                        D, d2x, d2y);
     HIPCHK(hipGetLastError());
     const rocblas_status rs = rocsolver_dsyevd_strided_batched(rb.h, rocblas_evect_original, rocblas_fill_lower, N2,
                                                                H, N2, per, Ev, N2, Ew, N2, info, nclass);
     require(rs == rocblas_status_success, TDSLDA_EDEVICE, "rocsolver_dsyevd_strided_batched failed");
-    const double scale = 1.0 / (s.nz * s.dz * s.dx * s.dy);
+    const double scale = 1.0 / vol_factor;
     hipLaunchKernelGGL(k_st_dens, dim3(gb), dim3(256), 0, 0, H, Ev, nclass, M, wc, scale, rho, nu);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemset(bad, 0, sizeof(int)));
     hipLaunchKernelGGL(k_st_pot, dim3(gb), dim3(256), 0, 0, M, rho, nu, vext, U, mu, s.ec, f.functional, f.B, f.C,
                        f.inv_g_bdg, Uo, Do, bad);
     HIPCHK(hipGetLastError());
-    hipLaunchKernelGGL(k_st_reduce, dim3(1), dim3(1024), 0, 0, M, rho, Uo, U, Do, D, s.nz * s.dz * s.dx * s.dy,
-                       red);
+    hipLaunchKernelGGL(k_st_reduce, dim3(1), dim3(1024), 0, 0, M, rho, Uo, U, Do, D, vol_factor, red);
     HIPCHK(hipGetLastError());
     std::vector<rocblas_int> ih(nclass);
     int b = 0;

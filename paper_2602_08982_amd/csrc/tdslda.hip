@@ -888,8 +888,13 @@ tdslda_status tdslda_abm_graph(tdslda_ctx* c, int64_t nsteps, double graph_ms[2]
     require(nsteps >= 0, TDSLDA_EINVAL, "nsteps < 0");
     if (nsteps == 0) return;
     HIPCHK(hipStreamSynchronize(c->stream));
+    // the previous call's graph has completed (its launch synchronised)
+    c->release_graph();
     hipStream_t user = c->stream, cs = c->stream;
-    if (cs == nullptr) HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    if (cs == nullptr) {  // capture needs a real stream: the context's private one
+      if (!c->graph_stream) HIPCHK(hipStreamCreateWithFlags(&c->graph_stream, hipStreamNonBlocking));
+      cs = c->graph_stream;
+    }
     c->stream = cs;
     hipGraph_t g = nullptr;
     hipGraphExec_t ge = nullptr;
@@ -910,7 +915,6 @@ tdslda_status tdslda_abm_graph(tdslda_ctx* c, int64_t nsteps, double graph_ms[2]
       if (ge) (void)hipGraphExecDestroy(ge);
       if (g) (void)hipGraphDestroy(g);
       c->stream = user;
-      if (cs != user) (void)hipStreamDestroy(cs);
     };
     try {
       const auto t0 = std::chrono::steady_clock::now();
@@ -950,7 +954,10 @@ tdslda_status tdslda_abm_graph(tdslda_ctx* c, int64_t nsteps, double graph_ms[2]
       }
       throw;
     }
-    cleanup();
+    // keep the executed graph until the next call or the context's end
+    c->graph = g;
+    c->graph_exec = ge;
+    c->stream = user;
   });
 }
 

@@ -42,7 +42,7 @@ class Static(C.Structure):
     _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("dx", C.c_double), ("dy", C.c_double),
                 ("dz", C.c_double), ("ec", C.c_double), ("mix", C.c_double), ("a_mu", C.c_double),
                 ("N_req", C.c_double), ("tol", C.c_double), ("eF_ref", C.c_double), ("maxit", C.c_int),
-                ("broyden", C.c_int), ("w0", C.c_double)]
+                ("broyden", C.c_int), ("w0", C.c_double), ("q1d", C.c_int)]
 
 
 class TdsldaError(RuntimeError):
@@ -381,8 +381,10 @@ def q1d_count(lattice, kperp2, hfield, delta, ecut):
 
 
 def static_params(nx, ny, nz, d=(1.0, 1.0, 1.0), ec=0.5 * np.pi ** 2, mix=0.5, a_mu=0.0, N_req=0.0, tol=1e-8,
-                  eF_ref=0.5, maxit=500, broyden=0, w0=0.01):
-    return Static(nx, ny, nz, d[0], d[1], d[2], ec, mix, a_mu, N_req, tol, eF_ref, maxit, broyden, w0)
+                  eF_ref=0.5, maxit=500, broyden=0, w0=0.01, q1d=False):
+    """q1d: the quasi-1D static geometry (nx lattice sites, ny plane waves
+    along y, nz along z; fields of length nx)."""
+    return Static(nx, ny, nz, d[0], d[1], d[2], ec, mix, a_mu, N_req, tol, eF_ref, maxit, broyden, w0, int(q1d))
 
 
 def static_map(params, fun, vext, U, delta, mu):

@@ -10,7 +10,9 @@ reference Fermi momentum k_F = 1 (eF_ref = 1/2); the warm start is the
 network's prediction of (U, Delta, mu) from V_ext.  Both are iterated by the
 same mixing to r < tol (linear mixing, and the modified Broyden mixing as
 the non-learned accelerator to compare with); when the warm start does not
-converge the plain start is used (and counted).
+converge the plain start is used (and counted).  The non-learned starts of
+Sec. 5.2 run beside it: the coarse-lattice start (refining lattice
+resolution) and the symmetry-release start (quasi-1D first).
 """
 import time
 
@@ -100,6 +102,29 @@ def coarse_start(cfg, fun, N_req, seed, nxc, broyden=0):
     Uf = T.interp2d(U, (d, d), shape, (1.0, 1.0))
     Df = T.interp2d(D, (d, d), shape, (1.0, 1.0))
     return (Uf, Df, mu), res
+
+
+def release_start(cfg, fun, N_req, broyden=0):
+    """Sec. 5.2, releasing symmetry constraints: first the quasi-1D problem
+    with the trap along y switched off (omega_y = 0; the obstacles, which
+    break the symmetry, are left out): an nx-site x lattice with ny plane
+    waves along y (the target's L_y) and nz along z, V = 1/2 omega^2 x^2, the
+    same N_req, from the plain start; then its (U(x), Delta(x)) repeated
+    along y and its mu start the quasi-2D solve.  The first stage does not
+    depend on the obstacles.  Returns (start, quasi-1D result)."""
+    nx, ny = cfg["nx"], cfg["ny"]
+    x = (np.arange(nx) - nx // 2) * 1.0
+    v1 = 0.5 * cfg["omega"] ** 2 * x ** 2
+    p = T.static_params(nx, ny, cfg["nz"], d=(1.0, 1.0, 1.0), ec=0.5 * np.pi ** 2, mix=cfg["mix"],
+                        a_mu=cfg["a_mu"], N_req=N_req, tol=cfg["tol"], eF_ref=EF_REF, maxit=cfg["maxit"],
+                        broyden=broyden, w0=cfg.get("w0", 0.01), q1d=True)
+    U0 = np.full(nx, fun.B * EF_REF)
+    D0 = np.full(nx, DELTA_UFG * EF_REF)
+    t0 = time.perf_counter()
+    U, D, mu, it, ok, hist = T.static_solve(p, fun, v1, U0, D0, XI_UFG * EF_REF)
+    res = dict(iters=it, converged=ok, seconds=time.perf_counter() - t0)
+    start = (np.repeat(U[:, None], ny, axis=1), np.repeat(D[:, None], ny, axis=1), mu)
+    return start, res
 
 
 class WarmStart:
@@ -197,6 +222,14 @@ def experiment(cfg, train_seeds, test_seeds, epochs=300, log=None):
     mixings = ([("", 0)] if cfg.get("linear", True) else []) + ([("_broyden", nb)] if nb else [])
     coarse = {k: [] for k in ("coarse", "fine", "coarse_broyden", "fine_broyden")}
     coarse.update(fallbacks=0, coarse_s=0.0, coarse_it=0)
+    # releasing symmetry constraints: the quasi-1D stage is the same for
+    # every seed; it is solved once per mixing and charged to every seed
+    rel = {k: [] for k in ("fine", "fine_broyden")}
+    rel_stage = {}
+    if cfg.get("release", True):
+        for suffix, b in mixings:
+            rel_stage[suffix] = release_start(cfg, fun, N_req, broyden=b)
+    rel_fallbacks = 0
     for i, s in enumerate(test_seeds):
         if log and i and i % 5 == 0:
             log(f"held-out seeds: {i} of {len(test_seeds)}")
@@ -223,6 +256,11 @@ def experiment(cfg, train_seeds, test_seeds, epochs=300, log=None):
             coarse["fallbacks"] += 0 if (f["converged"] and cres["converged"]) else 1
             coarse["coarse_s"] += cres["seconds"]
             coarse["coarse_it"] += cres["iters"]
+        for suffix, b in (mixings if rel_stage else ()):
+            start, sres = rel_stage[suffix]
+            f = solve(cfg, fun, N_req, v, start, broyden=b)
+            rel["fine" + suffix].append(f["iters"] if f["converged"] else f["iters"] + cfg["maxit"])
+            rel_fallbacks += 0 if (f["converged"] and sres["converged"]) else 1
     ws.close()
     out = dict(lattice=[cfg["nx"], cfg["ny"], cfg["nz"]], n_train=len(V), n_test=len(test_seeds),
                train_data_seconds=t_data, fit_seconds=t_fit, fit=fit, fallbacks=fallbacks,
@@ -240,6 +278,21 @@ def experiment(cfg, train_seeds, test_seeds, epochs=300, log=None):
                 cres["linear" if not suffix else "broyden"] = dict(coarse_iters_mean=float(c), fine_iters_mean=float(f),
                                                                    target_equivalent=float(c * ratio + f))
         out["coarse_start"] = cres
+    if rel_stage:
+        # cost of a quasi-1D iteration in target-lattice iterations, measured
+        s1 = sum(r["seconds"] for _, r in rel_stage.values())
+        i1 = sum(r["iters"] for _, r in rel_stage.values())
+        ratio = (s1 / max(1, i1)) / out["seconds_per_iteration"]
+        rres = dict(stage1="quasi-1D: x lattice, plane waves along y and z, omega_y = 0, no obstacles, same N",
+                    cost_ratio=ratio, fallbacks=rel_fallbacks)
+        for suffix in ("", "_broyden"):
+            if rel["fine" + suffix]:
+                c1 = rel_stage[suffix][1]["iters"]
+                f = float(np.mean(rel["fine" + suffix]))
+                rres["linear" if not suffix else "broyden"] = dict(
+                    q1d_iters=int(c1), q2d_iters_mean=f, target_equivalent=float(c1 * ratio + f),
+                    target_equivalent_once=float(f + c1 * ratio / max(1, len(test_seeds))))
+        out["symmetry_release_start"] = rres
     if its["plain_broyden"]:
         out.update(plain_broyden_iters_mean=float(np.mean(its["plain_broyden"])),
                    warm_broyden_iters_mean=float(np.mean(its["warm_broyden"])),

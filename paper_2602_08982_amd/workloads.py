@@ -118,11 +118,12 @@ def q1d_dperp(cfg, hstatic, lo=0.3, hi=3.0, iters=40):
     raise RuntimeError("no d_perp gives a corner count in range")
 
 
-def setup_q1d(cfg, seed, stream=None, precision=None, nk=None):
+def setup_q1d(cfg, seed, stream=None, precision=None, nk=None, A=1.0):
     """Create the batched quasi-1D context: static states of every problem
     (bump on, U = 0, Delta = delta0) loaded on the device, trap-only V_ext
     for the evolution (bump removed at t = 0), regulator frozen with
-    E_c = ecut.  Returns (ctx, info)."""
+    E_c = ecut.  A != 1 evolves the same states with the general functional
+    (alpha = A, current potential).  Returns (ctx, info)."""
     import synth
     nk = cfg["nk"] if nk is None else nk
     bump = synth.gaussian_bump(seed)
@@ -135,7 +136,7 @@ def setup_q1d(cfg, seed, stream=None, precision=None, nk=None):
     counts, total = T.q1d_count(lat, kp2, hstatic, delta, cfg["ecut"])
     prec = cfg["precision"] if precision is None else precision
     run = T.run_config(precision=prec, integrator=T.AB4AM5, dt=cfg["dt"], selfstart=1, stream=stream)
-    ctx = T.Context(lat, T.functional_slda(cfg["mu"], cfg["ecut"]), run, int(total))
+    ctx = T.Context(lat, T.functional_slda(cfg["mu"], cfg["ecut"], A=A), run, int(total))
     ctx.set_external(vt, freeze_regulator=True)
     n = ctx.q1d_load_static(kp2, hstatic, delta, cfg["ecut"])
     assert n == total

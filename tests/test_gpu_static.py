@@ -145,3 +145,36 @@ def test_interp2d_rejects_a_different_box():
     with pytest.raises(t.TdsldaError) as ei:
         t.interp2d(np.zeros((6, 6)), (1.0, 1.0), (8, 8), (1.0, 1.0))
     assert ei.value.status == t.EINVAL
+
+
+def test_static_q1d_map_and_solve_match_oracle():
+    """Quasi-1D static geometry (the first stage of releasing symmetry
+    constraints, Sec. 5.2): nx lattice sites, plane waves along y and z.
+    One application of K element by element, then the fixed-N linear-mixing
+    solve (same iteration count, same fields and mu) against the oracle."""
+    t = T()
+    nx, ny, nz, dy = 16, 12, 6, 1.2
+    g = ST.GeometryQ1DStatic(nx, ny, nz, 1.0, dy, 1.0)
+    x = g.coords()[0]
+    vext = 0.5 * 0.3 ** 2 * x ** 2
+    fo = F.Functional(F.SLDA)
+    U = synth.uniform_field(21, nx, -0.3, 0.0)
+    D = synth.uniform_field(22, nx, 0.1, 0.4)
+    Uo, Do, rho, nu, N = ST.map_k(g, fo, vext, U, D, 0.9, EC)
+    p = t.static_params(nx, ny, nz, d=(1.0, dy, 1.0), ec=EC, q1d=True)
+    Ug, Dg, rg, ng, Ng = t.static_map(p, t.functional_slda(0.9, EC), vext, U, D, 0.9)
+    rel = lambda a, b: np.abs(a - b).max() / np.abs(b).max()
+    assert rel(rg, rho) < 1e-10 and rel(ng, np.real(nu)) < 1e-10
+    assert rel(Ug, Uo) < 1e-10 and rel(Dg, np.real(Do)) < 1e-10
+    assert abs(Ng - N) / N < 1e-12
+    N_req = 0.8 * N
+    Uo, Do, muo, ito, ok = ST.solve(g, fo, vext, np.zeros(nx), np.full(nx, 0.4), 0.9, EC, N_req=N_req,
+                                    maxit=600)
+    assert ok
+    p = t.static_params(nx, ny, nz, d=(1.0, dy, 1.0), ec=EC, mix=0.5, a_mu=0.5, N_req=N_req, tol=1e-8,
+                        maxit=600, q1d=True)
+    Ug, Dg, mug, itg, okg, hg = t.static_solve(p, t.functional_slda(0.9, EC), vext, np.zeros(nx),
+                                               np.full(nx, 0.4), 0.9)
+    assert okg and abs(itg - ito) <= 1
+    assert np.abs(Ug - Uo).max() < 1e-8 and np.abs(Dg - np.real(Do)).max() < 1e-8
+    assert abs(mug - muo) < 1e-8

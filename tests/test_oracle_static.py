@@ -124,3 +124,43 @@ def test_broyden_solve_reaches_the_linear_mixing_fixed_point():
     assert okl and okb
     assert itb < itl, (itb, itl)
     assert np.abs(Ub - Ul).max() < 1e-8 and np.abs(Db - Dl).max() < 1e-8 and abs(mub - mul) < 1e-8
+
+
+def test_q1d_static_classes_cover_the_transverse_grid():
+    """The quasi-1D classes (|k_y|, |k_z|) with multiplicities w_y w_z cover
+    every transverse momentum pair of the N_y x N_z plane-wave grid once."""
+    g = ST.GeometryQ1DStatic(6, 4, 8, 1.0, 1.2, 0.9)
+    ky, kz = L.kgrid(4, 1.2), L.kgrid(8, 0.9)
+    kp = np.sqrt(ky[:, None] ** 2 + kz[None, :] ** 2).ravel()
+    assert g.mult.sum() == kp.size
+    # each distinct |k_perp| carries as many pairs as the classes that share it
+    for k in np.unique(np.round(kp, 10)):
+        assert np.isclose(g.mult[np.isclose(g.kz, k)].sum(), np.sum(np.isclose(kp, k)))
+
+
+def test_q1d_static_is_the_q2d_one_for_y_independent_fields():
+    """Exact mode reduction (Sec. 3.1): for fields that do not depend on y,
+    the quasi-2D map (an N_y-site y lattice, spectral D2) and the quasi-1D
+    map (N_y plane waves along y, same L_y) give the same densities and
+    potentials, and a fixed-N solve of a trap in x converges to the same
+    fields and mu in both geometries."""
+    nx, ny, nz = 8, 4, 4
+    g2 = ST.GeometryQ2D(nx, ny, nz, 1.0, 1.5, 1.0)
+    g1 = ST.GeometryQ1DStatic(nx, ny, nz, 1.0, 1.5, 1.0)
+    x = g1.coords()[0]
+    vx = 0.5 * 0.3 ** 2 * x ** 2
+    U1 = 0.1 * synth.uniform_field(51, nx)
+    D1 = 0.4 + 0.1 * synth.uniform_field(52, nx)
+    mu = 0.9
+    b = lambda f: np.repeat(f[:, None], ny, axis=1)
+    o1 = ST.map_k(g1, FUN, vx, U1, D1, mu, EC)
+    o2 = ST.map_k(g2, FUN, b(vx), b(U1), b(D1), mu, EC)
+    for a1, a2 in zip(o1[:4], o2[:4]):
+        assert np.abs(b(a1) - a2).max() < 1e-12 * max(1.0, np.abs(a2).max())
+    assert o1[4] == pytest.approx(o2[4], rel=1e-13)
+    N_req = 0.9 * o1[4]
+    s1 = ST.solve(g1, FUN, vx, np.zeros(nx), np.full(nx, 0.5), mu, EC, N_req=N_req, maxit=400)
+    s2 = ST.solve(g2, FUN, b(vx), np.zeros((nx, ny)), np.full((nx, ny), 0.5), mu, EC, N_req=N_req, maxit=400)
+    assert s1[4] and s2[4]
+    assert np.abs(b(s1[0]) - s2[0]).max() < 1e-7 and np.abs(b(s1[1]) - s2[1]).max() < 1e-7
+    assert s1[2] == pytest.approx(s2[2], abs=1e-7)
