@@ -244,7 +244,9 @@ __global__ __launch_bounds__((SlabCfg<NX, NY, NZ>::TB)) void k_dens(
 //   grid = (ceil(M / (TB DS_P)), ceil(nstates / DG)), block = TB
 //   dens_part layout [group][3][M]
 constexpr int DS_TB = 256, DS_P = 2;
-template <typename R, int DG, int PS = DS_P>
+// NC: components per group in the partial layout (3; 4 when a fourth,
+// written by another pass, follows)
+template <typename R, int DG, int PS = DS_P, int NC = 3>
 __global__ __launch_bounds__(DS_TB) void k_dens_sum(
     const cpx<R>* __restrict__ X, int64_t nstates, int64_t M, const double* __restrict__ wu,
     const double* __restrict__ wv, const double* __restrict__ scale, double* __restrict__ dens_part) {
@@ -273,7 +275,7 @@ __global__ __launch_bounds__(DS_TB) void k_dens_sum(
       }
     }
   }
-  double* out = dens_part + int64_t(blockIdx.y) * 3 * M;
+  double* out = dens_part + int64_t(blockIdx.y) * NC * M;
 #pragma unroll
   for (int i = 0; i < PS; ++i) {
     const int64_t r = site0 + i * DS_TB;

@@ -742,24 +742,27 @@ __global__ __launch_bounds__(256) void q_fric_fields(int N, double dz, double dV
 // -(1 - A) j_z^2 / (2 rho^2); j_z is rebuilt with rho and nu at every field
 // build.
 
-// q_densj: rho, nu and j_z group partials of the normalised states,
+// q_jz: the j_z group partials of the normalised states,
 //   j_z = sum_n [f_v Im(v (D1 v)^*) - f_u Im(u (D1 u)^*)],
-// part layout [group][4][N] (rho, Re nu, Im nu, j_z).
+// written as component 3 of the [group][4][N] partial layout whose first
+// three components (rho, Re nu, Im nu) the transform-free density pass
+// writes; a component with zero weight in the whole state is skipped (T = 0:
+// f_u = 0 for E > 0).
 template <typename R, int A, int G, int TB>
-__global__ __launch_bounds__(TB) void q_densj(const cpx<R>* __restrict__ X, int64_t nstates,
-                                               const double* __restrict__ wu, const double* __restrict__ wv,
-                                               const double* __restrict__ scale, double* __restrict__ part,
-                                               const cpx<R>* __restrict__ tw, double kz) {
+__global__ __launch_bounds__(TB) void q_jz(const cpx<R>* __restrict__ X, int64_t nstates,
+                                            const double* __restrict__ wu, const double* __restrict__ wv,
+                                            const double* __restrict__ scale, double* __restrict__ part,
+                                            const cpx<R>* __restrict__ tw, double kz) {
   using CFG = Q1DCfg<R, A, TB>;
   constexpr int N = CFG::N, WS = CFG::WS;
   constexpr int NW = CFG::TB / kWave;
   __shared__ cpx<R> lds_all[WS][A * CFG::PAD];
-  __shared__ double red[NW][4 * N];
+  __shared__ double red[NW][N];
   const int tid = threadIdx.x, grp = tid / A, a = tid % A;
   cpx<R>* lds = lds_all[grp];
-  double ar[A], anr[A], ani[A], aj[A];
+  double aj[A];
 #pragma unroll
-  for (int b = 0; b < A; ++b) ar[b] = anr[b] = ani[b] = aj[b] = 0.0;
+  for (int b = 0; b < A; ++b) aj[b] = 0.0;
   const R inv_n = R(1.0 / N);
   const int64_t nbeg = int64_t(blockIdx.x) * G;
   for (int it = 0; it < G / WS; ++it) {
@@ -769,25 +772,17 @@ __global__ __launch_bounds__(TB) void q_densj(const cpx<R>* __restrict__ X, int6
     const R s = R(scale[nn]);
     const double fu = live ? wu[nn] : 0.0, fv = live ? wv[nn] : 0.0;
     const cpx<R>* Xn = X + nn * 2 * N;
-    cpx<R> x[A], d[A];
 #pragma unroll 1
     for (int comp = 0; comp < 2; ++comp) {
       const double wgt = comp ? fv : -fu;
+      // barriers inside the transforms: skip only when no state of the
+      // workgroup needs this component
+      if (!__syncthreads_or(wgt != 0.0)) continue;
+      cpx<R> x[A], d[A];
 #pragma unroll
       for (int b = 0; b < A; ++b) {
         x[b] = s * Xn[comp * N + a + A * b];
         d[b] = x[b];
-      }
-      if (comp == 0) {
-        // u: rho and nu need v at the same sites, read it here as well
-#pragma unroll
-        for (int b = 0; b < A; ++b) {
-          const cpx<R> v = s * Xn[N + a + A * b];
-          const double ur = x[b].x, ui = x[b].y, vr = v.x, vi = v.y;
-          ar[b] += fv * (vr * vr + vi * vi) + fu * (ur * ur + ui * ui);
-          anr[b] += (fv - fu) * (ur * vr + ui * vi);
-          ani[b] += (fv - fu) * (ui * vr - ur * vi);
-        }
       }
       q_fwd<R, A>(d, a, lds, tw);
       sfor<0, A>::run([&](auto pc) {
@@ -807,26 +802,16 @@ __global__ __launch_bounds__(TB) void q_densj(const cpx<R>* __restrict__ X, int6
 #pragma unroll
   for (int b = 0; b < A; ++b) {
 #pragma unroll
-    for (int o = A; o < kWave; o <<= 1) {
-      ar[b] += __shfl_xor(ar[b], o, kWave);
-      anr[b] += __shfl_xor(anr[b], o, kWave);
-      ani[b] += __shfl_xor(ani[b], o, kWave);
-      aj[b] += __shfl_xor(aj[b], o, kWave);
-    }
+    for (int o = A; o < kWave; o <<= 1) aj[b] += __shfl_xor(aj[b], o, kWave);
   }
   const int w = tid / kWave, lw = tid % kWave;
   if (lw < A) {
 #pragma unroll
-    for (int b = 0; b < A; ++b) {
-      red[w][a + A * b] = ar[b];
-      red[w][N + a + A * b] = anr[b];
-      red[w][2 * N + a + A * b] = ani[b];
-      red[w][3 * N + a + A * b] = aj[b];
-    }
+    for (int b = 0; b < A; ++b) red[w][a + A * b] = aj[b];
   }
   __syncthreads();
-  double* out = part + int64_t(blockIdx.x) * 4 * N;
-  for (int i = tid; i < 4 * N; i += CFG::TB) {
+  double* out = part + int64_t(blockIdx.x) * 4 * N + 3 * N;
+  for (int i = tid; i < N; i += CFG::TB) {
     double t = 0.0;
 #pragma unroll
     for (int w2 = 0; w2 < NW; ++w2) t += red[w2][i];
@@ -1091,12 +1076,16 @@ struct EngineQ1D final : Engine {
   void dens(Ctx& c, const void* X, const double* scale, int64_t nst) override {
     twiddles(c);
     const unsigned ng = cdiv(nst, G);
-    if (c.gen) {  // general functional: rho, nu and j_z
+    if (c.gen) {  // general functional: rho, nu (no transform) and j_z, groups of G states
       const double kz = 2 * kPi / (N * c.lat.dz);
+      c.launch(KC_DENS, [&] {
+        hipLaunchKernelGGL((k_dens_sum<R, G, 1, 4>), dim3(cdiv(N, DS_TB), ng), dim3(DS_TB), 0, c.stream,
+                           (const cpx<R>*)X, nst, int64_t(N), c.wu, c.wv, scale, c.dens_part);
+      });
       with_tb(tb[0], [&](auto t) {
         constexpr int TB = decltype(t)::value;
         c.launch(KC_DENS, [&] {
-          hipLaunchKernelGGL((q_densj<R, A, G, TB>), dim3(ng), dim3(TB), 0, c.stream, (const cpx<R>*)X, nst, c.wu,
+          hipLaunchKernelGGL((q_jz<R, A, G, TB>), dim3(ng), dim3(TB), 0, c.stream, (const cpx<R>*)X, nst, c.wu,
                              c.wv, scale, c.dens_part, tw, kz);
         });
       });

@@ -6,8 +6,9 @@
 `stats` tabulates calls / total / average duration per kernel.  `counters`
 turns the per-dispatch FETCH_SIZE and WRITE_SIZE readings (KiB) into HBM
 bytes per launch: each counter is scaled by the factor that maps its reading
-for the run's 4 GiB device-to-device copy (the largest __amd_rocclr_copyBuffer
-dispatch, 2^32 bytes read and 2^32 bytes written) onto those known sizes.
+for the run's 4 GiB device-to-device copy (the largest dispatch of the
+library's k_stream_copy, or of the runtime's __amd_rocclr_copyBuffer, 2^32
+bytes read and 2^32 bytes written) onto those known sizes.
 The counters summary records a digest of the 3D kernel sources and build
 flags so that a reader (bench.py) can tell whether the figures still describe
 the kernels as built.
@@ -46,12 +47,17 @@ def role(name):
     m = re.search(r"q_lap2<\w+, \d+, \d+, (\d)", name)
     if m:
         return "q1d_" + LAP2_MODES[int(m.group(1))]
+    m = re.search(r"q_gen<\w+, \d+, \d+, (\d)", name)
+    if m:
+        return "q1dgen_" + {**LAP2_MODES, 5: "lap1"}[int(m.group(1))]
     m = re.search(r"q_pointwise<\w+, \d+, \d+, (\d)", name)
     if m:
         return "q1d_" + PW_MODES.get(int(m.group(1)), "scale")
     for pat, r in (("k_lap1<", "lap1"), ("k_dens_sum<", "dens"), ("k_dens<", "dens_kin"),
                    ("k_reduce_pot", "reduce_pot"), ("k_finalize", "finalize"), ("q_lap1<", "q1d_lap1"),
-                   ("q_dens<", "q1d_dens_kin"), ("q_corr_split<", "q1d_lap2_corr"), ("q_fric<", "q1d_friction")):
+                   ("q_dens<", "q1d_dens_kin"), ("q_corr_split<", "q1d_lap2_corr"), ("q_fric<", "q1d_friction"),
+                   ("q_densj<", "q1dgen_dens"), ("q_reduce_gen<", "q1dgen_reduce_pot"),
+                   ("k_stream_copy", "stream_copy"), ("k_stream_read", "stream_read")):
         if pat in name:
             return r
     return None
@@ -115,10 +121,13 @@ def _per_kernel(path):
 
 
 def _copy_factor(agg):
-    copies = [v for k, vals in agg.items() if "copyBuffer" in k for v in vals]
-    if not copies:
-        raise SystemExit("no __amd_rocclr_copyBuffer dispatch in the counter file")
-    return COPY_BYTES / max(copies)
+    """The library's streaming copy of 4 GiB (its largest k_stream_copy
+    dispatch; else the runtime's largest copyBuffer dispatch)."""
+    for pat in ("k_stream_copy", "copyBuffer"):
+        copies = [v for k, vals in agg.items() if pat in k for v in vals]
+        if copies:
+            return COPY_BYTES / max(copies)
+    raise SystemExit("no 4 GiB copy dispatch in the counter file")
 
 
 def cmd_counters(args):

@@ -45,3 +45,13 @@ def test_roles_and_keys():
     assert P.key("void tdslda::(anonymous namespace)::q_lap2<float, 16, 64, 3, 4, 5>(...)") == "float:16:q1d_lap2_full"
     assert P.key("tdslda::k_finalize(long, tdslda::StateScalars, int)") == ":-:finalize"
     assert P.role("rocsolver::v33001::stedc_solve_kernel<double>(int)") is None
+    assert P.key("void tdslda::(anonymous namespace)::q_gen<float, 16, 256, 3, 4, 5>(...)") == "float:16:q1dgen_lap2_full"
+    assert P.role("void tdslda::(anonymous namespace)::q_gen<float, 16, 256, 5, 4, 5>(...)") == "q1dgen_lap1"
+    assert P.role("void tdslda::(anonymous namespace)::q_densj<float, 16, 512, 256>(...)") == "q1dgen_dens"
+
+
+def test_library_copy_calibrates(tmp_path):
+    """The library's own 4 GiB streaming copy is the calibration dispatch
+    (the largest k_stream_copy reading)."""
+    agg = {"tdslda::k_stream_copy(cp_v4i const*, cp_v4i*, long)": [2 ** 31 / 1024 * 1024.0, 100.0]}
+    assert abs(P._copy_factor(agg) - 2.0) < 1e-12
