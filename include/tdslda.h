@@ -70,9 +70,9 @@ typedef struct {
 
 typedef struct {
   int functional;       /* TDSLDA_FUNC_SLDA (Sec. 2.4, ASLDA at p=0) or TDSLDA_FUNC_BDG (Eq. HBdG) */
-  double A, B, C;       /* SLDA constants.  A = 1: Eq. h_sigma_A1 (3D and Q1D).  A != 1: the
-                           general functional of Eq. h_sigma (alpha = A, current potential
-                           (1 - A) j / rho), Q1D contexts only */
+  double A, B, C;       /* SLDA constants.  A = 1: Eq. h_sigma_A1.  A != 1: the general
+                           functional of Eq. h_sigma (alpha = A, current potential
+                           (1 - A) j / rho, rebuilt with j at every field build) */
   double inv_g_bdg;     /* BdG: 1/(4 pi a_s) */
   double ec_reg;        /* cut-off energy E_c of the regulator Lambda_c (Eq. Creg) */
   double mu;            /* chemical potential, fixed during TD */
@@ -157,20 +157,20 @@ tdslda_status tdslda_init_plane_waves(tdslda_ctx* ctx, int64_t n, const int32_t*
 tdslda_status tdslda_imprint_vortices(tdslda_ctx* ctx, int nv, const double* xyq);
 
 /* Linear-mode potentials of the general single-particle Hamiltonian
- * (Sec. 2.3, Eq. h_sigma): alpha[M] (inverse effective mass, > 0) and
- * az[M] (current potential along z), host FP64, quasi-1D contexts with
- * frozen fields (tdslda_set_fields first).  H then applies
- *   h = -1/2 d_z alpha d_z + 1/2 alpha k_perp^2 + U + V_ext - mu
- *       - (i/2) {A_z, d_z}
- * with the kinetic part in the symmetrised form of Eq. kinop-alpha
- * (1/2 [D2(alpha x) + alpha D2 x - x D2 alpha], D2 of Eq. D2) and the
- * current part A_z D1 x + D1(A_z x) (Eqs. Ad_dx, d_dxA; D1 with the Nyquist
- * mode zeroed), 7 transforms per component; -h^* on v.  A NULL array keeps
- * the functional's value (alpha = A, A_z = 0); both NULL return to the
- * functional's potentials.  tdslda_set_fields(NULL, NULL) also resets them.
- * Errors: EINVAL (3D context, non-finite or non-positive alpha), EORDER
- * (fields not frozen). */
-tdslda_status tdslda_set_current_fields(tdslda_ctx* ctx, const double* alpha, const double* az);
+ * (Sec. 2.3, Eq. h_sigma), host FP64, for a context with frozen fields
+ * (tdslda_set_fields first): alpha[M] (inverse effective mass, > 0) and the
+ * current potential avec (3D: [3][M], components x, y, z; quasi-1D: [M], the
+ * z component; the transverse ones vanish).  H then applies
+ *   h = -1/2 div(alpha grad) + U + V_ext - mu - (i/2) {A, grad}
+ * (quasi-1D: + 1/2 alpha k_perp^2) with the kinetic part in the symmetrised
+ * form of Eq. kinop-alpha (1/2 [D2(alpha x) + alpha D2 x - x D2 alpha] per
+ * axis, D2 of Eq. D2) and the current part A_d D1_d x + D1_d(A_d x) (Eqs.
+ * Ad_dx, d_dxA; D1 with the Nyquist mode zeroed), 7 transforms per
+ * component and axis; -h^* on v.  A NULL array keeps the functional's value
+ * (alpha = A, A = 0); both NULL return to the functional's potentials.
+ * tdslda_set_fields(NULL, NULL) also resets them.  Errors: EINVAL
+ * (non-finite values, alpha <= 0), EORDER (fields not frozen). */
+tdslda_status tdslda_set_current_fields(tdslda_ctx* ctx, const double* alpha, const double* avec);
 
 /* Freeze the mean fields (linear mode): U[M] and Delta[M][2] (host FP64) are
  * used by every later H application and never rebuilt.  Pass NULLs to go

@@ -140,6 +140,8 @@ struct tdslda_ctx {
   // effective mass alpha, its D2, and the current potential A_z, [M] in the
   // context precision; gen = the general operator is in use
   void *hAl = nullptr, *hLa = nullptr, *hAz = nullptr;
+  void *hAx = nullptr, *hAy = nullptr;  // 3D: the x and y components of A
+  double* jpart = nullptr;              // 3D: current group partials [group][3][M]
   bool gen = false;
   double* gscratch = nullptr;  // [gchunk][4][M] doubles (tau_s, j_s); also FP64 staging
   int64_t gchunk = 1;

@@ -3,6 +3,7 @@
 #pragma once
 
 #include "ctx.h"
+#include "kernels3d_gen.h"
 
 namespace tdslda {
 
@@ -13,6 +14,7 @@ struct Engine3D final : Engine {
   using CFG = SlabCfg<NX, NY, NZ>;
   static constexpr int G = 32;     // states per density group
   static constexpr int TB1 = 64;   // lap1 block
+  static constexpr int GTB = 64;   // line passes of the general functional
   static constexpr int M = NX * NY * NZ;
   static constexpr int NYZ = NY * NZ;
   int ngx() const override { return CFG::NGX; }
@@ -24,7 +26,59 @@ struct Engine3D final : Engine {
   double cy2(const Ctx& c) const { double k = 2 * kPi / (NY * c.lat.dy); return k * k; }
   double cz2(const Ctx& c) const { double k = 2 * kPi / (NZ * c.lat.dz); return k * k; }
 
+  // general functional: rho, nu by the transform-free density pass and the
+  // current j by one line pass per axis, both over groups of DG states
+  void gen_dens(Ctx& c, const void* X, const double* scale, int64_t nst) {
+    const unsigned ng = cdiv(nst, DG);
+    c.launch(KC_DENS, [&] {
+      hipLaunchKernelGGL((k_dens_sum<R, DG>), dim3(cdiv(M, DS_TB * DS_P), ng), dim3(DS_TB), 0, c.stream,
+                         (const cpx<R>*)X, nst, int64_t(M), c.wu, c.wv, scale, c.dens_part);
+    });
+    const cpx<R>* x = (const cpx<R>*)X;
+    c.launch(KC_DENS, [&] {
+      hipLaunchKernelGGL((k_jline<R, NX, NY, NZ, 0, GTB, DG>), dim3(cdiv(NYZ, GTB), ng), dim3(GTB), 0, c.stream, x,
+                         nst, scale, c.wu, c.wv, 2 * kPi / (NX * c.lat.dx), c.jpart);
+    });
+    c.launch(KC_DENS, [&] {
+      hipLaunchKernelGGL((k_jline<R, NX, NY, NZ, 1, GTB, DG>), dim3(cdiv(NX * NZ, GTB), ng), dim3(GTB), 0, c.stream,
+                         x, nst, scale, c.wu, c.wv, 2 * kPi / (NY * c.lat.dy), c.jpart);
+    });
+    c.launch(KC_DENS, [&] {
+      hipLaunchKernelGGL((k_jline<R, NX, NY, NZ, 2, GTB, DG>), dim3(cdiv(NX * NY, GTB), ng), dim3(GTB), 0, c.stream,
+                         x, nst, scale, c.wu, c.wv, 2 * kPi / (NZ * c.lat.dz), c.jpart);
+    });
+    c.nsg_used = int(ng);
+  }
+  // general functional: H phi of every state into T (or out) by three line
+  // passes; with hp the <H>_n partials go to the h slots after the NGX raw
+  // slots (which the last pass clears)
+  void gen_apply(Ctx& c, const void* X, const double* scale, double* hp, void* out, int64_t nst) {
+    require(int(cdiv(NX * NY, GTB)) <= ncb(), TDSLDA_EINVAL, "internal: too few h slots for the z-line pass");
+    const cpx<R>* x = (const cpx<R>*)X;
+    cpx<R>* T = (cpx<R>*)c.T;
+    const R *al = (const R*)c.hAl, *la = (const R*)c.hLa, *hA = (const R*)c.hA;
+    const cpx<R>* hD = (const cpx<R>*)c.hD;
+    c.launch(KC_LAP1, [&] {
+      hipLaunchKernelGGL((k_opline<R, NX, NY, NZ, 0, GTB, false>), dim3(cdiv(NYZ, GTB), nst), dim3(GTB), 0, c.stream,
+                         x, scale, T, nullptr, al, la, (const R*)c.hAx, hA, hD, nullptr, c.h_stride, CFG::NGX,
+                         ncb(), 2 * kPi / (NX * c.lat.dx), c.dV);
+    });
+    c.launch(KC_LAP1, [&] {
+      hipLaunchKernelGGL((k_opline<R, NX, NY, NZ, 1, GTB, false>), dim3(cdiv(NX * NZ, GTB), nst), dim3(GTB), 0,
+                         c.stream, x, scale, T, nullptr, al, la, (const R*)c.hAy, hA, hD, nullptr, c.h_stride,
+                         CFG::NGX, ncb(), 2 * kPi / (NY * c.lat.dy), c.dV);
+    });
+    c.launch(KC_LAP1, [&] {
+      hipLaunchKernelGGL((k_opline<R, NX, NY, NZ, 2, GTB, true>), dim3(cdiv(NX * NY, GTB), nst), dim3(GTB), 0,
+                         c.stream, x, scale, T, (cpx<R>*)out, al, la, (const R*)c.hAz, hA, hD, hp, c.h_stride,
+                         CFG::NGX, ncb(), 2 * kPi / (NZ * c.lat.dz), c.dV);
+    });
+  }
   void dens(Ctx& c, const void* X, const double* scale, int64_t nst) override {
+    if (c.gen) {
+      gen_dens(c, X, scale, nst);
+      return;
+    }
     dim3 grid(CFG::NGX, cdiv(nst, G));
     c.launch(KC_DENS_KIN, [&] {
       hipLaunchKernelGGL((k_dens<R, NX, NY, NZ, G>), grid, dim3(CFG::TB), 0, c.stream,
@@ -36,6 +90,10 @@ struct Engine3D final : Engine {
   // states per dens_sum group (FP64: 256 measured 12% faster than 64 at 32^3)
   static constexpr int DG = sizeof(R) == 8 ? 256 : 128;
   void dens_sum(Ctx& c, const void* X, const double* scale, int64_t nst) override {
+    if (c.gen) {
+      gen_dens(c, X, scale, nst);
+      return;
+    }
     dim3 grid(cdiv(M, DS_TB * DS_P), cdiv(nst, DG));
     c.launch(KC_DENS, [&] {
       hipLaunchKernelGGL((k_dens_sum<R, DG>), grid, dim3(DS_TB), 0, c.stream, (const cpx<R>*)X, nst,
@@ -47,6 +105,15 @@ struct Engine3D final : Engine {
   int raw_h_slots() const override { return CFG::NGX; }
   void reduce_pot(Ctx& c, bool update) override {
     FunParams fp{c.fun.functional, c.fun.B, c.fun.C, c.fun.inv_g_bdg, c.fun.mu, c.ainv, c.dext};
+    if (c.gen) {
+      c.launch(KC_REDUCE_POT, [&] {
+        hipLaunchKernelGGL((k_reduce_gen3d<R>), dim3(cdiv(M, 256)), dim3(256), 0, c.stream, c.dens_part, c.jpart,
+                           c.nsg_used, int64_t(M), fp, c.fun.A, c.lam, c.vext, c.rho, c.nu, c.jc, c.U, c.delta,
+                           (R*)c.hA, (cpx<R>*)c.hD, (R*)c.hAx, (R*)c.hAy, (R*)c.hAz,
+                           int(update && c.fun.functional == TDSLDA_FUNC_SLDA));
+      });
+      return;
+    }
     c.launch(KC_REDUCE_POT, [&] {
       hipLaunchKernelGGL((k_reduce_pot<R>), dim3(cdiv(M, 256)), dim3(256), 0, c.stream, c.dens_part,
                          c.nsg_used, int64_t(M), fp, c.lam, c.vext, c.rho, c.nu, c.U, c.delta, (R*)c.hA,
@@ -54,6 +121,10 @@ struct Engine3D final : Engine {
     });
   }
   void lap1(Ctx& c, const void* X, const double* scale, bool hpart, int64_t nst) override {
+    if (c.gen) {  // the whole H phi into T (the evaluation's lap2 is then pointwise)
+      gen_apply(c, X, scale, hpart ? c.h_part : nullptr, nullptr, nst);
+      return;
+    }
     dim3 grid(cdiv(NYZ, TB1), nst);
     c.launch(KC_LAP1, [&] {
       hipLaunchKernelGGL((k_lap1<R, NX, NYZ, TB1>), grid, dim3(TB1), 0, c.stream, (const cpx<R>*)X,
@@ -91,6 +162,32 @@ struct Engine3D final : Engine {
     A.h_stride = c.h_stride;
     A.dV = c.dV;
     dim3 grid(CFG::NGX, nst), block(CFG::TB);
+    if (c.gen) {  // T holds H phi (lap1): the integrator arithmetic only
+      switch (d.mode) {
+        case L2_H:
+          c.launch(KC_LAP2_H, [&] { hipLaunchKernelGGL((k_pw_gen<R, NX, NY, NZ, L2_H>), grid, block, 0, c.stream, A); });
+          break;
+        case L2_F:
+          c.launch(KC_LAP2_F, [&] { hipLaunchKernelGGL((k_pw_gen<R, NX, NY, NZ, L2_F>), grid, block, 0, c.stream, A); });
+          break;
+        case L2_CORR:
+          c.launch(KC_LAP2_CORR, [&] { hipLaunchKernelGGL((k_pw_gen<R, NX, NY, NZ, L2_CORR>), grid, block, 0, c.stream, A); });
+          break;
+        case L2_FULL:
+          c.launch(KC_LAP2_FULL, [&] {
+            if (c.np == 3)
+              hipLaunchKernelGGL((k_pw_gen<R, NX, NY, NZ, L2_FULL, 3, 4>), grid, block, 0, c.stream, A);
+            else if (c.np == 5)
+              hipLaunchKernelGGL((k_pw_gen<R, NX, NY, NZ, L2_FULL, 5, 5>), grid, block, 0, c.stream, A);
+            else
+              hipLaunchKernelGGL((k_pw_gen<R, NX, NY, NZ, L2_FULL, 4, 5>), grid, block, 0, c.stream, A);
+          });
+          break;
+        default:
+          c.launch(KC_LAP2_TAYLOR, [&] { hipLaunchKernelGGL((k_pw_gen<R, NX, NY, NZ, L2_TAYLOR>), grid, block, 0, c.stream, A); });
+      }
+      return;
+    }
     switch (d.mode) {
       case L2_H:
         c.launch(KC_LAP2_H, [&] { hipLaunchKernelGGL((k_lap2<R, NX, NY, NZ, L2_H>), grid, block, 0, c.stream, A); });

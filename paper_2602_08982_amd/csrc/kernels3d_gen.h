@@ -1,0 +1,363 @@
+// Device kernels of the general functional (A != 1; Sec. 2.3, Eq. h_sigma)
+// on the full 3D lattice.  The single-particle Hamiltonian carries an
+// inverse effective mass alpha(r) and a current potential A(r):
+//   h = -1/2 div(alpha grad) + hfield - (i/2) {A, grad},
+// the kinetic part in the symmetrised form of Eq. kinop-alpha,
+//   K x = -1/4 [lap(alpha x) + alpha lap x - x lap alpha],
+// the current part as the anticommutator of the matrix forms of Eqs. Ad_dx
+// and d_dxA, C x = -(i/2) sum_d [A_d D1_d x + D1_d(A_d x)] (D1 with the
+// Nyquist bin zeroed, D2 with the full k^2).  Rows: u -> K u + C u +
+// hfield u + Delta v;  v -> -K v + C v - hfield v + Delta^* u.
+//
+// Every derivative is taken along one axis at a time by a line pass (one
+// thread owns one line of one state and transforms it in registers):
+//   k_jline  - the current j_d of a group of states (field builds),
+//   k_opline - the d-part of K and C of every state into T; the last axis
+//              adds the local terms (T = H phi) and the partials of <H>_n,
+// and k_pw_gen does the integrator arithmetic from T = H phi pointwise.
+#pragma once
+
+#include "kernels3d.h"
+
+namespace tdslda {
+
+// lines along AXIS of an NX x NY x NZ lattice: line l enumerates (outer,
+// inner) with the axis between; site(l, k) = site0(l) + k STRIDE
+template <int NX, int NY, int NZ, int AXIS>
+struct LineGeo {
+  static constexpr int NL = AXIS == 0 ? NX : (AXIS == 1 ? NY : NZ);
+  static constexpr int STRIDE = AXIS == 0 ? NY * NZ : (AXIS == 1 ? NZ : 1);
+  static constexpr int NLINES = NX * NY * NZ / NL;
+  __device__ static int site0(int l) {
+    const int outer = l / STRIDE, in = l - outer * STRIDE;
+    return outer * STRIDE * NL + in;
+  }
+};
+
+// j_AXIS group partials over DG states of the normalised states:
+//   jpart[g][AXIS][site] = sum_n f_v Im(v (D1 v)^*) - f_u Im(u (D1 u)^*)
+// (a component of zero weight is skipped: f_u = 0 for E > 0 at T = 0).
+//   grid = (ceil(NLINES / TBG), number of groups), block = TBG
+template <typename R, int NX, int NY, int NZ, int AXIS, int TBG, int DG>
+__global__ __launch_bounds__(TBG) void k_jline(const cpx<R>* __restrict__ X, int64_t nstates,
+                                               const double* __restrict__ scale, const double* __restrict__ wu,
+                                               const double* __restrict__ wv, double kscale,
+                                               double* __restrict__ jpart) {
+  using LG = LineGeo<NX, NY, NZ, AXIS>;
+  constexpr int NL = LG::NL, ST = LG::STRIDE;
+  constexpr int64_t M = int64_t(NX) * NY * NZ;
+  constexpr int ES = sizeof(cpx<R>);
+  const int l = blockIdx.x * TBG + threadIdx.x;
+  if (l >= LG::NLINES) return;  // no barriers below
+  const int s0 = LG::site0(l);
+  const int64_t nbeg = int64_t(blockIdx.y) * DG;
+  const int nloc = int(nstates - nbeg < DG ? nstates - nbeg : DG);
+  double acc[NL];
+#pragma unroll
+  for (int k = 0; k < NL; ++k) acc[k] = 0.0;
+  for (int ls = 0; ls < nloc; ++ls) {
+    const int64_t n = nbeg + ls;
+    const R s = R(scale[n]);
+    const double fu = wu[n], fv = wv[n];
+    const bi32x4 rX = make_rsrc(X + n * 2 * M, uint32_t(2 * M * ES));
+#pragma unroll 1
+    for (int comp = 0; comp < 2; ++comp) {
+      const double w = comp ? fv : -fu;
+      if (w == 0.0) continue;
+      cpx<R> d[NL], ny;
+#pragma unroll
+      for (int k = 0; k < NL; ++k) d[k] = s * bload<R>(rX, s0 * ES, int(comp * M + k * ST) * ES);
+      first_derivative<NL>(d, R(kscale), ny);
+#pragma unroll
+      for (int k = 0; k < NL; ++k) {
+        const cpx<R> f = s * bload<R>(rX, s0 * ES, int(comp * M + k * ST) * ES);  // re-read (cached)
+        acc[k] += w * (double(f.y) * double(d[k].x) - double(f.x) * double(d[k].y));  // Im(f (D1 f)^*)
+      }
+    }
+  }
+  double* out = jpart + (int64_t(blockIdx.y) * 3 + AXIS) * M + s0;
+#pragma unroll
+  for (int k = 0; k < NL; ++k) out[k * ST] = acc[k];
+}
+
+// -(i/2) c
+template <typename R>
+__device__ __forceinline__ cpx<R> minus_half_i(cpx<R> c) {
+  return cpx<R>{R(0.5) * c.y, R(-0.5) * c.x};
+}
+
+// The AXIS part of K and C of every state, row-signed, into T (AXIS 0
+// writes, the others add); LAST also adds the local terms,
+//   u: + (1/4 lap alpha + hfield) u + Delta v,  v: - (1/4 lap alpha + hfield) v + Delta^* u,
+// so that the destination (out when given, else T) holds H phi, and when
+// h_part is given writes the block's partial of <H>_n = Re int phi^* H phi
+// dV into h slot h_off + blockIdx.x; block 0 clears the slots [0, h_off)
+// and [h_off + gridDim.x, h_off + n_slots).  phi = scale x X (scale NULL = 1).
+//   grid = (ceil(NLINES / TBG), nstates), block = TBG
+template <typename R, int NX, int NY, int NZ, int AXIS, int TBG, bool LAST>
+__global__ __launch_bounds__(TBG) void k_opline(const cpx<R>* __restrict__ X, const double* __restrict__ scale,
+                                                cpx<R>* __restrict__ T, cpx<R>* __restrict__ out,
+                                                const R* __restrict__ hAl, const R* __restrict__ hLa,
+                                                const R* __restrict__ hAd, const R* __restrict__ hA,
+                                                const cpx<R>* __restrict__ hD, double* __restrict__ h_part,
+                                                int h_stride, int h_off, int n_slots, double kscale, double dV) {
+  using LG = LineGeo<NX, NY, NZ, AXIS>;
+  constexpr int NL = LG::NL, ST = LG::STRIDE;
+  constexpr int64_t M = int64_t(NX) * NY * NZ;
+  constexpr int ES = sizeof(cpx<R>), RS = sizeof(R);
+  __shared__ double red[TBG / kWave];
+  const int l = blockIdx.x * TBG + threadIdx.x;
+  const bool act = l < LG::NLINES;
+  const int s0 = act ? LG::site0(l) : 0;
+  const int64_t n = blockIdx.y;
+  const R s = scale ? R(scale[n]) : R(1);
+  const uint32_t SB = uint32_t(2 * M * ES);
+  const bi32x4 rX = make_rsrc(X + n * 2 * M, SB);
+  const bi32x4 rT = make_rsrc(T + n * 2 * M, SB);
+  cpx<R>* dst = (LAST && out) ? out : T;
+  const bi32x4 rO = make_rsrc(dst + n * 2 * M, SB);
+  const bi32x4 rAl = make_rsrc(hAl, uint32_t(M * RS)), rAd = make_rsrc(hAd, uint32_t(M * RS));
+  const int vo = s0 * ES, va = s0 * RS;
+  const R kk = R(kscale), inv_n = R(1.0 / NL);
+  double hloc = 0.0;
+  if (act) {
+#pragma unroll 1
+    for (int comp = 0; comp < 2; ++comp) {
+      const R sg = comp ? R(-1) : R(1);
+      const int cb = int(comp * M);
+      cpx<R> t[NL], d1[NL], res[NL];
+      // D2 x and D1 x from one forward transform
+#pragma unroll
+      for (int k = 0; k < NL; ++k) t[k] = s * bload<R>(rX, vo, (cb + k * ST) * ES);
+      fwd<NL>(t);
+      sfor<0, NL>::run([&](auto pc) {
+        constexpr int p = decltype(pc)::value;
+        constexpr int fq = freq_of_pos<NL>(p);
+        constexpr int m = wavenum<NL>(fq);
+        const cpx<R> y = inv_n * t[p];
+        const R km = kk * R(m);
+        d1[p] = fq == NL / 2 ? cpx<R>{R(0), R(0)} : km * mul_i(y);
+        t[p] = (-km * km) * y;
+      });
+      inv<NL>(t);
+      inv<NL>(d1);
+#pragma unroll
+      for (int k = 0; k < NL; ++k) {
+        const R al = bload_real<R>(rAl, va, k * ST * RS), ad = bload_real<R>(rAd, va, k * ST * RS);
+        res[k] = (sg * R(-0.25) * al) * t[k] + minus_half_i(ad * d1[k]);
+        t[k] = al * (s * bload<R>(rX, vo, (cb + k * ST) * ES));
+      }
+      // D2(alpha x)
+      fwd<NL>(t);
+      sfor<0, NL>::run([&](auto pc) {
+        constexpr int p = decltype(pc)::value;
+        constexpr int m = wavenum_at<NL>(p);
+        const R km = kk * R(m);
+        t[p] = (-km * km * inv_n) * t[p];
+      });
+      inv<NL>(t);
+#pragma unroll
+      for (int k = 0; k < NL; ++k) {
+        res[k] = res[k] + (sg * R(-0.25)) * t[k];
+        t[k] = bload_real<R>(rAd, va, k * ST * RS) * (s * bload<R>(rX, vo, (cb + k * ST) * ES));
+      }
+      // D1(A_d x)
+      cpx<R> nyq;
+      first_derivative<NL>(t, kk, nyq);
+#pragma unroll
+      for (int k = 0; k < NL; ++k) {
+        cpx<R> r = res[k] + minus_half_i(t[k]);
+        const int o = (cb + k * ST) * ES;
+        if constexpr (AXIS > 0) r = r + bload<R>(rT, vo, o);
+        if constexpr (LAST) {
+          const int site = s0 + k * ST;
+          const cpx<R> x = s * bload<R>(rX, vo, o);
+          const cpx<R> y = s * bload<R>(rX, vo, (int((1 - comp) * M) + k * ST) * ES);
+          const cpx<R> D = hD[site];
+          const cpx<R> Dc = comp ? conj(D) : D;
+          r = r + (sg * (R(0.25) * hLa[site] + hA[site])) * x + Dc * y;
+          hloc += double(x.x) * double(r.x) + double(x.y) * double(r.y);
+        }
+        bstore<R>(r, rO, vo, o);
+      }
+    }
+  }
+  if constexpr (LAST) {
+    if (h_part) {
+      double v = wave_sum(hloc);
+      if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = v;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < TBG / kWave; ++w) t += red[w];
+        double* hp = h_part + n * h_stride;
+        hp[h_off + blockIdx.x] = t * dV;
+        if (blockIdx.x == 0) {
+          for (int i = 0; i < h_off; ++i) hp[i] = 0.0;
+          for (int i = int(gridDim.x); i < n_slots; ++i) hp[h_off + i] = 0.0;
+        }
+      }
+    }
+  }
+}
+
+// The integrator arithmetic from T = H phi (built by k_opline), pointwise
+// over the slab tiling of k_pointwise; phi = scale x X, h = hshift[n]:
+//   H: out = T;  F: out = -i (T - h phi);  TAYLOR: out = c (T - h phi), acc
+//   += out;  CORR: phi_new = c + dt a_0 f;  FULL: f_k, next predictor p
+//   (over the input), partial corrector c; norm partials of the written
+//   state per slab group (as k_lap2).
+//   grid = (NGX, nstates), block = TB
+template <typename R, int NX, int NY, int NZ, int MODE, int NP = 4, int NQ = 5>
+__global__ __launch_bounds__((SlabCfg<NX, NY, NZ>::TB)) void k_pw_gen(Lap2Args<R> A) {
+  using CFG = SlabCfg<NX, NY, NZ>;
+  constexpr int TB = CFG::TB, P = CFG::P, SS = CFG::SS;
+  constexpr int M = NX * NY * NZ;
+  constexpr int HD = (NP > NQ - 1) ? NP : NQ - 1;
+  __shared__ double red[TB / kWave];
+  const int g = blockIdx.x, tid = threadIdx.x;
+  const int64_t n = blockIdx.y;
+  constexpr int ES = sizeof(cpx<R>);
+  const int64_t so = n * 2 * M;
+  const uint32_t SB = 2 * M * ES;
+  const R s = A.scale ? R(A.scale[n]) : R(1);
+  const R h = A.hshift ? R(A.hshift[n]) : R(0);
+  const bi32x4 rX = make_rsrc(A.X + so, SB);
+  const bi32x4 rT = make_rsrc(A.T + so, SB);
+  bi32x4 rO{}, rXo{}, rC{}, rAcc{}, rH[HD] = {};
+  if constexpr (MODE != L2_CORR) rO = make_rsrc(A.out + so, SB);
+  if constexpr (MODE == L2_CORR || MODE == L2_FULL) rXo = make_rsrc(A.Xout + so, SB);
+  if constexpr (MODE == L2_TAYLOR) rAcc = make_rsrc(A.acc + so, SB);
+  if constexpr (MODE == L2_CORR) rH[0] = make_rsrc(A.hist[0] + so, SB);
+  if constexpr (MODE == L2_FULL) {
+    rC = make_rsrc(A.cout + so, SB);
+    sfor<1, HD>::run([&](auto jc) {
+      constexpr int j = decltype(jc)::value;
+      rH[j] = make_rsrc(A.hist[j] + so, SB);
+    });
+  }
+  const int vt = tid * ES;
+  double nacc = 0.0;
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    const int p = tid + i * TB;
+    if (p < SS) {
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const int o = int(int64_t(g) * SS + i * TB + c * M) * ES;
+        const cpx<R> hx = bload<R>(rT, vt, o);
+        if constexpr (MODE == L2_H) {
+          bstore<R>(hx, rO, vt, o);
+        } else {
+          const cpx<R> x = s * bload<R>(rX, vt, o);
+          const cpx<R> gg = hx - h * x;
+          if constexpr (MODE == L2_TAYLOR) {
+            const cpx<R> cf{R(A.tay_re), R(A.tay_im)};
+            const cpx<R> ov = cf * gg;
+            const cpx<R> sm = A.init_acc ? x + ov : bload<R>(rAcc, vt, o) + ov;
+            bstore<R>(ov, rO, vt, o);
+            bstore<R>(sm, rAcc, vt, o);
+            nacc += norm2(sm);
+          } else {
+            const cpx<R> f{gg.y, -gg.x};  // -i g
+            if constexpr (MODE == L2_F) {
+              bstore<R>(f, rO, vt, o);
+            } else if constexpr (MODE == L2_CORR) {
+              const cpx<R> nw = bload<R>(rH[0], vt, o) + R(A.a[0]) * f;
+              bstore<R>(nw, rXo, vt, o);
+              nacc += norm2(nw);
+            } else {  // L2_FULL
+              cpx<R> pp = x + R(A.b[0]) * f, cc = x + R(A.a[1]) * f;
+              sfor<1, HD>::run([&](auto jc) {
+                constexpr int j = decltype(jc)::value;
+                const cpx<R> hj = bload<R>(rH[j], vt, o);
+                if constexpr (j < NP) pp = pp + R(A.b[j]) * hj;
+                if constexpr (j + 1 < NQ) cc = cc + R(A.a[j + 1]) * hj;
+              });
+              bstore<R>(f, rO, vt, o);
+              bstore<R>(pp, rXo, vt, o);
+              bstore<R>(cc, rC, vt, o);
+              nacc += norm2(pp);
+            }
+          }
+        }
+      }
+    }
+  }
+  if (A.nrm_part && MODE != L2_H && MODE != L2_F) {
+    const double t = block_sum<TB>(nacc, red);
+    if (tid == 0) A.nrm_part[n * A.nrm_stride + g] = t;
+  }
+}
+
+// Sums of the density and current group partials (fixed order, one thread
+// per site) and the potentials of the SLDA functional at A != 1
+// (spin-symmetric, per spin): Delta = -g_eff nu, U = B eF - |Delta|^2 /
+// (3 C rho_+^(2/3)) - (1 - A) |j|^2 / (2 rho^2), A_vec = (1 - A) j / rho.
+template <typename R>
+__global__ __launch_bounds__(256) void k_reduce_gen3d(
+    const double* __restrict__ dens_part, const double* __restrict__ jpart, int ngroups, int64_t M,
+    FunParams fp, double Aconst, const double* __restrict__ lam, const double* __restrict__ vext,
+    double* __restrict__ rho, double* __restrict__ nu, double* __restrict__ jc, double* __restrict__ U,
+    double* __restrict__ delta, R* __restrict__ hA, cpx<R>* __restrict__ hD, R* __restrict__ hAx,
+    R* __restrict__ hAy, R* __restrict__ hAz, int update_fields) {
+  const int64_t r = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (r >= M) return;
+  double sr = 0.0, snr = 0.0, sni = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+  for (int g = 0; g < ngroups; ++g) {
+    const double* p = dens_part + int64_t(g) * 3 * M;
+    const double* q = jpart + int64_t(g) * 3 * M;
+    sr += p[r];
+    snr += p[M + r];
+    sni += p[2 * M + r];
+    jx += q[r];
+    jy += q[M + r];
+    jz += q[2 * M + r];
+  }
+  sr *= fp.ainv, snr *= fp.ainv, sni *= fp.ainv, jx *= fp.ainv, jy *= fp.ainv, jz *= fp.ainv;
+  rho[r] = sr;
+  nu[2 * r] = snr;
+  nu[2 * r + 1] = sni;
+  jc[r] = jx;
+  jc[M + r] = jy;
+  jc[2 * M + r] = jz;
+  if (!update_fields) return;
+  const double rp = fmax(2.0 * sr, 1e-14);
+  const double gg = 1.0 / (cbrt(rp) / fp.C - lam[r]);
+  const double dr = -gg * snr, di = -gg * sni;
+  const double ef = 0.5 * pow(3.0 * kPi * kPi * (2.0 * sr), 2.0 / 3.0);
+  const double c23 = cbrt(rp);
+  const double rs = fmax(sr, 0.5e-14), cA = 1.0 - Aconst;
+  const double jsq = jx * jx + jy * jy + jz * jz;
+  const double u = fp.B * ef - (dr * dr + di * di) / (3.0 * fp.C * c23 * c23) - cA * jsq / (2.0 * rs * rs);
+  U[r] = u;
+  delta[2 * r] = dr;
+  delta[2 * r + 1] = di;
+  hA[r] = R(u + vext[r] - fp.mu);
+  hD[r] = cpx<R>{R(dr + fp.dext[2 * r]), R(di + fp.dext[2 * r + 1])};
+  hAx[r] = R(cA * jx / rs);
+  hAy[r] = R(cA * jy / rs);
+  hAz[r] = R(cA * jz / rs);
+}
+
+// lap f of a real field by the D2 circulants of the three axes (Eq. D2 in
+// real space; c2x[m] = (D2_x)_{i, i-m}), and f converted to the context
+// precision: one thread per site
+template <typename R>
+__global__ void k_field_lap3d(int nx, int ny, int nz, const double* __restrict__ f, const double* __restrict__ c2x,
+                              const double* __restrict__ c2y, const double* __restrict__ c2z, R* __restrict__ fout,
+                              R* __restrict__ lap) {
+  const int64_t M = int64_t(nx) * ny * nz;
+  const int64_t r = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (r >= M) return;
+  const int x = int(r / (int64_t(ny) * nz)), rem = int(r - int64_t(x) * ny * nz), y = rem / nz, z = rem - y * nz;
+  double acc = 0.0;
+  for (int q = 0; q < nx; ++q) acc += c2x[((x - q) % nx + nx) % nx] * f[(int64_t(q) * ny + y) * nz + z];
+  for (int q = 0; q < ny; ++q) acc += c2y[((y - q) % ny + ny) % ny] * f[(int64_t(x) * ny + q) * nz + z];
+  for (int q = 0; q < nz; ++q) acc += c2z[((z - q) % nz + nz) % nz] * f[(int64_t(x) * ny + y) * nz + q];
+  lap[r] = R(acc);
+  fout[r] = R(f[r]);
+}
+
+}  // namespace tdslda

@@ -26,6 +26,11 @@
 
 #include "ctx.h"
 #include "kernels_host.h"
+#include "kernels3d_gen.h"
+
+namespace tdslda {
+std::vector<double> spectral_d2_circulant(int N, double dz);  // q1dstatic.hip
+}
 
 namespace {
 
@@ -75,7 +80,7 @@ int64_t memory_bytes(const tdslda_lattice& lat, const tdslda_run& run, int64_t n
   int64_t b = (depth + 2) * n * S;                               // state buffers + T
   b += n * 8 * (4 + (depth + 1) + 1);                            // per-state arrays
   b += n * 8 * (eng->ngx() + eng->ngx() + eng->ncb());           // partial slots
-  b += int64_t(cdiv(n, eng->group())) * 3 * M * 8;              // density partials
+  b += int64_t(cdiv(n, eng->group())) * 3 * M * 8 * (lat.mode == TDSLDA_MODE_3D ? 2 : 1);  // density (+ current) partials
   b += M * 8 * 16 + M * (es / 2 + es);                          // fields
   b += gchunk * 4 * M * 8;                                      // gradient scratch
   (void)run;
@@ -373,7 +378,8 @@ void reset_current_fields(Ctx& c) {
       hipLaunchKernelGGL((k_fill_real<float>), dim3(cdiv(c.M, 256)), dim3(256), 0, c.stream, c.M, a, (float*)c.hAl);
   });
   HIPCHK(hipMemsetAsync(c.hLa, 0, c.M * c.esz / 2, c.stream));
-  HIPCHK(hipMemsetAsync(c.hAz, 0, c.M * c.esz / 2, c.stream));
+  for (void* p : {c.hAx, c.hAy, c.hAz})
+    if (p) HIPCHK(hipMemsetAsync(p, 0, c.M * c.esz / 2, c.stream));
   c.gen = a != 1.0;
 }
 
@@ -498,9 +504,6 @@ tdslda_status tdslda_create(const tdslda_lattice* lat, const tdslda_functional* 
             "unknown precision");
     require(fun->functional == TDSLDA_FUNC_SLDA || fun->functional == TDSLDA_FUNC_BDG, TDSLDA_EINVAL,
             "unknown functional");
-    require(fun->functional != TDSLDA_FUNC_SLDA || std::fabs(fun->A - 1.0) < 1e-15 ||
-                lat->mode == TDSLDA_MODE_Q1D,
-            TDSLDA_EINVAL, "A_sigma != 1 (the general functional) is built for the quasi-1D kernel set only");
     require(fun->functional != TDSLDA_FUNC_SLDA || (std::isfinite(fun->A) && fun->A > 0), TDSLDA_EINVAL,
             "A must be positive");
     require(std::isfinite(run->dt) && run->dt != 0.0, TDSLDA_EINVAL, "dt must be finite and non-zero");
@@ -560,6 +563,11 @@ tdslda_status tdslda_create(const tdslda_lattice* lat, const tdslda_functional* 
     c->hAl = c->dalloc(M * c->esz / 2);
     c->hLa = c->dalloc(M * c->esz / 2);
     c->hAz = c->dalloc(M * c->esz / 2);
+    if (!c->q1d) {
+      c->hAx = c->dalloc(M * c->esz / 2);
+      c->hAy = c->dalloc(M * c->esz / 2);
+      c->jpart = (double*)c->dalloc(size_t(c->nsg_max) * 3 * M * 8);
+    }
     reset_current_fields(*c);
     HIPCHK(hipMemsetAsync(c->vext, 0, 8 * M, c->stream));
     HIPCHK(hipMemsetAsync(c->lam, 0, 8 * M, c->stream));
@@ -807,21 +815,63 @@ tdslda_status tdslda_apply_hbdg(tdslda_ctx* c, const void* in_dev, void* out_dev
   });
 }
 
-tdslda_status tdslda_set_current_fields(tdslda_ctx* c, const double* alpha, const double* az) {
+tdslda_status tdslda_set_current_fields(tdslda_ctx* c, const double* alpha, const double* avec) {
+  const double* az = avec;
   return guard(c, [&] {
-    require(c->q1d, TDSLDA_EINVAL, "the general operator is built for the quasi-1D kernel set");
     if (!alpha && !az) {
       reset_current_fields(*c);
       HIPCHK(hipStreamSynchronize(c->stream));
       return;
     }
     require(c->frozen, TDSLDA_EORDER, "freeze the fields (tdslda_set_fields) first");
-    for (int64_t i = 0; i < c->M; ++i) {
+    const int ncomp = c->q1d ? 1 : 3;  // quasi-1D: A_z only; 3D: A_x, A_y, A_z
+    for (int64_t i = 0; i < c->M; ++i)
       require(!alpha || (std::isfinite(alpha[i]) && alpha[i] > 0.0), TDSLDA_EINVAL, "alpha must be finite, > 0");
-      require(!az || std::isfinite(az[i]), TDSLDA_EINVAL, "A_z must be finite");
-    }
+    for (int64_t i = 0; az && i < ncomp * c->M; ++i) require(std::isfinite(az[i]), TDSLDA_EINVAL, "A must be finite");
     reset_current_fields(*c);
-    // staging in the gradient scratch (>= 2 M doubles): alpha, A_z
+    if (!c->q1d) {
+      // staging in the gradient scratch (>= 4 M doubles): alpha, then each A_d
+      const auto cx = spectral_d2_circulant(c->lat.nx, c->lat.dx), cy = spectral_d2_circulant(c->lat.ny, c->lat.dy),
+                 cz = spectral_d2_circulant(c->lat.nz, c->lat.dz);
+      if (alpha) {
+        double* st = c->gscratch;
+        double* cc = st + c->M;  // circulants after the field
+        HIPCHK(hipMemcpyAsync(st, alpha, 8 * c->M, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(hipMemcpyAsync(cc, cx.data(), 8 * cx.size(), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(hipMemcpyAsync(cc + cx.size(), cy.data(), 8 * cy.size(), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(hipMemcpyAsync(cc + cx.size() + cy.size(), cz.data(), 8 * cz.size(), hipMemcpyHostToDevice, c->stream));
+        c->launch(KC_SETUP, [&] {
+          if (c->esz == 16)
+            hipLaunchKernelGGL((k_field_lap3d<double>), dim3(cdiv(c->M, 256)), dim3(256), 0, c->stream, c->lat.nx,
+                               c->lat.ny, c->lat.nz, st, cc, cc + cx.size(), cc + cx.size() + cy.size(),
+                               (double*)c->hAl, (double*)c->hLa);
+          else
+            hipLaunchKernelGGL((k_field_lap3d<float>), dim3(cdiv(c->M, 256)), dim3(256), 0, c->stream, c->lat.nx,
+                               c->lat.ny, c->lat.nz, st, cc, cc + cx.size(), cc + cx.size() + cy.size(),
+                               (float*)c->hAl, (float*)c->hLa);
+        });
+        HIPCHK(hipStreamSynchronize(c->stream));
+      }
+      if (az) {
+        void* dst[3] = {c->hAx, c->hAy, c->hAz};
+        for (int d = 0; d < 3; ++d) {
+          HIPCHK(hipMemcpyAsync(c->gscratch, az + d * c->M, 8 * c->M, hipMemcpyHostToDevice, c->stream));
+          c->launch(KC_SETUP, [&] {
+            if (c->esz == 16)
+              hipLaunchKernelGGL((k_convert_real<double>), dim3(cdiv(c->M, 256)), dim3(256), 0, c->stream, c->M,
+                                 c->gscratch, (double*)dst[d]);
+            else
+              hipLaunchKernelGGL((k_convert_real<float>), dim3(cdiv(c->M, 256)), dim3(256), 0, c->stream, c->M,
+                                 c->gscratch, (float*)dst[d]);
+          });
+          HIPCHK(hipStreamSynchronize(c->stream));
+        }
+      }
+      c->gen = true;
+      HIPCHK(hipStreamSynchronize(c->stream));
+      return;
+    }
+    // quasi-1D: staging in the gradient scratch (>= 2 M doubles): alpha, A_z
     if (alpha) {
       HIPCHK(hipMemcpyAsync(c->gscratch, alpha, 8 * c->M, hipMemcpyHostToDevice, c->stream));
       c->launch(KC_SETUP, [&] {

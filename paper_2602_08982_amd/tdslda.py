@@ -261,11 +261,12 @@ class Context:
         d = _c128_as_f64(np.asarray(delta).ravel())
         self._chk(self.lib.tdslda_set_fields(self.h, _p(u), _p(d)))
 
-    def set_current_fields(self, alpha=None, az=None):
-        """tdslda_set_current_fields: linear-mode alpha(z) and A_z(z) of the
-        general operator (None keeps the functional's value)."""
+    def set_current_fields(self, alpha=None, avec=None):
+        """tdslda_set_current_fields: linear-mode alpha(r) and current
+        potential of the general operator (3D: avec = (A_x, A_y, A_z) fields;
+        quasi-1D: avec = A_z(z)); None keeps the functional's value."""
         a = None if alpha is None else _f64(alpha).ravel()
-        z = None if az is None else _f64(az).ravel()
+        z = None if avec is None else _f64(avec).ravel()
         self._chk(self.lib.tdslda_set_current_fields(self.h, _p(a), _p(z)))
 
     # --- evaluation ---------------------------------------------------------

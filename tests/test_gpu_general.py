@@ -145,7 +145,3 @@ def test_general_td_selfconsistent(prec):
         ctx.close()
 
 
-def test_general_functional_rejected_in_3d():
-    from paper_2602_08982_amd import tdslda as T
-    with pytest.raises(T.TdsldaError):
-        T.Context(T.lattice_3d(8), T.functional_slda(1.0, 10.0, A=1.094), T.run_config(), 4)
