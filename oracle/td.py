@@ -20,6 +20,7 @@ from math import factorial
 from . import bdg
 from . import densities as D
 from . import functional as F
+from . import lattice as L
 
 # Adams-Bashforth predictors (Eqs. AB3, AB4, AB5): weights of f_{k-1}, f_{k-2}, ...
 AB = {
@@ -62,6 +63,29 @@ class Geometry3D:
     def rho_nu_j(self, phi, wu, wv):
         rho, _, nu, j = D.spin_symmetric(phi, wu, wv, self.lat)
         return rho, nu, j
+
+    def friction_sources(self, phi, wu, wv):
+        """What the dissipative fields of the quantum-friction evolution need
+        (Sec. 5.2, correcting the initial state by a time-dependent approach)
+        on the full 3D lattice:
+          div j = sum_d D1_d j_d (D1 with the Nyquist mode zeroed, as j itself),
+          B'    = -1/2 sum_n (f_v - f_u) [u lap v^* + v^* lap u]
+                  (lap = the full spectral Laplacian of Eq. D2; the weights of nu),
+          N     = int rho_+ d^3r.
+        Returns (div_j, B', N)."""
+        lat = self.lat
+        rho, _, _, j = D.spin_symmetric(phi, wu, wv, lat)
+        div_j = np.zeros(lat.shape)
+        for d in range(3):
+            div_j += np.real(L.spectral_derivative(j[d], lat.k[d], d, 1))
+        w = (np.asarray(wv, float) - np.asarray(wu, float)).reshape(-1, 1, 1, 1)
+        Bp = np.zeros(lat.shape, complex)
+        for s in range(0, phi.shape[0], D.CHUNK):
+            u, v = phi[s:s + D.CHUNK, 0], phi[s:s + D.CHUNK, 1]
+            lu, lv = L.laplacian(u, lat), L.laplacian(v, lat)
+            Bp += -0.5 * np.sum(w[s:s + D.CHUNK] * (u * np.conj(lv) + np.conj(v) * lu), axis=0)
+        N = self.dV_energy * np.sum(2.0 * rho)
+        return div_j, Bp, N
 
     def full_densities(self, phi, wu, wv):
         return D.spin_symmetric(phi, wu, wv, self.lat)
