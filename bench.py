@@ -73,7 +73,7 @@ def step_roofline(S):
     return PEAK_HBM / (12.0 * S)
 
 
-def run_workload(cfg, steps, warmup, seed_vortex, profile=True, precision=None, observe=False):
+def run_workload(cfg, steps, warmup, seed_vortex, profile=True, precision=None, observe=False, A=1.0):
     import torch
     from paper_2602_08982_amd import tdslda as T
     from paper_2602_08982_amd import workloads as W
@@ -86,7 +86,7 @@ def run_workload(cfg, steps, warmup, seed_vortex, profile=True, precision=None, 
         (x1, y1), (x2, y2) = synth.vortex_pair(seed_vortex)
         vort = [(x1, y1, 1.0), (x2, y2, -1.0)]
     stream = torch.cuda.current_stream().cuda_stream
-    ctx, kidx = W.setup(cfg, vort, stream=stream, precision=precision)
+    ctx, kidx = W.setup(cfg, vort, stream=stream, precision=precision, A=A)
     nst = len(kidx)
     t0 = time.time()
     ctx.abm_step(warmup)          # includes the Taylor start-up
@@ -360,6 +360,10 @@ def main():
                     help="steps of the batched quasi-1D run (one graph launch)")
     ap.add_argument("--q1d-fp64-steps", type=int, default=500,
                     help="steps of the FP64 run of the batched quasi-1D workload (one graph launch; 0 = skip)")
+    ap.add_argument("--general-steps", type=int, default=None,
+                    help="steps of the FP64 32^3 workload evolved with the general functional A = 1.094, after "
+                         "the same warm-up (default: --steps, so that its cost compares with the A = 1 step; "
+                         "0 = skip)")
     ap.add_argument("--q1d-eager", action="store_true",
                     help="run the batched quasi-1D steps eagerly (tdslda_abm_step) instead of one graph launch")
     ap.add_argument("--q1d-general-steps", type=int, default=500,
@@ -405,6 +409,13 @@ def main():
     plain["steps"] = args.steps
     print(f"# plain fp64 32^3: {plain['value']:.4g} state-steps/s, {plain['ms_per_step']:.2f} ms/step",
           file=sys.stderr, flush=True)
+    plaingen = None
+    gsteps = args.steps if args.general_steps is None else args.general_steps
+    if gsteps > 0:
+        plaingen = run_workload(W.PLAIN, gsteps, args.warmup, args.seed, A=1.094)
+        plaingen["steps"] = gsteps
+        print(f"# plain fp64 32^3, general functional A = 1.094: {plaingen['value']:.4g} state-steps/s, "
+              f"{plaingen['ms_per_step']:.2f} ms/step", file=sys.stderr, flush=True)
     mixed = None
     if not args.no_mixed:
         msteps = args.mixed_steps or args.steps
@@ -504,6 +515,20 @@ def main():
         "kernels": plain["kernels"],
         "check": plain["check"],
     }
+    if plaingen is not None:
+        pk = plaingen["kernels"]
+        line["general_functional_3d"] = {
+            "workload": "the FP64 32^3 workload (same start) evolved with the general functional A = 1.094 "
+                        "(alpha = A, current potential (1 - A) j / rho; Eq. h_sigma with Eq. kinop-alpha: line "
+                        "passes per axis, 7 transforms per component and axis)",
+            "value": plaingen["value"], "unit": "state-steps/s", "ms_per_step": plaingen["ms_per_step"],
+            "steps": plaingen["steps"],
+            "cost_vs_A1": plaingen["ms_per_step"] / plain["ms_per_step"],
+            "cost_vs_A1_note": "same steps and warm-up as the A = 1 run (one predictor pass and one closing F-only "
+                               "evaluation per call in both)",
+            "kernels": {k: dict(launches=v["launches"], avg_ms=v["avg_ms"]) for k, v in pk.items()},
+            "check": plaingen["check"],
+        }
     if mixed is not None:
         line["fp32_mixed"] = {
             "workload": "FP32-mixed 48^3 elongated trap, vortex pair, 8192 lowest-|E| states",

@@ -194,18 +194,20 @@ tdslda_status tdslda_get_fields(tdslda_ctx* ctx, double* U, double* delta_reim);
 tdslda_status tdslda_apply_hbdg(tdslda_ctx* ctx, const void* in_dev, void* out_dev, int64_t n);
 
 /* Quantum friction (Sec. 5.2, correcting the initial state by a
- * time-dependent approach): from the next field build on, the evolution
- * adds the dissipative fields
- *   U_diss     = -(alpha / rho0) d_z j_z,
+ * time-dependent approach; Eqs. cooling_alpha, Deltadiss2): from the next
+ * field build on, the evolution adds the dissipative fields
+ *   U_diss     = -(alpha / rho0) div j,
  *   Delta_diss = Delta [beta sin(theta_nu - theta_B') + i gamma (N - N_req) / N_req],
  * theta_nu = arg nu, theta_B' = arg B', B' = -1/2 sum_n (f_v - f_u)
- * [u lap v^* + v^* lap u] (lap = D2z - k_perp^2, normalised states,
- * 1/(L_x L_y)), j_z with D1z (Nyquist zeroed), N = int rho_+ d^3r.  The
- * gamma term is off when N_req <= 0; all of alpha, beta and the gamma term
- * zero switch friction off.  Each field build then takes one more pass over
- * the states (the derivatives by four-step DFTs).  Quasi-1D contexts only;
- * not stored by tdslda_save.  Errors: EINVAL (3D context, non-finite
- * parameters, rho0 <= 0), ENOMEM. */
+ * [u lap v^* + v^* lap u] on the normalised states, N = int rho_+ d^3r.
+ * 3D: lap the full Laplacian (Eq. D2), div j = sum_d D1_d j_d (D1 with the
+ * Nyquist mode zeroed, as j); one line pass per axis for j and for B' over
+ * the states, then line passes over the current field.  Quasi-1D: lap =
+ * D2z - k_perp^2 and div j = D1z j_z, with 1/(L_x L_y); one pass over the
+ * states (four-step DFTs).  The gamma term is off when N_req <= 0; all of
+ * alpha, beta and the gamma term zero switch friction off.  Not with the
+ * general (A != 1) operator; not stored by tdslda_save.  Errors: EINVAL
+ * (general operator, non-finite parameters, rho0 <= 0), ENOMEM. */
 tdslda_status tdslda_set_friction(tdslda_ctx* ctx, double alpha, double beta, double gamma, double rho0,
                                   double N_req);
 

@@ -130,7 +130,7 @@ struct tdslda_ctx {
   double *nrm_part = nullptr, *h_part = nullptr, *hshift = nullptr;
   int nrm_stride = 1, h_stride = 1;
   double* dens_part = nullptr;
-  int nsg_max = 1, nsg_used = 1;
+  int nsg_max = 1, nsg_used = 1, njg_used = 1;
   double *rho = nullptr, *nu = nullptr, *tau = nullptr, *jc = nullptr;
   double *U = nullptr, *delta = nullptr, *vext = nullptr, *lam = nullptr, *theta = nullptr;
   double* dext = nullptr;  // external pairing potential [M][2] (zero unless set)
@@ -154,6 +154,7 @@ struct tdslda_ctx {
   bool fric = false;
   double f_alpha = 0, f_beta = 0, f_gamma = 0, f_rho0 = 1, f_Nreq = 0;
   double *fric_part = nullptr, *fric_j = nullptr, *fric_bp = nullptr;
+  double *fric_div = nullptr, *fric_N = nullptr;  // 3D: div j [M], N
 
   // integrator state
   bool kin_ready[6] = {false, false, false, false, false, false};  // h slots hold this buffer's partials

@@ -15,6 +15,7 @@ struct Engine3D final : Engine {
   static constexpr int G = 32;     // states per density group
   static constexpr int TB1 = 64;   // lap1 block
   static constexpr int GTB = 64;   // line passes of the general functional
+  static constexpr int JG = sizeof(R) == 8 ? 256 : 128;  // states per group of the current / B' line passes
   static constexpr int M = NX * NY * NZ;
   static constexpr int NYZ = NY * NZ;
   int ngx() const override { return CFG::NGX; }
@@ -34,20 +35,26 @@ struct Engine3D final : Engine {
       hipLaunchKernelGGL((k_dens_sum<R, DG>), dim3(cdiv(M, DS_TB * DS_P), ng), dim3(DS_TB), 0, c.stream,
                          (const cpx<R>*)X, nst, int64_t(M), c.wu, c.wv, scale, c.dens_part);
     });
+    jlines(c, X, scale, nst);
+    c.nsg_used = int(ng);
+  }
+  // the current's group partials (groups of JG states) into c.jpart
+  void jlines(Ctx& c, const void* X, const double* scale, int64_t nst) {
+    const unsigned jg = cdiv(nst, JG);
     const cpx<R>* x = (const cpx<R>*)X;
     c.launch(KC_DENS, [&] {
-      hipLaunchKernelGGL((k_jline<R, NX, NY, NZ, 0, GTB, DG>), dim3(cdiv(NYZ, GTB), ng), dim3(GTB), 0, c.stream, x,
+      hipLaunchKernelGGL((k_jline<R, NX, NY, NZ, 0, GTB, JG>), dim3(cdiv(NYZ, GTB), jg), dim3(GTB), 0, c.stream, x,
                          nst, scale, c.wu, c.wv, 2 * kPi / (NX * c.lat.dx), c.jpart);
     });
     c.launch(KC_DENS, [&] {
-      hipLaunchKernelGGL((k_jline<R, NX, NY, NZ, 1, GTB, DG>), dim3(cdiv(NX * NZ, GTB), ng), dim3(GTB), 0, c.stream,
+      hipLaunchKernelGGL((k_jline<R, NX, NY, NZ, 1, GTB, JG>), dim3(cdiv(NX * NZ, GTB), jg), dim3(GTB), 0, c.stream,
                          x, nst, scale, c.wu, c.wv, 2 * kPi / (NY * c.lat.dy), c.jpart);
     });
     c.launch(KC_DENS, [&] {
-      hipLaunchKernelGGL((k_jline<R, NX, NY, NZ, 2, GTB, DG>), dim3(cdiv(NX * NY, GTB), ng), dim3(GTB), 0, c.stream,
+      hipLaunchKernelGGL((k_jline<R, NX, NY, NZ, 2, GTB, JG>), dim3(cdiv(NX * NY, GTB), jg), dim3(GTB), 0, c.stream,
                          x, nst, scale, c.wu, c.wv, 2 * kPi / (NZ * c.lat.dz), c.jpart);
     });
-    c.nsg_used = int(ng);
+    c.njg_used = int(jg);
   }
   // general functional: H phi of every state into T (or out) by three line
   // passes; with hp the <H>_n partials go to the h slots after the NGX raw
@@ -72,6 +79,34 @@ struct Engine3D final : Engine {
       hipLaunchKernelGGL((k_opline<R, NX, NY, NZ, 2, GTB, true>), dim3(cdiv(NX * NY, GTB), nst), dim3(GTB), 0,
                          c.stream, x, scale, T, (cpx<R>*)out, al, la, (const R*)c.hAz, hA, hD, hp, c.h_stride,
                          CFG::NGX, ncb(), 2 * kPi / (NZ * c.lat.dz), c.dV);
+    });
+  }
+  // quantum friction: j and B' by line passes over state groups, div j by
+  // line passes over the current field, N, then the dissipative fields
+  void friction(Ctx& c, const void* X, const double* scale, int64_t nst) override {
+    const unsigned ng = cdiv(nst, JG);
+    const cpx<R>* x = (const cpx<R>*)X;
+    const double kx = 2 * kPi / (NX * c.lat.dx), ky = 2 * kPi / (NY * c.lat.dy), kz = 2 * kPi / (NZ * c.lat.dz);
+    jlines(c, X, scale, nst);
+    c.launch(KC_FRICTION, [&] {
+      hipLaunchKernelGGL((k_bpline<R, NX, NY, NZ, 0, GTB, JG>), dim3(cdiv(NYZ, GTB), ng), dim3(GTB), 0, c.stream, x,
+                         nst, scale, c.wu, c.wv, kx * kx, c.fric_part);
+      hipLaunchKernelGGL((k_bpline<R, NX, NY, NZ, 1, GTB, JG>), dim3(cdiv(NX * NZ, GTB), ng), dim3(GTB), 0, c.stream,
+                         x, nst, scale, c.wu, c.wv, ky * ky, c.fric_part);
+      hipLaunchKernelGGL((k_bpline<R, NX, NY, NZ, 2, GTB, JG>), dim3(cdiv(NX * NY, GTB), ng), dim3(GTB), 0, c.stream,
+                         x, nst, scale, c.wu, c.wv, kz * kz, c.fric_part);
+      hipLaunchKernelGGL(k_fric_sum3d, dim3(cdiv(M, 256)), dim3(256), 0, c.stream, c.jpart, c.fric_part, int(ng),
+                         int64_t(M), c.ainv, c.fric_j, c.fric_bp);
+      hipLaunchKernelGGL((k_field_d1line<NX, NY, NZ, 0, GTB>), dim3(cdiv(NYZ, GTB)), dim3(GTB), 0, c.stream,
+                         c.fric_j, kx, c.fric_div);
+      hipLaunchKernelGGL((k_field_d1line<NX, NY, NZ, 1, GTB>), dim3(cdiv(NX * NZ, GTB)), dim3(GTB), 0, c.stream,
+                         c.fric_j, ky, c.fric_div);
+      hipLaunchKernelGGL((k_field_d1line<NX, NY, NZ, 2, GTB>), dim3(cdiv(NX * NY, GTB)), dim3(GTB), 0, c.stream,
+                         c.fric_j, kz, c.fric_div);
+      hipLaunchKernelGGL(k_sum_N, dim3(1), dim3(1024), 0, c.stream, int64_t(M), c.rho, c.dVe, c.fric_N);
+      hipLaunchKernelGGL((k_fric3d_fields<R>), dim3(cdiv(M, 256)), dim3(256), 0, c.stream, int64_t(M), c.fric_div,
+                         c.fric_bp, c.fric_N, c.nu, c.U, c.delta, c.vext, c.dext, c.fun.mu, c.f_alpha, c.f_beta,
+                         c.f_gamma, c.f_rho0, c.f_Nreq, (R*)c.hA, (cpx<R>*)c.hD);
     });
   }
   void dens(Ctx& c, const void* X, const double* scale, int64_t nst) override {
@@ -108,7 +143,7 @@ struct Engine3D final : Engine {
     if (c.gen) {
       c.launch(KC_REDUCE_POT, [&] {
         hipLaunchKernelGGL((k_reduce_gen3d<R>), dim3(cdiv(M, 256)), dim3(256), 0, c.stream, c.dens_part, c.jpart,
-                           c.nsg_used, int64_t(M), fp, c.fun.A, c.lam, c.vext, c.rho, c.nu, c.jc, c.U, c.delta,
+                           c.nsg_used, c.njg_used, int64_t(M), fp, c.fun.A, c.lam, c.vext, c.rho, c.nu, c.jc, c.U, c.delta,
                            (R*)c.hA, (cpx<R>*)c.hD, (R*)c.hAx, (R*)c.hAy, (R*)c.hAz,
                            int(update && c.fun.functional == TDSLDA_FUNC_SLDA));
       });

@@ -291,13 +291,13 @@ __global__ __launch_bounds__((SlabCfg<NX, NY, NZ>::TB)) void k_pw_gen(Lap2Args<R
   }
 }
 
-// Sums of the density and current group partials (fixed order, one thread
+// Sums of the density and the current group partials (fixed order, one thread
 // per site) and the potentials of the SLDA functional at A != 1
 // (spin-symmetric, per spin): Delta = -g_eff nu, U = B eF - |Delta|^2 /
 // (3 C rho_+^(2/3)) - (1 - A) |j|^2 / (2 rho^2), A_vec = (1 - A) j / rho.
 template <typename R>
 __global__ __launch_bounds__(256) void k_reduce_gen3d(
-    const double* __restrict__ dens_part, const double* __restrict__ jpart, int ngroups, int64_t M,
+    const double* __restrict__ dens_part, const double* __restrict__ jpart, int ngroups, int jgroups, int64_t M,
     FunParams fp, double Aconst, const double* __restrict__ lam, const double* __restrict__ vext,
     double* __restrict__ rho, double* __restrict__ nu, double* __restrict__ jc, double* __restrict__ U,
     double* __restrict__ delta, R* __restrict__ hA, cpx<R>* __restrict__ hD, R* __restrict__ hAx,
@@ -307,10 +307,12 @@ __global__ __launch_bounds__(256) void k_reduce_gen3d(
   double sr = 0.0, snr = 0.0, sni = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
   for (int g = 0; g < ngroups; ++g) {
     const double* p = dens_part + int64_t(g) * 3 * M;
-    const double* q = jpart + int64_t(g) * 3 * M;
     sr += p[r];
     snr += p[M + r];
     sni += p[2 * M + r];
+  }
+  for (int g = 0; g < jgroups; ++g) {
+    const double* q = jpart + int64_t(g) * 3 * M;
     jx += q[r];
     jy += q[M + r];
     jz += q[2 * M + r];
@@ -358,6 +360,158 @@ __global__ void k_field_lap3d(int nx, int ny, int nz, const double* __restrict__
   for (int q = 0; q < nz; ++q) acc += c2z[((z - q) % nz + nz) % nz] * f[(int64_t(x) * ny + y) * nz + q];
   lap[r] = R(acc);
   fout[r] = R(f[r]);
+}
+
+// ---------------------------------------------------------------------------
+// Quantum friction on the full 3D lattice (the dissipative fields of Sec.
+// 5.2, correcting the initial state by a time-dependent approach):
+//   U_diss = -(alpha / rho0) div j,
+//   Delta_diss = Delta [beta sin(theta_nu - theta_B') + i gamma (N - N_req) / N_req],
+//   B' = -1/2 sum_n (f_v - f_u) [u lap v^* + v^* lap u]  (lap: full D2 Laplacian).
+// j comes from k_jline; B' from one line pass per axis (the Laplacian is the
+// sum of the per-axis D2), summed over groups; div j from line passes over
+// the summed current field.
+
+// B'_AXIS group partials over DG states, bpart[g][re|im][site] (AXIS 0
+// writes, the other axes add):  -1/2 (f_v - f_u) [u (D2 v)^* + v^* D2 u]
+//   grid = (ceil(NLINES / TBG), number of groups), block = TBG
+template <typename R, int NX, int NY, int NZ, int AXIS, int TBG, int DG>
+__global__ __launch_bounds__(TBG) void k_bpline(const cpx<R>* __restrict__ X, int64_t nstates,
+                                                const double* __restrict__ scale, const double* __restrict__ wu,
+                                                const double* __restrict__ wv, double kscale2,
+                                                double* __restrict__ bpart) {
+  using LG = LineGeo<NX, NY, NZ, AXIS>;
+  constexpr int NL = LG::NL, ST = LG::STRIDE;
+  constexpr int64_t M = int64_t(NX) * NY * NZ;
+  constexpr int ES = sizeof(cpx<R>);
+  const int l = blockIdx.x * TBG + threadIdx.x;
+  if (l >= LG::NLINES) return;  // no barriers below
+  const int s0 = LG::site0(l);
+  const int64_t nbeg = int64_t(blockIdx.y) * DG;
+  const int nloc = int(nstates - nbeg < DG ? nstates - nbeg : DG);
+  double br[NL], bi[NL];
+#pragma unroll
+  for (int k = 0; k < NL; ++k) br[k] = bi[k] = 0.0;
+  for (int ls = 0; ls < nloc; ++ls) {
+    const int64_t n = nbeg + ls;
+    const double fw = wv[n] - wu[n];
+    if (fw == 0.0) continue;
+    const R s = R(scale[n]);
+    const bi32x4 rX = make_rsrc(X + n * 2 * M, uint32_t(2 * M * ES));
+    // u (D2 v)^* first, then v^* D2 u: one transformed line live
+    cpx<R> t[NL];
+#pragma unroll 1
+    for (int comp = 1; comp >= 0; --comp) {
+#pragma unroll
+      for (int k = 0; k < NL; ++k) t[k] = s * bload<R>(rX, s0 * ES, int(comp * M + k * ST) * ES);
+      second_derivative<NL>(t, R(kscale2));
+#pragma unroll
+      for (int k = 0; k < NL; ++k) {
+        if (comp == 1) {  // u (D2 v)^*
+          const cpx<R> u = s * bload<R>(rX, s0 * ES, k * ST * ES);
+          br[k] += -0.5 * fw * (double(u.x) * t[k].x + double(u.y) * t[k].y);
+          bi[k] += -0.5 * fw * (double(u.y) * t[k].x - double(u.x) * t[k].y);
+        } else {  // v^* D2 u
+          const cpx<R> v = s * bload<R>(rX, s0 * ES, int(M + k * ST) * ES);
+          br[k] += -0.5 * fw * (double(v.x) * t[k].x + double(v.y) * t[k].y);
+          bi[k] += -0.5 * fw * (double(v.x) * t[k].y - double(v.y) * t[k].x);
+        }
+      }
+    }
+  }
+  double* out = bpart + int64_t(blockIdx.y) * 2 * M + s0;
+#pragma unroll
+  for (int k = 0; k < NL; ++k) {
+    if constexpr (AXIS == 0) {
+      out[k * ST] = br[k];
+      out[M + k * ST] = bi[k];
+    } else {
+      out[k * ST] += br[k];
+      out[M + k * ST] += bi[k];
+    }
+  }
+}
+
+// per site: the current field j[3][M] and B'[M][2] from the group partials
+// (fixed order) times ainv
+static __global__ __launch_bounds__(256) void k_fric_sum3d(const double* __restrict__ jpart,
+                                                    const double* __restrict__ bpart, int ngroups, int64_t M,
+                                                    double ainv, double* __restrict__ jf, double* __restrict__ bp) {
+  const int64_t r = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (r >= M) return;
+  double jx = 0.0, jy = 0.0, jz = 0.0, b0 = 0.0, b1 = 0.0;
+  for (int g = 0; g < ngroups; ++g) {
+    const double* q = jpart + int64_t(g) * 3 * M;
+    const double* b = bpart + int64_t(g) * 2 * M;
+    jx += q[r];
+    jy += q[M + r];
+    jz += q[2 * M + r];
+    b0 += b[r];
+    b1 += b[M + r];
+  }
+  jf[r] = ainv * jx;
+  jf[M + r] = ainv * jy;
+  jf[2 * M + r] = ainv * jz;
+  bp[2 * r] = ainv * b0;
+  bp[2 * r + 1] = ainv * b1;
+}
+
+// div j: D1_AXIS (Nyquist zeroed) of the field j_AXIS = jf[AXIS][M] along its
+// lines into divj (AXIS 0 writes, the other axes add); one thread per line
+template <int NX, int NY, int NZ, int AXIS, int TBG>
+__global__ __launch_bounds__(TBG) void k_field_d1line(const double* __restrict__ jf, double kscale,
+                                                      double* __restrict__ divj) {
+  using LG = LineGeo<NX, NY, NZ, AXIS>;
+  constexpr int NL = LG::NL, ST = LG::STRIDE;
+  constexpr int64_t M = int64_t(NX) * NY * NZ;
+  const int l = blockIdx.x * TBG + threadIdx.x;
+  if (l >= LG::NLINES) return;
+  const int s0 = LG::site0(l);
+  cpx<double> a[NL], ny;
+#pragma unroll
+  for (int k = 0; k < NL; ++k) a[k] = cpx<double>{jf[AXIS * M + s0 + k * ST], 0.0};
+  first_derivative<NL>(a, kscale, ny);
+#pragma unroll
+  for (int k = 0; k < NL; ++k) {
+    if constexpr (AXIS == 0) {
+      divj[s0 + k * ST] = a[k].x;
+    } else {
+      divj[s0 + k * ST] += a[k].x;
+    }
+  }
+}
+
+// N = dVe sum_r 2 rho (one workgroup, fixed order)
+static __global__ __launch_bounds__(1024) void k_sum_N(int64_t M, const double* __restrict__ rho, double dVe,
+                                                double* __restrict__ out) {
+  __shared__ double red[1024 / kWave];
+  double v = 0.0;
+  for (int64_t r = threadIdx.x; r < M; r += 1024) v += 2.0 * rho[r];
+  const double t = block_sum<1024>(v, red);
+  if (threadIdx.x == 0) out[0] = dVe * t;
+}
+
+// the fields with the dissipative terms, one thread per site:
+//   hA = U + V_ext - mu - (alpha / rho0) div j,
+//   hD = Delta [1 + beta sin(theta_nu - theta_B') + i gamma (N - N_req) / N_req] + Delta_ext
+template <typename R>
+__global__ __launch_bounds__(256) void k_fric3d_fields(int64_t M, const double* __restrict__ divj,
+                                                       const double* __restrict__ bp, const double* __restrict__ Nsum,
+                                                       const double* __restrict__ nu, const double* __restrict__ U,
+                                                       const double* __restrict__ delta,
+                                                       const double* __restrict__ vext, const double* __restrict__ dext,
+                                                       double mu, double alpha, double beta, double gamma,
+                                                       double rho0, double N_req, R* __restrict__ hA,
+                                                       cpx<R>* __restrict__ hD) {
+  const int64_t r = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (r >= M) return;
+  const double gt = N_req > 0.0 ? gamma * (Nsum[0] - N_req) / N_req : 0.0;
+  const double th_nu = atan2(nu[2 * r + 1], nu[2 * r]);
+  const double th_b = atan2(bp[2 * r + 1], bp[2 * r]);
+  const double fr = 1.0 + beta * sin(th_nu - th_b), fi = gt;
+  const double dr = delta[2 * r], di = delta[2 * r + 1];
+  hA[r] = R(U[r] + vext[r] - mu - alpha / rho0 * divj[r]);
+  hD[r] = cpx<R>{R(dr * fr - di * fi + dext[2 * r]), R(dr * fi + di * fr + dext[2 * r + 1])};
 }
 
 }  // namespace tdslda

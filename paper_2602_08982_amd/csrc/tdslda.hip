@@ -902,7 +902,6 @@ tdslda_status tdslda_set_current_fields(tdslda_ctx* c, const double* alpha, cons
 tdslda_status tdslda_set_friction(tdslda_ctx* c, double alpha, double beta, double gamma, double rho0,
                                   double N_req) {
   return guard(c, [&] {
-    require(c->q1d, TDSLDA_EINVAL, "quantum friction is built for the quasi-1D kernel set");
     require(!c->gen, TDSLDA_EINVAL, "quantum friction is built for the A = 1 operator");
     require(std::isfinite(alpha) && std::isfinite(beta) && std::isfinite(gamma) && std::isfinite(N_req) &&
                 std::isfinite(rho0) && rho0 > 0.0,
@@ -916,8 +915,12 @@ tdslda_status tdslda_set_friction(tdslda_ctx* c, double alpha, double beta, doub
     if (c->fric && !c->fric_part) {
       const int64_t ng = cdiv(c->cap, c->eng->group());
       c->fric_part = (double*)c->dalloc(sizeof(double) * 3 * size_t(ng) * c->M);
-      c->fric_j = (double*)c->dalloc(sizeof(double) * c->M);
+      c->fric_j = (double*)c->dalloc(sizeof(double) * (c->q1d ? 1 : 3) * c->M);
       c->fric_bp = (double*)c->dalloc(sizeof(double) * 2 * c->M);
+      if (!c->q1d) {
+        c->fric_div = (double*)c->dalloc(sizeof(double) * c->M);
+        c->fric_N = (double*)c->dalloc(sizeof(double) * 2);
+      }
     }
   });
 }

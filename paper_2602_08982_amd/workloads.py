@@ -49,10 +49,11 @@ MIXED = dict(name="mixed_fp32_48", n=(48, 48, 48), d=(1.0, 1.0, 1.0), mu=1.0, u0
              omega=(0.08, 0.08, 0.02), precision=T.FP32_MIXED, dt=0.005, nstates=8192)
 
 
-def setup(cfg, vortices, stream=None, precision=None, integrator=T.AB4AM5):
+def setup(cfg, vortices, stream=None, precision=None, integrator=T.AB4AM5, A=1.0):
     """Create a context, switch on the trap (regulator frozen with V_+ =
     V_ext), generate the plane-wave states on the device and imprint the
-    vortices.  Returns (ctx, kidx)."""
+    vortices.  A != 1 evolves the same start with the general functional.
+    Returns (ctx, kidx)."""
     n, d = cfg["n"], cfg["d"]
     prec = cfg["precision"] if precision is None else precision
     ec = 0.5 * (np.pi / d[0]) ** 2
@@ -61,7 +62,7 @@ def setup(cfg, vortices, stream=None, precision=None, integrator=T.AB4AM5):
     else:
         kidx = lowest_xi_kidx(n, d, cfg["mu"], cfg["u0"], cfg["nstates"])
     run = T.run_config(precision=prec, integrator=integrator, dt=cfg["dt"], selfstart=1, stream=stream)
-    ctx = T.Context(T.lattice_3d(n, d), T.functional_slda(cfg["mu"], ec), run, len(kidx))
+    ctx = T.Context(T.lattice_3d(n, d), T.functional_slda(cfg["mu"], ec, A=A), run, len(kidx))
     ctx.set_external(harmonic(n, d, cfg["omega"]), freeze_regulator=True)
     ctx.init_plane_waves(kidx, cfg["u0"], cfg["delta0"])
     if len(vortices):

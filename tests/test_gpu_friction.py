@@ -2,7 +2,9 @@
 correcting the initial state by a time-dependent approach) against the
 oracle: densities and energy after steps with all three dissipative terms
 on (FP64 to 1e-10, FP32-mixed to 1e-5), the energy decrease of the beta
-term on the device, and the refusal on a 3D context."""
+term on the device; the same terms in the full-3D kernel set (an 8^3
+complete set with a vortex, and the 32^3 benchmark start); the refusal
+with the general (A != 1) operator."""
 import numpy as np
 import pytest
 
@@ -94,10 +96,109 @@ def test_beta_friction_lowers_the_energy_on_the_device():
     assert np.all(np.diff(es) < 0), es
 
 
-def test_friction_needs_a_quasi_1d_context():
+# ---------------------------------------------------------------------------
+# full 3D
+
+def problem3d(n=8):
+    """The complete E > 0 set of the uniform n^3 state with a vortex imprint
+    in a weak trap switched on at t = 0 (currents and a pairing field out of
+    equilibrium)."""
+    from oracle import bdg
+    lat = L.Lattice(n, n, n)
+    mu = 1.0
+    E, phi = bdg.eigenstates(np.full(lat.shape, -mu), np.full(lat.shape, 0.5 + 0j), lat)
+    pos = E > 0
+    E, phi = E[pos], phi[pos]
+    phi = bdg.imprint_phase(phi, bdg.vortex_phase(lat, [(0.3, -0.2, 1.0)]))
+    X, Y, Z = lat.coords()
+    trap = 0.5 * 0.12 ** 2 * (X ** 2 + Y ** 2 + Z ** 2)
+    lam = F.lambda_c(np.zeros(lat.shape), mu, 0.5 * np.pi ** 2)
+    return lat, mu, trap, lam, E, phi
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_friction_3d_matches_oracle(prec):
+    """All three dissipative terms on an 8^3 complete set: Taylor start-up +
+    6 steps; densities, current, energy, N and (FP64) the states against the
+    oracle."""
+    from oracle import densities as D
+    lat, mu, trap, lam, E, phi = problem3d()
+    plain = td.TDSystem(td.Geometry3D(lat), F.Functional(F.SLDA), mu, trap, lam, F.fermi_weight(E),
+                        F.fermi_weight(-E))
+    N0 = td.observables(plain, phi)["N"]
+    fr = td.Friction(alpha=5.0, beta=5.0, gamma=0.1, rho0=0.05, N_req=1.01 * N0)
+    sysm = td.TDSystem(td.Geometry3D(lat), F.Functional(F.SLDA), mu, trap, lam, F.fermi_weight(E),
+                       F.fermi_weight(-E), friction=fr)
+    ref = td.evolve(sysm, phi, 0.01, 6)
+    rho, tau, nu, j = D.spin_symmetric(ref, sysm.wu, sysm.wv, lat)
+    o = td.observables(sysm, ref)
     t = T()
-    lt = t.Lattice(t.MODE_3D, 6, 6, 6, 1.0, 1.0, 1.0, 0.0, 0.0)
-    ctx = t.Context(lt, t.functional_slda(0.5, 10.0), t.run_config(), 4)
+    ctx = t.Context(t.lattice_3d(lat.n), t.functional_slda(mu, 0.5 * np.pi ** 2), t.run_config(precision=prec,
+                                                                                                dt=0.01), len(E))
+    try:
+        ctx.set_external(trap, freeze_regulator=False)
+        ctx.set_regulator(lam)
+        ctx.load_states(phi, E)
+        ctx.set_friction(alpha=5.0, beta=5.0, gamma=0.1, rho0=0.05, N_req=1.01 * N0)
+        ctx.abm_step(6)
+        d = ctx.densities()
+        e = ctx.energy()
+        tol = 1e-10 if prec == 0 else 1e-5
+        assert rel(d["rho"], rho) < tol and rel(d["nu"], nu) < tol
+        jn = np.sqrt(sum(np.sum(np.abs(c) ** 2) for c in j))
+        for c in range(3):
+            assert np.linalg.norm(d["j"][c] - j[c]) / jn < tol
+        for k in ("total", "N"):
+            assert abs(e[k] - o[k]) <= tol * abs(o[k]), (k, e[k], o[k])
+        if prec == 0:
+            assert rel(ctx.get_states(), ref) < 1e-10
+        # the friction did act: the energy left the plain evolution's
+        ref0 = td.evolve(plain, phi, 0.01, 6)
+        assert abs(td.observables(plain, ref0)["total"] - o["total"]) > 1e-4 * abs(o["EFG"])
+    finally:
+        ctx.close()
+
+
+def test_friction_3d_benchmarked_shape():
+    """32^3 FP64 with the benchmark's start (plane waves, trap, vortex) for
+    300 seeded momenta (more than one 256-state group of the line passes),
+    beta and alpha on: Taylor start-up + 3 steps against the oracle."""
+    from oracle import bdg, densities as D
+    n, nst = 32, 300
+    lat = L.Lattice(n, n, n)
+    mu, ec = 1.0, 0.5 * np.pi ** 2
+    g = synth.rng(341)
+    flat = np.sort(g.choice(n ** 3, size=nst, replace=False))
+    kidx = np.stack([flat // (n * n), (flat // n) % n, flat % n], axis=1).astype(np.int32)
+    E, phi = bdg.plane_wave_states(lat, kidx, -mu, 0.5)
+    vort = [(*synth.vortex_offset(2), 1.0)]
+    phi = bdg.imprint_phase(phi, bdg.vortex_phase(lat, vort))
+    X, Y, Z = lat.coords()
+    vext = 0.5 * 0.05 ** 2 * (X ** 2 + Y ** 2 + Z ** 2)
+    lam = F.lambda_c(vext, mu, ec)
+    fr = td.Friction(alpha=5.0, beta=5.0, rho0=0.05)
+    sysm = td.TDSystem(td.Geometry3D(lat), F.Functional(F.SLDA), mu, vext, lam, F.fermi_weight(E),
+                       F.fermi_weight(-E), friction=fr)
+    ref = td.evolve(sysm, phi, 0.005, 3)
+    t = T()
+    ctx = t.Context(t.lattice_3d((n,) * 3), t.functional_slda(mu, ec), t.run_config(dt=0.005), nst)
+    try:
+        ctx.set_external(vext, freeze_regulator=True)
+        ctx.init_plane_waves(kidx, 0.0, 0.5)
+        ctx.imprint_vortices(vort)
+        ctx.set_friction(alpha=5.0, beta=5.0, gamma=0.0, rho0=0.05, N_req=0.0)
+        ctx.abm_step(3)
+        d = ctx.densities()
+        rho, tau, nu, j = D.spin_symmetric(ref, sysm.wu, sysm.wv, lat)
+        assert rel(d["rho"], rho) < 1e-10 and rel(d["nu"], nu) < 1e-10
+        assert rel(ctx.get_states(), ref) < 1e-10
+    finally:
+        ctx.close()
+
+
+def test_friction_needs_the_a1_operator():
+    t = T()
+    ctx = t.Context(t.lattice_3d((6, 6, 6)), t.functional_slda(0.5, 10.0, A=1.094), t.run_config(), 4)
     with pytest.raises(t.TdsldaError) as ei:
         ctx.set_friction(beta=5.0)
     assert ei.value.status == t.EINVAL
