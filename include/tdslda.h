@@ -22,6 +22,12 @@
  *    Quasi-1D mode (Sec. 3.1, quasi-1D item): states live on the z axis only
  *    (M = N_z), every state carries its transverse momentum squared
  *    k_perp^2, and the transverse box is L_x x L_y.
+ *    Quasi-2D mode (Sec. 3.1, quasi-2D item): states live on the x-y lattice
+ *    (M = N_x N_y, flat index ix*N_y + iy, normalised on the x-y lattice),
+ *    every state carries its plane-wave momentum squared k_z^2 (one of the
+ *    N_z/2 + 1 distinct |k_z| = 2 pi m / L_z, L_z = N_z dz) and a
+ *    multiplicity (the two signs of k_z share one problem); densities carry
+ *    1/L_z and tau the k_z^2 term.  A = 1 functional only.
  *  - A state is (u_n, v_n) = (u_{n,a}, v_{n,b}); host arrays of states are
  *    double precision, layout [n][2][M][2] (state, component u|v, site,
  *    re|im).  States are normalised as int (|u|^2 + |v|^2) dV = 1.
@@ -54,7 +60,7 @@ typedef enum {
   TDSLDA_EUNSTABLE = -5  /* conservation or NaN check failed (Sec. 4.5.1) */
 } tdslda_status;
 
-enum { TDSLDA_MODE_3D = 3, TDSLDA_MODE_Q1D = 1 };
+enum { TDSLDA_MODE_3D = 3, TDSLDA_MODE_Q1D = 1, TDSLDA_MODE_Q2D = 2 };
 enum { TDSLDA_FUNC_SLDA = 1, TDSLDA_FUNC_BDG = 2 };
 enum { TDSLDA_FP64 = 0, TDSLDA_FP32_MIXED = 1 };
 enum { TDSLDA_AB3AM4 = 34, TDSLDA_AB4AM5 = 45, TDSLDA_AB5AM5 = 55 };
@@ -62,9 +68,10 @@ enum { TDSLDA_AB3AM4 = 34, TDSLDA_AB4AM5 = 45, TDSLDA_AB5AM5 = 55 };
 typedef struct tdslda_ctx tdslda_ctx;
 
 typedef struct {
-  int mode;             /* TDSLDA_MODE_3D or TDSLDA_MODE_Q1D */
-  int nx, ny, nz;       /* 3D: lattice sizes; Q1D: nx = ny = 1, nz = N_z */
-  double dx, dy, dz;    /* spacings (Q1D: dz only) */
+  int mode;             /* TDSLDA_MODE_3D, TDSLDA_MODE_Q1D or TDSLDA_MODE_Q2D */
+  int nx, ny, nz;       /* 3D: lattice sizes; Q1D: nx = ny = 1, nz = N_z; Q2D: the
+                           x-y lattice nx, ny and nz = N_z plane waves along z */
+  double dx, dy, dz;    /* spacings (Q1D: dz only; Q2D: dz sets L_z = nz dz) */
   double lx_perp, ly_perp; /* Q1D: transverse box L_x, L_y (densities carry 1/(L_x L_y)) */
 } tdslda_lattice;
 
@@ -96,9 +103,11 @@ typedef struct {
  * device buffers: (history depth + 1) state buffers plus one intermediate
  * buffer (the x-derivative of every state), per-state scalars and the FP64
  * fields.  Supported shapes: cubic N^3 with N in {4,6,8,12,16,24,32,48},
- * 8x8x16 (3D); N_z in {16,64,256} (Q1D: N_z = A^2 with A lanes per state).
- * The quasi-1D F / CORR / FULL evaluations do not use the intermediate
- * buffer.  Errors: EINVAL (including an unsupported shape), ENOMEM. */
+ * 8x8x16 (3D); N_z in {16,64,256} (Q1D: N_z = A^2 with A lanes per state);
+ * N_x x N_y in {8x8, 12x12, 16x16, 24x16, 32x32, 48x48, 64x64} (Q2D: a state
+ * per workgroup, its 2D Laplacian in LDS).  The quasi-1D and quasi-2D
+ * evaluations do not use the intermediate buffer.  Errors: EINVAL
+ * (including an unsupported shape, and A != 1 in Q2D), ENOMEM. */
 tdslda_status tdslda_create(const tdslda_lattice* lat, const tdslda_functional* fun,
                             const tdslda_run* run, int64_t capacity, tdslda_ctx** out);
 tdslda_status tdslda_destroy(tdslda_ctx* ctx);
@@ -129,7 +138,8 @@ tdslda_status tdslda_set_regulator(tdslda_ctx* ctx, const double* lam);
 /* Load n <= capacity states (host, [n][2][M][2] FP64, copied and rounded to
  * the context precision) with their static quasiparticle energies E[n] (the
  * frozen weights f(E), f(-E) are computed from them) and, in Q1D mode,
- * kperp2[n] (else NULL).  Resets the integrator. */
+ * kperp2[n], in Q2D mode k_z^2 in the same array (else NULL).  Every
+ * multiplicity is reset to 1.  Resets the integrator. */
 tdslda_status tdslda_load_states(tdslda_ctx* ctx, int64_t n, const double* uv, const double* E,
                                  const double* kperp2);
 /* Same from a device array of the context precision ([n][2][M] complex of
@@ -137,12 +147,25 @@ tdslda_status tdslda_load_states(tdslda_ctx* ctx, int64_t n, const double* uv, c
 tdslda_status tdslda_load_states_device(tdslda_ctx* ctx, int64_t n, const void* uv_dev,
                                         const double* E, const double* kperp2);
 
+/* Multiplicity of each loaded state (host FP64 [n], n = the loaded count,
+ * each > 0): the weights become mult f(E), mult f(-E), so that one evolved
+ * state stands for mult equal problems (Q2D: 2 for the classes 0 < |k_z| <
+ * the Nyquist momentum, whose +k_z and -k_z problems coincide; Sec. 3.1,
+ * quasi-2D item).  Between a load and the first step only; the fields are
+ * rebuilt.  Errors: EINVAL (count, values), EORDER (nothing loaded, or
+ * the integrator already started). */
+tdslda_status tdslda_set_multiplicity(tdslda_ctx* ctx, int64_t n, const double* mult);
+
 /* Uniform-system start (Sec. 4.5.1 "uniform-system solution"): n plane-wave
  * eigenstates of the uniform H with constant U = u0 and Delta = delta0
  * (real, > 0) at momenta k = 2 pi m / L with integer triples kidx[n][3]
  * (grid indices 0..N-1 of Sec. 3.1), generated on the device:
  * u = sqrt((1 + xi/E)/2), v = sqrt((1 - xi/E)/2), xi = k^2/2 + u0 - mu,
- * times exp(i k.r)/sqrt(V).  E_n of each state sets its frozen weights. */
+ * times exp(i k.r)/sqrt(V).  E_n of each state sets its frozen weights.
+ * Q2D: kidx[n] = (l_x, l_y, m) with m in [0, nz/2] the |k_z| class
+ * (k_z = 2 pi m / L_z enters xi), the x-y plane wave normalised on the x-y
+ * lattice, and the multiplicity of the class (1 for m = 0 and m = nz/2,
+ * else 2) set with k_z^2. */
 tdslda_status tdslda_init_plane_waves(tdslda_ctx* ctx, int64_t n, const int32_t* kidx,
                                       double u0, double delta0);
 /* Vortex imprint on every loaded state (a phase e^{i theta} on Delta; Delta
@@ -153,7 +176,7 @@ tdslda_status tdslda_init_plane_waves(tdslda_ctx* ctx, int64_t n, const int32_t*
  * the spin-symmetric reduction (Sec. 2.3), so the evolved E > 0 states keep
  * standing for a complete set.  theta = sum_j q_j atan2(y - y_j, x - x_j)
  * (straight lines along z, centred coordinates).  xyq: [nv][3] host array
- * of (x_j, y_j, q_j).  3D only. */
+ * of (x_j, y_j, q_j).  3D and Q2D. */
 tdslda_status tdslda_imprint_vortices(tdslda_ctx* ctx, int nv, const double* xyq);
 
 /* Linear-mode potentials of the general single-particle Hamiltonian
@@ -189,8 +212,8 @@ tdslda_status tdslda_get_fields(tdslda_ctx* ctx, double* U, double* delta_reim);
 
 /* H psi with the current fields, unshifted and unnormalised, for n states of
  * device arrays in the context precision (layout as the loaded states).
- * n <= capacity; in and out must not overlap.  Q1D: kperp2 of the loaded
- * states with the same index is used. */
+ * n <= capacity; in and out must not overlap.  Q1D (Q2D): kperp2 (k_z^2) of
+ * the loaded state with the same index is used. */
 tdslda_status tdslda_apply_hbdg(tdslda_ctx* ctx, const void* in_dev, void* out_dev, int64_t n);
 
 /* Quantum friction (Sec. 5.2, correcting the initial state by a
@@ -206,8 +229,9 @@ tdslda_status tdslda_apply_hbdg(tdslda_ctx* ctx, const void* in_dev, void* out_d
  * D2z - k_perp^2 and div j = D1z j_z, with 1/(L_x L_y); one pass over the
  * states (four-step DFTs).  The gamma term is off when N_req <= 0; all of
  * alpha, beta and the gamma term zero switch friction off.  Not with the
- * general (A != 1) operator; not stored by tdslda_save.  Errors: EINVAL
- * (general operator, non-finite parameters, rho0 <= 0), ENOMEM. */
+ * general (A != 1) operator, not in Q2D; not stored by tdslda_save.
+ * Errors: EINVAL (general operator, Q2D, non-finite parameters,
+ * rho0 <= 0), ENOMEM. */
 tdslda_status tdslda_set_friction(tdslda_ctx* ctx, double alpha, double beta, double gamma, double rho0,
                                   double N_req);
 

@@ -106,3 +106,28 @@ def eigenstates(geom, hfield, delta, ec=None):
         ms.append(np.full(sel.size, w))
         phis.append(W[:, sel].T.reshape(sel.size, 2, geom.nx, geom.ny) / np.sqrt(geom.dV))
     return np.concatenate(Es), np.concatenate(kz2s), np.concatenate(ms), np.concatenate(phis, axis=0)
+
+
+def plane_wave_states(geom, kidx, hshift, delta0):
+    """Uniform-system start (Sec. 4.5.1) of the quasi-2D mode: for kidx[n] =
+    (l_x, l_y, m) the x-y lattice momentum (k_x, k_y) of grid indices l_x,
+    l_y and the |k_z| class m, xi = (k_x^2 + k_y^2 + k_z^2)/2 + hshift,
+    E = sqrt(xi^2 + |Delta|^2), u = sqrt((1 + xi/E)/2), v = sqrt((1 - xi/E)/2)
+    Delta^*/|Delta|, times exp(i (k_x x + k_y y)) / sqrt(L_x L_y) with x, y
+    measured from the lattice corner.  Returns (E, k_z^2, multiplicity, phi)."""
+    kidx = np.asarray(kidx)
+    kx = geom.k[0][kidx[:, 0]]
+    ky = geom.k[1][kidx[:, 1]]
+    kz = geom.static.kz[kidx[:, 2]]
+    xi = 0.5 * (kx ** 2 + ky ** 2 + kz ** 2) + hshift
+    ad = abs(delta0)
+    E = np.sqrt(xi ** 2 + ad ** 2)
+    uk = np.sqrt(0.5 * (1.0 + xi / E))
+    vk = np.sqrt(0.5 * (1.0 - xi / E)) * (np.conj(delta0) / ad)
+    x = np.arange(geom.nx) * geom.dx
+    y = np.arange(geom.ny) * geom.dy
+    ph = np.exp(1j * (kx[:, None, None] * x[None, :, None] + ky[:, None, None] * y[None, None, :]))
+    ph = ph / np.sqrt(geom.nx * geom.dx * geom.ny * geom.dy)
+    phi = np.stack([uk[:, None, None] * ph, vk[:, None, None] * ph], axis=1)
+    return E, kz ** 2, geom.static.mult[kidx[:, 2]], phi
+

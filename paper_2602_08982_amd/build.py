@@ -22,6 +22,7 @@ SOURCES = [
     "inst3d_f32_small.hip",
     "inst3d_f32_large.hip",
     "q1d.hip",
+    "q2d.hip",
     "q1dstatic.hip",
     "static.hip",
     "nn.hip",

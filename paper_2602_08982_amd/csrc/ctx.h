@@ -96,7 +96,7 @@ struct Engine {
   virtual void pointwise(Ctx& c, const PwDesc& d, int64_t nst) = 0;
   virtual void grad(Ctx& c, const void* X, const double* scale, int64_t n0, int64_t nchunk) = 0;
   // quantum friction: add the dissipative terms to the fields just built
-  // from the states X (only the quasi-1D kernel set has it)
+  // from the states X (the quasi-1D and full-3D kernel sets have it)
   virtual void friction(Ctx& c, const void* X, const double* scale, int64_t nst) {
     (void)c, (void)X, (void)scale, (void)nst;
     throw Fail{TDSLDA_EINVAL, "quantum friction is built for the quasi-1D kernel set"};
@@ -112,7 +112,7 @@ struct tdslda_ctx {
   tdslda_lattice lat{};
   tdslda_functional fun{};
   tdslda_run run{};
-  int q1d = 0;
+  int q1d = 0, q2d = 0;
   int64_t M = 0, cap = 0, nst = 0;
   double dV = 1, dVe = 1, vol = 1, ainv = 1;
   hipStream_t stream = nullptr;
@@ -127,6 +127,7 @@ struct tdslda_ctx {
   double* sscale[6] = {nullptr};
   void* T = nullptr;
   double *wu = nullptr, *wv = nullptr, *E = nullptr, *kperp2 = nullptr;
+  double* mult = nullptr;  // per-state multiplicity (weights are mult f(+-E))
   double *nrm_part = nullptr, *h_part = nullptr, *hshift = nullptr;
   int nrm_stride = 1, h_stride = 1;
   double* dens_part = nullptr;
@@ -277,6 +278,8 @@ std::unique_ptr<Engine> make3d_f32_small(int nx, int ny, int nz);
 std::unique_ptr<Engine> make3d_f32_large(int nx, int ny, int nz);
 std::unique_ptr<Engine> make_q1d_f64(int nz);
 std::unique_ptr<Engine> make_q1d_f32(int nz);
+std::unique_ptr<Engine> make_q2d_f64(int nx, int ny);
+std::unique_ptr<Engine> make_q2d_f32(int nx, int ny);
 // quasi-1D static states (q1dstatic.hip): counts per problem and, when X is
 // given, the kept eigenvectors written at X (slots 0 .. total-1) with E and
 // k_perp^2 per slot; returns the total number kept

@@ -210,18 +210,55 @@ __global__ void k_vortex_phase(int64_t M, int nx, int ny, int nz, double dx, dou
 }
 
 // Fermi weights of the frozen static energies
-__global__ void k_weights(int64_t n, const double* __restrict__ E, double T, double* __restrict__ wu,
-                          double* __restrict__ wv) {
+// times the state's multiplicity (the number of equal problems it stands
+// for: the two signs of k_z of a quasi-2D class)
+__global__ void k_weights(int64_t n, const double* __restrict__ E, double T, const double* __restrict__ mult,
+                          double* __restrict__ wu, double* __restrict__ wv) {
   const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
   if (i >= n) return;
-  const double e = E[i];
+  const double e = E[i], m = mult[i];
   if (T <= 0.0) {
-    wu[i] = e < 0 ? 1.0 : (e > 0 ? 0.0 : 0.5);
-    wv[i] = e > 0 ? 1.0 : (e < 0 ? 0.0 : 0.5);
+    wu[i] = m * (e < 0 ? 1.0 : (e > 0 ? 0.0 : 0.5));
+    wv[i] = m * (e > 0 ? 1.0 : (e < 0 ? 0.0 : 0.5));
   } else {
-    wu[i] = 1.0 / (exp(fmin(fmax(e / T, -700.0), 700.0)) + 1.0);
-    wv[i] = 1.0 / (exp(fmin(fmax(-e / T, -700.0), 700.0)) + 1.0);
+    wu[i] = m / (exp(fmin(fmax(e / T, -700.0), 700.0)) + 1.0);
+    wv[i] = m / (exp(fmin(fmax(-e / T, -700.0), 700.0)) + 1.0);
   }
+}
+
+// quasi-2D plane-wave states of the uniform H (one block row per state):
+// kidx[n] = (l_x, l_y, m_z), lattice momenta k = 2 pi l / L along x, y and
+// the |k_z| class m_z in [0, nkz/2] (k_z = 2 pi m_z / L_z), xi = k^2/2 +
+// hshift, u = sqrt((1 + xi/E)/2), v = sqrt((1 - xi/E)/2) times
+// exp(i (k_x x + k_y y)) / sqrt(L_x L_y); writes E, k_z^2 and the class
+// multiplicity (1 for m_z = 0 and the Nyquist class, 2 otherwise)
+template <typename R>
+__global__ void k_q2_plane_waves(int64_t M, int nx, int ny, int nkz, const int32_t* __restrict__ kidx,
+                                 double hshift, double delta0, double kx, double ky, double kz, double invsqrtA,
+                                 cpx<R>* __restrict__ X, double* __restrict__ E, double* __restrict__ kz2,
+                                 double* __restrict__ mult) {
+  const int64_t n = blockIdx.y;
+  const int64_t r = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  const int lx = kidx[3 * n], ly = kidx[3 * n + 1], mz = kidx[3 * n + 2];
+  const int mx = lx < nx / 2 ? lx : lx - nx, my = ly < ny / 2 ? ly : ly - ny;
+  const double kz2n = kz * kz * mz * mz;
+  const double k2 = kx * kx * mx * mx + ky * ky * my * my + kz2n;
+  const double xi = 0.5 * k2 + hshift;
+  const double e = sqrt(xi * xi + delta0 * delta0);
+  const double uk = sqrt(0.5 * (1.0 + xi / e)), vk = sqrt(0.5 * (1.0 - xi / e));
+  if (r == 0) {
+    E[n] = e;
+    kz2[n] = kz2n;
+    mult[n] = (mz == 0 || 2 * mz == nkz) ? 1.0 : 2.0;
+  }
+  if (r >= M) return;
+  const int ix = int(r / ny), iy = int(r % ny);
+  const long fx = (long(lx) * ix) % nx, fy = (long(ly) * iy) % ny;
+  const double frac = double(fx) / nx + double(fy) / ny;
+  double sn, cs;
+  sincospi(2.0 * frac, &sn, &cs);
+  X[n * 2 * M + r] = cpx<R>{R(uk * cs * invsqrtA), R(uk * sn * invsqrtA)};
+  X[n * 2 * M + M + r] = cpx<R>{R(vk * cs * invsqrtA), R(vk * sn * invsqrtA)};
 }
 
 }  // namespace tdslda

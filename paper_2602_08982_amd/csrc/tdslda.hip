@@ -44,6 +44,8 @@ std::unique_ptr<Engine> make_engine(const tdslda_lattice& lat, int prec) {
       e = make3d_f32_small(lat.nx, lat.ny, lat.nz);
       if (!e) e = make3d_f32_large(lat.nx, lat.ny, lat.nz);
     }
+  } else if (lat.mode == TDSLDA_MODE_Q2D) {
+    e = prec == TDSLDA_FP64 ? make_q2d_f64(lat.nx, lat.ny) : make_q2d_f32(lat.nx, lat.ny);
   } else {
     e = prec == TDSLDA_FP64 ? make_q1d_f64(lat.nz) : make_q1d_f32(lat.nz);
   }
@@ -74,11 +76,13 @@ void set_scheme(Ctx& c) {
 
 int64_t memory_bytes(const tdslda_lattice& lat, const tdslda_run& run, int64_t n, Engine* eng,
                      int depth, int64_t gchunk) {
-  const int64_t M = lat.mode == TDSLDA_MODE_3D ? int64_t(lat.nx) * lat.ny * lat.nz : lat.nz;
+  const int64_t M = lat.mode == TDSLDA_MODE_3D    ? int64_t(lat.nx) * lat.ny * lat.nz
+                    : lat.mode == TDSLDA_MODE_Q2D ? int64_t(lat.nx) * lat.ny
+                                                  : lat.nz;
   const int64_t es = int64_t(eng->elem_size());
   const int64_t S = 2 * M * es;
   int64_t b = (depth + 2) * n * S;                               // state buffers + T
-  b += n * 8 * (4 + (depth + 1) + 1);                            // per-state arrays
+  b += n * 8 * (5 + (depth + 1) + 1);                            // per-state arrays
   b += n * 8 * (eng->ngx() + eng->ngx() + eng->ncb());           // partial slots
   b += int64_t(cdiv(n, eng->group())) * 3 * M * 8 * (lat.mode == TDSLDA_MODE_3D ? 2 : 1);  // density (+ current) partials
   b += M * 8 * 16 + M * (es / 2 + es);                          // fields
@@ -403,7 +407,8 @@ void after_load(Ctx& c) {
 void set_weights(Ctx& c, int64_t n, const double* E_host) {
   if (E_host) HIPCHK(hipMemcpyAsync(c.E, E_host, n * 8, hipMemcpyHostToDevice, c.stream));
   c.launch(KC_SETUP, [&] {
-    hipLaunchKernelGGL(k_weights, dim3(cdiv(n, 256)), dim3(256), 0, c.stream, n, c.E, c.fun.temperature, c.wu, c.wv);
+    hipLaunchKernelGGL(k_weights, dim3(cdiv(n, 256)), dim3(256), 0, c.stream, n, c.E, c.fun.temperature, c.mult,
+                       c.wu, c.wv);
   });
 }
 
@@ -434,6 +439,11 @@ void check_lattice(const tdslda_lattice& lat) {
   } else if (lat.mode == TDSLDA_MODE_Q1D) {
     require(lat.nz > 0 && lat.nz % 2 == 0 && lat.dz > 0, TDSLDA_EINVAL, "bad quasi-1D lattice");
     require(lat.lx_perp > 0 && lat.ly_perp > 0, TDSLDA_EINVAL, "quasi-1D needs the transverse box");
+  } else if (lat.mode == TDSLDA_MODE_Q2D) {
+    require(lat.nx > 0 && lat.ny > 0 && lat.nx % 2 == 0 && lat.ny % 2 == 0, TDSLDA_EINVAL,
+            "quasi-2D lattice sizes must be positive and even");
+    require(lat.nz > 0 && lat.nz % 2 == 0, TDSLDA_EINVAL, "quasi-2D needs an even number of k_z plane waves");
+    require(lat.dx > 0 && lat.dy > 0 && lat.dz > 0, TDSLDA_EINVAL, "lattice spacings must be positive");
   } else {
     throw Fail{TDSLDA_EINVAL, "unknown lattice mode"};
   }
@@ -483,7 +493,9 @@ tdslda_status tdslda_memory_plan(const tdslda_lattice* lat, const tdslda_run* ru
     tdslda_ctx tmp;
     tmp.run = *run;
     set_scheme(tmp);
-    const int64_t M = lat->mode == TDSLDA_MODE_3D ? int64_t(lat->nx) * lat->ny * lat->nz : lat->nz;
+    const int64_t M = lat->mode == TDSLDA_MODE_3D    ? int64_t(lat->nx) * lat->ny * lat->nz
+                      : lat->mode == TDSLDA_MODE_Q2D ? int64_t(lat->nx) * lat->ny
+                                                     : lat->nz;
     (void)M;
     *bytes_out = memory_bytes(*lat, *run, nstates, eng.get(), tmp.depth, std::min<int64_t>(nstates, 64));
     return TDSLDA_OK;
@@ -511,6 +523,9 @@ tdslda_status tdslda_create(const tdslda_lattice* lat, const tdslda_functional* 
     c->fun = *fun;
     c->run = *run;
     c->q1d = lat->mode == TDSLDA_MODE_Q1D;
+    c->q2d = lat->mode == TDSLDA_MODE_Q2D;
+    require(!c->q2d || fun->functional != TDSLDA_FUNC_SLDA || fun->A == 1.0, TDSLDA_EINVAL,
+            "the quasi-2D kernel set is built for the A = 1 functional");
     c->stream = (hipStream_t)run->hip_stream;
     set_scheme(*c);
     c->eng = make_engine(*lat, run->precision);
@@ -522,6 +537,13 @@ tdslda_status tdslda_create(const tdslda_lattice* lat, const tdslda_functional* 
       c->ainv = 1.0 / (lat->lx_perp * lat->ly_perp);
       c->dVe = lat->dz * lat->lx_perp * lat->ly_perp;
       c->vol = lat->nz * lat->dz * lat->lx_perp * lat->ly_perp;
+    } else if (c->q2d) {
+      const double Lz = lat->nz * lat->dz;
+      c->M = int64_t(lat->nx) * lat->ny;
+      c->dV = lat->dx * lat->dy;
+      c->ainv = 1.0 / Lz;
+      c->dVe = c->dV * Lz;
+      c->vol = c->M * c->dVe;
     } else {
       c->M = int64_t(lat->nx) * lat->ny * lat->nz;
       c->dV = lat->dx * lat->dy * lat->dz;
@@ -540,6 +562,10 @@ tdslda_status tdslda_create(const tdslda_lattice* lat, const tdslda_functional* 
     c->E = (double*)c->dalloc(8 * capacity);
     c->kperp2 = (double*)c->dalloc(8 * capacity);
     HIPCHK(hipMemsetAsync(c->kperp2, 0, 8 * capacity, c->stream));
+    c->mult = (double*)c->dalloc(8 * capacity);
+    hipLaunchKernelGGL(k_fill_real<double>, dim3(cdiv(capacity, 256)), dim3(256), 0, c->stream, capacity, 1.0,
+                       c->mult);
+    HIPCHK(hipGetLastError());
     c->hshift = (double*)c->dalloc(8 * capacity);
     c->nrm_stride = c->eng->ngx();
     c->h_stride = c->eng->ngx() + c->eng->ncb();
@@ -563,7 +589,7 @@ tdslda_status tdslda_create(const tdslda_lattice* lat, const tdslda_functional* 
     c->hAl = c->dalloc(M * c->esz / 2);
     c->hLa = c->dalloc(M * c->esz / 2);
     c->hAz = c->dalloc(M * c->esz / 2);
-    if (!c->q1d) {
+    if (lat->mode == TDSLDA_MODE_3D) {
       c->hAx = c->dalloc(M * c->esz / 2);
       c->hAy = c->dalloc(M * c->esz / 2);
       c->jpart = (double*)c->dalloc(size_t(c->nsg_max) * 3 * M * 8);
@@ -642,10 +668,12 @@ tdslda_status tdslda_set_regulator(tdslda_ctx* c, const double* lam) {
 static void load_common(tdslda_ctx* c, int64_t n, const double* E, const double* kperp2) {
   require(n > 0 && n <= c->cap, TDSLDA_EINVAL, "state count out of range [1, capacity]");
   require(E != nullptr, TDSLDA_EINVAL, "E is NULL");
-  if (c->q1d) {
-    require(kperp2 != nullptr, TDSLDA_EINVAL, "quasi-1D states need kperp2");
+  if (c->q1d || c->q2d) {
+    require(kperp2 != nullptr, TDSLDA_EINVAL, c->q1d ? "quasi-1D states need kperp2" : "quasi-2D states need k_z^2");
     HIPCHK(hipMemcpyAsync(c->kperp2, kperp2, 8 * n, hipMemcpyHostToDevice, c->stream));
   }
+  hipLaunchKernelGGL(k_fill_real<double>, dim3(cdiv(n, 256)), dim3(256), 0, c->stream, n, 1.0, c->mult);
+  HIPCHK(hipGetLastError());
   c->nst = n;
   set_weights(*c, n, E);
 }
@@ -685,14 +713,29 @@ tdslda_status tdslda_load_states_device(tdslda_ctx* c, int64_t n, const void* uv
   });
 }
 
+tdslda_status tdslda_set_multiplicity(tdslda_ctx* c, int64_t n, const double* mult) {
+  return guard(c, [&] {
+    require(c->loaded, TDSLDA_EORDER, "load states first");
+    require(!c->started, TDSLDA_EORDER, "set the multiplicities before the first step");
+    require(mult != nullptr && n == c->nst, TDSLDA_EINVAL, "give one multiplicity per loaded state");
+    for (int64_t i = 0; i < n; ++i)
+      require(std::isfinite(mult[i]) && mult[i] > 0.0, TDSLDA_EINVAL, "multiplicities must be finite, > 0");
+    HIPCHK(hipMemcpyAsync(c->mult, mult, 8 * n, hipMemcpyHostToDevice, c->stream));
+    set_weights(*c, n, nullptr);
+    after_load(*c);
+    HIPCHK(hipStreamSynchronize(c->stream));
+  });
+}
+
 tdslda_status tdslda_init_plane_waves(tdslda_ctx* c, int64_t n, const int32_t* kidx, double u0, double delta0) {
   return guard(c, [&] {
-    require(!c->q1d, TDSLDA_EINVAL, "plane-wave start is a 3D option");
+    require(!c->q1d, TDSLDA_EINVAL, "plane-wave start is a 3D and quasi-2D option");
     require(kidx != nullptr && n > 0 && n <= c->cap, TDSLDA_EINVAL, "bad plane-wave list");
     require(delta0 > 0, TDSLDA_EINVAL, "delta0 must be > 0");
+    const int zmax = c->q2d ? c->lat.nz / 2 + 1 : c->lat.nz;  // quasi-2D: |k_z| classes 0 .. nz/2
     for (int64_t i = 0; i < n; ++i) {
       require(kidx[3 * i] >= 0 && kidx[3 * i] < c->lat.nx && kidx[3 * i + 1] >= 0 && kidx[3 * i + 1] < c->lat.ny &&
-                  kidx[3 * i + 2] >= 0 && kidx[3 * i + 2] < c->lat.nz,
+                  kidx[3 * i + 2] >= 0 && kidx[3 * i + 2] < zmax,
               TDSLDA_EINVAL, "k index out of range");
     }
     if (c->kidx_cap < n) {
@@ -703,6 +746,23 @@ tdslda_status tdslda_init_plane_waves(tdslda_ctx* c, int64_t n, const int32_t* k
     c->nst = n;
     const double kx = 2 * kPi / (c->lat.nx * c->lat.dx), ky = 2 * kPi / (c->lat.ny * c->lat.dy),
                  kz = 2 * kPi / (c->lat.nz * c->lat.dz);
+    if (c->q2d) {
+      const double isa = 1.0 / std::sqrt(c->M * c->dV);  // 2D normalisation (1/L_z is in the densities)
+      c->launch(KC_SETUP, [&] {
+        if (c->esz == 16)
+          hipLaunchKernelGGL((k_q2_plane_waves<double>), dim3(cdiv(c->M, 256), n), dim3(256), 0, c->stream, c->M,
+                             c->lat.nx, c->lat.ny, c->lat.nz, c->kidx_dev, u0 - c->fun.mu, delta0, kx, ky, kz, isa,
+                             (cpx<double>*)c->sb[0], c->E, c->kperp2, c->mult);
+        else
+          hipLaunchKernelGGL((k_q2_plane_waves<float>), dim3(cdiv(c->M, 256), n), dim3(256), 0, c->stream, c->M,
+                             c->lat.nx, c->lat.ny, c->lat.nz, c->kidx_dev, u0 - c->fun.mu, delta0, kx, ky, kz, isa,
+                             (cpx<float>*)c->sb[0], c->E, c->kperp2, c->mult);
+      });
+      set_weights(*c, n, nullptr);
+      after_load(*c);
+      HIPCHK(hipStreamSynchronize(c->stream));
+      return;
+    }
     const double isv = 1.0 / std::sqrt(c->vol);
     c->launch(KC_SETUP, [&] {
       if (c->esz == 16)
@@ -722,14 +782,14 @@ tdslda_status tdslda_init_plane_waves(tdslda_ctx* c, int64_t n, const int32_t* k
 
 tdslda_status tdslda_imprint_vortices(tdslda_ctx* c, int nv, const double* xyq) {
   return guard(c, [&] {
-    require(!c->q1d, TDSLDA_EINVAL, "vortex imprint is a 3D option");
+    require(!c->q1d, TDSLDA_EINVAL, "vortex imprint is a 3D and quasi-2D option");
     require(c->loaded, TDSLDA_EORDER, "load states first");
     require(nv > 0 && nv <= 64 && xyq, TDSLDA_EINVAL, "bad vortex list");
     double* buf = c->gscratch;
     HIPCHK(hipMemcpyAsync(buf, xyq, nv * 3 * 8, hipMemcpyHostToDevice, c->stream));
     c->launch(KC_SETUP, [&] {
       hipLaunchKernelGGL(k_vortex_phase, dim3(cdiv(c->M, 256)), dim3(256), 0, c->stream, c->M, c->lat.nx,
-                         c->lat.ny, c->lat.nz, c->lat.dx, c->lat.dy, nv, buf, c->theta);
+                         c->lat.ny, c->q2d ? 1 : c->lat.nz, c->lat.dx, c->lat.dy, nv, buf, c->theta);
     });
     c->launch(KC_SETUP, [&] {
       if (c->esz == 16)
@@ -823,6 +883,7 @@ tdslda_status tdslda_set_current_fields(tdslda_ctx* c, const double* alpha, cons
       HIPCHK(hipStreamSynchronize(c->stream));
       return;
     }
+    require(!c->q2d, TDSLDA_EINVAL, "the general operator is not built for the quasi-2D kernel set");
     require(c->frozen, TDSLDA_EORDER, "freeze the fields (tdslda_set_fields) first");
     const int ncomp = c->q1d ? 1 : 3;  // quasi-1D: A_z only; 3D: A_x, A_y, A_z
     for (int64_t i = 0; i < c->M; ++i)
@@ -903,6 +964,7 @@ tdslda_status tdslda_set_friction(tdslda_ctx* c, double alpha, double beta, doub
                                   double N_req) {
   return guard(c, [&] {
     require(!c->gen, TDSLDA_EINVAL, "quantum friction is built for the A = 1 operator");
+    require(!c->q2d, TDSLDA_EINVAL, "quantum friction is not built for the quasi-2D kernel set");
     require(std::isfinite(alpha) && std::isfinite(beta) && std::isfinite(gamma) && std::isfinite(N_req) &&
                 std::isfinite(rho0) && rho0 > 0.0,
             TDSLDA_EINVAL, "friction parameters must be finite, rho0 > 0");

@@ -14,7 +14,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtdslda.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, EORDER, EUNSTABLE = 0, -1, -2, -3, -4, -5
-MODE_3D, MODE_Q1D = 3, 1
+MODE_3D, MODE_Q1D, MODE_Q2D = 3, 1, 2
 FUNC_SLDA, FUNC_BDG = 1, 2
 FP64, FP32_MIXED = 0, 1
 AB3AM4, AB4AM5, AB5AM5 = 34, 45, 55
@@ -63,6 +63,7 @@ _SIGS = {
     "tdslda_load_states": [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p],
     "tdslda_load_states_device": [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p],
     "tdslda_init_plane_waves": [C.c_void_p, C.c_int64, C.c_void_p, C.c_double, C.c_double],
+    "tdslda_set_multiplicity": [C.c_void_p, C.c_int64, C.c_void_p],
     "tdslda_imprint_vortices": [C.c_void_p, C.c_int, C.c_void_p],
     "tdslda_set_fields": [C.c_void_p, C.c_void_p, C.c_void_p],
     "tdslda_set_current_fields": [C.c_void_p, C.c_void_p, C.c_void_p],
@@ -199,6 +200,8 @@ class Context:
         self.h = h
         if lattice.mode == MODE_3D:
             self.grid = (lattice.nx, lattice.ny, lattice.nz)
+        elif lattice.mode == MODE_Q2D:
+            self.grid = (lattice.nx, lattice.ny)
         else:
             self.grid = (lattice.nz,)
         self.M = int(np.prod(self.grid))
@@ -248,6 +251,10 @@ class Context:
     def init_plane_waves(self, kidx, u0, delta0):
         k = np.ascontiguousarray(kidx, dtype=np.int32)
         self._chk(self.lib.tdslda_init_plane_waves(self.h, k.shape[0], _p(k), float(u0), float(delta0)))
+
+    def set_multiplicity(self, mult):
+        m = _f64(mult).ravel()
+        self._chk(self.lib.tdslda_set_multiplicity(self.h, m.size, _p(m)))
 
     def imprint_vortices(self, vortices):
         v = _f64(vortices).reshape(-1, 3)
@@ -529,6 +536,12 @@ def lattice_3d(n, d=1.0):
 
 def lattice_q1d(nz, dz, lx, ly):
     return Lattice(MODE_Q1D, 1, 1, nz, 1.0, 1.0, dz, lx, ly)
+
+
+def lattice_q2d(nx, ny, nz, d=(1.0, 1.0, 1.0)):
+    """Quasi-2D: nx x ny x-y lattice, nz plane waves along z (L_z = nz dz)."""
+    dx, dy, dz = (d, d, d) if np.isscalar(d) else d
+    return Lattice(MODE_Q2D, nx, ny, nz, dx, dy, dz, 0.0, 0.0)
 
 
 def functional_slda(mu, ec_reg, A=1.0, B=None, C_=-11.11, temperature=0.0):

@@ -70,3 +70,20 @@ def test_td_matches_3d_product_states():
     o2, o3 = td.observables(s2, p2), td.observables(s3, p3)
     for key in ("kin", "pot", "pair", "curr", "potext", "N", "total"):
         assert o2[key] == pytest.approx(o3[key], rel=1e-10, abs=1e-12)
+
+
+def test_plane_waves_are_eigenstates_of_the_uniform_problem():
+    """The quasi-2D uniform start is an eigenvector of H with constant
+    fields (hfield = U - mu, Delta real) with eigenvalue E, for every class,
+    and normalised on the x-y lattice; the multiplicities count the two
+    signs of k_z except for k_z = 0 and the Nyquist class."""
+    geom = q2d.GeometryQ2D(6, 4, 6, 1.0, 1.3, 0.9)
+    kidx = np.array([(a, b, m) for a in range(6) for b in range(4) for m in range(4)])
+    E, kz2, mult, phi = q2d.plane_wave_states(geom, kidx, -0.7, 0.4)
+    geom.set_states(kz2)
+    hphi = geom.apply_h(phi, np.full(geom.shape, -0.7), np.full(geom.shape, 0.4 + 0j))
+    assert np.abs(hphi - E[:, None, None, None] * phi).max() < 1e-13
+    assert np.abs(geom.dV * np.sum(np.abs(phi) ** 2, axis=(1, 2, 3)) - 1).max() < 1e-13
+    assert set(mult[kidx[:, 2] == 0]) == {1.0} and set(mult[kidx[:, 2] == 3]) == {1.0}
+    assert set(mult[(kidx[:, 2] == 1) | (kidx[:, 2] == 2)]) == {2.0}
+    assert np.allclose(kz2, (2 * np.pi * kidx[:, 2] / (6 * 0.9)) ** 2)
