@@ -6,8 +6,10 @@ One step = one AB4AM5 step (two right-hand-side evaluations, each with a
 full density rebuild) of every evolved state.  The default workload is the
 plain FP64 32^3 trapped gas with one vortex (32,768 evolved states, 65,536
 represented); the FP32-mixed 48^3 run (8,192 evolved states) is reported in
-the same JSON line under "fp32_mixed".  value = evolved states x steps /
-wall time of the timed region (inputs resident in HBM, start-up excluded).
+the same JSON line under "fp32_mixed"; the batched quasi-1D, quasi-2D
+(64x64, N_z = 64, 135,168 states) and warm-start experiments follow under
+their own keys.  value = evolved states x steps / wall time of the timed
+region (inputs resident in HBM, start-up excluded).
 """
 import argparse
 import json
@@ -216,6 +218,50 @@ def run_q1d(steps, warmup, seed=7, profile_steps=2, friction=False, precision=No
                 check=dict(status=st, **chk), problems=info)
 
 
+def run_q2d(steps, warmup, seed_vortex=2, profile_steps=2, precision=None):
+    """Quasi-2D workload (workloads.Q2D): set-up, start-up and warm-up
+    steps, then `steps` steps of tdslda_abm_step timed between two device
+    synchronisations (one launch per kernel), then `profile_steps` more
+    with per-kernel events."""
+    import torch
+    from paper_2602_08982_amd import tdslda as T
+    from paper_2602_08982_amd import workloads as W
+    import synth
+    dx, dy = synth.vortex_offset(seed_vortex)
+    vort = [(dx, dy, 1.0)]
+    t0 = time.perf_counter()
+    ctx, kidx = W.setup_q2d(W.Q2D, vort, stream=torch.cuda.current_stream().cuda_stream, precision=precision)
+    ctx.abm_step(warmup)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    nst = len(kidx)
+    prec = W.Q2D["precision"] if precision is None else precision
+    M = W.Q2D["n"][0] * W.Q2D["n"][1]
+    S = 2 * M * (16 if prec == T.FP64 else 8)
+    t0 = time.perf_counter()
+    ctx.abm_step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kern = {}
+    if profile_steps:
+        ctx.set_profiling(True)
+        ctx.abm_step(profile_steps)
+        stats = ctx.kernel_stats()
+        ctx.set_profiling(False)
+        for k, (n, ms) in stats.items():
+            if n == 0:
+                continue
+            b = algorithmic_bytes(k, S, nst, 4, fused=True)
+            avg = ms / n
+            kern[k] = dict(launches=n, avg_ms=avg, total_ms=ms, gbps=(b / (avg * 1e-3) / 1e9) if b else None)
+    st, chk = ctx.check()
+    e = ctx.energy()
+    ctx.close()
+    return dict(nst=nst, steps=steps, seconds=dt, value=nst * steps / dt, ms_per_step=1e3 * dt / steps,
+                setup_seconds=t_setup, kernels=kern, profile_steps=profile_steps, S=S,
+                check=dict(status=st, **chk), N=e["N"], vortices=vort)
+
+
 def stream_rates():
     """This device's HBM stream rates from the library's own streaming
     kernels over 4 GiB (median of 5, HIP events on the launch stream):
@@ -351,6 +397,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--no-q1d", action="store_true")
+    ap.add_argument("--no-q2d", action="store_true")
+    ap.add_argument("--q2d-steps", type=int, default=100,
+                    help="steps of the quasi-2D 64x64 (N_z = 64) workload, FP32-mixed; half as many in FP64")
     ap.add_argument("--no-warmstart", action="store_true")
     ap.add_argument("--warmstart-size", choices=["small", "medium", "default", "large"], default="default",
                     help="small: 8x8x4 lattice, 48 training / 8 held-out solves (seconds); medium: 16x16x8, "
@@ -455,6 +504,14 @@ def main():
         q1dgen = run_q1d(args.q1d_general_steps, max(1, args.warmup), A=1.094, eager=args.q1d_eager)
         print(f"# batched q1d, general functional A = 1.094: {q1dgen['value']:.4g} state-steps/s over "
               f"{q1dgen['steps']} steps", file=sys.stderr, flush=True)
+    q2d = q2d64 = None
+    if not args.no_q2d and args.q2d_steps > 0:
+        q2d = run_q2d(args.q2d_steps, max(1, args.warmup))
+        print(f"# quasi-2D 64x64 (N_z = 64): {q2d['value']:.4g} state-steps/s, {q2d['ms_per_step']:.2f} ms/step "
+              f"({q2d['nst']} states)", file=sys.stderr, flush=True)
+        q2d64 = run_q2d(max(1, args.q2d_steps // 2), max(1, args.warmup), precision=T.FP64)
+        print(f"# quasi-2D FP64: {q2d64['value']:.4g} state-steps/s, {q2d64['ms_per_step']:.2f} ms/step",
+              file=sys.stderr, flush=True)
     warm = None
     if not args.no_warmstart:
         from paper_2602_08982_amd import warmstart as WS
@@ -571,6 +628,21 @@ def main():
             "kernels": q1dgen["kernels"], "check": q1dgen["check"],
             "roofline": roofline(dict(q1dgen, steps=q1dgen["profile_steps"]), rates, "float", 16, "q1dgen_",
                                  fused=True) if q1dgen["kernels"] else None,
+        }
+    if q2d is not None:
+        line["quasi2d"] = {
+            "workload": "quasi-2D trapped gas, 64x64 x-y lattice, N_z = 64 plane waves along z (33 |k_z| "
+                        "classes), one vortex line, all 135,168 plane-wave states, FP32 states / FP64 sums, "
+                        f"{q2d['steps']} AB4AM5 steps (one launch per kernel)",
+            "value": q2d["value"], "unit": "state-steps/s", "ms_per_step": q2d["ms_per_step"],
+            "states_evolved": q2d["nst"], "setup_seconds": q2d["setup_seconds"], "kernels": q2d["kernels"],
+            "check": q2d["check"],
+            "roofline": roofline(dict(q2d, steps=q2d["profile_steps"]), rates, "float", 64, "q2d_", fused=True)
+            if q2d["kernels"] else None,
+            "fp64": dict(value=q2d64["value"], ms_per_step=q2d64["ms_per_step"], steps=q2d64["steps"],
+                         kernels=q2d64["kernels"], check=q2d64["check"],
+                         roofline=roofline(dict(q2d64, steps=q2d64["profile_steps"]), rates, "double", 64, "q2d_",
+                                           fused=True) if q2d64["kernels"] else None),
         }
     if warm is not None:
         line["learned_warm_start"] = {

@@ -105,9 +105,11 @@ typedef struct {
  * fields.  Supported shapes: cubic N^3 with N in {4,6,8,12,16,24,32,48},
  * 8x8x16 (3D); N_z in {16,64,256} (Q1D: N_z = A^2 with A lanes per state);
  * N_x x N_y in {8x8, 12x12, 16x16, 24x16, 32x32, 48x48, 64x64} (Q2D: a state
- * per workgroup, its 2D Laplacian in LDS).  The quasi-1D and quasi-2D
- * evaluations do not use the intermediate buffer.  Errors: EINVAL
- * (including an unsupported shape, and A != 1 in Q2D), ENOMEM. */
+ * per workgroup, its 2D Laplacian in LDS; no intermediate buffer).  The
+ * quasi-1D evaluations use the intermediate buffer only in the start-up.
+ * Full-3D contexts hold at most 65535 states.  Errors: EINVAL (including an
+ * unsupported shape, a 3D capacity above 65535, and A != 1 in Q2D),
+ * ENOMEM. */
 tdslda_status tdslda_create(const tdslda_lattice* lat, const tdslda_functional* fun,
                             const tdslda_run* run, int64_t capacity, tdslda_ctx** out);
 tdslda_status tdslda_destroy(tdslda_ctx* ctx);

@@ -262,7 +262,8 @@ struct Engine3D final : Engine {
       A.a[i] = c.aco[i];
     }
     A.out64 = (cpx<double>*)d.out64;
-    dim3 grid(CFG::NGX, nst), block(CFG::TB);
+    A.nst = nst;
+    dim3 grid(CFG::NGX, state_rows(nst)), block(CFG::TB);
     if (d.mode == PW_NORM)
       c.launch(KC_NORM, [&] { hipLaunchKernelGGL((k_pointwise<R, NX, NY, NZ, PW_NORM>), grid, block, 0, c.stream, A); });
     else if (d.mode == PW_PRED)

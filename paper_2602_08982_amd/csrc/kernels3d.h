@@ -725,7 +725,11 @@ struct PwArgs {
   int np, nq;
   double b[5], a[5];
   cpx<double>* out64;     // SCALE: FP64 copy of the normalised state
+  int64_t nst;            // states (grid rows stride over them)
 };
+
+// grid rows of a per-state launch: states beyond it are strided over
+inline unsigned state_rows(int64_t nst) { return unsigned(nst < 65535 ? nst : 65535); }
 
 template <typename R, int NX, int NY, int NZ, int MODE, int NP = 4, int NQ = 5>
 __global__ __launch_bounds__((SlabCfg<NX, NY, NZ>::TB)) void k_pointwise(PwArgs<R> A) {
@@ -734,7 +738,7 @@ __global__ __launch_bounds__((SlabCfg<NX, NY, NZ>::TB)) void k_pointwise(PwArgs<
   constexpr int M = NX * NY * NZ;
   __shared__ double red[TB / kWave];
   const int g = blockIdx.x, tid = threadIdx.x;
-  const int64_t n = blockIdx.y;
+  for (int64_t n = blockIdx.y; n < A.nst; n += gridDim.y) {
   constexpr int ES = sizeof(cpx<R>);
   const int64_t so = n * 2 * M;
   const uint32_t SB = 2 * M * ES;
@@ -783,6 +787,7 @@ __global__ __launch_bounds__((SlabCfg<NX, NY, NZ>::TB)) void k_pointwise(PwArgs<
   if (MODE != PW_SCALE && A.nrm_part) {
     const double t = block_sum<TB>(nacc, red);
     if (tid == 0) A.nrm_part[n * A.nrm_stride + g] = t;
+  }
   }
 }
 
@@ -845,11 +850,11 @@ __global__ __launch_bounds__(TBG) void k_grad_axis(
 
 // plane-wave states of the uniform H; one block row per state
 template <typename R>
-__global__ void k_plane_waves(int64_t M, int nx, int ny, int nz, const int32_t* __restrict__ kidx,
+__global__ void k_plane_waves(int64_t M, int64_t nstates, int nx, int ny, int nz, const int32_t* __restrict__ kidx,
                               double hshift, double delta0, double kx, double ky, double kz,
                               double invsqrtV, cpx<R>* __restrict__ X, double* __restrict__ E) {
-  const int64_t n = blockIdx.y;
   const int64_t r = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  for (int64_t n = blockIdx.y; n < nstates; n += gridDim.y) {
   const int lx = kidx[3 * n], ly = kidx[3 * n + 1], lz = kidx[3 * n + 2];
   const int mx = lx < nx / 2 ? lx : lx - nx, my = ly < ny / 2 ? ly : ly - ny,
             mz = lz < nz / 2 ? lz : lz - nz;
@@ -858,7 +863,7 @@ __global__ void k_plane_waves(int64_t M, int nx, int ny, int nz, const int32_t* 
   const double e = sqrt(xi * xi + delta0 * delta0);
   const double uk = sqrt(0.5 * (1.0 + xi / e)), vk = sqrt(0.5 * (1.0 - xi / e));
   if (r == 0) E[n] = e;
-  if (r >= M) return;
+  if (r >= M) continue;
   const int ix = int(r / (int64_t(ny) * nz)), iy = int((r / nz) % ny), iz = int(r % nz);
   // phase / (2 pi) reduced exactly with integers
   const long fx = ((long(lx) * ix) % nx), fy = ((long(ly) * iy) % ny), fz = ((long(lz) * iz) % nz);
@@ -867,6 +872,7 @@ __global__ void k_plane_waves(int64_t M, int nx, int ny, int nz, const int32_t* 
   sincospi(2.0 * frac, &sn, &cs);
   X[n * 2 * M + r] = cpx<R>{R(uk * cs * invsqrtV), R(uk * sn * invsqrtV)};
   X[n * 2 * M + M + r] = cpx<R>{R(vk * cs * invsqrtV), R(vk * sn * invsqrtV)};
+  }
 }
 
 // vortex imprint: gauge rotation of both components by theta/2,
@@ -877,14 +883,15 @@ template <typename R>
 __global__ void k_imprint(int64_t M, int64_t nstates, const double* __restrict__ theta,
                           cpx<R>* __restrict__ X) {
   const int64_t r = int64_t(blockIdx.x) * 256 + threadIdx.x;
-  const int64_t n = blockIdx.y;
-  if (r >= M || n >= nstates) return;
+  if (r >= M) return;
   double sn, cs;
   sincos(0.5 * theta[r], &sn, &cs);
-  const cpx<R> u = X[n * 2 * M + r], v = X[n * 2 * M + M + r];
-  const double ur = u.x, ui = u.y, vr = v.x, vi = v.y;
-  X[n * 2 * M + r] = cpx<R>{R(ur * cs - ui * sn), R(ur * sn + ui * cs)};
-  X[n * 2 * M + M + r] = cpx<R>{R(vr * cs + vi * sn), R(vi * cs - vr * sn)};
+  for (int64_t n = blockIdx.y; n < nstates; n += gridDim.y) {
+    const cpx<R> u = X[n * 2 * M + r], v = X[n * 2 * M + M + r];
+    const double ur = u.x, ui = u.y, vr = v.x, vi = v.y;
+    X[n * 2 * M + r] = cpx<R>{R(ur * cs - ui * sn), R(ur * sn + ui * cs)};
+    X[n * 2 * M + M + r] = cpx<R>{R(vr * cs + vi * sn), R(vi * cs - vr * sn)};
+  }
 }
 
 // host FP64 states -> context precision (and back)

@@ -233,12 +233,12 @@ __global__ void k_weights(int64_t n, const double* __restrict__ E, double T, con
 // exp(i (k_x x + k_y y)) / sqrt(L_x L_y); writes E, k_z^2 and the class
 // multiplicity (1 for m_z = 0 and the Nyquist class, 2 otherwise)
 template <typename R>
-__global__ void k_q2_plane_waves(int64_t M, int nx, int ny, int nkz, const int32_t* __restrict__ kidx,
+__global__ void k_q2_plane_waves(int64_t M, int64_t nstates, int nx, int ny, int nkz, const int32_t* __restrict__ kidx,
                                  double hshift, double delta0, double kx, double ky, double kz, double invsqrtA,
                                  cpx<R>* __restrict__ X, double* __restrict__ E, double* __restrict__ kz2,
                                  double* __restrict__ mult) {
-  const int64_t n = blockIdx.y;
   const int64_t r = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  for (int64_t n = blockIdx.y; n < nstates; n += gridDim.y) {
   const int lx = kidx[3 * n], ly = kidx[3 * n + 1], mz = kidx[3 * n + 2];
   const int mx = lx < nx / 2 ? lx : lx - nx, my = ly < ny / 2 ? ly : ly - ny;
   const double kz2n = kz * kz * mz * mz;
@@ -251,7 +251,7 @@ __global__ void k_q2_plane_waves(int64_t M, int nx, int ny, int nkz, const int32
     kz2[n] = kz2n;
     mult[n] = (mz == 0 || 2 * mz == nkz) ? 1.0 : 2.0;
   }
-  if (r >= M) return;
+  if (r >= M) continue;
   const int ix = int(r / ny), iy = int(r % ny);
   const long fx = (long(lx) * ix) % nx, fy = (long(ly) * iy) % ny;
   const double frac = double(fx) / nx + double(fy) / ny;
@@ -259,6 +259,7 @@ __global__ void k_q2_plane_waves(int64_t M, int nx, int ny, int nkz, const int32
   sincospi(2.0 * frac, &sn, &cs);
   X[n * 2 * M + r] = cpx<R>{R(uk * cs * invsqrtA), R(uk * sn * invsqrtA)};
   X[n * 2 * M + M + r] = cpx<R>{R(vk * cs * invsqrtA), R(vk * sn * invsqrtA)};
+  }
 }
 
 }  // namespace tdslda

@@ -402,7 +402,8 @@ struct EngineQ2D final : Engine {
       A.a[i] = c.aco[i];
     }
     A.out64 = (cpx<double>*)d.out64;
-    const dim3 grid(1, nst), block(PCFG::TB);
+    A.nst = nst;
+    const dim3 grid(1, state_rows(nst)), block(PCFG::TB);
     if (d.mode == PW_NORM)
       c.launch(KC_NORM, [&] { hipLaunchKernelGGL((k_pointwise<R, 1, NX, NY, PW_NORM>), grid, block, 0, c.stream, A); });
     else if (d.mode == PW_PRED)

@@ -81,7 +81,7 @@ int64_t memory_bytes(const tdslda_lattice& lat, const tdslda_run& run, int64_t n
                                                   : lat.nz;
   const int64_t es = int64_t(eng->elem_size());
   const int64_t S = 2 * M * es;
-  int64_t b = (depth + 2) * n * S;                               // state buffers + T
+  int64_t b = (depth + (lat.mode == TDSLDA_MODE_Q2D ? 1 : 2)) * n * S;  // state buffers + T
   b += n * 8 * (5 + (depth + 1) + 1);                            // per-state arrays
   b += n * 8 * (eng->ngx() + eng->ngx() + eng->ncb());           // partial slots
   b += int64_t(cdiv(n, eng->group())) * 3 * M * 8 * (lat.mode == TDSLDA_MODE_3D ? 2 : 1);  // density (+ current) partials
@@ -551,11 +551,13 @@ tdslda_status tdslda_create(const tdslda_lattice* lat, const tdslda_functional* 
       c->dVe = c->dV;
       c->vol = c->M * c->dV;
     }
+    require(lat->mode != TDSLDA_MODE_3D || capacity <= 65535, TDSLDA_EINVAL,
+            "full-3D contexts hold at most 65535 states (one grid row per state)");
     c->cap = capacity;
     const int64_t M = c->M;
     const size_t S = size_t(2 * M) * c->esz;
     for (int b = 0; b <= c->depth; ++b) c->sb[b] = c->dalloc(S * capacity);
-    c->T = c->dalloc(S * capacity);
+    if (!c->q2d) c->T = c->dalloc(S * capacity);  // the quasi-2D passes need no intermediate
     for (int b = 0; b <= c->depth; ++b) c->sscale[b] = (double*)c->dalloc(8 * capacity);
     c->wu = (double*)c->dalloc(8 * capacity);
     c->wv = (double*)c->dalloc(8 * capacity);
@@ -750,11 +752,11 @@ tdslda_status tdslda_init_plane_waves(tdslda_ctx* c, int64_t n, const int32_t* k
       const double isa = 1.0 / std::sqrt(c->M * c->dV);  // 2D normalisation (1/L_z is in the densities)
       c->launch(KC_SETUP, [&] {
         if (c->esz == 16)
-          hipLaunchKernelGGL((k_q2_plane_waves<double>), dim3(cdiv(c->M, 256), n), dim3(256), 0, c->stream, c->M,
+          hipLaunchKernelGGL((k_q2_plane_waves<double>), dim3(cdiv(c->M, 256), state_rows(n)), dim3(256), 0, c->stream, c->M, n,
                              c->lat.nx, c->lat.ny, c->lat.nz, c->kidx_dev, u0 - c->fun.mu, delta0, kx, ky, kz, isa,
                              (cpx<double>*)c->sb[0], c->E, c->kperp2, c->mult);
         else
-          hipLaunchKernelGGL((k_q2_plane_waves<float>), dim3(cdiv(c->M, 256), n), dim3(256), 0, c->stream, c->M,
+          hipLaunchKernelGGL((k_q2_plane_waves<float>), dim3(cdiv(c->M, 256), state_rows(n)), dim3(256), 0, c->stream, c->M, n,
                              c->lat.nx, c->lat.ny, c->lat.nz, c->kidx_dev, u0 - c->fun.mu, delta0, kx, ky, kz, isa,
                              (cpx<float>*)c->sb[0], c->E, c->kperp2, c->mult);
       });
@@ -766,11 +768,11 @@ tdslda_status tdslda_init_plane_waves(tdslda_ctx* c, int64_t n, const int32_t* k
     const double isv = 1.0 / std::sqrt(c->vol);
     c->launch(KC_SETUP, [&] {
       if (c->esz == 16)
-        hipLaunchKernelGGL((k_plane_waves<double>), dim3(cdiv(c->M, 256), n), dim3(256), 0, c->stream, c->M,
+        hipLaunchKernelGGL((k_plane_waves<double>), dim3(cdiv(c->M, 256), state_rows(n)), dim3(256), 0, c->stream, c->M, n,
                            c->lat.nx, c->lat.ny, c->lat.nz, c->kidx_dev, u0 - c->fun.mu, delta0, kx, ky, kz, isv,
                            (cpx<double>*)c->sb[0], c->E);
       else
-        hipLaunchKernelGGL((k_plane_waves<float>), dim3(cdiv(c->M, 256), n), dim3(256), 0, c->stream, c->M,
+        hipLaunchKernelGGL((k_plane_waves<float>), dim3(cdiv(c->M, 256), state_rows(n)), dim3(256), 0, c->stream, c->M, n,
                            c->lat.nx, c->lat.ny, c->lat.nz, c->kidx_dev, u0 - c->fun.mu, delta0, kx, ky, kz, isv,
                            (cpx<float>*)c->sb[0], c->E);
     });
@@ -793,10 +795,10 @@ tdslda_status tdslda_imprint_vortices(tdslda_ctx* c, int nv, const double* xyq) 
     });
     c->launch(KC_SETUP, [&] {
       if (c->esz == 16)
-        hipLaunchKernelGGL((k_imprint<double>), dim3(cdiv(c->M, 256), c->nst), dim3(256), 0, c->stream, c->M,
+        hipLaunchKernelGGL((k_imprint<double>), dim3(cdiv(c->M, 256), state_rows(c->nst)), dim3(256), 0, c->stream, c->M,
                            c->nst, c->theta, (cpx<double>*)c->sb[c->phi]);
       else
-        hipLaunchKernelGGL((k_imprint<float>), dim3(cdiv(c->M, 256), c->nst), dim3(256), 0, c->stream, c->M,
+        hipLaunchKernelGGL((k_imprint<float>), dim3(cdiv(c->M, 256), state_rows(c->nst)), dim3(256), 0, c->stream, c->M,
                            c->nst, c->theta, (cpx<float>*)c->sb[c->phi]);
     });
     // a new initial state: restart the integrator from it

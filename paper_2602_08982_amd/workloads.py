@@ -10,6 +10,11 @@ The states themselves are generated and evolved by libtdslda.
                   with w_perp = 0.08, w_z = 0.02, a seeded vortex pair, the
                   8,192 plane-wave states with the smallest |xi_k| (16,384
                   quasiparticle states of both signs), complex64.
+  q2d_64        : quasi-2D, 64 x 64 x-y lattice, dx = 1, N_z = 64 plane waves
+                  along z (33 |k_z| classes), V_ext = omega^2 (x^2 + y^2)/2
+                  with omega = 0.05, one vortex line at the centre + a seeded
+                  offset, all 135,168 plane-wave states (every x-y momentum in
+                  every class), complex64 with FP64 sums.
 """
 import numpy as np
 
@@ -145,3 +150,37 @@ def setup_q1d(cfg, seed, stream=None, precision=None, nk=None, A=1.0):
                 count_min=int(counts.min()), count_mean=float(counts.mean()), count_max=int(counts.max()),
                 histogram=np.histogram(counts, bins=8)[0].tolist(), bump=bump, kperp2=kp2, counts=counts)
     return ctx, info
+
+
+# ---------------------------------------------------------------------------
+# Quasi-2D workload: the geometry of the static quasi-2D configuration (64 x
+# 64 x-y lattice, 64 plane waves along z) evolved in time.
+Q2D = dict(name="q2d_64", n=(64, 64), nz=64, d=(1.0, 1.0, 1.0), mu=1.0, u0=0.0, delta0=0.5, omega=0.05,
+           precision=T.FP32_MIXED, dt=0.005)
+
+
+def q2d_kidx(cfg):
+    """Every x-y lattice momentum in every |k_z| class m = 0 .. N_z/2,
+    class-major."""
+    nx, ny = cfg["n"]
+    m, a, b = np.meshgrid(np.arange(cfg["nz"] // 2 + 1), np.arange(nx), np.arange(ny), indexing="ij")
+    return np.stack([a.ravel(), b.ravel(), m.ravel()], axis=1).astype(np.int32)
+
+
+def setup_q2d(cfg, vortices, stream=None, precision=None, integrator=T.AB4AM5):
+    """Quasi-2D context: trap on (regulator frozen with V_+ = V_ext),
+    plane-wave states of every class generated on the device, vortices
+    imprinted.  Returns (ctx, kidx)."""
+    nx, ny = cfg["n"]
+    d = cfg["d"]
+    prec = cfg["precision"] if precision is None else precision
+    ec = 0.5 * (np.pi / d[0]) ** 2
+    kidx = q2d_kidx(cfg)
+    run = T.run_config(precision=prec, integrator=integrator, dt=cfg["dt"], selfstart=1, stream=stream)
+    ctx = T.Context(T.lattice_q2d(nx, ny, cfg["nz"], d), T.functional_slda(cfg["mu"], ec), run, len(kidx))
+    X, Y = np.meshgrid(centered(nx, d[0]), centered(ny, d[1]), indexing="ij")
+    ctx.set_external(0.5 * cfg["omega"] ** 2 * (X ** 2 + Y ** 2), freeze_regulator=True)
+    ctx.init_plane_waves(kidx, cfg["u0"], cfg["delta0"])
+    if len(vortices):
+        ctx.imprint_vortices(vortices)
+    return ctx, kidx

@@ -177,3 +177,54 @@ def test_q2d_refusals():
             ctx.set_current_fields(alpha=np.full(geom.shape, 1.1))
     finally:
         ctx.close()
+
+
+def test_q2d_bench_size_sampled():
+    """The 64 x 64, N_z = 64 workload of the benchmark in its own launch
+    configuration (135,168 states: more grid rows than one launch dimension
+    holds, so the per-state passes stride over states), FP32-mixed:
+    sampled start states against the oracle's plane-wave start with the
+    vortex, H phi of sampled states with the device's fields against the
+    oracle's operator, then 4 steps with the particle number and the norms
+    kept."""
+    from paper_2602_08982_amd import tdslda as T
+    from paper_2602_08982_amd import workloads as W
+    cfg = W.Q2D
+    vort = [(-0.95, -0.81, 1.0)]
+    ctx, kidx = W.setup_q2d(cfg, vort)
+    try:
+        nst = len(kidx)
+        assert nst == 64 * 64 * 33 > 65535
+        geom = q2d.GeometryQ2D(64, 64, 64, 1.0, 1.0, 1.0)
+        rng = np.random.default_rng(5)
+        pick = np.sort(np.concatenate([[0, nst - 1], rng.choice(nst, 62, replace=False)]))
+        E, kz2, mult, phi = q2d.plane_wave_states(geom, kidx[pick], cfg["u0"] - cfg["mu"], cfg["delta0"])
+        phi = bdg.imprint_phase(phi, q2d_vortex_theta(geom, np.array(vort)))
+        xd = torch.empty((nst, 2, 64 * 64), dtype=torch.complex64, device="cuda")
+        states = ctx.get_states()
+        assert np.abs(states[pick] - phi).max() < 2e-7
+        U, delta = ctx.get_fields()
+        X, Y = geom.static.coords()
+        vext = 0.5 * cfg["omega"] ** 2 * (X ** 2 + Y ** 2)
+        geom.set_states(kz2)
+        ref = geom.apply_h(phi, U + vext - cfg["mu"], delta)
+        xs = torch.from_numpy(states[pick].reshape(len(pick), 2, -1).astype(np.complex64)).cuda()
+        ys = torch.zeros_like(xs)
+        # apply_hbdg takes k_z^2 of the loaded state with the same index: put
+        # the sampled states at their own indices of a full-size input
+        xd.zero_()
+        xd[torch.from_numpy(pick).cuda()] = xs
+        yd = torch.zeros_like(xd)
+        ctx.apply_hbdg(xd, yd, nst)
+        torch.cuda.synchronize()
+        out = yd[torch.from_numpy(pick).cuda()].cpu().numpy().reshape(ref.shape)
+        assert np.abs(out - ref).max() / np.abs(ref).max() < 2e-6
+        del xd, yd, xs, ys
+        e0 = ctx.energy()
+        ctx.abm_step(4)
+        e1 = ctx.energy()
+        assert abs(e1["N"] - e0["N"]) / e0["N"] < 1e-6
+        st, chk = ctx.check()
+        assert chk["norm"] < 1e-5
+    finally:
+        ctx.close()
