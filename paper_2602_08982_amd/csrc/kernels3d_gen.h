@@ -80,6 +80,12 @@ __global__ __launch_bounds__(TBG) void k_jline(const cpx<R>* __restrict__ X, int
   for (int k = 0; k < NL; ++k) out[k * ST] = acc[k];
 }
 
+// A compiler-only memory fence (no instruction): the phases of a line pass
+// re-read phi and the fields instead of keeping them in registers across
+// the transforms (the loads would otherwise be merged or hoisted, which
+// costs more registers than the re-reads cost bandwidth)
+__device__ __forceinline__ void phase_fence() { __asm__ volatile("" ::: "memory"); }
+
 // -(i/2) c
 template <typename R>
 __device__ __forceinline__ cpx<R> minus_half_i(cpx<R> c) {
@@ -106,6 +112,9 @@ __global__ __launch_bounds__(TBG) void k_opline(const cpx<R>* __restrict__ X, co
   constexpr int64_t M = int64_t(NX) * NY * NZ;
   constexpr int ES = sizeof(cpx<R>), RS = sizeof(R);
   __shared__ double red[TBG / kWave];
+  // the running sum of the line's terms, element k of this thread's line at
+  // [k][thread]: one line array stays in registers (two more would spill)
+  __shared__ cpx<R> acc[NL][TBG];
   const int l = blockIdx.x * TBG + threadIdx.x;
   const bool act = l < LG::NLINES;
   const int s0 = act ? LG::site0(l) : 0;
@@ -119,35 +128,19 @@ __global__ __launch_bounds__(TBG) void k_opline(const cpx<R>* __restrict__ X, co
   const bi32x4 rAl = make_rsrc(hAl, uint32_t(M * RS)), rAd = make_rsrc(hAd, uint32_t(M * RS));
   const int vo = s0 * ES, va = s0 * RS;
   const R kk = R(kscale), inv_n = R(1.0 / NL);
+  const int tx = threadIdx.x;
   double hloc = 0.0;
   if (act) {
 #pragma unroll 1
     for (int comp = 0; comp < 2; ++comp) {
       const R sg = comp ? R(-1) : R(1);
       const int cb = int(comp * M);
-      cpx<R> t[NL], d1[NL], res[NL];
-      // D2 x and D1 x from one forward transform
+      cpx<R> t[NL];
+      cpx<R> nyq;
+      phase_fence();
+      // alpha D2 x
 #pragma unroll
       for (int k = 0; k < NL; ++k) t[k] = s * bload<R>(rX, vo, (cb + k * ST) * ES);
-      fwd<NL>(t);
-      sfor<0, NL>::run([&](auto pc) {
-        constexpr int p = decltype(pc)::value;
-        constexpr int fq = freq_of_pos<NL>(p);
-        constexpr int m = wavenum<NL>(fq);
-        const cpx<R> y = inv_n * t[p];
-        const R km = kk * R(m);
-        d1[p] = fq == NL / 2 ? cpx<R>{R(0), R(0)} : km * mul_i(y);
-        t[p] = (-km * km) * y;
-      });
-      inv<NL>(t);
-      inv<NL>(d1);
-#pragma unroll
-      for (int k = 0; k < NL; ++k) {
-        const R al = bload_real<R>(rAl, va, k * ST * RS), ad = bload_real<R>(rAd, va, k * ST * RS);
-        res[k] = (sg * R(-0.25) * al) * t[k] + minus_half_i(ad * d1[k]);
-        t[k] = al * (s * bload<R>(rX, vo, (cb + k * ST) * ES));
-      }
-      // D2(alpha x)
       fwd<NL>(t);
       sfor<0, NL>::run([&](auto pc) {
         constexpr int p = decltype(pc)::value;
@@ -157,16 +150,39 @@ __global__ __launch_bounds__(TBG) void k_opline(const cpx<R>* __restrict__ X, co
       });
       inv<NL>(t);
 #pragma unroll
-      for (int k = 0; k < NL; ++k) {
-        res[k] = res[k] + (sg * R(-0.25)) * t[k];
-        t[k] = bload_real<R>(rAd, va, k * ST * RS) * (s * bload<R>(rX, vo, (cb + k * ST) * ES));
-      }
-      // D1(A_d x)
-      cpx<R> nyq;
+      for (int k = 0; k < NL; ++k) acc[k][tx] = (sg * R(-0.25) * bload_real<R>(rAl, va, k * ST * RS)) * t[k];
+      phase_fence();
+      // A_d D1 x
+#pragma unroll
+      for (int k = 0; k < NL; ++k) t[k] = s * bload<R>(rX, vo, (cb + k * ST) * ES);
       first_derivative<NL>(t, kk, nyq);
 #pragma unroll
+      for (int k = 0; k < NL; ++k) acc[k][tx] = acc[k][tx] + minus_half_i(bload_real<R>(rAd, va, k * ST * RS) * t[k]);
+      phase_fence();
+      // D2(alpha x)
+#pragma unroll
+      for (int k = 0; k < NL; ++k)
+        t[k] = bload_real<R>(rAl, va, k * ST * RS) * (s * bload<R>(rX, vo, (cb + k * ST) * ES));
+      fwd<NL>(t);
+      sfor<0, NL>::run([&](auto pc) {
+        constexpr int p = decltype(pc)::value;
+        constexpr int m = wavenum_at<NL>(p);
+        const R km = kk * R(m);
+        t[p] = (-km * km * inv_n) * t[p];
+      });
+      inv<NL>(t);
+#pragma unroll
+      for (int k = 0; k < NL; ++k) acc[k][tx] = acc[k][tx] + (sg * R(-0.25)) * t[k];
+      phase_fence();
+      // D1(A_d x)
+#pragma unroll
+      for (int k = 0; k < NL; ++k)
+        t[k] = bload_real<R>(rAd, va, k * ST * RS) * (s * bload<R>(rX, vo, (cb + k * ST) * ES));
+      first_derivative<NL>(t, kk, nyq);
+      phase_fence();
+#pragma unroll
       for (int k = 0; k < NL; ++k) {
-        cpx<R> r = res[k] + minus_half_i(t[k]);
+        cpx<R> r = acc[k][tx] + minus_half_i(t[k]);
         const int o = (cb + k * ST) * ES;
         if constexpr (AXIS > 0) r = r + bload<R>(rT, vo, o);
         if constexpr (LAST) {
