@@ -61,7 +61,7 @@ typedef enum {
 } tdslda_status;
 
 enum { TDSLDA_MODE_3D = 3, TDSLDA_MODE_Q1D = 1, TDSLDA_MODE_Q2D = 2 };
-enum { TDSLDA_FUNC_SLDA = 1, TDSLDA_FUNC_BDG = 2 };
+enum { TDSLDA_FUNC_SLDA = 1, TDSLDA_FUNC_BDG = 2, TDSLDA_FUNC_ASLDA = 3 };
 enum { TDSLDA_FP64 = 0, TDSLDA_FP32_MIXED = 1 };
 enum { TDSLDA_AB3AM4 = 34, TDSLDA_AB4AM5 = 45, TDSLDA_AB5AM5 = 55 };
 
@@ -82,9 +82,22 @@ typedef struct {
                            (1 - A) j / rho, rebuilt with j at every field build) */
   double inv_g_bdg;     /* BdG: 1/(4 pi a_s) */
   double ec_reg;        /* cut-off energy E_c of the regulator Lambda_c (Eq. Creg) */
-  double mu;            /* chemical potential, fixed during TD */
+  double mu;            /* chemical potential, fixed during TD (ASLDA: mu_a) */
   double temperature;   /* T of the frozen weights f(E) = 1/(exp(E/T)+1); 0 = step */
+  double mu_b;          /* ASLDA: chemical potential of spin b (else unused) */
 } tdslda_functional;
+/* TDSLDA_FUNC_ASLDA (Sec. 2.4, ASLDA item; quasi-1D contexts only): the
+ * spin-imbalanced functional with A_a(p) = A(p), A_b(p) = A(-p), B(p) and
+ * C = -11.11 of the local polarisation p = (rho_a - rho_b) / rho_+.  Both
+ * branches of Eq. HpsiEpsi are evolved (load states of either sign of E; no
+ * E > 0 halving), the u row carries h_a - mu_a and the v row -h_b^* + mu_b,
+ * each h of Eq. h_sigma with its own alpha_s = A_s, current potential
+ * (1 - A_s) j_s / rho_s and V_s = dE/drho_s (the p-dependence of A_s and B
+ * included), densities of Eqs. na3D-jb3D with 1/(L_x L_y).  The fields
+ * A, B of this struct are not used.  Linear mode, friction and the
+ * general-operator fields are refused; tdslda_densities_spin gives the
+ * densities.  The regulator frozen by tdslda_set_external uses the spin
+ * averages A_+ = A(0), mu_+ = (mu_a + mu_b) / 2 (Eq. Creg). */
 
 typedef struct {
   int precision;        /* TDSLDA_FP64 or TDSLDA_FP32_MIXED (states, transforms and H.psi
@@ -209,7 +222,13 @@ tdslda_status tdslda_set_fields(tdslda_ctx* ctx, const double* U, const double* 
  * mode zeroed (Sec. 3.1).  Also refreshes the mean fields from rho, nu
  * unless they are frozen. */
 tdslda_status tdslda_densities(tdslda_ctx* ctx, double* rho, double* tau, double* nu_reim, double* j);
-/* Current mean fields (host FP64 out, any may be NULL): U[M], Delta[M][2]. */
+/* Spin-resolved densities of an ASLDA context (Eqs. na3D-jb3D), FP64 host
+ * outputs (any may be NULL): rho[2][M], tau[2][M] (spin a then b), nu[M][2],
+ * j[2][M] (the z component of j_a, j_b).  Also refreshes the mean fields.
+ * Errors: EINVAL (not an ASLDA context), EORDER (nothing loaded). */
+tdslda_status tdslda_densities_spin(tdslda_ctx* ctx, double* rho, double* tau, double* nu_reim, double* j);
+/* Current mean fields (host FP64 out, any may be NULL): U[M], Delta[M][2]
+ * (ASLDA: U[2][M], V_a then V_b). */
 tdslda_status tdslda_get_fields(tdslda_ctx* ctx, double* U, double* delta_reim);
 
 /* H psi with the current fields, unshifted and unnormalised, for n states of

@@ -144,6 +144,10 @@ struct tdslda_ctx {
   void *hAx = nullptr, *hAy = nullptr;  // 3D: the x and y components of A
   double* jpart = nullptr;              // 3D: current group partials [group][3][M]
   bool gen = false;
+  // spin-imbalanced ASLDA (quasi-1D kernel set): both branches evolved,
+  // spin-resolved densities and fields ([spin][M] for rho, tau, j, U and
+  // the fields of H)
+  bool aslda = false;
   double* gscratch = nullptr;  // [gchunk][4][M] doubles (tau_s, j_s); also FP64 staging
   int64_t gchunk = 1;
   double* eout = nullptr;

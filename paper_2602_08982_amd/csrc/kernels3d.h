@@ -244,9 +244,12 @@ __global__ __launch_bounds__((SlabCfg<NX, NY, NZ>::TB)) void k_dens(
 //   grid = (ceil(M / (TB DS_P)), ceil(nstates / DG)), block = TB
 //   dens_part layout [group][3][M]
 constexpr int DS_TB = 256, DS_P = 2;
-// NC: components per group in the partial layout (3; 4 when a fourth,
-// written by another pass, follows)
-template <typename R, int DG, int PS = DS_P, int NC = 3>
+// NC: components per group in the partial layout (3; more when further
+// components, written by another pass, follow).  SPIN: the spin-resolved
+// densities of both branches (Eqs. na3D-jb3D): rho_a = sum f_u |u|^2,
+// rho_b = sum f_v |v|^2 and nu = 1/2 sum (f_v - f_u) u v^*, in components
+// 0 .. 3 (rho_a, rho_b, Re nu, Im nu).
+template <typename R, int DG, int PS = DS_P, int NC = 3, bool SPIN = false>
 __global__ __launch_bounds__(DS_TB) void k_dens_sum(
     const cpx<R>* __restrict__ X, int64_t nstates, int64_t M, const double* __restrict__ wu,
     const double* __restrict__ wv, const double* __restrict__ scale, double* __restrict__ dens_part) {
@@ -254,14 +257,17 @@ __global__ __launch_bounds__(DS_TB) void k_dens_sum(
   const int64_t site0 = int64_t(blockIdx.x) * (DS_TB * PS) + tid;
   const int64_t nbeg = int64_t(blockIdx.y) * DG;
   const int nloc = int(nstates - nbeg < DG ? nstates - nbeg : DG);
-  double ar[PS], anr[PS], ani[PS];
+  double ar[PS], ab[SPIN ? PS : 1], anr[PS], ani[PS];
 #pragma unroll
-  for (int i = 0; i < PS; ++i) ar[i] = anr[i] = ani[i] = 0.0;
+  for (int i = 0; i < PS; ++i) {
+    ar[i] = anr[i] = ani[i] = 0.0;
+    if constexpr (SPIN) ab[i] = 0.0;
+  }
   const cpx<R>* xb = X + nbeg * 2 * M;
 #pragma unroll 4
   for (int ls = 0; ls < nloc; ++ls) {
     const double s = scale[nbeg + ls], fu = wu[nbeg + ls], fv = wv[nbeg + ls];
-    const double s2 = s * s, cu = fu * s2, cv = fv * s2, cw = (fv - fu) * s2;
+    const double s2 = s * s, cu = fu * s2, cv = fv * s2, cw = (SPIN ? 0.5 : 1.0) * (fv - fu) * s2;
     const cpx<R>* xs = xb + int64_t(ls) * 2 * M;
 #pragma unroll
     for (int i = 0; i < PS; ++i) {
@@ -269,20 +275,27 @@ __global__ __launch_bounds__(DS_TB) void k_dens_sum(
       if (r < M) {
         const cpx<R> u = ld_stream(xs + r), v = ld_stream(xs + M + r);
         const double ur = u.x, ui = u.y, vr = v.x, vi = v.y;
-        ar[i] += cv * (vr * vr + vi * vi) + cu * (ur * ur + ui * ui);
+        if constexpr (SPIN) {
+          ar[i] += cu * (ur * ur + ui * ui);
+          ab[i] += cv * (vr * vr + vi * vi);
+        } else {
+          ar[i] += cv * (vr * vr + vi * vi) + cu * (ur * ur + ui * ui);
+        }
         anr[i] += cw * (ur * vr + ui * vi);  // u v^*
         ani[i] += cw * (ui * vr - ur * vi);
       }
     }
   }
   double* out = dens_part + int64_t(blockIdx.y) * NC * M;
+  constexpr int ON = SPIN ? 2 : 1;  // first nu component
 #pragma unroll
   for (int i = 0; i < PS; ++i) {
     const int64_t r = site0 + i * DS_TB;
     if (r < M) {
       out[r] = ar[i];
-      out[M + r] = anr[i];
-      out[2 * M + r] = ani[i];
+      if constexpr (SPIN) out[M + r] = ab[i];
+      out[ON * M + r] = anr[i];
+      out[(ON + 1) * M + r] = ani[i];
     }
   }
 }
@@ -892,6 +905,38 @@ __global__ void k_imprint(int64_t M, int64_t nstates, const double* __restrict__
     X[n * 2 * M + r] = cpx<R>{R(ur * cs - ui * sn), R(ur * sn + ui * cs)};
     X[n * 2 * M + M + r] = cpx<R>{R(vr * cs + vi * sn), R(vi * cs - vr * sn)};
   }
+}
+
+// D2 of a real field on an N-point periodic axis (N <= 256, one workgroup):
+// out = Re 1/N sum_k (-k^2) f~_k exp(2 pi i k z / N), f~ by direct sums,
+// the Nyquist mode kept (Eq. D2); f also converted to the context precision.
+template <typename R>
+__global__ __launch_bounds__(256) void k_field_d2(int N, double dz, const double* __restrict__ f,
+                                                  R* __restrict__ fout, R* __restrict__ out) {
+  __shared__ double fr[256], fi[256];
+  const int t = threadIdx.x;
+  if (t < N) {
+    double re = 0.0, im = 0.0;
+    for (int z = 0; z < N; ++z) {
+      double s_, c_;
+      sincos(-2.0 * kPi * double((int64_t(t) * z) % N) / N, &s_, &c_);
+      re += f[z] * c_;
+      im += f[z] * s_;
+    }
+    fr[t] = re;
+    fi[t] = im;
+  }
+  __syncthreads();
+  if (t >= N) return;
+  double acc = 0.0;
+  for (int k = 0; k < N; ++k) {
+    const double km = 2.0 * kPi / (N * dz) * double(k < N / 2 ? k : k - N);
+    double s_, c_;
+    sincos(2.0 * kPi * double((int64_t(k) * t) % N) / N, &s_, &c_);
+    acc += -km * km * (fr[k] * c_ - fi[k] * s_);
+  }
+  out[t] = R(acc / N);
+  fout[t] = R(f[t]);
 }
 
 // host FP64 states -> context precision (and back)

@@ -86,6 +86,49 @@ __global__ __launch_bounds__(1024) void k_energy(int64_t M, const double* __rest
   }
 }
 
+// Energy terms of the spin-imbalanced ASLDA functional (Sec. 2.4) from the
+// spin-resolved densities ([spin][M]: rho, tau, j_z; nu [M][2]; Delta as
+// built): E_kin = sum_s A_s/2 (tau_s - j_s^2/rho_s), E_pot = 3/5 B rho_+ eF,
+// E_pair = -Re Delta^* nu, E_curr = sum_s j_s^2 / (2 rho_s), E_ext =
+// V_ext rho_+, rho_+, E_pair.ext, each times dVe; out[7] = N_a, out[8] = N_b.
+__device__ __forceinline__ double host_aslda_A(double p) {
+  const double p2 = p * p;
+  return 1.094 + 0.156 * p * (1.0 - 2.0 * p2 / 3.0 + p2 * p2 / 5.0) - 0.532 * p2 * (1.0 - p2 + p2 * p2 / 3.0);
+}
+__global__ __launch_bounds__(1024) void k_energy_aslda(int64_t M, const double* __restrict__ rho,
+                                                       const double* __restrict__ tau,
+                                                       const double* __restrict__ nu,
+                                                       const double* __restrict__ j,
+                                                       const double* __restrict__ delta,
+                                                       const double* __restrict__ vext,
+                                                       const double* __restrict__ dext, double dVe,
+                                                       double* __restrict__ out) {
+  __shared__ double red[1024 / kWave];
+  double ek = 0, ep = 0, epa = 0, ec = 0, ee = 0, nn = 0, epx = 0, na = 0, nb = 0;
+  for (int64_t r = threadIdx.x; r < M; r += 1024) {
+    const double ra = fmax(rho[r], 0.5e-14), rb = fmax(rho[M + r], 0.5e-14), rp = ra + rb;
+    const double p = (ra - rb) / rp;
+    const double Aa = host_aslda_A(p), Ab = host_aslda_A(-p);
+    const double hp = 0.5 * (1.0 + p), hm = 0.5 * (1.0 - p);
+    const double B = 1.5874010519681994 * (0.357 + 0.642 * p * p - Aa * pow(hp, 5.0 / 3.0) - Ab * pow(hm, 5.0 / 3.0));
+    const double ja = j[r], jb = j[M + r];
+    ek += 0.5 * Aa * (tau[r] - ja * ja / ra) + 0.5 * Ab * (tau[M + r] - jb * jb / rb);
+    ep += 0.6 * B * rp * 0.5 * pow(3.0 * kPi * kPi * rp, 2.0 / 3.0);
+    epa -= delta[2 * r] * nu[2 * r] + delta[2 * r + 1] * nu[2 * r + 1];
+    ec += ja * ja / (2.0 * ra) + jb * jb / (2.0 * rb);
+    ee += vext[r] * (rho[r] + rho[M + r]);
+    nn += rho[r] + rho[M + r];
+    na += rho[r];
+    nb += rho[M + r];
+    epx -= 2.0 * (dext[2 * r] * nu[2 * r] + dext[2 * r + 1] * nu[2 * r + 1]);
+  }
+  double v[9] = {ek, ep, epa, ec, ee, nn, epx, na, nb};
+  for (int k = 0; k < 9; ++k) {
+    const double t = block_sum<1024>(v[k], red);
+    if (threadIdx.x == 0) out[k] = t * dVe;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Streaming copy: each thread moves CP_U 16-byte words with non-temporal
 // 128-bit loads and stores; consecutive lanes touch consecutive words.
@@ -165,37 +208,6 @@ __global__ void k_fill_real(int64_t M, double value, R* __restrict__ out) {
   if (r < M) out[r] = R(value);
 }
 
-// D2 of a real field on an N-point periodic axis (N <= 256, one workgroup):
-// out = Re 1/N sum_k (-k^2) f~_k exp(2 pi i k z / N), f~ by direct sums,
-// the Nyquist mode kept (Eq. D2); f also converted to the context precision.
-template <typename R>
-__global__ __launch_bounds__(256) void k_field_d2(int N, double dz, const double* __restrict__ f,
-                                                  R* __restrict__ fout, R* __restrict__ out) {
-  __shared__ double fr[256], fi[256];
-  const int t = threadIdx.x;
-  if (t < N) {
-    double re = 0.0, im = 0.0;
-    for (int z = 0; z < N; ++z) {
-      double s_, c_;
-      sincos(-2.0 * kPi * double((int64_t(t) * z) % N) / N, &s_, &c_);
-      re += f[z] * c_;
-      im += f[z] * s_;
-    }
-    fr[t] = re;
-    fi[t] = im;
-  }
-  __syncthreads();
-  if (t >= N) return;
-  double acc = 0.0;
-  for (int k = 0; k < N; ++k) {
-    const double km = 2.0 * kPi / (N * dz) * double(k < N / 2 ? k : k - N);
-    double s_, c_;
-    sincos(2.0 * kPi * double((int64_t(k) * t) % N) / N, &s_, &c_);
-    acc += -km * km * (fr[k] * c_ - fi[k] * s_);
-  }
-  out[t] = R(acc / N);
-  fout[t] = R(f[t]);
-}
 
 // theta(x, y) of straight vortex lines along z (centred coordinates)
 __global__ void k_vortex_phase(int64_t M, int nx, int ny, int nz, double dx, double dy, int nv,

@@ -880,6 +880,216 @@ __global__ __launch_bounds__(256) void q_reduce_gen(const double* __restrict__ p
   hAz[r] = R(cA * sj / rs);
 }
 
+// ---------------------------------------------------------------------------
+// Spin-imbalanced ASLDA (Sec. 2.4, ASLDA item; Sec. 2.3): both branches of
+// the reduced problem are evolved (states of either sign of E) and the
+// densities are spin-resolved (Eqs. na3D-jb3D); the functional parameters
+// depend on the local polarisation p = (rho_a - rho_b) / rho_+.
+//
+// q_taujs: per spin the kinetic and current densities of a group of G
+// states, as components 4..7 of the [group][8][N] layout whose components
+// 0..3 (rho_a, rho_b, Re nu, Im nu) the transform-free pass writes:
+//   tau_a = sum f_u (k_perp^2 |u|^2 + |D1 u|^2 + (pi/dz)^2 |c_u|^2),  tau_b with v, f_v,
+//   j_a = -sum f_u Im(u (D1 u)^*),  j_b = sum f_v Im(v (D1 v)^*),
+// D1 with the Nyquist bin zeroed and c the Nyquist amplitude; a component
+// with zero weight in every state of the workgroup is skipped.
+template <typename R, int A, int G, int TB>
+__global__ __launch_bounds__(TB) void q_taujs(const cpx<R>* __restrict__ X, int64_t nstates,
+                                               const double* __restrict__ wu, const double* __restrict__ wv,
+                                               const double* __restrict__ scale, const double* __restrict__ kperp2,
+                                               double* __restrict__ part, const cpx<R>* __restrict__ tw, double kz,
+                                               double nyq2) {
+  using CFG = Q1DCfg<R, A, TB>;
+  constexpr int N = CFG::N, WS = CFG::WS;
+  constexpr int NW = CFG::TB / kWave;
+  __shared__ cpx<R> lds_all[WS][A * CFG::PAD];
+  __shared__ cpx<R> nyq_s[WS];
+  __shared__ double red[NW][N];
+  const int tid = threadIdx.x, grp = tid / A, a = tid % A;
+  const int w = tid / kWave, lw = tid % kWave;
+  cpx<R>* lds = lds_all[grp];
+  const R f = R(kz / double(N));
+  const int64_t nbeg = int64_t(blockIdx.x) * G;
+  double* out = part + int64_t(blockIdx.x) * 8 * N;
+#pragma unroll 1
+  for (int comp = 0; comp < 2; ++comp) {
+    const double sgn = comp ? 1.0 : -1.0;
+    double at[A], aj[A];
+#pragma unroll
+    for (int b = 0; b < A; ++b) at[b] = aj[b] = 0.0;
+    for (int it = 0; it < G / WS; ++it) {
+      const int64_t n = nbeg + it * WS + grp;
+      const bool live = n < nstates;
+      const int64_t nn = live ? n : 0;
+      const double wgt = live ? (comp ? wv[nn] : wu[nn]) : 0.0;
+      if (!__syncthreads_or(wgt != 0.0)) continue;
+      const R s = R(scale[nn]);
+      const double kp = kperp2[nn];
+      const cpx<R>* src = X + nn * 2 * N + comp * N;
+      cpx<R> x[A], d[A];
+#pragma unroll
+      for (int b = 0; b < A; ++b) {
+        x[b] = s * src[a + A * b];
+        d[b] = x[b];
+      }
+      q_fwd<R, A>(d, a, lds, tw);
+      sfor<0, A>::run([&](auto pc) {
+        constexpr int p = decltype(pc)::value;
+        const int k = a + A * freq_of_pos<A>(p);
+        if (k == N / 2) {
+          nyq_s[grp] = (R(1) / R(N)) * d[p];
+          d[p] = cpx<R>{R(0), R(0)};
+        } else {
+          const int m = k < N / 2 ? k : k - N;
+          d[p] = (f * R(m)) * mul_i(d[p]);
+        }
+      });
+      q_inv<R, A>(d, a, lds, tw);  // its barriers make nyq_s visible
+      const double cn = nyq2 * norm2(nyq_s[grp]);
+#pragma unroll
+      for (int b = 0; b < A; ++b) {
+        at[b] += wgt * (kp * norm2(x[b]) + norm2(d[b]) + cn);
+        aj[b] += sgn * wgt * (double(x[b].y) * double(d[b].x) - double(x[b].x) * double(d[b].y));
+      }
+    }
+    // sum over the workgroup's lane groups: within a wave, then over waves
+#pragma unroll
+    for (int b = 0; b < A; ++b) {
+#pragma unroll
+      for (int o = A; o < kWave; o <<= 1) {
+        at[b] += __shfl_xor(at[b], o, kWave);
+        aj[b] += __shfl_xor(aj[b], o, kWave);
+      }
+    }
+    __syncthreads();
+    if (lw < A) {
+#pragma unroll
+      for (int b = 0; b < A; ++b) red[w][a + A * b] = at[b];
+    }
+    __syncthreads();
+    for (int i = tid; i < N; i += CFG::TB) {
+      double t = 0.0;
+#pragma unroll
+      for (int w2 = 0; w2 < NW; ++w2) t += red[w2][i];
+      out[(4 + comp) * N + i] = t;
+    }
+    __syncthreads();
+    if (lw < A) {
+#pragma unroll
+      for (int b = 0; b < A; ++b) red[w][a + A * b] = aj[b];
+    }
+    __syncthreads();
+    for (int i = tid; i < N; i += CFG::TB) {
+      double t = 0.0;
+#pragma unroll
+      for (int w2 = 0; w2 < NW; ++w2) t += red[w2][i];
+      out[(6 + comp) * N + i] = t;
+    }
+  }
+}
+
+// ASLDA parameters (Sec. 2.4): A(p), its derivative, B(p) and its derivative
+__device__ __forceinline__ double aslda_A(double p) {
+  const double p2 = p * p;
+  return 1.094 + 0.156 * p * (1.0 - 2.0 * p2 / 3.0 + p2 * p2 / 5.0) - 0.532 * p2 * (1.0 - p2 + p2 * p2 / 3.0);
+}
+__device__ __forceinline__ double aslda_dA(double p) {
+  const double p2 = p * p;
+  return 0.156 * (1.0 - 2.0 * p2 + p2 * p2) - 0.532 * (2.0 * p - 4.0 * p2 * p + 2.0 * p2 * p2 * p);
+}
+__device__ __forceinline__ double aslda_B(double p) {
+  const double hp = 0.5 * (1.0 + p), hm = 0.5 * (1.0 - p);
+  return 1.5874010519681994 * (0.357 + 0.642 * p * p - aslda_A(p) * pow(hp, 5.0 / 3.0) -
+                               aslda_A(-p) * pow(hm, 5.0 / 3.0));
+}
+__device__ __forceinline__ double aslda_dB(double p) {
+  const double hp = 0.5 * (1.0 + p), hm = 0.5 * (1.0 - p);
+  return 1.5874010519681994 *
+         (1.284 * p - aslda_dA(p) * pow(hp, 5.0 / 3.0) - aslda_A(p) * (5.0 / 6.0) * pow(hp, 2.0 / 3.0) +
+          aslda_dA(-p) * pow(hm, 5.0 / 3.0) + aslda_A(-p) * (5.0 / 6.0) * pow(hm, 2.0 / 3.0));
+}
+
+// one workgroup per site: the eight group partials summed in a fixed order
+// (times 1/(L_x L_y)), then the ASLDA potentials, the functional
+// derivatives of
+//   sum_s A_s/2 (tau_s - j_s^2/rho_s) + 3/5 B rho_+ eF(rho_+) + g_eff |nu|^2
+//   + sum_s j_s^2 / (2 rho_s),   A_a = A(p), A_b = A(-p):
+//   V_s = dp/drho_s [1/2 (A'(p) K_a - A'(-p) K_b) + 3/5 B'(p) rho_+ eF]
+//         + (A_s - 1) j_s^2 / (2 rho_s^2) + B eF - |Delta|^2 / (3 C rho_+^(2/3)),
+//   K_s = tau_s - j_s^2 / rho_s, dp/drho_a = 2 rho_b / rho_+^2,
+//   dp/drho_b = -2 rho_a / rho_+^2;  alpha_s = A_s, A_s,z = (1 - A_s) j_s / rho_s,
+//   Delta = -g_eff nu.  Spin-resolved arrays are [spin][N] (a first); the
+// fields of H: hA = V_s + V_ext - mu_s, hAz, and alpha_s into aout (FP64,
+// for the D2 alpha pass).
+template <typename R>
+__global__ __launch_bounds__(256) void q_reduce_aslda(const double* __restrict__ part, int ngroups, int N,
+                                                      FunParams fp, double mu_b, const double* __restrict__ lam,
+                                                      const double* __restrict__ vext, double* __restrict__ rho,
+                                                      double* __restrict__ tau, double* __restrict__ nu,
+                                                      double* __restrict__ jc, double* __restrict__ U,
+                                                      double* __restrict__ delta, R* __restrict__ hA,
+                                                      cpx<R>* __restrict__ hD, R* __restrict__ hAz,
+                                                      double* __restrict__ aout, int update_fields) {
+  __shared__ double t8[8][256];
+  const int r = blockIdx.x, t = threadIdx.x;
+  double acc[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) acc[c] = 0.0;
+  for (int g = t; g < ngroups; g += 256) {
+    const double* p = part + int64_t(g) * 8 * N;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) acc[c] += p[c * N + r];
+  }
+#pragma unroll
+  for (int c = 0; c < 8; ++c) t8[c][t] = acc[c];
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (t < k) {
+#pragma unroll
+      for (int c = 0; c < 8; ++c) t8[c][t] += t8[c][t + k];
+    }
+    __syncthreads();
+  }
+  if (t != 0) return;
+  double v[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) v[c] = fp.ainv * t8[c][0];
+  const double sra = v[0], srb = v[1], snr = v[2], sni = v[3], ta = v[4], tb = v[5], ja = v[6], jb = v[7];
+  rho[r] = sra;
+  rho[N + r] = srb;
+  nu[2 * r] = snr;
+  nu[2 * r + 1] = sni;
+  tau[r] = ta;
+  tau[N + r] = tb;
+  jc[r] = ja;
+  jc[N + r] = jb;
+  jc[2 * N + r] = 0.0;
+  if (!update_fields) return;
+  const double ra = fmax(sra, 0.5e-14), rb = fmax(srb, 0.5e-14), rp = ra + rb;
+  const double p = (ra - rb) / rp;
+  const double Aa = aslda_A(p), Ab = aslda_A(-p), B = aslda_B(p);
+  const double gg = 1.0 / (cbrt(rp) / fp.C - lam[r]);
+  const double dr = -gg * snr, di = -gg * sni;
+  const double ef = 0.5 * pow(3.0 * kPi * kPi * rp, 2.0 / 3.0);
+  const double c23 = cbrt(rp);
+  const double Ka = ta - ja * ja / ra, Kb = tb - jb * jb / rb;
+  const double common = 0.5 * (aslda_dA(p) * Ka - aslda_dA(-p) * Kb) + 0.6 * aslda_dB(p) * rp * ef;
+  const double base = B * ef - (dr * dr + di * di) / (3.0 * fp.C * c23 * c23);
+  const double Va = 2.0 * rb / (rp * rp) * common + (Aa - 1.0) * ja * ja / (2.0 * ra * ra) + base;
+  const double Vb = -2.0 * ra / (rp * rp) * common + (Ab - 1.0) * jb * jb / (2.0 * rb * rb) + base;
+  U[r] = Va;
+  U[N + r] = Vb;
+  delta[2 * r] = dr;
+  delta[2 * r + 1] = di;
+  hA[r] = R(Va + vext[r] - fp.mu);
+  hA[N + r] = R(Vb + vext[r] - mu_b);
+  hD[r] = cpx<R>{R(dr + fp.dext[2 * r]), R(di + fp.dext[2 * r + 1])};
+  hAz[r] = R((1.0 - Aa) * ja / ra);
+  hAz[N + r] = R((1.0 - Ab) * jb / rb);
+  aout[r] = Aa;
+  aout[N + r] = Ab;
+}
+
 // the general operator in the split layout (as q_corr_split: 2A lanes per
 // state, u on the first A, v on the others), every mode:
 //   H / TAYLOR: the operator of the prepared fields with the given shift,
@@ -893,7 +1103,8 @@ constexpr int L2_EXPECT = 5;
 template <typename R, int A, int TB, int MODE, int NP = 4, int NQ = 5>
 __global__ __launch_bounds__(TB) void q_gen(Lap2Args<R> P, int64_t nstates, const double* __restrict__ kperp2,
                                             const R* __restrict__ hAl, const R* __restrict__ hAz,
-                                            const R* __restrict__ hLa, const cpx<R>* __restrict__ tw, double kz) {
+                                            const R* __restrict__ hLa, const cpx<R>* __restrict__ tw, double kz,
+                                            int fcs) {
   constexpr int HD = (NP > NQ - 1) ? NP : NQ - 1;
   constexpr int N = A * A, L = 2 * A, WS = TB / L, PAD = A + 1;
   static_assert(TB % L == 0 && kWave % L == 0, "a state's lanes must sit in one wave");
@@ -908,6 +1119,12 @@ __global__ __launch_bounds__(TB) void q_gen(Lap2Args<R> P, int64_t nstates, cons
   const int64_t base = n * 2 * N + int64_t(comp) * N;
   cpx<R>* lds = lds_all[2 * grp + comp];
   const R inv_n = R(1.0 / N);
+  // fields of this row's spin (fcs = N: [spin][N] arrays; 0: one set)
+  const int fo = comp * fcs;
+  hAl += fo;
+  hAz += fo;
+  hLa += fo;
+  const R* hAs = P.hA + fo;
   cpx<R> x[A], t[A], d1[A], kx[A];
 #pragma unroll
   for (int b = 0; b < A; ++b) {
@@ -968,7 +1185,7 @@ __global__ __launch_bounds__(TB) void q_gen(Lap2Args<R> P, int64_t nstates, cons
     const cpx<R> D = P.hD[z];
     const cpx<R> Dc = comp ? conj(D) : D;
     const cpx<R> c = d1[b] + t[b];
-    kx[b] = sg * (kx[b] + P.hA[z] * x[b]) + cpx<R>{R(0.5) * c.y, R(-0.5) * c.x} + Dc * y;
+    kx[b] = sg * (kx[b] + hAs[z] * x[b]) + cpx<R>{R(0.5) * c.y, R(-0.5) * c.x} + Dc * y;
     hloc += double(x[b].x) * double(kx[b].x) + double(x[b].y) * double(kx[b].y);
   }
   R h;
@@ -1076,6 +1293,22 @@ struct EngineQ1D final : Engine {
   void dens(Ctx& c, const void* X, const double* scale, int64_t nst) override {
     twiddles(c);
     const unsigned ng = cdiv(nst, G);
+    if (c.aslda) {  // spin-resolved rho, nu (no transform), then tau and j per spin
+      const double kz = 2 * kPi / (N * c.lat.dz), pz = kPi / c.lat.dz;
+      c.launch(KC_DENS, [&] {
+        hipLaunchKernelGGL((k_dens_sum<R, G, 1, 8, true>), dim3(cdiv(N, DS_TB), ng), dim3(DS_TB), 0, c.stream,
+                           (const cpx<R>*)X, nst, int64_t(N), c.wu, c.wv, scale, c.dens_part);
+      });
+      with_tb(tb[0], [&](auto t) {
+        constexpr int TB = decltype(t)::value;
+        c.launch(KC_DENS, [&] {
+          hipLaunchKernelGGL((q_taujs<R, A, G, TB>), dim3(ng), dim3(TB), 0, c.stream, (const cpx<R>*)X, nst, c.wu,
+                             c.wv, scale, c.kperp2, c.dens_part, tw, kz, pz * pz);
+        });
+      });
+      c.nsg_used = int(ng);
+      return;
+    }
     if (c.gen) {  // general functional: rho, nu (no transform) and j_z, groups of G states
       const double kz = 2 * kPi / (N * c.lat.dz);
       c.launch(KC_DENS, [&] {
@@ -1103,7 +1336,7 @@ struct EngineQ1D final : Engine {
   }
   static constexpr int DGQ = G;  // states per dens_sum group (the partial buffer is sized for G)
   void dens_sum(Ctx& c, const void* X, const double* scale, int64_t nst) override {
-    if (c.gen) {
+    if (c.gen || c.aslda) {
       dens(c, X, scale, nst);
       return;
     }
@@ -1119,6 +1352,18 @@ struct EngineQ1D final : Engine {
   int raw_h_slots() const override { return 1; }
   void reduce_pot(Ctx& c, bool update) override {
     FunParams fp{c.fun.functional, c.fun.B, c.fun.C, c.fun.inv_g_bdg, c.fun.mu, c.ainv, c.dext};
+    if (c.aslda) {
+      c.launch(KC_REDUCE_POT, [&] {
+        hipLaunchKernelGGL((q_reduce_aslda<R>), dim3(N), dim3(256), 0, c.stream, c.dens_part, c.nsg_used, N, fp,
+                           c.fun.mu_b, c.lam, c.vext, c.rho, c.tau, c.nu, c.jc, c.U, c.delta, (R*)c.hA,
+                           (cpx<R>*)c.hD, (R*)c.hAz, c.gscratch, int(update));
+        if (update)  // alpha_s and D2 alpha_s of each spin (Eq. kinop-alpha)
+          for (int sp = 0; sp < 2; ++sp)
+            hipLaunchKernelGGL((k_field_d2<R>), dim3(1), dim3(256), 0, c.stream, N, c.lat.dz, c.gscratch + sp * N,
+                               (R*)c.hAl + sp * N, (R*)c.hLa + sp * N);
+      });
+      return;
+    }
     if (c.gen) {
       c.launch(KC_REDUCE_POT, [&] {
         hipLaunchKernelGGL((q_reduce_gen<R>), dim3(N), dim3(256), 0, c.stream, c.dens_part, c.nsg_used, N, fp,
@@ -1142,6 +1387,7 @@ struct EngineQ1D final : Engine {
   void gen(Ctx& c, int mode, const Lap2Args<R>& P, int64_t nst) {
     twiddles(c);
     const double kz = 2 * kPi / (N * c.lat.dz);
+    const int fcs = c.aslda ? N : 0;  // ASLDA: fields per spin
     const R* al = (const R*)c.hAl;
     const R* az = (const R*)c.hAz;
     const R* la = (const R*)c.hLa;
@@ -1153,27 +1399,27 @@ struct EngineQ1D final : Engine {
       c.launch(kc, [&] {
         switch (mode) {
           case L2_EXPECT:
-            hipLaunchKernelGGL((q_gen<R, A, TB, L2_EXPECT>), grid, block, 0, c.stream, P, nst, c.kperp2, al, az, la, tw, kz);
+            hipLaunchKernelGGL((q_gen<R, A, TB, L2_EXPECT>), grid, block, 0, c.stream, P, nst, c.kperp2, al, az, la, tw, kz, fcs);
             break;
           case L2_H:
-            hipLaunchKernelGGL((q_gen<R, A, TB, L2_H>), grid, block, 0, c.stream, P, nst, c.kperp2, al, az, la, tw, kz);
+            hipLaunchKernelGGL((q_gen<R, A, TB, L2_H>), grid, block, 0, c.stream, P, nst, c.kperp2, al, az, la, tw, kz, fcs);
             break;
           case L2_F:
-            hipLaunchKernelGGL((q_gen<R, A, TB, L2_F>), grid, block, 0, c.stream, P, nst, c.kperp2, al, az, la, tw, kz);
+            hipLaunchKernelGGL((q_gen<R, A, TB, L2_F>), grid, block, 0, c.stream, P, nst, c.kperp2, al, az, la, tw, kz, fcs);
             break;
           case L2_CORR:
-            hipLaunchKernelGGL((q_gen<R, A, TB, L2_CORR>), grid, block, 0, c.stream, P, nst, c.kperp2, al, az, la, tw, kz);
+            hipLaunchKernelGGL((q_gen<R, A, TB, L2_CORR>), grid, block, 0, c.stream, P, nst, c.kperp2, al, az, la, tw, kz, fcs);
             break;
           case L2_FULL:
             if (c.np == 3)
-              hipLaunchKernelGGL((q_gen<R, A, TB, L2_FULL, 3, 4>), grid, block, 0, c.stream, P, nst, c.kperp2, al, az, la, tw, kz);
+              hipLaunchKernelGGL((q_gen<R, A, TB, L2_FULL, 3, 4>), grid, block, 0, c.stream, P, nst, c.kperp2, al, az, la, tw, kz, fcs);
             else if (c.np == 5)
-              hipLaunchKernelGGL((q_gen<R, A, TB, L2_FULL, 5, 5>), grid, block, 0, c.stream, P, nst, c.kperp2, al, az, la, tw, kz);
+              hipLaunchKernelGGL((q_gen<R, A, TB, L2_FULL, 5, 5>), grid, block, 0, c.stream, P, nst, c.kperp2, al, az, la, tw, kz, fcs);
             else
-              hipLaunchKernelGGL((q_gen<R, A, TB, L2_FULL, 4, 5>), grid, block, 0, c.stream, P, nst, c.kperp2, al, az, la, tw, kz);
+              hipLaunchKernelGGL((q_gen<R, A, TB, L2_FULL, 4, 5>), grid, block, 0, c.stream, P, nst, c.kperp2, al, az, la, tw, kz, fcs);
             break;
           default:
-            hipLaunchKernelGGL((q_gen<R, A, TB, L2_TAYLOR>), grid, block, 0, c.stream, P, nst, c.kperp2, al, az, la, tw, kz);
+            hipLaunchKernelGGL((q_gen<R, A, TB, L2_TAYLOR>), grid, block, 0, c.stream, P, nst, c.kperp2, al, az, la, tw, kz, fcs);
         }
       });
     });

@@ -326,6 +326,7 @@ void full_densities(Ctx& c) {
   c.eng->dens(c, c.sb[b], c.sscale[b], c.nst);
   c.eng->reduce_pot(c, !c.frozen);
   if (!c.frozen) c.fields_valid = true;
+  if (c.aslda) return;  // the ASLDA density pass builds tau and j of both spins
   for (int64_t n0 = 0; n0 < c.nst; n0 += c.gchunk) {
     const int64_t nch = std::min(c.gchunk, c.nst - n0);
     c.eng->grad(c, c.sb[b], c.sscale[b], n0, nch);
@@ -338,6 +339,23 @@ void full_densities(Ctx& c) {
 
 void energy(Ctx& c, double* out8) {  // out8[9]
   full_densities(c);
+  if (c.aslda) {
+    c.launch(KC_ENERGY, [&] {
+      hipLaunchKernelGGL(k_energy_aslda, dim3(1), dim3(1024), 0, c.stream, c.M, c.rho, c.tau, c.nu, c.jc, c.delta,
+                         c.vext, c.dext, c.dVe, c.eout);
+    });
+    double h[9];
+    HIPCHK(hipMemcpyAsync(h, c.eout, sizeof(h), hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipStreamSynchronize(c.stream));
+    const double N = h[5];
+    const double ef = 0.5 * std::pow(3.0 * kPi * kPi * N / c.vol, 2.0 / 3.0);
+    for (int k = 0; k < 5; ++k) out8[k] = h[k];
+    out8[5] = h[0] + h[1] + h[2] + h[3] + h[4] + h[6];
+    out8[6] = N;
+    out8[7] = 0.6 * N * ef;
+    out8[8] = h[6];
+    return;
+  }
   c.launch(KC_ENERGY, [&] {
     hipLaunchKernelGGL(k_energy, dim3(1), dim3(1024), 0, c.stream, c.M, c.rho, c.tau, c.nu, c.jc, c.delta,
                        c.vext, c.dext, c.fun.B, c.fun.functional == TDSLDA_FUNC_SLDA ? c.fun.A : 1.0,
@@ -373,18 +391,20 @@ void set_frozen_fields(Ctx& c) {
 
 // the functional's own alpha (A; 1 for BdG), D2 alpha = 0, A_z = 0; the
 // general operator is in use when the functional has A != 1
+// ASLDA: A(p = 0) for both spins until the first field build
 void reset_current_fields(Ctx& c) {
-  const double a = c.fun.functional == TDSLDA_FUNC_SLDA ? c.fun.A : 1.0;
+  const double a = c.aslda ? 1.094 : c.fun.functional == TDSLDA_FUNC_SLDA ? c.fun.A : 1.0;
+  const int64_t nf = c.aslda ? 2 * c.M : c.M;  // field values ([spin][M] for ASLDA)
   c.launch(KC_SETUP, [&] {
     if (c.esz == 16)
-      hipLaunchKernelGGL((k_fill_real<double>), dim3(cdiv(c.M, 256)), dim3(256), 0, c.stream, c.M, a, (double*)c.hAl);
+      hipLaunchKernelGGL((k_fill_real<double>), dim3(cdiv(nf, 256)), dim3(256), 0, c.stream, nf, a, (double*)c.hAl);
     else
-      hipLaunchKernelGGL((k_fill_real<float>), dim3(cdiv(c.M, 256)), dim3(256), 0, c.stream, c.M, a, (float*)c.hAl);
+      hipLaunchKernelGGL((k_fill_real<float>), dim3(cdiv(nf, 256)), dim3(256), 0, c.stream, nf, a, (float*)c.hAl);
   });
-  HIPCHK(hipMemsetAsync(c.hLa, 0, c.M * c.esz / 2, c.stream));
+  HIPCHK(hipMemsetAsync(c.hLa, 0, nf * c.esz / 2, c.stream));
   for (void* p : {c.hAx, c.hAy, c.hAz})
-    if (p) HIPCHK(hipMemsetAsync(p, 0, c.M * c.esz / 2, c.stream));
-  c.gen = a != 1.0;
+    if (p) HIPCHK(hipMemsetAsync(p, 0, (p == c.hAz ? nf : c.M) * c.esz / 2, c.stream));
+  c.gen = c.aslda || a != 1.0;
 }
 
 void after_load(Ctx& c) {
@@ -514,8 +534,13 @@ tdslda_status tdslda_create(const tdslda_lattice* lat, const tdslda_functional* 
     check_lattice(*lat);
     require(run->precision == TDSLDA_FP64 || run->precision == TDSLDA_FP32_MIXED, TDSLDA_EINVAL,
             "unknown precision");
-    require(fun->functional == TDSLDA_FUNC_SLDA || fun->functional == TDSLDA_FUNC_BDG, TDSLDA_EINVAL,
-            "unknown functional");
+    require(fun->functional == TDSLDA_FUNC_SLDA || fun->functional == TDSLDA_FUNC_BDG ||
+                fun->functional == TDSLDA_FUNC_ASLDA,
+            TDSLDA_EINVAL, "unknown functional");
+    require(fun->functional != TDSLDA_FUNC_ASLDA || lat->mode == TDSLDA_MODE_Q1D, TDSLDA_EINVAL,
+            "the spin-imbalanced ASLDA functional is built for the quasi-1D kernel set");
+    require(fun->functional != TDSLDA_FUNC_ASLDA || (std::isfinite(fun->mu) && std::isfinite(fun->mu_b)),
+            TDSLDA_EINVAL, "mu_a and mu_b must be finite");
     require(fun->functional != TDSLDA_FUNC_SLDA || (std::isfinite(fun->A) && fun->A > 0), TDSLDA_EINVAL,
             "A must be positive");
     require(std::isfinite(run->dt) && run->dt != 0.0, TDSLDA_EINVAL, "dt must be finite and non-zero");
@@ -524,6 +549,8 @@ tdslda_status tdslda_create(const tdslda_lattice* lat, const tdslda_functional* 
     c->run = *run;
     c->q1d = lat->mode == TDSLDA_MODE_Q1D;
     c->q2d = lat->mode == TDSLDA_MODE_Q2D;
+    c->aslda = fun->functional == TDSLDA_FUNC_ASLDA;
+    if (c->aslda) c->fun.C = -11.11;  // C(p) of the ASLDA parametrisation
     require(!c->q2d || fun->functional != TDSLDA_FUNC_SLDA || fun->A == 1.0, TDSLDA_EINVAL,
             "the quasi-2D kernel set is built for the A = 1 functional");
     c->stream = (hipStream_t)run->hip_stream;
@@ -574,23 +601,24 @@ tdslda_status tdslda_create(const tdslda_lattice* lat, const tdslda_functional* 
     c->nrm_part = (double*)c->dalloc(8 * capacity * c->nrm_stride);
     c->h_part = (double*)c->dalloc(8 * capacity * c->h_stride);
     c->nsg_max = int(cdiv(capacity, c->eng->group()));
-    c->dens_part = (double*)c->dalloc(size_t(c->nsg_max) * (c->q1d ? 4 : 3) * M * 8);
-    c->rho = (double*)c->dalloc(8 * M);
+    c->dens_part = (double*)c->dalloc(size_t(c->nsg_max) * (c->aslda ? 8 : c->q1d ? 4 : 3) * M * 8);
+    const int64_t ns = c->aslda ? 2 : 1;  // spin-resolved densities and fields
+    c->rho = (double*)c->dalloc(8 * M * ns);
     c->nu = (double*)c->dalloc(16 * M);
-    c->tau = (double*)c->dalloc(8 * M);
+    c->tau = (double*)c->dalloc(8 * M * ns);
     c->jc = (double*)c->dalloc(24 * M);
-    c->U = (double*)c->dalloc(8 * M);
+    c->U = (double*)c->dalloc(8 * M * ns);
     c->delta = (double*)c->dalloc(16 * M);
     c->vext = (double*)c->dalloc(8 * M);
     c->lam = (double*)c->dalloc(8 * M);
     c->theta = (double*)c->dalloc(8 * M);
     c->dext = (double*)c->dalloc(16 * M);
     HIPCHK(hipMemsetAsync(c->dext, 0, 16 * M, c->stream));
-    c->hA = c->dalloc(M * c->esz / 2);
+    c->hA = c->dalloc(M * ns * c->esz / 2);
     c->hD = c->dalloc(M * c->esz);
-    c->hAl = c->dalloc(M * c->esz / 2);
-    c->hLa = c->dalloc(M * c->esz / 2);
-    c->hAz = c->dalloc(M * c->esz / 2);
+    c->hAl = c->dalloc(M * ns * c->esz / 2);
+    c->hLa = c->dalloc(M * ns * c->esz / 2);
+    c->hAz = c->dalloc(M * ns * c->esz / 2);
     if (lat->mode == TDSLDA_MODE_3D) {
       c->hAx = c->dalloc(M * c->esz / 2);
       c->hAy = c->dalloc(M * c->esz / 2);
@@ -601,7 +629,7 @@ tdslda_status tdslda_create(const tdslda_lattice* lat, const tdslda_functional* 
     HIPCHK(hipMemsetAsync(c->lam, 0, 8 * M, c->stream));
     c->gchunk = std::min<int64_t>(capacity, 64);
     c->gscratch = (double*)c->dalloc(size_t(c->gchunk) * 4 * M * 8);
-    c->eout = (double*)c->dalloc(64);
+    c->eout = (double*)c->dalloc(16 * sizeof(double));  // energy terms (up to 9)
     c->dflag = (int*)c->dalloc(16);
     HIPCHK(hipStreamSynchronize(c->stream));
   });
@@ -641,8 +669,10 @@ tdslda_status tdslda_set_external(tdslda_ctx* c, const double* vext, const doubl
     if (freeze_regulator) {
       HIPCHK(hipMemsetAsync(c->dflag, 0, 4, c->stream));
       c->launch(KC_SETUP, [&] {
-        hipLaunchKernelGGL(k_lambda, dim3(cdiv(c->M, 256)), dim3(256), 0, c->stream, c->M, c->vext, c->fun.mu,
-                           c->fun.ec_reg, c->fun.functional == TDSLDA_FUNC_SLDA ? c->fun.A : 1.0, c->lam,
+        // ASLDA: the spin averages A_+ = A(p = 0), mu_+ (Eq. Creg)
+        hipLaunchKernelGGL(k_lambda, dim3(cdiv(c->M, 256)), dim3(256), 0, c->stream, c->M, c->vext,
+                           c->aslda ? 0.5 * (c->fun.mu + c->fun.mu_b) : c->fun.mu, c->fun.ec_reg,
+                           c->aslda ? 1.094 : c->fun.functional == TDSLDA_FUNC_SLDA ? c->fun.A : 1.0, c->lam,
                            c->dflag);
       });
       int bad = 0;
@@ -831,6 +861,7 @@ tdslda_status tdslda_set_fields(tdslda_ctx* c, const double* U, const double* de
       return;
     }
     require(U && delta_reim, TDSLDA_EINVAL, "give both U and Delta, or neither");
+    require(!c->aslda, TDSLDA_EINVAL, "linear mode is not built for the ASLDA functional");
     HIPCHK(hipMemcpyAsync(c->U, U, 8 * c->M, hipMemcpyHostToDevice, c->stream));
     HIPCHK(hipMemcpyAsync(c->delta, delta_reim, 16 * c->M, hipMemcpyHostToDevice, c->stream));
     set_frozen_fields(*c);
@@ -843,6 +874,7 @@ tdslda_status tdslda_set_fields(tdslda_ctx* c, const double* U, const double* de
 tdslda_status tdslda_densities(tdslda_ctx* c, double* rho, double* tau, double* nu_reim, double* j) {
   return guard(c, [&] {
     require(c->loaded, TDSLDA_EORDER, "load states first");
+    require(!c->aslda, TDSLDA_EINVAL, "an ASLDA context has spin-resolved densities (tdslda_densities_spin)");
     full_densities(*c);
     if (rho) HIPCHK(hipMemcpyAsync(rho, c->rho, 8 * c->M, hipMemcpyDeviceToHost, c->stream));
     if (tau) HIPCHK(hipMemcpyAsync(tau, c->tau, 8 * c->M, hipMemcpyDeviceToHost, c->stream));
@@ -852,10 +884,23 @@ tdslda_status tdslda_densities(tdslda_ctx* c, double* rho, double* tau, double* 
   });
 }
 
+tdslda_status tdslda_densities_spin(tdslda_ctx* c, double* rho, double* tau, double* nu_reim, double* j) {
+  return guard(c, [&] {
+    require(c->aslda, TDSLDA_EINVAL, "not an ASLDA context");
+    require(c->loaded, TDSLDA_EORDER, "load states first");
+    full_densities(*c);
+    if (rho) HIPCHK(hipMemcpyAsync(rho, c->rho, 16 * c->M, hipMemcpyDeviceToHost, c->stream));
+    if (tau) HIPCHK(hipMemcpyAsync(tau, c->tau, 16 * c->M, hipMemcpyDeviceToHost, c->stream));
+    if (nu_reim) HIPCHK(hipMemcpyAsync(nu_reim, c->nu, 16 * c->M, hipMemcpyDeviceToHost, c->stream));
+    if (j) HIPCHK(hipMemcpyAsync(j, c->jc, 16 * c->M, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+  });
+}
+
 tdslda_status tdslda_get_fields(tdslda_ctx* c, double* U, double* delta_reim) {
   return guard(c, [&] {
     require(c->fields_valid, TDSLDA_EORDER, "no fields yet");
-    if (U) HIPCHK(hipMemcpyAsync(U, c->U, 8 * c->M, hipMemcpyDeviceToHost, c->stream));
+    if (U) HIPCHK(hipMemcpyAsync(U, c->U, 8 * c->M * (c->aslda ? 2 : 1), hipMemcpyDeviceToHost, c->stream));
     if (delta_reim) HIPCHK(hipMemcpyAsync(delta_reim, c->delta, 16 * c->M, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
   });
@@ -886,6 +931,7 @@ tdslda_status tdslda_set_current_fields(tdslda_ctx* c, const double* alpha, cons
       return;
     }
     require(!c->q2d, TDSLDA_EINVAL, "the general operator is not built for the quasi-2D kernel set");
+    require(!c->aslda, TDSLDA_EINVAL, "the ASLDA functional builds its own alpha and A fields");
     require(c->frozen, TDSLDA_EORDER, "freeze the fields (tdslda_set_fields) first");
     const int ncomp = c->q1d ? 1 : 3;  // quasi-1D: A_z only; 3D: A_x, A_y, A_z
     for (int64_t i = 0; i < c->M; ++i)
@@ -967,6 +1013,7 @@ tdslda_status tdslda_set_friction(tdslda_ctx* c, double alpha, double beta, doub
   return guard(c, [&] {
     require(!c->gen, TDSLDA_EINVAL, "quantum friction is built for the A = 1 operator");
     require(!c->q2d, TDSLDA_EINVAL, "quantum friction is not built for the quasi-2D kernel set");
+    require(!c->aslda, TDSLDA_EINVAL, "quantum friction is not built for the ASLDA functional");
     require(std::isfinite(alpha) && std::isfinite(beta) && std::isfinite(gamma) && std::isfinite(N_req) &&
                 std::isfinite(rho0) && rho0 > 0.0,
             TDSLDA_EINVAL, "friction parameters must be finite, rho0 > 0");

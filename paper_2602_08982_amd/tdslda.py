@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libtdslda.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, EORDER, EUNSTABLE = 0, -1, -2, -3, -4, -5
 MODE_3D, MODE_Q1D, MODE_Q2D = 3, 1, 2
-FUNC_SLDA, FUNC_BDG = 1, 2
+FUNC_SLDA, FUNC_BDG, FUNC_ASLDA = 1, 2, 3
 FP64, FP32_MIXED = 0, 1
 AB3AM4, AB4AM5, AB5AM5 = 34, 45, 55
 
@@ -29,7 +29,7 @@ class Lattice(C.Structure):
 class Functional(C.Structure):
     _fields_ = [("functional", C.c_int), ("A", C.c_double), ("B", C.c_double), ("C", C.c_double),
                 ("inv_g_bdg", C.c_double), ("ec_reg", C.c_double), ("mu", C.c_double),
-                ("temperature", C.c_double)]
+                ("temperature", C.c_double), ("mu_b", C.c_double)]
 
 
 class Run(C.Structure):
@@ -69,6 +69,7 @@ _SIGS = {
     "tdslda_set_current_fields": [C.c_void_p, C.c_void_p, C.c_void_p],
     "tdslda_densities": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
     "tdslda_get_fields": [C.c_void_p, C.c_void_p, C.c_void_p],
+    "tdslda_densities_spin": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
     "tdslda_apply_hbdg": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64],
     "tdslda_abm_step": [C.c_void_p, C.c_int64],
     "tdslda_energy": [C.c_void_p, C.c_void_p],
@@ -287,11 +288,25 @@ class Context:
         return dict(rho=rho.reshape(g), tau=tau.reshape(g), nu=nu.view(np.complex128).reshape(g),
                     j=[j[i * self.M:(i + 1) * self.M].reshape(g) for i in range(3)])
 
+    def densities_spin(self):
+        """Spin-resolved densities of an ASLDA context: rho, tau, j as
+        (spin a, spin b) pairs, nu."""
+        rho = np.empty(2 * self.M)
+        tau = np.empty(2 * self.M)
+        nu = np.empty(2 * self.M)
+        j = np.empty(2 * self.M)
+        self._chk(self.lib.tdslda_densities_spin(self.h, _p(rho), _p(tau), _p(nu), _p(j)))
+        g = self.grid
+        sp = lambda a: (a[:self.M].reshape(g), a[self.M:].reshape(g))
+        return dict(rho=sp(rho), tau=sp(tau), nu=nu.view(np.complex128).reshape(g), j=sp(j))
+
     def get_fields(self):
-        U = np.empty(self.M)
+        ns = 2 if self.functional.functional == FUNC_ASLDA else 1
+        U = np.empty(ns * self.M)
         d = np.empty(2 * self.M)
         self._chk(self.lib.tdslda_get_fields(self.h, _p(U), _p(d)))
-        return U.reshape(self.grid), d.view(np.complex128).reshape(self.grid)
+        U = U.reshape(self.grid) if ns == 1 else (U[:self.M].reshape(self.grid), U[self.M:].reshape(self.grid))
+        return U, d.view(np.complex128).reshape(self.grid)
 
     def apply_hbdg(self, x_dev, y_dev, n):
         self._chk(self.lib.tdslda_apply_hbdg(self.h, _dev_ptr(x_dev), _dev_ptr(y_dev), int(n)))
@@ -551,6 +566,12 @@ def functional_slda(mu, ec_reg, A=1.0, B=None, C_=-11.11, temperature=0.0):
     if B is None:
         B = 2.0 ** (2.0 / 3.0) * 0.357 - A
     return Functional(FUNC_SLDA, A, B, C_, 0.0, ec_reg, mu, temperature)
+
+
+def functional_aslda(mu_a, mu_b, ec_reg, temperature=0.0):
+    """Spin-imbalanced ASLDA (A_a(p), A_b(p), B(p), C = -11.11 of the local
+    polarisation) with the chemical potentials of both spins."""
+    return Functional(FUNC_ASLDA, 0.0, 0.0, -11.11, 0.0, ec_reg, mu_a, temperature, mu_b)
 
 
 def functional_bdg(mu, ec_reg, a_s, temperature=0.0):
