@@ -218,6 +218,43 @@ def run_q1d(steps, warmup, seed=7, profile_steps=2, friction=False, precision=No
                 check=dict(status=st, **chk), problems=info)
 
 
+def run_q1d_aslda(steps, warmup, profile_steps=2, precision=None):
+    """Spin-imbalanced batched quasi-1D workload (workloads.Q1D_ASLDA): both
+    branches from the device eigensolver, start-up and warm-up, launch-shape
+    tuning, then `steps` steps in one HIP-graph launch; the polarisation and
+    the conservation check after the run."""
+    import torch
+    from paper_2602_08982_amd import tdslda as T
+    from paper_2602_08982_amd import workloads as W
+    t0 = time.perf_counter()
+    ctx, info = W.setup_q1d_aslda(W.Q1D_ASLDA, stream=torch.cuda.current_stream().cuda_stream, precision=precision)
+    t_setup = time.perf_counter() - t0
+    nst = info["states"]
+    prec = W.Q1D_ASLDA["precision"] if precision is None else precision
+    S = 2 * W.Q1D_ASLDA["nz"] * (16 if prec == T.FP64 else 8)
+    ctx.abm_step(warmup)
+    tuned = ctx.autotune()
+    rec_ms, run_ms = ctx.abm_graph(steps)
+    dt = run_ms * 1e-3
+    kern = {}
+    if profile_steps:
+        ctx.set_profiling(True)
+        ctx.abm_step(profile_steps)
+        stats = ctx.kernel_stats()
+        ctx.set_profiling(False)
+        for k, (n, ms) in stats.items():
+            if n:
+                kern[k] = dict(launches=n, avg_ms=ms / n, total_ms=ms)
+    d = ctx.densities_spin()
+    ra, rb = d["rho"]
+    pol = float(((ra - rb) / np.maximum(ra + rb, 1e-30)).max())
+    st, chk = ctx.check()
+    ctx.close()
+    return dict(nst=nst, steps=steps, seconds=dt, value=nst * steps / dt, ms_per_step=1e3 * dt / steps,
+                setup_seconds=t_setup, tuned=tuned, kernels=kern, S=S, max_polarisation=pol,
+                check=dict(status=st, **chk), problems=info)
+
+
 def run_q2d(steps, warmup, seed_vortex=2, profile_steps=2, precision=None):
     """Quasi-2D workload (workloads.Q2D): set-up, start-up and warm-up
     steps, then `steps` steps of tdslda_abm_step timed between two device
@@ -398,6 +435,8 @@ def main():
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--no-q1d", action="store_true")
     ap.add_argument("--no-q2d", action="store_true")
+    ap.add_argument("--q1d-aslda-steps", type=int, default=500,
+                    help="steps of the spin-imbalanced (ASLDA) batched quasi-1D run (0 = skip)")
     ap.add_argument("--q2d-steps", type=int, default=100,
                     help="steps of the quasi-2D 64x64 (N_z = 64) workload, FP32-mixed; half as many in FP64")
     ap.add_argument("--no-warmstart", action="store_true")
@@ -504,6 +543,12 @@ def main():
         q1dgen = run_q1d(args.q1d_general_steps, max(1, args.warmup), A=1.094, eager=args.q1d_eager)
         print(f"# batched q1d, general functional A = 1.094: {q1dgen['value']:.4g} state-steps/s over "
               f"{q1dgen['steps']} steps", file=sys.stderr, flush=True)
+    q1das = None
+    if not args.no_q1d and args.q1d_aslda_steps > 0:
+        q1das = run_q1d_aslda(args.q1d_aslda_steps, max(1, args.warmup))
+        print(f"# batched q1d, spin-imbalanced ASLDA: {q1das['value']:.4g} state-steps/s over {q1das['steps']} "
+              f"steps ({q1das['nst']} states, max polarisation {q1das['max_polarisation']:.2f})",
+              file=sys.stderr, flush=True)
     q2d = q2d64 = None
     if not args.no_q2d and args.q2d_steps > 0:
         q2d = run_q2d(args.q2d_steps, max(1, args.warmup))
@@ -628,6 +673,16 @@ def main():
             "kernels": q1dgen["kernels"], "check": q1dgen["check"],
             "roofline": roofline(dict(q1dgen, steps=q1dgen["profile_steps"]), rates, "float", 16, "q1dgen_",
                                  fused=True) if q1dgen["kernels"] else None,
+        }
+    if q1das is not None:
+        line["batched_q1d_aslda"] = {
+            "workload": "spin-imbalanced ASLDA (p != 0), 576 quasi-1D problems (24x24 k_perp), N_z = 64, "
+                        "mu_a = 1.3, mu_b = 0.5, both branches with |E| < 6 from the device eigensolver, FP32 "
+                        f"states / FP64 sums, {q1das['steps']} AB4AM5 steps in one HIP-graph launch",
+            "value": q1das["value"], "unit": "state-steps/s", "ms_per_step": q1das["ms_per_step"],
+            "states_evolved": q1das["nst"], "max_polarisation": q1das["max_polarisation"],
+            "setup_seconds": q1das["setup_seconds"], "tuned_workgroups": q1das["tuned"],
+            "kernels": q1das["kernels"], "check": q1das["check"], "problems": q1das["problems"],
         }
     if q2d is not None:
         line["quasi2d"] = {

@@ -303,6 +303,16 @@ tdslda_status tdslda_q1d_count(const tdslda_lattice* lat, int nprob, const doubl
                                const double* delta, double ecut, int32_t* counts, int64_t* total);
 tdslda_status tdslda_q1d_load_static(tdslda_ctx* ctx, int nprob, const double* kperp2, const double* hfield,
                                      const double* delta, double ecut, int64_t* nloaded);
+/* The same for spin-imbalanced problems (Sec. 2.3, Eq. HpsiEpsi without the
+ * spin symmetry): the upper block carries hfield_a (h_a - mu_a), the lower
+ * -(hfield_b) (-(h_b - mu_b)), and both branches are kept, every eigenpair
+ * with |E| < ecut (the states an ASLDA context evolves). */
+tdslda_status tdslda_q1d_count_spin(const tdslda_lattice* lat, int nprob, const double* kperp2,
+                                    const double* hfield_a, const double* hfield_b, const double* delta, double ecut,
+                                    int32_t* counts, int64_t* total);
+tdslda_status tdslda_q1d_load_static_spin(tdslda_ctx* ctx, int nprob, const double* kperp2, const double* hfield_a,
+                                          const double* hfield_b, const double* delta, double ecut,
+                                          int64_t* nloaded);
 
 /* Static self-consistent solve, quasi-2D geometry (Sec. 3.2, Alg. MapK;
  * Sec. 3.1 quasi-2D item): an nx x ny periodic x-y lattice (spacings dx, dy)

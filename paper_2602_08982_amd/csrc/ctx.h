@@ -289,6 +289,6 @@ std::unique_ptr<Engine> make_q2d_f32(int nx, int ny);
 // k_perp^2 per slot; returns the total number kept
 int64_t q1d_static(hipStream_t st, int N, double dz, int nprob, const double* kperp2, const double* hfield,
                    const double* delta, double ecut, int32_t* counts, void* X, size_t esz, double* E_dev,
-                   double* kp_dev, int64_t cap);
+                   double* kp_dev, int64_t cap, const double* hfield_b = nullptr, bool both = false);
 struct StaticSolver;
 }  // namespace tdslda

@@ -5,7 +5,9 @@
 // Eq. D2, Nyquist mode kept) is built on the device and diagonalised in
 // batches with rocSOLVER; the eigenpairs with 0 < E < E_c are the states
 // that are evolved (E > 0 half of the spin-symmetric spectrum, cutoff of the
-// quasi-1D configurations).
+// quasi-1D configurations).  Spin-imbalanced problems carry their own
+// diagonal in each block (h_a - mu_a above, -(h_b - mu_b) below) and keep
+// both branches, |E| < E_c.
 #include <hip/hip_runtime.h>
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
@@ -22,11 +24,12 @@ namespace {
 
 // H of problems p0 .. p0+nb-1, column-major 2N x 2N each (symmetric, so the
 // storage order only fixes which triangle rocSOLVER reads):
-//   [ h      diag(D) ]     h = -1/2 D2 + diag(hfield) + k_perp^2/2
-//   [ diag(D)   -h   ]     (real pairing field D)
+//   [ h_a      diag(D) ]     h_s = -1/2 D2 + diag(hfield_s) + k_perp^2/2
+//   [ diag(D)   -h_b   ]     (real pairing field D; hfield_b = hfield_a
+//                             for the spin-symmetric problem)
 __global__ void k_q1d_build(double* __restrict__ H, int nb, int p0, int N, const double* __restrict__ kp2,
-                            const double* __restrict__ hfield, const double* __restrict__ delta,
-                            const double* __restrict__ d2) {
+                            const double* __restrict__ hfield, const double* __restrict__ hfield_b,
+                            const double* __restrict__ delta, const double* __restrict__ d2) {
   const int N2 = 2 * N;
   const int64_t idx = int64_t(blockIdx.x) * 256 + threadIdx.x;
   const int64_t per = int64_t(N2) * N2;
@@ -39,7 +42,7 @@ __global__ void k_q1d_build(double* __restrict__ H, int nb, int p0, int N, const
   if (ib == jb) {
     const int m = ((i - j) % N + N) % N;
     double h = -0.5 * d2[m];
-    if (i == j) h += hfield[i] + 0.5 * kp2[p0 + b];
+    if (i == j) h += (ib == 0 ? hfield[i] : hfield_b[i]) + 0.5 * kp2[p0 + b];
     v = ib == 0 ? h : -h;
   } else if (i == j) {
     v = delta[i];
@@ -92,7 +95,7 @@ std::vector<double> spectral_d2_circulant(int N, double dz) {
 
 int64_t q1d_static(hipStream_t st, int N, double dz, int nprob, const double* kperp2, const double* hfield,
                    const double* delta, double ecut, int32_t* counts, void* X, size_t esz, double* E_dev,
-                   double* kp_dev, int64_t cap) {
+                   double* kp_dev, int64_t cap, const double* hfield_b, bool both) {
   const int N2 = 2 * N;
   const bool vectors = X != nullptr;
   const int64_t per = int64_t(N2) * N2;
@@ -115,7 +118,7 @@ int64_t q1d_static(hipStream_t st, int N, double dz, int nprob, const double* kp
   double* Ework = (double*)alloc(sizeof(double) * N2 * B);
   rocblas_int* info = (rocblas_int*)alloc(sizeof(rocblas_int) * B);
   double* kp_d = (double*)alloc(sizeof(double) * nprob);
-  double* hf_d = (double*)alloc(sizeof(double) * N);
+  double* hf_d = (double*)alloc(sizeof(double) * 2 * N);
   double* de_d = (double*)alloc(sizeof(double) * N);
   double* d2_d = (double*)alloc(sizeof(double) * N);
   int32_t* jobs_d = (int32_t*)alloc(sizeof(int32_t) * 3 * N2 * B);
@@ -123,6 +126,7 @@ int64_t q1d_static(hipStream_t st, int N, double dz, int nprob, const double* kp
   try {
     HIPCHK(hipMemcpyAsync(kp_d, kperp2, sizeof(double) * nprob, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(hf_d, hfield, sizeof(double) * N, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(hf_d + N, hfield_b ? hfield_b : hfield, sizeof(double) * N, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(de_d, delta, sizeof(double) * N, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(d2_d, d2.data(), sizeof(double) * N, hipMemcpyHostToDevice, st));
     std::vector<double> Dh(size_t(N2) * B);
@@ -133,7 +137,7 @@ int64_t q1d_static(hipStream_t st, int N, double dz, int nprob, const double* kp
     for (int p0 = 0; p0 < nprob; p0 += B) {
       const int nb = std::min(B, nprob - p0);
       hipLaunchKernelGGL(k_q1d_build, dim3(cdiv(per * nb, 256)), dim3(256), 0, st, H, nb, p0, N, kp_d, hf_d,
-                         de_d, d2_d);
+                         hf_d + N, de_d, d2_d);
       HIPCHK(hipGetLastError());
       const rocblas_status rs = rocsolver_dsyevd_strided_batched(
           rb.h, vectors ? rocblas_evect_original : rocblas_evect_none, rocblas_fill_lower, N2, H, N2, per, D, N2,
@@ -150,7 +154,7 @@ int64_t q1d_static(hipStream_t st, int N, double dz, int nprob, const double* kp
         int cnt = 0;
         for (int k = 0; k < N2; ++k) {
           const double e = Dh[size_t(b) * N2 + k];
-          if (e > 0.0 && e < ecut) {
+          if (both ? std::fabs(e) < ecut : (e > 0.0 && e < ecut)) {
             if (vectors) {
               require(total < cap, TDSLDA_EINVAL, "context capacity below the number of kept states");
               jobs.push_back(b);

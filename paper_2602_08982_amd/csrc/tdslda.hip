@@ -1164,6 +1164,46 @@ tdslda_status tdslda_q1d_load_static(tdslda_ctx* c, int nprob, const double* kpe
                                  c->sb[0], c->esz, c->E, c->kperp2, c->cap);
     require(n > 0, TDSLDA_EINVAL, "no state below the cutoff");
     c->nst = n;
+    hipLaunchKernelGGL(k_fill_real<double>, dim3(cdiv(n, 256)), dim3(256), 0, c->stream, n, 1.0, c->mult);
+    HIPCHK(hipGetLastError());
+    set_weights(*c, n, nullptr);
+    after_load(*c);
+    if (nloaded) *nloaded = n;
+    HIPCHK(hipStreamSynchronize(c->stream));
+  });
+}
+
+tdslda_status tdslda_q1d_count_spin(const tdslda_lattice* lat, int nprob, const double* kperp2,
+                                    const double* hfield_a, const double* hfield_b, const double* delta, double ecut,
+                                    int32_t* counts, int64_t* total) {
+  if (!lat || !kperp2 || !hfield_a || !hfield_b || !delta || nprob <= 0 || lat->mode != TDSLDA_MODE_Q1D)
+    return TDSLDA_EINVAL;
+  try {
+    check_lattice(*lat);
+    const int64_t t = q1d_static(nullptr, lat->nz, lat->dz, nprob, kperp2, hfield_a, delta, ecut, counts, nullptr,
+                                 0, nullptr, nullptr, 0, hfield_b, true);
+    if (total) *total = t;
+    return TDSLDA_OK;
+  } catch (const Fail& e) {
+    std::fprintf(stderr, "tdslda_q1d_count_spin: %s\n", e.msg.c_str());
+    return e.st;
+  } catch (...) {
+    return TDSLDA_EDEVICE;
+  }
+}
+
+tdslda_status tdslda_q1d_load_static_spin(tdslda_ctx* c, int nprob, const double* kperp2, const double* hfield_a,
+                                          const double* hfield_b, const double* delta, double ecut,
+                                          int64_t* nloaded) {
+  return guard(c, [&] {
+    require(c->q1d, TDSLDA_EINVAL, "static quasi-1D states need a quasi-1D context");
+    require(kperp2 && hfield_a && hfield_b && delta && nprob > 0, TDSLDA_EINVAL, "bad problem list");
+    const int64_t n = q1d_static(c->stream, c->lat.nz, c->lat.dz, nprob, kperp2, hfield_a, delta, ecut, nullptr,
+                                 c->sb[0], c->esz, c->E, c->kperp2, c->cap, hfield_b, true);
+    require(n > 0, TDSLDA_EINVAL, "no state below the cutoff");
+    c->nst = n;
+    hipLaunchKernelGGL(k_fill_real<double>, dim3(cdiv(n, 256)), dim3(256), 0, c->stream, n, 1.0, c->mult);
+    HIPCHK(hipGetLastError());
     set_weights(*c, n, nullptr);
     after_load(*c);
     if (nloaded) *nloaded = n;

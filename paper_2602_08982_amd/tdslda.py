@@ -108,6 +108,10 @@ _SIGS = {
                              C.c_void_p],
     "tdslda_q1d_load_static": [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
                                C.POINTER(C.c_int64)],
+    "tdslda_q1d_count_spin": [C.POINTER(Lattice), C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                              C.c_double, C.c_void_p, C.POINTER(C.c_int64)],
+    "tdslda_q1d_load_static_spin": [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                    C.c_double, C.POINTER(C.c_int64)],
 }
 
 EXPORTED = tuple(_SIGS)
@@ -374,6 +378,18 @@ class Context:
                                                   C.byref(n)))
         return n.value
 
+    def q1d_load_static_spin(self, kperp2, hfield_a, hfield_b, delta, ecut):
+        """Load both branches (|E| < ecut) of every spin-imbalanced quasi-1D
+        problem; returns the number loaded."""
+        kp = _f64(kperp2).ravel()
+        ha = _f64(hfield_a).ravel()
+        hb = _f64(hfield_b).ravel()
+        de = _f64(delta).ravel()
+        n = C.c_int64()
+        self._chk(self.lib.tdslda_q1d_load_static_spin(self.h, kp.size, _p(kp), _p(ha), _p(hb), _p(de),
+                                                       float(ecut), C.byref(n)))
+        return n.value
+
     # --- profiling ----------------------------------------------------------
     def set_profiling(self, on=True):
         self._chk(self.lib.tdslda_set_profiling(self.h, int(on)))
@@ -385,6 +401,23 @@ class Context:
             self._chk(self.lib.tdslda_kernel_stats(self.h, k, C.byref(n), C.byref(ms)))
             out[name] = (n.value, ms.value)
         return out
+
+
+def q1d_count_spin(lattice, kperp2, hfield_a, hfield_b, delta, ecut):
+    """Per-problem counts of both branches with |E| < ecut of the
+    spin-imbalanced quasi-1D problems, and their total."""
+    lib = load_library()
+    kp = _f64(kperp2).ravel()
+    ha = _f64(hfield_a).ravel()
+    hb = _f64(hfield_b).ravel()
+    de = _f64(delta).ravel()
+    counts = np.zeros(kp.size, dtype=np.int32)
+    tot = C.c_int64()
+    st = lib.tdslda_q1d_count_spin(C.byref(lattice), kp.size, _p(kp), _p(ha), _p(hb), _p(de), float(ecut),
+                                   _p(counts), C.byref(tot))
+    if st != OK:
+        raise TdsldaError(st, "tdslda_q1d_count_spin failed")
+    return counts, tot.value
 
 
 def q1d_count(lattice, kperp2, hfield, delta, ecut):

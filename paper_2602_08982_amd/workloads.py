@@ -184,3 +184,35 @@ def setup_q2d(cfg, vortices, stream=None, precision=None, integrator=T.AB4AM5):
     if len(vortices):
         ctx.imprint_vortices(vortices)
     return ctx, kidx
+
+
+# ---------------------------------------------------------------------------
+# Spin-imbalanced batched quasi-1D workload (ASLDA at p != 0): N_z = 64,
+# dz = 1, transverse momenta on a 24 x 24 grid, trap omega_z = 0.07,
+# mu_a = 1.3, mu_b = 0.5 (a Zeeman split above the pairing gap), static
+# states of the A = 1 reduced problem with U = 0, Delta = 0.3, both branches
+# with |E| < 6, FP32 states with FP64 sums.
+Q1D_ASLDA = dict(name="batched_q1d_aslda_64", nz=64, dz=1.0, nk=24, dperp=2.0, mu_a=1.3, mu_b=0.5, delta0=0.3,
+                 omega_z=0.07, ecut=6.0, precision=T.FP32_MIXED, dt=0.005)
+
+
+def setup_q1d_aslda(cfg, stream=None, precision=None):
+    """Create the spin-imbalanced batched quasi-1D context: both branches of
+    every problem from the device eigensolver, trap V_ext, regulator frozen
+    with the spin averages.  Returns (ctx, info)."""
+    kp2 = q1d_kperp2(cfg["nk"], cfg["dperp"])
+    z = centered(cfg["nz"], cfg["dz"])
+    vt = 0.5 * cfg["omega_z"] ** 2 * z * z
+    delta = np.full(cfg["nz"], cfg["delta0"])
+    L_perp = cfg["nk"] * cfg["dperp"]
+    lat = T.lattice_q1d(cfg["nz"], cfg["dz"], L_perp, L_perp)
+    ha, hb = vt - cfg["mu_a"], vt - cfg["mu_b"]
+    counts, total = T.q1d_count_spin(lat, kp2, ha, hb, delta, cfg["ecut"])
+    prec = cfg["precision"] if precision is None else precision
+    run = T.run_config(precision=prec, integrator=T.AB4AM5, dt=cfg["dt"], selfstart=1, stream=stream)
+    ctx = T.Context(lat, T.functional_aslda(cfg["mu_a"], cfg["mu_b"], cfg["ecut"]), run, int(total))
+    ctx.set_external(vt, freeze_regulator=True)
+    n = ctx.q1d_load_static_spin(kp2, ha, hb, delta, cfg["ecut"])
+    assert n == total
+    return ctx, dict(nproblems=int(kp2.size), states=int(total), count_min=int(counts.min()),
+                     count_max=int(counts.max()))

@@ -102,3 +102,40 @@ def test_aslda_refusals():
         assert d["rho"][0].sum() > d["rho"][1].sum()
     finally:
         ctx.close()
+
+
+def test_aslda_static_states_both_branches():
+    """tdslda_q1d_load_static_spin: per problem every eigenpair of the
+    spin-imbalanced reduced matrix with |E| < ecut (both branches), from the
+    device eigensolver; the counts, the eigenvalues and the spin-resolved
+    densities of the loaded set equal the oracle's dense diagonalisation
+    (the densities fix the kept subspaces independently of the eigenvector
+    phases)."""
+    from paper_2602_08982_amd import tdslda as T
+    geom, vext, E, kp2, phi, mu_a, mu_b = problem(64, 4, 2.0, 3.0)
+    z = L.centered_coords(64, 1.0)
+    delta = 0.15 + 0.05 * np.sin(np.arange(64) * 0.9 * 16 / 64)
+    probs = np.array([k for k, _ in geom.problems()])
+    lat = T.lattice_q1d(64, 1.0, geom.Lx, geom.Ly)
+    counts, tot = T.q1d_count_spin(lat, probs, vext - mu_a, vext - mu_b, delta, 3.0)
+    assert tot == len(E)
+    want = [int(np.sum(np.abs(np.linalg.eigvalsh(AS.dense_h_imbalanced(vext - mu_a, vext - mu_b, delta, 64, 1.0, k)))
+                       < 3.0)) for k in probs]
+    assert list(counts) == want
+    ctx = T.Context(lat, T.functional_aslda(mu_a, mu_b, 3.0), T.run_config(), tot)
+    try:
+        ctx.set_external(vext, freeze_regulator=True)
+        n = ctx.q1d_load_static_spin(probs, vext - mu_a, vext - mu_b, delta, 3.0)
+        assert n == tot
+        d = ctx.densities_spin()
+        sg = AS.SpinGeometryQ1D(geom)
+        sg.set_states(kp2)
+        ra, rb, ta, tb, nu, ja, jb = sg.densities(phi, F.fermi_weight(E), F.fermi_weight(-E))
+        assert rel(d["rho"][0], ra) < 1e-10 and rel(d["rho"][1], rb) < 1e-10
+        assert rel(d["tau"][0], ta) < 1e-10 and rel(d["tau"][1], tb) < 1e-10
+        assert rel(d["nu"], nu) < 1e-10
+        st = ctx.get_states()
+        norms = np.sum(np.abs(st) ** 2, axis=(1, 2))
+        assert np.abs(norms - 1.0).max() < 1e-12
+    finally:
+        ctx.close()
