@@ -21,7 +21,7 @@ import os
 import re
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = ["csrc/kernels3d.h", "csrc/engine3d.h", "csrc/bufio.h", "csrc/fft.h", "build.py"]
+KERNEL_SOURCES = ["csrc/kernels3d.h", "csrc/engine3d.h", "csrc/q2d.hip", "csrc/bufio.h", "csrc/fft.h", "build.py"]
 COPY_BYTES = 1 << 32
 
 LAP2_MODES = {0: "lap2_h", 1: "lap2_f", 2: "lap2_corr", 3: "lap2_full", 4: "lap2_taylor"}
@@ -50,6 +50,15 @@ def role(name):
     m = re.search(r"q_gen<\w+, \d+, \d+, (\d)", name)
     if m:
         return "q1dgen_" + {**LAP2_MODES, 5: "lap1"}[int(m.group(1))]
+    m = re.search(r"k_opline<\w+, \d+, \d+, \d+, (\d)", name)
+    if m:
+        return "gen3d_opline_" + "xyz"[int(m.group(1))]
+    m = re.search(r"k_pw_gen<\w+, \d+, \d+, \d+, (\d)", name)
+    if m:
+        return "gen3d_" + LAP2_MODES[int(m.group(1))]
+    m = re.search(r"q2_lap<\w+, \d+, \d+, (\d)", name)
+    if m:
+        return "q2d_" + {**LAP2_MODES, 5: "lap1"}[int(m.group(1))]
     m = re.search(r"q_pointwise<\w+, \d+, \d+, (\d)", name)
     if m:
         return "q1d_" + PW_MODES.get(int(m.group(1)), "scale")
@@ -57,6 +66,9 @@ def role(name):
                    ("k_reduce_pot", "reduce_pot"), ("k_finalize", "finalize"), ("q_lap1<", "q1d_lap1"),
                    ("q_dens<", "q1d_dens_kin"), ("q_corr_split<", "q1d_lap2_corr"), ("q_fric<", "q1d_friction"),
                    ("q_densj<", "q1dgen_dens"), ("q_reduce_gen<", "q1dgen_reduce_pot"),
+                   ("q_jz<", "q1dgen_dens"), ("q_taujs<", "q1das_dens"), ("q_reduce_aslda<", "q1das_reduce_pot"),
+                   ("q2_kz_tau<", "q2d_grad"), ("k_jline<", "gen3d_jline"), ("k_reduce_gen3d<", "gen3d_reduce_pot"),
+                   ("k_grad_axis<", "grad"), ("k_grad_reduce", "grad_reduce"),
                    ("k_stream_copy", "stream_copy"), ("k_stream_read", "stream_read")):
         if pat in name:
             return r
@@ -96,17 +108,19 @@ def cmd_stats(args):
     for r in rows:
         nm = r["Name"]
         rl = role(nm)
+        small = float(r["Percentage"]) < args.min_pct
         if rl is None:
             others += 1
-            if others > args.others:
-                skipped += 1
-                skipped_ms += int(r["TotalDurationNs"]) / 1e6
-                continue
+        if (rl is None and others > args.others) or small:
+            skipped += 1
+            skipped_ms += int(r["TotalDurationNs"]) / 1e6
+            continue
         rl = f"{rl} ({precision(nm)})" if rl else ""
         out.append(f"| `{short(nm)}` | {rl} | {r['Calls']} | {int(r['TotalDurationNs']) / 1e6:.3f} | "
                    f"{float(r['AverageNs']) / 1e6:.3f} | {r['Percentage']} |")
     if skipped:
-        out += ["", f"{skipped} further kernels outside the path ({skipped_ms:.1f} ms in total) are not listed."]
+        out += ["", f"{skipped} further kernels (outside the path, or below {args.min_pct}% of the time; "
+                    f"{skipped_ms:.1f} ms in total) are not listed."]
     if args.note:
         out += ["", args.note]
     with open(args.out, "w") as f:
@@ -187,6 +201,7 @@ def main():
     s.add_argument("--title", default="Kernel trace")
     s.add_argument("--note", default="")
     s.add_argument("--others", type=int, default=12, help="kernels outside the path to list")
+    s.add_argument("--min-pct", type=float, default=0.05, help="list no kernel below this share of the time")
     c = sub.add_parser("counters")
     c.add_argument("fetch")
     c.add_argument("write")
