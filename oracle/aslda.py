@@ -1,6 +1,6 @@
 """Spin-imbalanced ASLDA (paper Sec. 2.4, ASLDA item; Sec. 2.3, Eqs.
 HpsiEpsi, h_sigma, na3D-jb3D and the SLDA-type energy density) in the
-quasi-1D geometry.
+quasi-1D and full 3D geometries.
 
 Without spin symmetry both branches of the reduced problem are evolved
 (states of either sign of E, no halving): a state is (u_a, v_b), the u row
@@ -23,6 +23,8 @@ the benchmark's CPU baseline use it; the product path never does).
 """
 import numpy as np
 
+from . import bdg
+from . import densities as D
 from . import functional as F
 from . import lattice as L
 
@@ -116,12 +118,12 @@ class SpinGeometryQ1D:
     def set_states(self, kperp2):
         self.base.set_states(kperp2)
 
-    def apply_h(self, phi, hf_a, hf_b, delta, al_a, al_b, az_a, az_b):
+    def apply_h(self, phi, hf_a, hf_b, delta, al_a, al_b, av_a, av_b):
         """u row: h_a u (hf_a = V_a + V_ext - mu_a) + Delta v;
         v row: Delta^* u - h_b^* v (hf_b = V_b + V_ext - mu_b); each h with
-        its own alpha_s and A_s (z component)."""
-        ha = self.base.apply_h(phi, hf_a, delta, al_a, [0, 0, az_a])
-        hb = self.base.apply_h(phi, hf_b, delta, al_b, [0, 0, az_b])
+        its own alpha_s and A_s (av_s: [A_s,z])."""
+        ha = self.base.apply_h(phi, hf_a, delta, al_a, [0, 0, av_a[0]])
+        hb = self.base.apply_h(phi, hf_b, delta, al_b, [0, 0, av_b[0]])
         return np.stack([ha[:, 0], hb[:, 1]], axis=1)
 
     def densities(self, phi, wu, wv, tau_form="gradient"):
@@ -167,6 +169,33 @@ class SpinGeometryQ1D:
         return rho_a, rho_b, tau_a, tau_b, nu, ja, jb
 
 
+class SpinGeometry3D:
+    """Full 3D lattice with the spin-resolved densities of Eqs. na3D-jb3D
+    (oracle.densities.general) and the rows of the reduced problem carrying
+    their own spin's fields (the 3D general operator, oracle.bdg)."""
+
+    def __init__(self, lat):
+        self.lat = lat
+        self.shape = lat.shape
+        self.dV = lat.dV
+        self.dV_energy = lat.dV
+
+    def apply_h(self, phi, hf_a, hf_b, delta, al_a, al_b, av_a, av_b):
+        ha = bdg.apply_h_general(phi, hf_a, delta, al_a, av_a, self.lat)
+        hb = bdg.apply_h_general(phi, hf_b, delta, al_b, av_b, self.lat)
+        return np.stack([ha[:, 0], hb[:, 1]], axis=1)
+
+    def densities(self, phi, wu, wv, tau_form="gradient"):
+        if tau_form != "gradient":
+            raise NotImplementedError("the 3D geometry takes the paper's gradient form of tau")
+        d = D.general(phi, wu, wv, self.lat)
+        return d["rho_a"], d["rho_b"], d["tau_a"], d["tau_b"], d["nu"], d["j_a"], d["j_b"]
+
+
+def _as_list(j):
+    return j if isinstance(j, list) else [j]
+
+
 class ASLDASystem:
     """What the right-hand side needs (the TDSystem interface of td.py):
     mu_a, mu_b fixed, vext static, lam the frozen regulator, wu, wv the
@@ -184,8 +213,8 @@ class ASLDASystem:
 
     def fields(self, phi):
         ra, rb, ta, tb, nu, ja, jb = self.geom.densities(phi, self.wu, self.wv, self.tau_form)
-        Va, Vb, delta, Aa, Ab, Ava, Avb = potentials(ra, rb, ta, tb, [ja], [jb], nu, self.lam)
-        return (Va + self.vext - self.mu_a, Vb + self.vext - self.mu_b, delta, Aa, Ab, Ava[0], Avb[0])
+        Va, Vb, delta, Aa, Ab, Ava, Avb = potentials(ra, rb, ta, tb, _as_list(ja), _as_list(jb), nu, self.lam)
+        return (Va + self.vext - self.mu_a, Vb + self.vext - self.mu_b, delta, Aa, Ab, Ava, Avb)
 
     def expect(self, phi, hphi):
         ax = tuple(range(1, phi.ndim))
@@ -204,7 +233,7 @@ class ASLDASystem:
     def observables(self, phi):
         """E = int [energy density + V_ext rho_+] dV_e and N_a, N_b."""
         ra, rb, ta, tb, nu, ja, jb = self.geom.densities(phi, self.wu, self.wv, self.tau_form)
-        e = energy_density(ra, rb, ta, tb, [ja], [jb], nu, self.lam) + self.vext * (ra + rb)
+        e = energy_density(ra, rb, ta, tb, _as_list(ja), _as_list(jb), nu, self.lam) + self.vext * (ra + rb)
         dVe = self.geom.dV_energy
         return dict(E=dVe * np.sum(e), Na=dVe * np.sum(ra), Nb=dVe * np.sum(rb))
 

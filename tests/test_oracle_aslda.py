@@ -144,3 +144,43 @@ def test_imbalanced_complete_set_conserves_energy_and_particle_numbers(monkeypat
     monkeypatch.setattr(AS, "dB_dp", lambda q: 0.0 * q)
     ob0, ob1, _ = _imbalanced(0.005, 80)
     assert abs(ob1["E"] - ob0["E"]) > 100 * err2
+
+
+def test_3d_evolution_of_product_states_is_the_quasi_1d_one():
+    """3D ASLDA on product states exp(i k_perp . r_perp) phi(z) / sqrt(L_x L_y)
+    of a complete polarised quasi-1D set (fields depending on z only)
+    reproduces the quasi-1D ASLDA evolution: spin-resolved densities, tau,
+    nu, j and the energy (exact mode reduction, Sec. 3.1)."""
+    nz, nxy, dxy = 8, 4, 2.0
+    geom = q1d.GeometryQ1D(nz, 1.0, nxy, nxy, dxy)
+    lat = L.Lattice(nxy, nxy, nz, dxy, dxy, 1.0)
+    z = L.centered_coords(nz, 1.0)
+    vext = 0.5 * 0.2 ** 2 * z ** 2 - 0.03 * z
+    mu_a, mu_b = 1.3, 0.5
+    delta = 0.15 + 0.05 * np.sin(np.arange(nz) * 0.9)
+    E, kp2, phi1 = AS.eigenstates_imbalanced(geom, vext - mu_a, vext - mu_b, delta, 1e9)
+    probs = geom.problems()
+    per = 2 * nz  # eigenpairs per problem (complete set)
+    x = np.arange(nxy) * dxy
+    phi3 = np.empty((len(E), 2) + lat.shape, complex)
+    for n in range(len(E)):
+        ix, iy = probs[n // per][1]
+        pw = np.exp(1j * (geom.kx[ix] * x[:, None] + geom.ky[iy] * x[None, :])) / np.sqrt(geom.area)
+        phi3[n] = pw[None, :, :, None] * phi1[n][:, None, None, :]
+    lam = F.lambda_c(vext, 0.5 * (mu_a + mu_b), 0.5 * np.pi ** 2, A=1.094)
+    wu, wv = F.fermi_weight(E), F.fermi_weight(-E)
+    s1g = AS.SpinGeometryQ1D(geom)
+    s1g.set_states(kp2)
+    s1 = AS.ASLDASystem(s1g, mu_a, mu_b, vext, lam, wu, wv)
+    b = lambda f: np.broadcast_to(f, lat.shape).copy()
+    s3 = AS.ASLDASystem(AS.SpinGeometry3D(lat), mu_a, mu_b, b(vext), b(lam), wu, wv)
+    p1 = td.evolve(s1, phi1, 0.01, 5)
+    p3 = td.evolve(s3, phi3, 0.01, 5)
+    d1 = s1g.densities(p1, wu, wv)
+    d3 = s3.geom.densities(p3, wu, wv)
+    for k in range(5):
+        assert np.abs(d3[k] - b(d1[k])).max() < 1e-11 * max(1.0, np.abs(d1[k]).max()), k
+    assert np.abs(d3[5][2] - b(d1[5])).max() < 1e-11 and np.abs(d3[6][2] - b(d1[6])).max() < 1e-11
+    assert max(np.abs(d3[5][0]).max(), np.abs(d3[6][1]).max()) < 1e-12
+    assert ((d1[0] - d1[1]) / (d1[0] + d1[1])).max() > 0.2  # polarised
+    assert s1.observables(p1)["E"] == pytest.approx(s3.observables(p3)["E"], rel=1e-11)
