@@ -86,14 +86,14 @@ typedef struct {
   double temperature;   /* T of the frozen weights f(E) = 1/(exp(E/T)+1); 0 = step */
   double mu_b;          /* ASLDA: chemical potential of spin b (else unused) */
 } tdslda_functional;
-/* TDSLDA_FUNC_ASLDA (Sec. 2.4, ASLDA item; quasi-1D contexts only): the
+/* TDSLDA_FUNC_ASLDA (Sec. 2.4, ASLDA item; quasi-1D and full-3D contexts): the
  * spin-imbalanced functional with A_a(p) = A(p), A_b(p) = A(-p), B(p) and
  * C = -11.11 of the local polarisation p = (rho_a - rho_b) / rho_+.  Both
  * branches of Eq. HpsiEpsi are evolved (load states of either sign of E; no
  * E > 0 halving), the u row carries h_a - mu_a and the v row -h_b^* + mu_b,
  * each h of Eq. h_sigma with its own alpha_s = A_s, current potential
  * (1 - A_s) j_s / rho_s and V_s = dE/drho_s (the p-dependence of A_s and B
- * included), densities of Eqs. na3D-jb3D with 1/(L_x L_y).  The fields
+ * included), densities of Eqs. na3D-jb3D (quasi-1D: with 1/(L_x L_y)).  The fields
  * A, B of this struct are not used.  Linear mode, friction and the
  * general-operator fields are refused; tdslda_densities_spin gives the
  * densities.  The regulator frozen by tdslda_set_external uses the spin
@@ -224,7 +224,8 @@ tdslda_status tdslda_set_fields(tdslda_ctx* ctx, const double* U, const double* 
 tdslda_status tdslda_densities(tdslda_ctx* ctx, double* rho, double* tau, double* nu_reim, double* j);
 /* Spin-resolved densities of an ASLDA context (Eqs. na3D-jb3D), FP64 host
  * outputs (any may be NULL): rho[2][M], tau[2][M] (spin a then b), nu[M][2],
- * j[2][M] (the z component of j_a, j_b).  Also refreshes the mean fields.
+ * j[2][3][M] (x, y, z components of j_a, then j_b; quasi-1D: z only, x and y
+ * zero).  Also refreshes the mean fields.
  * Errors: EINVAL (not an ASLDA context), EORDER (nothing loaded). */
 tdslda_status tdslda_densities_spin(tdslda_ctx* ctx, double* rho, double* tau, double* nu_reim, double* j);
 /* Current mean fields (host FP64 out, any may be NULL): U[M], Delta[M][2]

@@ -257,3 +257,23 @@ def eigenstates_imbalanced(geom, hf_a, hf_b, delta, ec):
         kps.append(np.full(sel.size, kp2))
         phis.append(W[:, sel].T.reshape(sel.size, 2, geom.nz) / np.sqrt(geom.dz))
     return np.concatenate(Es), np.concatenate(kps), np.concatenate(phis, axis=0)
+
+
+def dense_h_imbalanced_3d(lat, hf_a, hf_b, delta):
+    """Dense reduced matrix [[h_a, D], [D^*, -h_b]] on the 3D lattice with
+    A = 1: h_s = -1/2 (D2_x + D2_y + D2_z) + hf_s (Eq. D2 per axis, flat
+    index (ix N_y + iy) N_z + iz)."""
+    nx, ny, nz = lat.n
+    d2 = [L.d2_matrix(n, d) for n, d in zip(lat.n, lat.d)]
+    K = -0.5 * (np.kron(np.kron(d2[0], np.eye(ny)), np.eye(nz)) + np.kron(np.kron(np.eye(nx), d2[1]), np.eye(nz))
+                + np.kron(np.kron(np.eye(nx), np.eye(ny)), d2[2]))
+    d = np.diag(np.ravel(delta).astype(complex))
+    return np.block([[K + np.diag(np.ravel(hf_a)), d], [np.conj(d), -(K + np.diag(np.ravel(hf_b)))]])
+
+
+def eigenstates_imbalanced_3d(lat, hf_a, hf_b, delta, ec):
+    """Both branches: every eigenpair with |E| < ec of the 3D reduced
+    matrix, normalised to int (|u|^2 + |v|^2) dV = 1.  Returns (E, phi)."""
+    E, W = np.linalg.eigh(dense_h_imbalanced_3d(lat, hf_a, hf_b, delta))
+    sel = np.nonzero(np.abs(E) < ec)[0]
+    return E[sel], W[:, sel].T.reshape((sel.size, 2) + lat.shape) / np.sqrt(lat.dV)

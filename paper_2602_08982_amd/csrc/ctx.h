@@ -148,6 +148,7 @@ struct tdslda_ctx {
   // spin-resolved densities and fields ([spin][M] for rho, tau, j, U and
   // the fields of H)
   bool aslda = false;
+  double* circ = nullptr;  // 3D ASLDA: the D2 circulants of the x, y, z axes (for Laplacians of alpha_s)
   double* gscratch = nullptr;  // [gchunk][4][M] doubles (tau_s, j_s); also FP64 staging
   int64_t gchunk = 1;
   double* eout = nullptr;

@@ -61,6 +61,7 @@ struct Engine3D final : Engine {
   // slots (which the last pass clears)
   void gen_apply(Ctx& c, const void* X, const double* scale, double* hp, void* out, int64_t nst) {
     require(int(cdiv(NX * NY, GTB)) <= ncb(), TDSLDA_EINVAL, "internal: too few h slots for the z-line pass");
+    const int64_t fcs = c.aslda ? M : 0;  // ASLDA: fields per spin
     const cpx<R>* x = (const cpx<R>*)X;
     cpx<R>* T = (cpx<R>*)c.T;
     const R *al = (const R*)c.hAl, *la = (const R*)c.hLa, *hA = (const R*)c.hA;
@@ -68,17 +69,17 @@ struct Engine3D final : Engine {
     c.launch(KC_LAP1, [&] {
       hipLaunchKernelGGL((k_opline<R, NX, NY, NZ, 0, GTB, false>), dim3(cdiv(NYZ, GTB), nst), dim3(GTB), 0, c.stream,
                          x, scale, T, nullptr, al, la, (const R*)c.hAx, hA, hD, nullptr, c.h_stride, CFG::NGX,
-                         ncb(), 2 * kPi / (NX * c.lat.dx), c.dV);
+                         ncb(), 2 * kPi / (NX * c.lat.dx), c.dV, fcs);
     });
     c.launch(KC_LAP1, [&] {
       hipLaunchKernelGGL((k_opline<R, NX, NY, NZ, 1, GTB, false>), dim3(cdiv(NX * NZ, GTB), nst), dim3(GTB), 0,
                          c.stream, x, scale, T, nullptr, al, la, (const R*)c.hAy, hA, hD, nullptr, c.h_stride,
-                         CFG::NGX, ncb(), 2 * kPi / (NY * c.lat.dy), c.dV);
+                         CFG::NGX, ncb(), 2 * kPi / (NY * c.lat.dy), c.dV, fcs);
     });
     c.launch(KC_LAP1, [&] {
       hipLaunchKernelGGL((k_opline<R, NX, NY, NZ, 2, GTB, true>), dim3(cdiv(NX * NY, GTB), nst), dim3(GTB), 0,
                          c.stream, x, scale, T, (cpx<R>*)out, al, la, (const R*)c.hAz, hA, hD, hp, c.h_stride,
-                         CFG::NGX, ncb(), 2 * kPi / (NZ * c.lat.dz), c.dV);
+                         CFG::NGX, ncb(), 2 * kPi / (NZ * c.lat.dz), c.dV, fcs);
     });
   }
   // quantum friction: j and B' by line passes over state groups, div j by
@@ -109,7 +110,30 @@ struct Engine3D final : Engine {
                          c.f_gamma, c.f_rho0, c.f_Nreq, (R*)c.hA, (cpx<R>*)c.hD);
     });
   }
+  // spin-imbalanced ASLDA: spin-resolved rho, nu (transform-free) and tau,
+  // j by one line pass per axis, all over groups of DG states
+  void aslda_dens(Ctx& c, const void* X, const double* scale, int64_t nst) {
+    const unsigned ng = cdiv(nst, DG);
+    const cpx<R>* x = (const cpx<R>*)X;
+    const double kx = 2 * kPi / (NX * c.lat.dx), ky = 2 * kPi / (NY * c.lat.dy), kz = 2 * kPi / (NZ * c.lat.dz);
+    const double px = kPi / c.lat.dx, py = kPi / c.lat.dy, pz = kPi / c.lat.dz;
+    c.launch(KC_DENS, [&] {
+      hipLaunchKernelGGL((k_dens_sum<R, DG, DS_P, 12, true>), dim3(cdiv(M, DS_TB * DS_P), ng), dim3(DS_TB), 0,
+                         c.stream, x, nst, int64_t(M), c.wu, c.wv, scale, c.dens_part);
+      hipLaunchKernelGGL((k_taujline<R, NX, NY, NZ, 0, GTB, DG>), dim3(cdiv(NYZ, GTB), ng), dim3(GTB), 0, c.stream,
+                         x, nst, scale, c.wu, c.wv, kx, px * px, c.dens_part);
+      hipLaunchKernelGGL((k_taujline<R, NX, NY, NZ, 1, GTB, DG>), dim3(cdiv(NX * NZ, GTB), ng), dim3(GTB), 0,
+                         c.stream, x, nst, scale, c.wu, c.wv, ky, py * py, c.dens_part);
+      hipLaunchKernelGGL((k_taujline<R, NX, NY, NZ, 2, GTB, DG>), dim3(cdiv(NX * NY, GTB), ng), dim3(GTB), 0,
+                         c.stream, x, nst, scale, c.wu, c.wv, kz, pz * pz, c.dens_part);
+    });
+    c.nsg_used = int(ng);
+  }
   void dens(Ctx& c, const void* X, const double* scale, int64_t nst) override {
+    if (c.aslda) {
+      aslda_dens(c, X, scale, nst);
+      return;
+    }
     if (c.gen) {
       gen_dens(c, X, scale, nst);
       return;
@@ -125,6 +149,10 @@ struct Engine3D final : Engine {
   // states per dens_sum group (FP64: 256 measured 12% faster than 64 at 32^3)
   static constexpr int DG = sizeof(R) == 8 ? 256 : 128;
   void dens_sum(Ctx& c, const void* X, const double* scale, int64_t nst) override {
+    if (c.aslda) {
+      aslda_dens(c, X, scale, nst);
+      return;
+    }
     if (c.gen) {
       gen_dens(c, X, scale, nst);
       return;
@@ -140,6 +168,19 @@ struct Engine3D final : Engine {
   int raw_h_slots() const override { return CFG::NGX; }
   void reduce_pot(Ctx& c, bool update) override {
     FunParams fp{c.fun.functional, c.fun.B, c.fun.C, c.fun.inv_g_bdg, c.fun.mu, c.ainv, c.dext};
+    if (c.aslda) {
+      c.launch(KC_REDUCE_POT, [&] {
+        hipLaunchKernelGGL((k_reduce_aslda3d<R>), dim3(cdiv(M, 256)), dim3(256), 0, c.stream, c.dens_part,
+                           c.nsg_used, int64_t(M), fp, c.fun.mu_b, c.lam, c.vext, c.rho, c.tau, c.nu, c.jc, c.U,
+                           c.delta, (R*)c.hA, (cpx<R>*)c.hD, (R*)c.hAx, (R*)c.hAy, (R*)c.hAz, c.gscratch, int(update));
+        if (update)  // alpha_s and its Laplacian (Eq. kinop-alpha) for each spin
+          for (int sp = 0; sp < 2; ++sp)
+            hipLaunchKernelGGL((k_field_lap3d<R>), dim3(cdiv(M, 256)), dim3(256), 0, c.stream, NX, NY, NZ,
+                               c.gscratch + sp * M, c.circ, c.circ + NX, c.circ + NX + NY, (R*)c.hAl + sp * M,
+                               (R*)c.hLa + sp * M);
+      });
+      return;
+    }
     if (c.gen) {
       c.launch(KC_REDUCE_POT, [&] {
         hipLaunchKernelGGL((k_reduce_gen3d<R>), dim3(cdiv(M, 256)), dim3(256), 0, c.stream, c.dens_part, c.jpart,

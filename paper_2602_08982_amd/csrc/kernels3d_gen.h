@@ -80,6 +80,154 @@ __global__ __launch_bounds__(TBG) void k_jline(const cpx<R>* __restrict__ X, int
   for (int k = 0; k < NL; ++k) out[k * ST] = acc[k];
 }
 
+// Spin-imbalanced ASLDA (Sec. 2.4, ASLDA item; Eqs. na3D-jb3D), both
+// branches evolved: the AXIS part of tau_s and j_s of a group of DG states,
+// per line, into the [group][12][M] layout (0 rho_a, 1 rho_b, 2 Re nu,
+// 3 Im nu from the transform-free pass; 4 tau_a, 5 tau_b; 6..8 j_a,
+// 9..11 j_b by axis):
+//   tau_a += sum f_u (|D1 u|^2 + (pi/d)^2 |c_u|^2),  tau_b with v, f_v
+//   (AXIS 0 writes, the other axes add), j_a,AXIS = -sum f_u Im(u (D1 u)^*),
+//   j_b,AXIS = sum f_v Im(v (D1 v)^*); D1 with the Nyquist bin zeroed, c the
+//   Nyquist amplitude.
+//   grid = (ceil(NLINES / TBG), number of groups), block = TBG
+template <typename R, int NX, int NY, int NZ, int AXIS, int TBG, int DG>
+__global__ __launch_bounds__(TBG) void k_taujline(const cpx<R>* __restrict__ X, int64_t nstates,
+                                                  const double* __restrict__ scale, const double* __restrict__ wu,
+                                                  const double* __restrict__ wv, double kscale, double nyq2,
+                                                  double* __restrict__ part) {
+  using LG = LineGeo<NX, NY, NZ, AXIS>;
+  constexpr int NL = LG::NL, ST = LG::STRIDE;
+  constexpr int64_t M = int64_t(NX) * NY * NZ;
+  constexpr int ES = sizeof(cpx<R>);
+  const int l = blockIdx.x * TBG + threadIdx.x;
+  if (l >= LG::NLINES) return;  // no barriers below
+  const int s0 = LG::site0(l);
+  const int64_t nbeg = int64_t(blockIdx.y) * DG;
+  const int nloc = int(nstates - nbeg < DG ? nstates - nbeg : DG);
+  double* gp = part + int64_t(blockIdx.y) * 12 * M + s0;
+#pragma unroll 1
+  for (int comp = 0; comp < 2; ++comp) {
+    const double sgn = comp ? 1.0 : -1.0;
+    double at[NL], aj[NL];
+#pragma unroll
+    for (int k = 0; k < NL; ++k) at[k] = aj[k] = 0.0;
+    for (int ls = 0; ls < nloc; ++ls) {
+      const int64_t n = nbeg + ls;
+      const double w = comp ? wv[n] : wu[n];
+      if (w == 0.0) continue;
+      const R s = R(scale[n]);
+      const bi32x4 rX = make_rsrc(X + n * 2 * M, uint32_t(2 * M * ES));
+      cpx<R> d[NL], ny;
+#pragma unroll
+      for (int k = 0; k < NL; ++k) d[k] = s * bload<R>(rX, s0 * ES, int(comp * M + k * ST) * ES);
+      first_derivative<NL>(d, R(kscale), ny);
+      const double cn = nyq2 * norm2(ny);
+#pragma unroll
+      for (int k = 0; k < NL; ++k) {
+        const cpx<R> f = s * bload<R>(rX, s0 * ES, int(comp * M + k * ST) * ES);  // re-read (cached)
+        at[k] += w * (norm2(d[k]) + cn);
+        aj[k] += sgn * w * (double(f.y) * double(d[k].x) - double(f.x) * double(d[k].y));  // Im(f (D1 f)^*)
+      }
+    }
+    double* ot = gp + (4 + comp) * M;
+    double* oj = gp + (6 + 3 * comp + AXIS) * M;
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+      if constexpr (AXIS == 0)
+        ot[k * ST] = at[k];
+      else
+        ot[k * ST] += at[k];
+      oj[k * ST] = aj[k];
+    }
+  }
+}
+
+// ASLDA parameters (Sec. 2.4): A(p), A'(p), B(p), B'(p)
+__device__ __forceinline__ double as3_A(double p) {
+  const double p2 = p * p;
+  return 1.094 + 0.156 * p * (1.0 - 2.0 * p2 / 3.0 + p2 * p2 / 5.0) - 0.532 * p2 * (1.0 - p2 + p2 * p2 / 3.0);
+}
+__device__ __forceinline__ double as3_dA(double p) {
+  const double p2 = p * p;
+  return 0.156 * (1.0 - 2.0 * p2 + p2 * p2) - 0.532 * (2.0 * p - 4.0 * p2 * p + 2.0 * p2 * p2 * p);
+}
+__device__ __forceinline__ double as3_B(double p) {
+  const double hp = 0.5 * (1.0 + p), hm = 0.5 * (1.0 - p);
+  return 1.5874010519681994 * (0.357 + 0.642 * p * p - as3_A(p) * pow(hp, 5.0 / 3.0) - as3_A(-p) * pow(hm, 5.0 / 3.0));
+}
+__device__ __forceinline__ double as3_dB(double p) {
+  const double hp = 0.5 * (1.0 + p), hm = 0.5 * (1.0 - p);
+  return 1.5874010519681994 *
+         (1.284 * p - as3_dA(p) * pow(hp, 5.0 / 3.0) - as3_A(p) * (5.0 / 6.0) * pow(hp, 2.0 / 3.0) +
+          as3_dA(-p) * pow(hm, 5.0 / 3.0) + as3_A(-p) * (5.0 / 6.0) * pow(hm, 2.0 / 3.0));
+}
+
+// one thread per site: the twelve group partials summed in a fixed order,
+// then the ASLDA potentials (functional derivatives of the SLDA-type energy
+// density with A_a = A(p), A_b = A(-p), B(p); see the quasi-1D kernel set):
+//   V_s = dp/drho_s [1/2 (A'(p) K_a - A'(-p) K_b) + 3/5 B'(p) rho_+ eF]
+//         + (A_s - 1) |j_s|^2 / (2 rho_s^2) + B eF - |Delta|^2 / (3 C rho_+^(2/3)),
+//   A_s = (1 - A_s) j_s / rho_s (three components), Delta = -g_eff nu,
+// spin-resolved arrays [spin][M] (j: [spin][3][M]); alpha_s into aout.
+template <typename R>
+__global__ __launch_bounds__(256) void k_reduce_aslda3d(
+    const double* __restrict__ part, int ngroups, int64_t M, FunParams fp, double mu_b,
+    const double* __restrict__ lam, const double* __restrict__ vext, double* __restrict__ rho,
+    double* __restrict__ tau, double* __restrict__ nu, double* __restrict__ jc, double* __restrict__ U,
+    double* __restrict__ delta, R* __restrict__ hA, cpx<R>* __restrict__ hD, R* __restrict__ hAx,
+    R* __restrict__ hAy, R* __restrict__ hAz, double* __restrict__ aout, int update_fields) {
+  const int64_t r = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (r >= M) return;
+  double v[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) v[c] = 0.0;
+  for (int g = 0; g < ngroups; ++g) {
+    const double* p = part + int64_t(g) * 12 * M + r;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) v[c] += p[c * M];
+  }
+#pragma unroll
+  for (int c = 0; c < 12; ++c) v[c] *= fp.ainv;
+  rho[r] = v[0];
+  rho[M + r] = v[1];
+  nu[2 * r] = v[2];
+  nu[2 * r + 1] = v[3];
+  tau[r] = v[4];
+  tau[M + r] = v[5];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) jc[c * M + r] = v[6 + c];
+  if (!update_fields) return;
+  const double ra = fmax(v[0], 0.5e-14), rb = fmax(v[1], 0.5e-14), rp = ra + rb;
+  const double p = (ra - rb) / rp;
+  const double Aa = as3_A(p), Ab = as3_A(-p), B = as3_B(p);
+  const double gg = 1.0 / (cbrt(rp) / fp.C - lam[r]);
+  const double dr = -gg * v[2], di = -gg * v[3];
+  const double ef = 0.5 * pow(3.0 * kPi * kPi * rp, 2.0 / 3.0);
+  const double c23 = cbrt(rp);
+  const double jsa = v[6] * v[6] + v[7] * v[7] + v[8] * v[8], jsb = v[9] * v[9] + v[10] * v[10] + v[11] * v[11];
+  const double Ka = v[4] - jsa / ra, Kb = v[5] - jsb / rb;
+  const double common = 0.5 * (as3_dA(p) * Ka - as3_dA(-p) * Kb) + 0.6 * as3_dB(p) * rp * ef;
+  const double base = B * ef - (dr * dr + di * di) / (3.0 * fp.C * c23 * c23);
+  const double Va = 2.0 * rb / (rp * rp) * common + (Aa - 1.0) * jsa / (2.0 * ra * ra) + base;
+  const double Vb = -2.0 * ra / (rp * rp) * common + (Ab - 1.0) * jsb / (2.0 * rb * rb) + base;
+  U[r] = Va;
+  U[M + r] = Vb;
+  delta[2 * r] = dr;
+  delta[2 * r + 1] = di;
+  hA[r] = R(Va + vext[r] - fp.mu);
+  hA[M + r] = R(Vb + vext[r] - mu_b);
+  hD[r] = cpx<R>{R(dr + fp.dext[2 * r]), R(di + fp.dext[2 * r + 1])};
+  const double ca = (1.0 - Aa) / ra, cb = (1.0 - Ab) / rb;
+  hAx[r] = R(ca * v[6]);
+  hAy[r] = R(ca * v[7]);
+  hAz[r] = R(ca * v[8]);
+  hAx[M + r] = R(cb * v[9]);
+  hAy[M + r] = R(cb * v[10]);
+  hAz[M + r] = R(cb * v[11]);
+  aout[r] = Aa;
+  aout[M + r] = Ab;
+}
+
 // A compiler-only memory fence (no instruction): the phases of a line pass
 // re-read phi and the fields instead of keeping them in registers across
 // the transforms (the loads would otherwise be merged or hoisted, which
@@ -106,7 +254,8 @@ __global__ __launch_bounds__(TBG) void k_opline(const cpx<R>* __restrict__ X, co
                                                 const R* __restrict__ hAl, const R* __restrict__ hLa,
                                                 const R* __restrict__ hAd, const R* __restrict__ hA,
                                                 const cpx<R>* __restrict__ hD, double* __restrict__ h_part,
-                                                int h_stride, int h_off, int n_slots, double kscale, double dV) {
+                                                int h_stride, int h_off, int n_slots, double kscale, double dV,
+                                                int64_t fcs) {
   using LG = LineGeo<NX, NY, NZ, AXIS>;
   constexpr int NL = LG::NL, ST = LG::STRIDE;
   constexpr int64_t M = int64_t(NX) * NY * NZ;
@@ -125,7 +274,6 @@ __global__ __launch_bounds__(TBG) void k_opline(const cpx<R>* __restrict__ X, co
   const bi32x4 rT = make_rsrc(T + n * 2 * M, SB);
   cpx<R>* dst = (LAST && out) ? out : T;
   const bi32x4 rO = make_rsrc(dst + n * 2 * M, SB);
-  const bi32x4 rAl = make_rsrc(hAl, uint32_t(M * RS)), rAd = make_rsrc(hAd, uint32_t(M * RS));
   const int vo = s0 * ES, va = s0 * RS;
   const R kk = R(kscale), inv_n = R(1.0 / NL);
   const int tx = threadIdx.x;
@@ -135,6 +283,9 @@ __global__ __launch_bounds__(TBG) void k_opline(const cpx<R>* __restrict__ X, co
     for (int comp = 0; comp < 2; ++comp) {
       const R sg = comp ? R(-1) : R(1);
       const int cb = int(comp * M);
+      // the fields of this row's spin (fcs = M: [spin][M] arrays; 0: one set)
+      const int64_t fo = comp * fcs;
+      const bi32x4 rAl = make_rsrc(hAl + fo, uint32_t(M * RS)), rAd = make_rsrc(hAd + fo, uint32_t(M * RS));
       cpx<R> t[NL];
       cpx<R> nyq;
       phase_fence();
@@ -191,7 +342,7 @@ __global__ __launch_bounds__(TBG) void k_opline(const cpx<R>* __restrict__ X, co
           const cpx<R> y = s * bload<R>(rX, vo, (int((1 - comp) * M) + k * ST) * ES);
           const cpx<R> D = hD[site];
           const cpx<R> Dc = comp ? conj(D) : D;
-          r = r + (sg * (R(0.25) * hLa[site] + hA[site])) * x + Dc * y;
+          r = r + (sg * (R(0.25) * hLa[fo + site] + hA[fo + site])) * x + Dc * y;
           hloc += double(x.x) * double(r.x) + double(x.y) * double(r.y);
         }
         bstore<R>(r, rO, vo, o);

@@ -87,7 +87,7 @@ __global__ __launch_bounds__(1024) void k_energy(int64_t M, const double* __rest
 }
 
 // Energy terms of the spin-imbalanced ASLDA functional (Sec. 2.4) from the
-// spin-resolved densities ([spin][M]: rho, tau, j_z; nu [M][2]; Delta as
+// spin-resolved densities ([spin][M]: rho, tau; j [spin][3][M]; nu [M][2]; Delta as
 // built): E_kin = sum_s A_s/2 (tau_s - j_s^2/rho_s), E_pot = 3/5 B rho_+ eF,
 // E_pair = -Re Delta^* nu, E_curr = sum_s j_s^2 / (2 rho_s), E_ext =
 // V_ext rho_+, rho_+, E_pair.ext, each times dVe; out[7] = N_a, out[8] = N_b.
@@ -111,11 +111,15 @@ __global__ __launch_bounds__(1024) void k_energy_aslda(int64_t M, const double* 
     const double Aa = host_aslda_A(p), Ab = host_aslda_A(-p);
     const double hp = 0.5 * (1.0 + p), hm = 0.5 * (1.0 - p);
     const double B = 1.5874010519681994 * (0.357 + 0.642 * p * p - Aa * pow(hp, 5.0 / 3.0) - Ab * pow(hm, 5.0 / 3.0));
-    const double ja = j[r], jb = j[M + r];
-    ek += 0.5 * Aa * (tau[r] - ja * ja / ra) + 0.5 * Ab * (tau[M + r] - jb * jb / rb);
+    double jsa = 0.0, jsb = 0.0;
+    for (int c = 0; c < 3; ++c) {
+      jsa += j[c * M + r] * j[c * M + r];
+      jsb += j[(3 + c) * M + r] * j[(3 + c) * M + r];
+    }
+    ek += 0.5 * Aa * (tau[r] - jsa / ra) + 0.5 * Ab * (tau[M + r] - jsb / rb);
     ep += 0.6 * B * rp * 0.5 * pow(3.0 * kPi * kPi * rp, 2.0 / 3.0);
     epa -= delta[2 * r] * nu[2 * r] + delta[2 * r + 1] * nu[2 * r + 1];
-    ec += ja * ja / (2.0 * ra) + jb * jb / (2.0 * rb);
+    ec += jsa / (2.0 * ra) + jsb / (2.0 * rb);
     ee += vext[r] * (rho[r] + rho[M + r]);
     nn += rho[r] + rho[M + r];
     na += rho[r];

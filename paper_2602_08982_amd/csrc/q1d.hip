@@ -1018,9 +1018,9 @@ __device__ __forceinline__ double aslda_dB(double p) {
 //         + (A_s - 1) j_s^2 / (2 rho_s^2) + B eF - |Delta|^2 / (3 C rho_+^(2/3)),
 //   K_s = tau_s - j_s^2 / rho_s, dp/drho_a = 2 rho_b / rho_+^2,
 //   dp/drho_b = -2 rho_a / rho_+^2;  alpha_s = A_s, A_s,z = (1 - A_s) j_s / rho_s,
-//   Delta = -g_eff nu.  Spin-resolved arrays are [spin][N] (a first); the
-// fields of H: hA = V_s + V_ext - mu_s, hAz, and alpha_s into aout (FP64,
-// for the D2 alpha pass).
+//   Delta = -g_eff nu.  Spin-resolved arrays are [spin][N] (a first; j
+// [spin][3][N] with the z component filled); the fields of H: hA = V_s +
+// V_ext - mu_s, hAz, and alpha_s into aout (FP64, for the D2 alpha pass).
 template <typename R>
 __global__ __launch_bounds__(256) void q_reduce_aslda(const double* __restrict__ part, int ngroups, int N,
                                                       FunParams fp, double mu_b, const double* __restrict__ lam,
@@ -1061,9 +1061,13 @@ __global__ __launch_bounds__(256) void q_reduce_aslda(const double* __restrict__
   nu[2 * r + 1] = sni;
   tau[r] = ta;
   tau[N + r] = tb;
-  jc[r] = ja;
-  jc[N + r] = jb;
-  jc[2 * N + r] = 0.0;
+  // j: [spin][3][N], the z components carry the quasi-1D currents
+  jc[r] = 0.0;
+  jc[N + r] = 0.0;
+  jc[2 * N + r] = ja;
+  jc[3 * N + r] = 0.0;
+  jc[4 * N + r] = 0.0;
+  jc[5 * N + r] = jb;
   if (!update_fields) return;
   const double ra = fmax(sra, 0.5e-14), rb = fmax(srb, 0.5e-14), rp = ra + rb;
   const double p = (ra - rb) / rp;

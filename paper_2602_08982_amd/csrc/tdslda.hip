@@ -403,7 +403,7 @@ void reset_current_fields(Ctx& c) {
   });
   HIPCHK(hipMemsetAsync(c.hLa, 0, nf * c.esz / 2, c.stream));
   for (void* p : {c.hAx, c.hAy, c.hAz})
-    if (p) HIPCHK(hipMemsetAsync(p, 0, (p == c.hAz ? nf : c.M) * c.esz / 2, c.stream));
+    if (p) HIPCHK(hipMemsetAsync(p, 0, nf * c.esz / 2, c.stream));
   c.gen = c.aslda || a != 1.0;
 }
 
@@ -537,8 +537,8 @@ tdslda_status tdslda_create(const tdslda_lattice* lat, const tdslda_functional* 
     require(fun->functional == TDSLDA_FUNC_SLDA || fun->functional == TDSLDA_FUNC_BDG ||
                 fun->functional == TDSLDA_FUNC_ASLDA,
             TDSLDA_EINVAL, "unknown functional");
-    require(fun->functional != TDSLDA_FUNC_ASLDA || lat->mode == TDSLDA_MODE_Q1D, TDSLDA_EINVAL,
-            "the spin-imbalanced ASLDA functional is built for the quasi-1D kernel set");
+    require(fun->functional != TDSLDA_FUNC_ASLDA || lat->mode == TDSLDA_MODE_Q1D || lat->mode == TDSLDA_MODE_3D,
+            TDSLDA_EINVAL, "the spin-imbalanced ASLDA functional is built for the quasi-1D and full-3D kernel sets");
     require(fun->functional != TDSLDA_FUNC_ASLDA || (std::isfinite(fun->mu) && std::isfinite(fun->mu_b)),
             TDSLDA_EINVAL, "mu_a and mu_b must be finite");
     require(fun->functional != TDSLDA_FUNC_SLDA || (std::isfinite(fun->A) && fun->A > 0), TDSLDA_EINVAL,
@@ -601,12 +601,13 @@ tdslda_status tdslda_create(const tdslda_lattice* lat, const tdslda_functional* 
     c->nrm_part = (double*)c->dalloc(8 * capacity * c->nrm_stride);
     c->h_part = (double*)c->dalloc(8 * capacity * c->h_stride);
     c->nsg_max = int(cdiv(capacity, c->eng->group()));
-    c->dens_part = (double*)c->dalloc(size_t(c->nsg_max) * (c->aslda ? 8 : c->q1d ? 4 : 3) * M * 8);
+    const int ncomp_part = c->aslda ? (c->q1d ? 8 : 12) : c->q1d ? 4 : 3;  // density partials per group
+    c->dens_part = (double*)c->dalloc(size_t(c->nsg_max) * ncomp_part * M * 8);
     const int64_t ns = c->aslda ? 2 : 1;  // spin-resolved densities and fields
     c->rho = (double*)c->dalloc(8 * M * ns);
     c->nu = (double*)c->dalloc(16 * M);
     c->tau = (double*)c->dalloc(8 * M * ns);
-    c->jc = (double*)c->dalloc(24 * M);
+    c->jc = (double*)c->dalloc(24 * M * ns);  // [spin][3][M] for ASLDA
     c->U = (double*)c->dalloc(8 * M * ns);
     c->delta = (double*)c->dalloc(16 * M);
     c->vext = (double*)c->dalloc(8 * M);
@@ -620,8 +621,18 @@ tdslda_status tdslda_create(const tdslda_lattice* lat, const tdslda_functional* 
     c->hLa = c->dalloc(M * ns * c->esz / 2);
     c->hAz = c->dalloc(M * ns * c->esz / 2);
     if (lat->mode == TDSLDA_MODE_3D) {
-      c->hAx = c->dalloc(M * c->esz / 2);
-      c->hAy = c->dalloc(M * c->esz / 2);
+      c->hAx = c->dalloc(M * ns * c->esz / 2);
+      c->hAy = c->dalloc(M * ns * c->esz / 2);
+      if (c->aslda) {  // the D2 circulants of the three axes, for the Laplacians of alpha_s
+        const auto cx = spectral_d2_circulant(lat->nx, lat->dx), cy = spectral_d2_circulant(lat->ny, lat->dy),
+                   cz = spectral_d2_circulant(lat->nz, lat->dz);
+        c->circ = (double*)c->dalloc(8 * (cx.size() + cy.size() + cz.size()));
+        HIPCHK(hipMemcpyAsync(c->circ, cx.data(), 8 * cx.size(), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(hipMemcpyAsync(c->circ + cx.size(), cy.data(), 8 * cy.size(), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(hipMemcpyAsync(c->circ + cx.size() + cy.size(), cz.data(), 8 * cz.size(), hipMemcpyHostToDevice,
+                              c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));  // the host vectors go out of scope
+      }
       c->jpart = (double*)c->dalloc(size_t(c->nsg_max) * 3 * M * 8);
     }
     reset_current_fields(*c);
@@ -892,7 +903,7 @@ tdslda_status tdslda_densities_spin(tdslda_ctx* c, double* rho, double* tau, dou
     if (rho) HIPCHK(hipMemcpyAsync(rho, c->rho, 16 * c->M, hipMemcpyDeviceToHost, c->stream));
     if (tau) HIPCHK(hipMemcpyAsync(tau, c->tau, 16 * c->M, hipMemcpyDeviceToHost, c->stream));
     if (nu_reim) HIPCHK(hipMemcpyAsync(nu_reim, c->nu, 16 * c->M, hipMemcpyDeviceToHost, c->stream));
-    if (j) HIPCHK(hipMemcpyAsync(j, c->jc, 16 * c->M, hipMemcpyDeviceToHost, c->stream));
+    if (j) HIPCHK(hipMemcpyAsync(j, c->jc, 48 * c->M, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
   });
 }

@@ -298,11 +298,12 @@ class Context:
         rho = np.empty(2 * self.M)
         tau = np.empty(2 * self.M)
         nu = np.empty(2 * self.M)
-        j = np.empty(2 * self.M)
+        j = np.empty(6 * self.M)
         self._chk(self.lib.tdslda_densities_spin(self.h, _p(rho), _p(tau), _p(nu), _p(j)))
         g = self.grid
         sp = lambda a: (a[:self.M].reshape(g), a[self.M:].reshape(g))
-        return dict(rho=sp(rho), tau=sp(tau), nu=nu.view(np.complex128).reshape(g), j=sp(j))
+        jj = j.reshape((2, 3) + g)
+        return dict(rho=sp(rho), tau=sp(tau), nu=nu.view(np.complex128).reshape(g), j=(jj[0], jj[1]))
 
     def get_fields(self):
         ns = 2 if self.functional.functional == FUNC_ASLDA else 1
