@@ -255,6 +255,39 @@ def run_q1d_aslda(steps, warmup, profile_steps=2, precision=None):
                 check=dict(status=st, **chk), problems=info)
 
 
+def run_aslda3d(steps, warmup, profile_steps=1):
+    """Spin-imbalanced 3D workload (workloads.ASLDA3D): both branches of the
+    uniform start, start-up and warm-up, `steps` steps timed between two
+    device synchronisations, then `profile_steps` with per-kernel events."""
+    import torch
+    from paper_2602_08982_amd import workloads as W
+    t0 = time.perf_counter()
+    ctx, kidx = W.setup_aslda3d(W.ASLDA3D, stream=torch.cuda.current_stream().cuda_stream)
+    ctx.abm_step(warmup)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    nst = 2 * len(kidx)
+    t0 = time.perf_counter()
+    ctx.abm_step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kern = {}
+    if profile_steps:
+        ctx.set_profiling(True)
+        ctx.abm_step(profile_steps)
+        for k, (n, ms) in ctx.kernel_stats().items():
+            if n:
+                kern[k] = dict(launches=n, avg_ms=ms / n, total_ms=ms)
+        ctx.set_profiling(False)
+    d = ctx.densities_spin()
+    ra, rb = d["rho"]
+    pol = float(((ra - rb) / np.maximum(ra + rb, 1e-30)).max())
+    st, chk = ctx.check()
+    ctx.close()
+    return dict(nst=nst, steps=steps, seconds=dt, value=nst * steps / dt, ms_per_step=1e3 * dt / steps,
+                setup_seconds=t_setup, kernels=kern, max_polarisation=pol, check=dict(status=st, **chk))
+
+
 def run_q2d(steps, warmup, seed_vortex=2, profile_steps=2, precision=None):
     """Quasi-2D workload (workloads.Q2D): set-up, start-up and warm-up
     steps, then `steps` steps of tdslda_abm_step timed between two device
@@ -435,6 +468,8 @@ def main():
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--no-q1d", action="store_true")
     ap.add_argument("--no-q2d", action="store_true")
+    ap.add_argument("--aslda3d-steps", type=int, default=10,
+                    help="steps of the spin-imbalanced (ASLDA) FP64 32^3 run, 32,768 states (0 = skip)")
     ap.add_argument("--q1d-aslda-steps", type=int, default=500,
                     help="steps of the spin-imbalanced (ASLDA) batched quasi-1D run (0 = skip)")
     ap.add_argument("--q2d-steps", type=int, default=100,
@@ -549,6 +584,12 @@ def main():
         print(f"# batched q1d, spin-imbalanced ASLDA: {q1das['value']:.4g} state-steps/s over {q1das['steps']} "
               f"steps ({q1das['nst']} states, max polarisation {q1das['max_polarisation']:.2f})",
               file=sys.stderr, flush=True)
+    as3 = None
+    if args.aslda3d_steps > 0:
+        as3 = run_aslda3d(args.aslda3d_steps, max(1, args.warmup))
+        print(f"# FP64 32^3 spin-imbalanced ASLDA: {as3['value']:.4g} state-steps/s, {as3['ms_per_step']:.1f} "
+              f"ms/step ({as3['nst']} states, max polarisation {as3['max_polarisation']:.2f})", file=sys.stderr,
+              flush=True)
     q2d = q2d64 = None
     if not args.no_q2d and args.q2d_steps > 0:
         q2d = run_q2d(args.q2d_steps, max(1, args.warmup))
@@ -683,6 +724,16 @@ def main():
             "states_evolved": q1das["nst"], "max_polarisation": q1das["max_polarisation"],
             "setup_seconds": q1das["setup_seconds"], "tuned_workgroups": q1das["tuned"],
             "kernels": q1das["kernels"], "check": q1das["check"], "problems": q1das["problems"],
+        }
+    if as3 is not None:
+        line["aslda_3d"] = {
+            "workload": "spin-imbalanced ASLDA (p != 0), FP64 32^3 trap (omega = 0.05), mu_a = 1.4, mu_b = 0.6, "
+                        "both branches of the 16,384 lowest-|xi| momenta of the uniform start (32,768 states), "
+                        f"{as3['steps']} AB4AM5 steps (the general line passes with per-spin fields)",
+            "value": as3["value"], "unit": "state-steps/s", "ms_per_step": as3["ms_per_step"],
+            "states_evolved": as3["nst"], "max_polarisation": as3["max_polarisation"],
+            "cost_per_state_vs_A1": (as3["ms_per_step"] / as3["nst"]) / (plain["ms_per_step"] / plain["nst"]),
+            "setup_seconds": as3["setup_seconds"], "kernels": as3["kernels"], "check": as3["check"],
         }
     if q2d is not None:
         line["quasi2d"] = {

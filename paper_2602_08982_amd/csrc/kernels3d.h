@@ -861,21 +861,31 @@ __global__ __launch_bounds__(TBG) void k_grad_axis(
   }
 }
 
-// plane-wave states of the uniform H; one block row per state
+// plane-wave states of the uniform H; one block row per state.  both = 0:
+// the E > 0 state of every listed momentum (xi = k^2/2 + hshift,
+// E = sqrt(xi^2 + Delta^2), u = sqrt((1 + xi/E)/2), v = sqrt((1 - xi/E)/2)).
+// both = 1 (spin-imbalanced uniform problem, both branches): for the i-th
+// momentum states 2i and 2i+1, (u, v) at dshift + E and (-v, u) at
+// dshift - E, with hshift = U - (mu_a + mu_b)/2 and dshift = -(mu_a - mu_b)/2
+// (the reduced matrix of the momentum is dshift + the symmetric one).
 template <typename R>
 __global__ void k_plane_waves(int64_t M, int64_t nstates, int nx, int ny, int nz, const int32_t* __restrict__ kidx,
                               double hshift, double delta0, double kx, double ky, double kz,
-                              double invsqrtV, cpx<R>* __restrict__ X, double* __restrict__ E) {
+                              double invsqrtV, cpx<R>* __restrict__ X, double* __restrict__ E, int both,
+                              double dshift) {
   const int64_t r = int64_t(blockIdx.x) * 256 + threadIdx.x;
   for (int64_t n = blockIdx.y; n < nstates; n += gridDim.y) {
-  const int lx = kidx[3 * n], ly = kidx[3 * n + 1], lz = kidx[3 * n + 2];
+  const int64_t i = both ? n / 2 : n;
+  const bool minus = both && (n % 2 == 1);
+  const int lx = kidx[3 * i], ly = kidx[3 * i + 1], lz = kidx[3 * i + 2];
   const int mx = lx < nx / 2 ? lx : lx - nx, my = ly < ny / 2 ? ly : ly - ny,
             mz = lz < nz / 2 ? lz : lz - nz;
   const double k2 = kx * kx * mx * mx + ky * ky * my * my + kz * kz * mz * mz;
   const double xi = 0.5 * k2 + hshift;
   const double e = sqrt(xi * xi + delta0 * delta0);
-  const double uk = sqrt(0.5 * (1.0 + xi / e)), vk = sqrt(0.5 * (1.0 - xi / e));
-  if (r == 0) E[n] = e;
+  const double uk0 = sqrt(0.5 * (1.0 + xi / e)), vk0 = sqrt(0.5 * (1.0 - xi / e));
+  const double uk = minus ? -vk0 : uk0, vk = minus ? uk0 : vk0;
+  if (r == 0) E[n] = both ? (minus ? dshift - e : dshift + e) : e;
   if (r >= M) continue;
   const int ix = int(r / (int64_t(ny) * nz)), iy = int((r / nz) % ny), iz = int(r % nz);
   // phase / (2 pi) reduced exactly with integers

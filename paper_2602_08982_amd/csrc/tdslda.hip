@@ -773,7 +773,8 @@ tdslda_status tdslda_set_multiplicity(tdslda_ctx* c, int64_t n, const double* mu
 tdslda_status tdslda_init_plane_waves(tdslda_ctx* c, int64_t n, const int32_t* kidx, double u0, double delta0) {
   return guard(c, [&] {
     require(!c->q1d, TDSLDA_EINVAL, "plane-wave start is a 3D and quasi-2D option");
-    require(kidx != nullptr && n > 0 && n <= c->cap, TDSLDA_EINVAL, "bad plane-wave list");
+    const int64_t nout = c->aslda ? 2 * n : n;  // ASLDA: both branches of every momentum
+    require(kidx != nullptr && n > 0 && nout <= c->cap, TDSLDA_EINVAL, "bad plane-wave list");
     require(delta0 > 0, TDSLDA_EINVAL, "delta0 must be > 0");
     const int zmax = c->q2d ? c->lat.nz / 2 + 1 : c->lat.nz;  // quasi-2D: |k_z| classes 0 .. nz/2
     for (int64_t i = 0; i < n; ++i) {
@@ -786,7 +787,7 @@ tdslda_status tdslda_init_plane_waves(tdslda_ctx* c, int64_t n, const int32_t* k
       c->kidx_cap = n;
     }
     HIPCHK(hipMemcpyAsync(c->kidx_dev, kidx, size_t(n) * 12, hipMemcpyHostToDevice, c->stream));
-    c->nst = n;
+    c->nst = nout;
     const double kx = 2 * kPi / (c->lat.nx * c->lat.dx), ky = 2 * kPi / (c->lat.ny * c->lat.dy),
                  kz = 2 * kPi / (c->lat.nz * c->lat.dz);
     if (c->q2d) {
@@ -807,17 +808,21 @@ tdslda_status tdslda_init_plane_waves(tdslda_ctx* c, int64_t n, const int32_t* k
       return;
     }
     const double isv = 1.0 / std::sqrt(c->vol);
+    const double mubar = c->aslda ? 0.5 * (c->fun.mu + c->fun.mu_b) : c->fun.mu;
+    const double dsh = c->aslda ? -0.5 * (c->fun.mu - c->fun.mu_b) : 0.0;
     c->launch(KC_SETUP, [&] {
       if (c->esz == 16)
-        hipLaunchKernelGGL((k_plane_waves<double>), dim3(cdiv(c->M, 256), state_rows(n)), dim3(256), 0, c->stream, c->M, n,
-                           c->lat.nx, c->lat.ny, c->lat.nz, c->kidx_dev, u0 - c->fun.mu, delta0, kx, ky, kz, isv,
-                           (cpx<double>*)c->sb[0], c->E);
+        hipLaunchKernelGGL((k_plane_waves<double>), dim3(cdiv(c->M, 256), state_rows(nout)), dim3(256), 0, c->stream,
+                           c->M, nout, c->lat.nx, c->lat.ny, c->lat.nz, c->kidx_dev, u0 - mubar, delta0, kx, ky, kz,
+                           isv, (cpx<double>*)c->sb[0], c->E, int(c->aslda), dsh);
       else
-        hipLaunchKernelGGL((k_plane_waves<float>), dim3(cdiv(c->M, 256), state_rows(n)), dim3(256), 0, c->stream, c->M, n,
-                           c->lat.nx, c->lat.ny, c->lat.nz, c->kidx_dev, u0 - c->fun.mu, delta0, kx, ky, kz, isv,
-                           (cpx<float>*)c->sb[0], c->E);
+        hipLaunchKernelGGL((k_plane_waves<float>), dim3(cdiv(c->M, 256), state_rows(nout)), dim3(256), 0, c->stream,
+                           c->M, nout, c->lat.nx, c->lat.ny, c->lat.nz, c->kidx_dev, u0 - mubar, delta0, kx, ky, kz,
+                           isv, (cpx<float>*)c->sb[0], c->E, int(c->aslda), dsh);
     });
-    set_weights(*c, n, nullptr);
+    hipLaunchKernelGGL(k_fill_real<double>, dim3(cdiv(nout, 256)), dim3(256), 0, c->stream, nout, 1.0, c->mult);
+    HIPCHK(hipGetLastError());
+    set_weights(*c, nout, nullptr);
     after_load(*c);
     HIPCHK(hipStreamSynchronize(c->stream));
   });

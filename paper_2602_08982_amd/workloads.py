@@ -216,3 +216,28 @@ def setup_q1d_aslda(cfg, stream=None, precision=None):
     assert n == total
     return ctx, dict(nproblems=int(kp2.size), states=int(total), count_min=int(counts.min()),
                      count_max=int(counts.max()))
+
+
+# ---------------------------------------------------------------------------
+# Spin-imbalanced 3D workload (ASLDA at p != 0): the 32^3 trapped gas of the
+# headline with mu_a = 1.4, mu_b = 0.6 (a Zeeman split above the start's
+# pairing gap), the 16,384 momenta with the smallest |xi| of the uniform
+# start, both branches of each (32,768 states), FP64.
+ASLDA3D = dict(name="aslda_fp64_32", n=(32, 32, 32), d=(1.0, 1.0, 1.0), mu_a=1.4, mu_b=0.6, u0=0.0, delta0=0.3,
+               omega=(0.05, 0.05, 0.05), precision=T.FP64, dt=0.005, nmomenta=16384)
+
+
+def setup_aslda3d(cfg, stream=None, precision=None):
+    """Create the spin-imbalanced 3D context: trap on (regulator frozen with
+    the spin averages), both branches of the uniform start generated on the
+    device.  Returns (ctx, kidx)."""
+    n, d = cfg["n"], cfg["d"]
+    prec = cfg["precision"] if precision is None else precision
+    ec = 0.5 * (np.pi / d[0]) ** 2
+    mubar = 0.5 * (cfg["mu_a"] + cfg["mu_b"])
+    kidx = lowest_xi_kidx(n, d, mubar, cfg["u0"], cfg["nmomenta"])
+    run = T.run_config(precision=prec, integrator=T.AB4AM5, dt=cfg["dt"], selfstart=1, stream=stream)
+    ctx = T.Context(T.lattice_3d(n, d), T.functional_aslda(cfg["mu_a"], cfg["mu_b"], ec), run, 2 * len(kidx))
+    ctx.set_external(harmonic(n, d, cfg["omega"]), freeze_regulator=True)
+    ctx.init_plane_waves(kidx, cfg["u0"], cfg["delta0"])
+    return ctx, kidx

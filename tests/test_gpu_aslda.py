@@ -7,7 +7,7 @@ mean field."""
 import numpy as np
 import pytest
 
-from oracle import aslda as AS, functional as F, td, q1d
+from oracle import aslda as AS, bdg, functional as F, td, q1d
 from oracle import lattice as L
 
 pytestmark = pytest.mark.gpu
@@ -184,6 +184,58 @@ def test_aslda_3d_td(n, ec, prec):
         e = ctx.energy()
         o = sysa.observables(ref)
         assert abs(e["total"] - o["E"]) / abs(o["E"]) < tol
+        if prec == 0:
+            assert np.abs(ctx.get_states() - ref).max() < 1e-9
+    finally:
+        ctx.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_aslda_3d_plane_waves(prec):
+    """Both branches of the uniform start generated on the device for a
+    spin-imbalanced 3D context: state 2i is the positive branch of momentum
+    i at the spin-averaged xi, state 2i + 1 its partner (-v, u), with
+    E = -(mu_a - mu_b)/2 +- e; then 6 steps in a trap (regulator frozen with
+    the spin averages) against the oracle started from the same states with
+    the weights of those energies."""
+    from paper_2602_08982_amd import tdslda as T
+    n, mu_a, mu_b, u0, d0 = 8, 1.4, 0.6, 0.0, 0.3
+    lat = L.Lattice(n, n, n, 1.0, 1.0, 1.0)
+    X, Y, Z = np.meshgrid(*[L.centered_coords(n, 1.0)] * 3, indexing="ij")
+    vext = 0.5 * (1.5 / n) ** 2 * (X ** 2 + Y ** 2 + Z ** 2)
+    rng = np.random.default_rng(4)
+    kall = np.array([(a, b, c) for a in range(n) for b in range(n) for c in range(n)], np.int32)
+    kidx = kall[np.sort(rng.choice(len(kall), 150, replace=False))]
+    mubar, dsh = 0.5 * (mu_a + mu_b), -0.5 * (mu_a - mu_b)
+    e, pp = bdg.plane_wave_states(lat, kidx, u0 - mubar, d0)
+    phi = np.empty((2 * len(kidx),) + pp.shape[1:], complex)
+    phi[0::2] = pp
+    phi[1::2, 0], phi[1::2, 1] = -pp[:, 1], pp[:, 0]
+    E = np.empty(2 * len(kidx))
+    E[0::2], E[1::2] = dsh + e, dsh - e
+    assert np.any(np.all(E.reshape(-1, 2) < 0, axis=1))  # momenta with both branches filled: polarised
+    ecreg = 0.5 * np.pi ** 2
+    lam = F.lambda_c(vext, mubar, ecreg, A=1.094)
+    sysa = AS.ASLDASystem(AS.SpinGeometry3D(lat), mu_a, mu_b, vext, lam, F.fermi_weight(E), F.fermi_weight(-E))
+    ref = td.evolve(sysa, phi, 0.005, 6)
+    ctx = T.Context(T.lattice_3d(n), T.functional_aslda(mu_a, mu_b, ecreg), T.run_config(precision=prec, dt=0.005),
+                    len(E))
+    try:
+        ctx.set_external(vext, freeze_regulator=True)
+        ctx.init_plane_waves(kidx, u0, d0)
+        tol0 = 1e-14 if prec == 0 else 1e-7
+        assert np.abs(ctx.get_states() - phi).max() < tol0 * np.abs(phi).max() * 10
+        ctx.abm_step(6)
+        d = ctx.densities_spin()
+        ra, rb, ta, tb, nu, ja, jb = sysa.geom.densities(ref, sysa.wu, sysa.wv)
+        assert ((ra - rb) / (ra + rb)).max() > 0.05
+        tol = 1e-10 if prec == 0 else 1e-5
+        for a, b in ((d["rho"][0], ra), (d["rho"][1], rb), (d["tau"][0], ta), (d["tau"][1], tb), (d["nu"], nu)):
+            assert rel(a, b) < tol
+        e_ = ctx.energy()
+        o = sysa.observables(ref)
+        assert abs(e_["total"] - o["E"]) / abs(o["E"]) < tol
+        assert abs(e_["N"] - (o["Na"] + o["Nb"])) / (o["Na"] + o["Nb"]) < tol
         if prec == 0:
             assert np.abs(ctx.get_states() - ref).max() < 1e-9
     finally:
