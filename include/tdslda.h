@@ -180,7 +180,13 @@ tdslda_status tdslda_set_multiplicity(tdslda_ctx* ctx, int64_t n, const double* 
  * Q2D: kidx[n] = (l_x, l_y, m) with m in [0, nz/2] the |k_z| class
  * (k_z = 2 pi m / L_z enters xi), the x-y plane wave normalised on the x-y
  * lattice, and the multiplicity of the class (1 for m = 0 and m = nz/2,
- * else 2) set with k_z^2. */
+ * else 2) set with k_z^2.  ASLDA (3D): both branches of every listed
+ * momentum, 2n states (capacity >= 2n): with constant fields the
+ * imbalanced problem is the balanced one at the spin-averaged
+ * xi = k^2/2 + u0 - (mu_a + mu_b)/2, shifted by -(mu_a - mu_b)/2, so state
+ * 2i is (u, v) above at E = -(mu_a - mu_b)/2 + e and state 2i + 1 its
+ * partner (-v, u) at -(mu_a - mu_b)/2 - e, e = sqrt(xi^2 + delta0^2).
+ * Errors: EINVAL (Q1D context, n or an index out of range, delta0 <= 0). */
 tdslda_status tdslda_init_plane_waves(tdslda_ctx* ctx, int64_t n, const int32_t* kidx,
                                       double u0, double delta0);
 /* Vortex imprint on every loaded state (a phase e^{i theta} on Delta; Delta

@@ -14,7 +14,12 @@ struct Engine3D final : Engine {
   using CFG = SlabCfg<NX, NY, NZ>;
   static constexpr int G = 32;     // states per density group
   static constexpr int TB1 = 64;   // lap1 block
-  static constexpr int GTB = 64;   // line passes of the general functional
+  static constexpr int GTB = 64;   // line passes of the general functional (a thread per line)
+  // operator line passes (a lane pair per line): 256 threads, fewer where
+  // the block's running sums (NL/2 samples per thread) would pass 64 KB
+  static constexpr int NLMAX = NX > NY ? (NX > NZ ? NX : NZ) : (NY > NZ ? NY : NZ);
+  static constexpr int OTB_FIT = int(65536 / ((NLMAX / 2) * sizeof(cpx<R>))) / kWave * kWave;
+  static constexpr int OTB = OTB_FIT < 256 ? (OTB_FIT < kWave ? kWave : OTB_FIT) : 256;
   static constexpr int JG = sizeof(R) == 8 ? 256 : 128;  // states per group of the current / B' line passes
   static constexpr int M = NX * NY * NZ;
   static constexpr int NYZ = NY * NZ;
@@ -60,24 +65,25 @@ struct Engine3D final : Engine {
   // passes; with hp the <H>_n partials go to the h slots after the NGX raw
   // slots (which the last pass clears)
   void gen_apply(Ctx& c, const void* X, const double* scale, double* hp, void* out, int64_t nst) {
-    require(int(cdiv(NX * NY, GTB)) <= ncb(), TDSLDA_EINVAL, "internal: too few h slots for the z-line pass");
+    require(int(cdiv(NX * NY, OTB / 2)) <= ncb(), TDSLDA_EINVAL, "internal: too few h slots for the z-line pass");
     const int64_t fcs = c.aslda ? M : 0;  // ASLDA: fields per spin
     const cpx<R>* x = (const cpx<R>*)X;
     cpx<R>* T = (cpx<R>*)c.T;
     const R *al = (const R*)c.hAl, *la = (const R*)c.hLa, *hA = (const R*)c.hA;
     const cpx<R>* hD = (const cpx<R>*)c.hD;
+    constexpr int LPB = OTB / 2;  // lines per block
     c.launch(KC_LAP1, [&] {
-      hipLaunchKernelGGL((k_opline<R, NX, NY, NZ, 0, GTB, false>), dim3(cdiv(NYZ, GTB), nst), dim3(GTB), 0, c.stream,
+      hipLaunchKernelGGL((k_opline<R, NX, NY, NZ, 0, OTB, false>), dim3(cdiv(NYZ, LPB), nst), dim3(OTB), 0, c.stream,
                          x, scale, T, nullptr, al, la, (const R*)c.hAx, hA, hD, nullptr, c.h_stride, CFG::NGX,
                          ncb(), 2 * kPi / (NX * c.lat.dx), c.dV, fcs);
     });
     c.launch(KC_LAP1, [&] {
-      hipLaunchKernelGGL((k_opline<R, NX, NY, NZ, 1, GTB, false>), dim3(cdiv(NX * NZ, GTB), nst), dim3(GTB), 0,
+      hipLaunchKernelGGL((k_opline<R, NX, NY, NZ, 1, OTB, false>), dim3(cdiv(NX * NZ, LPB), nst), dim3(OTB), 0,
                          c.stream, x, scale, T, nullptr, al, la, (const R*)c.hAy, hA, hD, nullptr, c.h_stride,
                          CFG::NGX, ncb(), 2 * kPi / (NY * c.lat.dy), c.dV, fcs);
     });
     c.launch(KC_LAP1, [&] {
-      hipLaunchKernelGGL((k_opline<R, NX, NY, NZ, 2, GTB, true>), dim3(cdiv(NX * NY, GTB), nst), dim3(GTB), 0,
+      hipLaunchKernelGGL((k_opline<R, NX, NY, NZ, 2, OTB, true>), dim3(cdiv(NX * NY, LPB), nst), dim3(OTB), 0,
                          c.stream, x, scale, T, (cpx<R>*)out, al, la, (const R*)c.hAz, hA, hD, hp, c.h_stride,
                          CFG::NGX, ncb(), 2 * kPi / (NZ * c.lat.dz), c.dV, fcs);
     });

@@ -296,4 +296,77 @@ __host__ __device__ __forceinline__ void first_derivative(cpx<R> (&a)[N], R ksca
   inv<N>(a);
 }
 
+// ---------------------------------------------------------------------------
+// Lane-pair DFT of even length N: two adjacent lanes (parity b) share one
+// line, lane b holding the samples a[2j + b], j < N/2, so that a line needs
+// half the registers.  Radix-2 decimation in time across the pair: each lane
+// transforms its half (fwd<N/2>: position p holds frequency f =
+// freq_of_pos<N/2>(p)), the odd lane multiplies by w_N^-f, the lanes swap
+// values and combine, X[f] = E + w^-f O in the even lane and X[f + N/2] =
+// E - w^-f O in the odd one.  The inverse runs the flow graph backwards
+// (combine, odd-lane twiddle w_N^+f, inv<N/2>), back to the lane's samples.
+// The exchange is the only cross-lane step (device: a DPP swap of each
+// lane pair); the steps around it also compile for the host.
+template <int N, int SIGN, typename R>
+__host__ __device__ __forceinline__ void pair_twiddle(cpx<R> (&h)[N / 2], bool odd) {
+  constexpr int H = N / 2;
+  sfor<0, H>::run([&](auto pc) {
+    constexpr int p = decltype(pc)::value;
+    const cpx<R> t = twiddle<freq_of_pos<H>(p), N, SIGN>(h[p]);
+    // select per scalar (a select of the two values as a whole would take
+    // their addresses and keep the array out of registers)
+    h[p] = cpx<R>{odd ? t.x : h[p].x, odd ? t.y : h[p].y};
+  });
+}
+// h <- o + h (even lane), o - h (odd lane); o = the partner's h
+template <int H, typename R>
+__host__ __device__ __forceinline__ cpx<R> pair_butterfly(cpx<R> h, cpx<R> o, bool odd) {
+  const R sg = odd ? R(-1) : R(1);
+  return cpx<R>{o.x + sg * h.x, o.y + sg * h.y};
+}
+// signed wave number held at position p by lane parity odd after fwd_pair<N>
+template <int N, int P>
+__host__ __device__ __forceinline__ int pair_wavenum(bool odd) {
+  constexpr int H = N / 2, f = freq_of_pos<H>(P);
+  return odd ? f - H : f;
+}
+
+#ifdef __HIP__
+__device__ __forceinline__ float lane_pair_swap(float x) {
+  // quad_perm [1, 0, 3, 2]: lanes 2i and 2i + 1 exchange
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0xB1, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double lane_pair_swap(double x) {
+  const long long v = __builtin_bit_cast(long long, x);
+  const int lo = __builtin_amdgcn_mov_dpp(int(v), 0xB1, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(int(v >> 32), 0xB1, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, (long long)(unsigned(lo)) | ((long long)hi << 32));
+}
+template <typename R>
+__device__ __forceinline__ cpx<R> lane_pair_swap(cpx<R> c) {
+  return cpx<R>{lane_pair_swap(c.x), lane_pair_swap(c.y)};
+}
+// both lanes of every pair must be active
+template <int N, typename R>
+__device__ __forceinline__ void fwd_pair(cpx<R> (&h)[N / 2], bool odd) {
+  constexpr int H = N / 2;
+  fwd<H>(h);
+  pair_twiddle<N, -1>(h, odd);
+  sfor<0, H>::run([&](auto pc) {
+    constexpr int p = decltype(pc)::value;
+    h[p] = pair_butterfly<H>(h[p], lane_pair_swap(h[p]), odd);
+  });
+}
+template <int N, typename R>
+__device__ __forceinline__ void inv_pair(cpx<R> (&h)[N / 2], bool odd) {
+  constexpr int H = N / 2;
+  sfor<0, H>::run([&](auto pc) {
+    constexpr int p = decltype(pc)::value;
+    h[p] = pair_butterfly<H>(h[p], lane_pair_swap(h[p]), odd);
+  });
+  pair_twiddle<N, +1>(h, odd);
+  inv<H>(h);
+}
+#endif
+
 }  // namespace tdslda

@@ -247,7 +247,9 @@ __device__ __forceinline__ cpx<R> minus_half_i(cpx<R> c) {
 // h_part is given writes the block's partial of <H>_n = Re int phi^* H phi
 // dV into h slot h_off + blockIdx.x; block 0 clears the slots [0, h_off)
 // and [h_off + gridDim.x, h_off + n_slots).  phi = scale x X (scale NULL = 1).
-//   grid = (ceil(NLINES / TBG), nstates), block = TBG
+// Each line is held by a lane pair (the lane-pair DFT of fft.h: lane parity
+// b owns the samples 2j + b), which halves the registers of a line.
+//   grid = (ceil(NLINES / (TBG / 2)), nstates), block = TBG
 template <typename R, int NX, int NY, int NZ, int AXIS, int TBG, bool LAST>
 __global__ __launch_bounds__(TBG) void k_opline(const cpx<R>* __restrict__ X, const double* __restrict__ scale,
                                                 cpx<R>* __restrict__ T, cpx<R>* __restrict__ out,
@@ -257,16 +259,19 @@ __global__ __launch_bounds__(TBG) void k_opline(const cpx<R>* __restrict__ X, co
                                                 int h_stride, int h_off, int n_slots, double kscale, double dV,
                                                 int64_t fcs) {
   using LG = LineGeo<NX, NY, NZ, AXIS>;
-  constexpr int NL = LG::NL, ST = LG::STRIDE;
+  constexpr int NL = LG::NL, ST = LG::STRIDE, HL = NL / 2;
+  static_assert(NL % 2 == 0 && TBG % kWave == 0, "lane pairs");
   constexpr int64_t M = int64_t(NX) * NY * NZ;
   constexpr int ES = sizeof(cpx<R>), RS = sizeof(R);
   __shared__ double red[TBG / kWave];
-  // the running sum of the line's terms, element k of this thread's line at
-  // [k][thread]: one line array stays in registers (two more would spill)
-  __shared__ cpx<R> acc[NL][TBG];
-  const int l = blockIdx.x * TBG + threadIdx.x;
-  const bool act = l < LG::NLINES;
-  const int s0 = act ? LG::site0(l) : 0;
+  // the running sum of the line's terms, sample j of this lane at [j][lane]:
+  // one half-line array stays in registers
+  __shared__ cpx<R> acc[HL][TBG];
+  const int tx = threadIdx.x;
+  const int l = blockIdx.x * (TBG / 2) + tx / 2;
+  const bool odd = tx & 1;
+  const bool act = l < LG::NLINES;  // the same for both lanes of a pair
+  const int s0 = (act ? LG::site0(l) : 0) + (odd ? ST : 0);  // this lane's first sample
   const int64_t n = blockIdx.y;
   const R s = scale ? R(scale[n]) : R(1);
   const uint32_t SB = uint32_t(2 * M * ES);
@@ -276,8 +281,24 @@ __global__ __launch_bounds__(TBG) void k_opline(const cpx<R>* __restrict__ X, co
   const bi32x4 rO = make_rsrc(dst + n * 2 * M, SB);
   const int vo = s0 * ES, va = s0 * RS;
   const R kk = R(kscale), inv_n = R(1.0 / NL);
-  const int tx = threadIdx.x;
   double hloc = 0.0;
+  // spectral factors at position p: -k^2 / N (D2, the Nyquist bin kept) and
+  // i k / N (D1, the Nyquist bin zeroed)
+  auto d2 = [&](cpx<R>(&t)[HL]) {
+    sfor<0, HL>::run([&](auto pc) {
+      constexpr int p = decltype(pc)::value;
+      const R km = kk * R(pair_wavenum<NL, p>(odd));
+      t[p] = (-km * km * inv_n) * t[p];
+    });
+  };
+  auto d1 = [&](cpx<R>(&t)[HL]) {
+    sfor<0, HL>::run([&](auto pc) {
+      constexpr int p = decltype(pc)::value;
+      const int m = pair_wavenum<NL, p>(odd);
+      const R km = (m == -HL) ? R(0) : kk * R(m);
+      t[p] = (km * inv_n) * mul_i(t[p]);
+    });
+  };
   if (act) {
 #pragma unroll 1
     for (int comp = 0; comp < 2; ++comp) {
@@ -286,60 +307,55 @@ __global__ __launch_bounds__(TBG) void k_opline(const cpx<R>* __restrict__ X, co
       // the fields of this row's spin (fcs = M: [spin][M] arrays; 0: one set)
       const int64_t fo = comp * fcs;
       const bi32x4 rAl = make_rsrc(hAl + fo, uint32_t(M * RS)), rAd = make_rsrc(hAd + fo, uint32_t(M * RS));
-      cpx<R> t[NL];
-      cpx<R> nyq;
+      cpx<R> t[HL];
       phase_fence();
       // alpha D2 x
 #pragma unroll
-      for (int k = 0; k < NL; ++k) t[k] = s * bload<R>(rX, vo, (cb + k * ST) * ES);
-      fwd<NL>(t);
-      sfor<0, NL>::run([&](auto pc) {
-        constexpr int p = decltype(pc)::value;
-        constexpr int m = wavenum_at<NL>(p);
-        const R km = kk * R(m);
-        t[p] = (-km * km * inv_n) * t[p];
-      });
-      inv<NL>(t);
+      for (int j = 0; j < HL; ++j) t[j] = s * bload<R>(rX, vo, (cb + 2 * j * ST) * ES);
+      fwd_pair<NL>(t, odd);
+      d2(t);
+      inv_pair<NL>(t, odd);
 #pragma unroll
-      for (int k = 0; k < NL; ++k) acc[k][tx] = (sg * R(-0.25) * bload_real<R>(rAl, va, k * ST * RS)) * t[k];
+      for (int j = 0; j < HL; ++j)
+        acc[j][tx] = (sg * R(-0.25) * bload_real<R>(rAl, va, 2 * j * ST * RS)) * t[j];
       phase_fence();
       // A_d D1 x
 #pragma unroll
-      for (int k = 0; k < NL; ++k) t[k] = s * bload<R>(rX, vo, (cb + k * ST) * ES);
-      first_derivative<NL>(t, kk, nyq);
+      for (int j = 0; j < HL; ++j) t[j] = s * bload<R>(rX, vo, (cb + 2 * j * ST) * ES);
+      fwd_pair<NL>(t, odd);
+      d1(t);
+      inv_pair<NL>(t, odd);
 #pragma unroll
-      for (int k = 0; k < NL; ++k) acc[k][tx] = acc[k][tx] + minus_half_i(bload_real<R>(rAd, va, k * ST * RS) * t[k]);
+      for (int j = 0; j < HL; ++j)
+        acc[j][tx] = acc[j][tx] + minus_half_i(bload_real<R>(rAd, va, 2 * j * ST * RS) * t[j]);
       phase_fence();
       // D2(alpha x)
 #pragma unroll
-      for (int k = 0; k < NL; ++k)
-        t[k] = bload_real<R>(rAl, va, k * ST * RS) * (s * bload<R>(rX, vo, (cb + k * ST) * ES));
-      fwd<NL>(t);
-      sfor<0, NL>::run([&](auto pc) {
-        constexpr int p = decltype(pc)::value;
-        constexpr int m = wavenum_at<NL>(p);
-        const R km = kk * R(m);
-        t[p] = (-km * km * inv_n) * t[p];
-      });
-      inv<NL>(t);
+      for (int j = 0; j < HL; ++j)
+        t[j] = bload_real<R>(rAl, va, 2 * j * ST * RS) * (s * bload<R>(rX, vo, (cb + 2 * j * ST) * ES));
+      fwd_pair<NL>(t, odd);
+      d2(t);
+      inv_pair<NL>(t, odd);
 #pragma unroll
-      for (int k = 0; k < NL; ++k) acc[k][tx] = acc[k][tx] + (sg * R(-0.25)) * t[k];
+      for (int j = 0; j < HL; ++j) acc[j][tx] = acc[j][tx] + (sg * R(-0.25)) * t[j];
       phase_fence();
       // D1(A_d x)
 #pragma unroll
-      for (int k = 0; k < NL; ++k)
-        t[k] = bload_real<R>(rAd, va, k * ST * RS) * (s * bload<R>(rX, vo, (cb + k * ST) * ES));
-      first_derivative<NL>(t, kk, nyq);
+      for (int j = 0; j < HL; ++j)
+        t[j] = bload_real<R>(rAd, va, 2 * j * ST * RS) * (s * bload<R>(rX, vo, (cb + 2 * j * ST) * ES));
+      fwd_pair<NL>(t, odd);
+      d1(t);
+      inv_pair<NL>(t, odd);
       phase_fence();
 #pragma unroll
-      for (int k = 0; k < NL; ++k) {
-        cpx<R> r = acc[k][tx] + minus_half_i(t[k]);
-        const int o = (cb + k * ST) * ES;
+      for (int j = 0; j < HL; ++j) {
+        cpx<R> r = acc[j][tx] + minus_half_i(t[j]);
+        const int o = (cb + 2 * j * ST) * ES;
         if constexpr (AXIS > 0) r = r + bload<R>(rT, vo, o);
         if constexpr (LAST) {
-          const int site = s0 + k * ST;
+          const int site = s0 + 2 * j * ST;
           const cpx<R> x = s * bload<R>(rX, vo, o);
-          const cpx<R> y = s * bload<R>(rX, vo, (int((1 - comp) * M) + k * ST) * ES);
+          const cpx<R> y = s * bload<R>(rX, vo, (int((1 - comp) * M) + 2 * j * ST) * ES);
           const cpx<R> D = hD[site];
           const cpx<R> Dc = comp ? conj(D) : D;
           r = r + (sg * (R(0.25) * hLa[fo + site] + hA[fo + site])) * x + Dc * y;
@@ -352,9 +368,9 @@ __global__ __launch_bounds__(TBG) void k_opline(const cpx<R>* __restrict__ X, co
   if constexpr (LAST) {
     if (h_part) {
       double v = wave_sum(hloc);
-      if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = v;
+      if (tx % kWave == 0) red[tx / kWave] = v;
       __syncthreads();
-      if (threadIdx.x == 0) {
+      if (tx == 0) {
         double t = 0.0;
 #pragma unroll
         for (int w = 0; w < TBG / kWave; ++w) t += red[w];

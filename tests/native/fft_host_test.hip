@@ -78,8 +78,66 @@ static double check() {
   return std::fmax(std::fmax(err, err2), std::fmax(err1, errk));
 }
 
+// lane-pair form: two lanes simulated by two arrays, the exchange by
+// swapping them; forward against the direct sum (the even lane holding
+// frequency f, the odd one f + N/2 at position p), wave numbers, and the
+// inverse back to the samples
+template <int N>
+static double check_pair() {
+  constexpr int H = N / 2;
+  std::mt19937_64 g(N + 1000);
+  std::normal_distribution<double> nd;
+  cpx<double> a[N], out[N];
+  for (int j = 0; j < N; ++j) a[j] = {nd(g), nd(g)};
+  dft_natural<N, -1>(a, out);
+  cpx<double> h[2][H], o[2][H];
+  for (int b = 0; b < 2; ++b)
+    for (int j = 0; j < H; ++j) h[b][j] = a[2 * j + b];
+  for (int b = 0; b < 2; ++b) {
+    fwd<H>(h[b]);
+    pair_twiddle<N, -1>(h[b], b == 1);
+  }
+  for (int b = 0; b < 2; ++b)
+    for (int p = 0; p < H; ++p) o[b][p] = h[1 - b][p];
+  for (int b = 0; b < 2; ++b)
+    for (int p = 0; p < H; ++p) h[b][p] = pair_butterfly<H>(h[b][p], o[b][p], b == 1);
+  double err = 0, mx = 0;
+  int bad_m = 0;
+  sfor<0, H>::run([&](auto pc) {
+    constexpr int p = decltype(pc)::value;
+    for (int b = 0; b < 2; ++b) {
+      const int k = freq_of_pos<H>(p) + b * H;
+      err = std::fmax(err, std::hypot(h[b][p].x - out[k].x, h[b][p].y - out[k].y));
+      mx = std::fmax(mx, std::hypot(out[k].x, out[k].y));
+      const int m = pair_wavenum<N, p>(b == 1);
+      if (m != wavenum<N>(k) && !(k == H && m == -H)) ++bad_m;
+    }
+  });
+  for (int b = 0; b < 2; ++b)
+    for (int p = 0; p < H; ++p) o[b][p] = h[1 - b][p];
+  for (int b = 0; b < 2; ++b) {
+    for (int p = 0; p < H; ++p) h[b][p] = pair_butterfly<H>(h[b][p], o[b][p], b == 1);
+    pair_twiddle<N, +1>(h[b], b == 1);
+    inv<H>(h[b]);
+  }
+  double erri = 0;
+  for (int b = 0; b < 2; ++b)
+    for (int j = 0; j < H; ++j)
+      erri = std::fmax(erri, std::hypot(h[b][j].x / N - a[2 * j + b].x, h[b][j].y / N - a[2 * j + b].y));
+  std::printf("pair N=%d dft=%.3e inverse=%.3e wavenumbers %s\n", N, err / mx, erri, bad_m ? "WRONG" : "ok");
+  return bad_m ? 1.0 : std::fmax(err / mx, erri);
+}
+
 int main() {
   double e = 0;
+  e = std::fmax(e, check_pair<4>());
+  e = std::fmax(e, check_pair<6>());
+  e = std::fmax(e, check_pair<8>());
+  e = std::fmax(e, check_pair<12>());
+  e = std::fmax(e, check_pair<16>());
+  e = std::fmax(e, check_pair<24>());
+  e = std::fmax(e, check_pair<32>());
+  e = std::fmax(e, check_pair<48>());
   e = std::fmax(e, check<2>());
   e = std::fmax(e, check<4>());
   e = std::fmax(e, check<6>());

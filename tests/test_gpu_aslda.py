@@ -218,6 +218,13 @@ def test_aslda_3d_plane_waves(prec):
     lam = F.lambda_c(vext, mubar, ecreg, A=1.094)
     sysa = AS.ASLDASystem(AS.SpinGeometry3D(lat), mu_a, mu_b, vext, lam, F.fermi_weight(E), F.fermi_weight(-E))
     ref = td.evolve(sysa, phi, 0.005, 6)
+    small = T.Context(T.lattice_3d(n), T.functional_aslda(mu_a, mu_b, ecreg), T.run_config(precision=prec),
+                      len(E) - 1)
+    try:  # both branches need capacity 2n
+        with pytest.raises(T.TdsldaError):
+            small.init_plane_waves(kidx, u0, d0)
+    finally:
+        small.close()
     ctx = T.Context(T.lattice_3d(n), T.functional_aslda(mu_a, mu_b, ecreg), T.run_config(precision=prec, dt=0.005),
                     len(E))
     try:
