@@ -14,7 +14,7 @@ struct Engine3D final : Engine {
   using CFG = SlabCfg<NX, NY, NZ>;
   static constexpr int G = 32;     // states per density group
   static constexpr int TB1 = 64;   // lap1 block
-  static constexpr int GTB = 64;   // line passes of the general functional (a thread per line)
+  static constexpr int GTB = 64;   // line passes of the current, tau and B' (a lane pair per line) and of the field derivatives (a thread per line)
   // operator line passes (a lane pair per line): 256 threads, fewer where
   // the block's running sums (NL/2 samples per thread) would pass 64 KB
   static constexpr int NLMAX = NX > NY ? (NX > NZ ? NX : NZ) : (NY > NZ ? NY : NZ);
@@ -48,15 +48,15 @@ struct Engine3D final : Engine {
     const unsigned jg = cdiv(nst, JG);
     const cpx<R>* x = (const cpx<R>*)X;
     c.launch(KC_DENS, [&] {
-      hipLaunchKernelGGL((k_jline<R, NX, NY, NZ, 0, GTB, JG>), dim3(cdiv(NYZ, GTB), jg), dim3(GTB), 0, c.stream, x,
+      hipLaunchKernelGGL((k_jline<R, NX, NY, NZ, 0, GTB, JG>), dim3(cdiv(NYZ, GTB / 2), jg), dim3(GTB), 0, c.stream, x,
                          nst, scale, c.wu, c.wv, 2 * kPi / (NX * c.lat.dx), c.jpart);
     });
     c.launch(KC_DENS, [&] {
-      hipLaunchKernelGGL((k_jline<R, NX, NY, NZ, 1, GTB, JG>), dim3(cdiv(NX * NZ, GTB), jg), dim3(GTB), 0, c.stream,
+      hipLaunchKernelGGL((k_jline<R, NX, NY, NZ, 1, GTB, JG>), dim3(cdiv(NX * NZ, GTB / 2), jg), dim3(GTB), 0, c.stream,
                          x, nst, scale, c.wu, c.wv, 2 * kPi / (NY * c.lat.dy), c.jpart);
     });
     c.launch(KC_DENS, [&] {
-      hipLaunchKernelGGL((k_jline<R, NX, NY, NZ, 2, GTB, JG>), dim3(cdiv(NX * NY, GTB), jg), dim3(GTB), 0, c.stream,
+      hipLaunchKernelGGL((k_jline<R, NX, NY, NZ, 2, GTB, JG>), dim3(cdiv(NX * NY, GTB / 2), jg), dim3(GTB), 0, c.stream,
                          x, nst, scale, c.wu, c.wv, 2 * kPi / (NZ * c.lat.dz), c.jpart);
     });
     c.njg_used = int(jg);
@@ -96,11 +96,11 @@ struct Engine3D final : Engine {
     const double kx = 2 * kPi / (NX * c.lat.dx), ky = 2 * kPi / (NY * c.lat.dy), kz = 2 * kPi / (NZ * c.lat.dz);
     jlines(c, X, scale, nst);
     c.launch(KC_FRICTION, [&] {
-      hipLaunchKernelGGL((k_bpline<R, NX, NY, NZ, 0, GTB, JG>), dim3(cdiv(NYZ, GTB), ng), dim3(GTB), 0, c.stream, x,
+      hipLaunchKernelGGL((k_bpline<R, NX, NY, NZ, 0, GTB, JG>), dim3(cdiv(NYZ, GTB / 2), ng), dim3(GTB), 0, c.stream, x,
                          nst, scale, c.wu, c.wv, kx * kx, c.fric_part);
-      hipLaunchKernelGGL((k_bpline<R, NX, NY, NZ, 1, GTB, JG>), dim3(cdiv(NX * NZ, GTB), ng), dim3(GTB), 0, c.stream,
+      hipLaunchKernelGGL((k_bpline<R, NX, NY, NZ, 1, GTB, JG>), dim3(cdiv(NX * NZ, GTB / 2), ng), dim3(GTB), 0, c.stream,
                          x, nst, scale, c.wu, c.wv, ky * ky, c.fric_part);
-      hipLaunchKernelGGL((k_bpline<R, NX, NY, NZ, 2, GTB, JG>), dim3(cdiv(NX * NY, GTB), ng), dim3(GTB), 0, c.stream,
+      hipLaunchKernelGGL((k_bpline<R, NX, NY, NZ, 2, GTB, JG>), dim3(cdiv(NX * NY, GTB / 2), ng), dim3(GTB), 0, c.stream,
                          x, nst, scale, c.wu, c.wv, kz * kz, c.fric_part);
       hipLaunchKernelGGL(k_fric_sum3d, dim3(cdiv(M, 256)), dim3(256), 0, c.stream, c.jpart, c.fric_part, int(ng),
                          int64_t(M), c.ainv, c.fric_j, c.fric_bp);
@@ -126,11 +126,11 @@ struct Engine3D final : Engine {
     c.launch(KC_DENS, [&] {
       hipLaunchKernelGGL((k_dens_sum<R, DG, DS_P, 12, true>), dim3(cdiv(M, DS_TB * DS_P), ng), dim3(DS_TB), 0,
                          c.stream, x, nst, int64_t(M), c.wu, c.wv, scale, c.dens_part);
-      hipLaunchKernelGGL((k_taujline<R, NX, NY, NZ, 0, GTB, DG>), dim3(cdiv(NYZ, GTB), ng), dim3(GTB), 0, c.stream,
+      hipLaunchKernelGGL((k_taujline<R, NX, NY, NZ, 0, GTB, DG>), dim3(cdiv(NYZ, GTB / 2), ng), dim3(GTB), 0, c.stream,
                          x, nst, scale, c.wu, c.wv, kx, px * px, c.dens_part);
-      hipLaunchKernelGGL((k_taujline<R, NX, NY, NZ, 1, GTB, DG>), dim3(cdiv(NX * NZ, GTB), ng), dim3(GTB), 0,
+      hipLaunchKernelGGL((k_taujline<R, NX, NY, NZ, 1, GTB, DG>), dim3(cdiv(NX * NZ, GTB / 2), ng), dim3(GTB), 0,
                          c.stream, x, nst, scale, c.wu, c.wv, ky, py * py, c.dens_part);
-      hipLaunchKernelGGL((k_taujline<R, NX, NY, NZ, 2, GTB, DG>), dim3(cdiv(NX * NY, GTB), ng), dim3(GTB), 0,
+      hipLaunchKernelGGL((k_taujline<R, NX, NY, NZ, 2, GTB, DG>), dim3(cdiv(NX * NY, GTB / 2), ng), dim3(GTB), 0,
                          c.stream, x, nst, scale, c.wu, c.wv, kz, pz * pz, c.dens_part);
     });
     c.nsg_used = int(ng);

@@ -331,6 +331,14 @@ __host__ __device__ __forceinline__ int pair_wavenum(bool odd) {
   return odd ? f - H : f;
 }
 
+// the same at run time for row position q = 2p + b of a line stored by
+// lane pairs
+template <int N>
+__host__ __device__ __forceinline__ int pair_wavenum_at(int q) {
+  const int f = freq_of_pos<N / 2>(q >> 1);
+  return (q & 1) ? f - N / 2 : f;
+}
+
 #ifdef __HIP__
 __device__ __forceinline__ float lane_pair_swap(float x) {
   // quad_perm [1, 0, 3, 2]: lanes 2i and 2i + 1 exchange
@@ -366,6 +374,34 @@ __device__ __forceinline__ void inv_pair(cpx<R> (&h)[N / 2], bool odd) {
   });
   pair_twiddle<N, +1>(h, odd);
   inv<H>(h);
+}
+// second_derivative / first_derivative in the lane-pair form (each lane's
+// half of the line in place); nyq = DFT(a)[N/2] / N in both lanes
+template <int N, typename R>
+__device__ __forceinline__ void second_derivative_pair(cpx<R> (&h)[N / 2], R kscale2, bool odd) {
+  fwd_pair<N>(h, odd);
+  const R f = -kscale2 / R(N);
+  sfor<0, N / 2>::run([&](auto pc) {
+    constexpr int p = decltype(pc)::value;
+    const R m = R(pair_wavenum<N, p>(odd));
+    h[p] = (f * m * m) * h[p];
+  });
+  inv_pair<N>(h, odd);
+}
+template <int N, typename R>
+__device__ __forceinline__ void first_derivative_pair(cpx<R> (&h)[N / 2], R kscale, bool odd, cpx<R>& nyq) {
+  fwd_pair<N>(h, odd);
+  // the Nyquist bin is position 0 of the odd lane
+  const cpx<R> other = lane_pair_swap(h[0]);
+  nyq = (R(1) / R(N)) * cpx<R>{odd ? h[0].x : other.x, odd ? h[0].y : other.y};
+  const R f = kscale / R(N);
+  sfor<0, N / 2>::run([&](auto pc) {
+    constexpr int p = decltype(pc)::value;
+    const int m = pair_wavenum<N, p>(odd);
+    const R km = (m == -N / 2) ? R(0) : f * R(m);
+    h[p] = km * mul_i(h[p]);
+  });
+  inv_pair<N>(h, odd);
 }
 #endif
 

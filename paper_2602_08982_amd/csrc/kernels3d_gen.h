@@ -37,24 +37,26 @@ struct LineGeo {
 // j_AXIS group partials over DG states of the normalised states:
 //   jpart[g][AXIS][site] = sum_n f_v Im(v (D1 v)^*) - f_u Im(u (D1 u)^*)
 // (a component of zero weight is skipped: f_u = 0 for E > 0 at T = 0).
-//   grid = (ceil(NLINES / TBG), number of groups), block = TBG
+// A lane pair per line (lane parity b: samples 2j + b).
+//   grid = (ceil(NLINES / (TBG / 2)), number of groups), block = TBG
 template <typename R, int NX, int NY, int NZ, int AXIS, int TBG, int DG>
 __global__ __launch_bounds__(TBG) void k_jline(const cpx<R>* __restrict__ X, int64_t nstates,
                                                const double* __restrict__ scale, const double* __restrict__ wu,
                                                const double* __restrict__ wv, double kscale,
                                                double* __restrict__ jpart) {
   using LG = LineGeo<NX, NY, NZ, AXIS>;
-  constexpr int NL = LG::NL, ST = LG::STRIDE;
+  constexpr int NL = LG::NL, ST = LG::STRIDE, HL = NL / 2;
   constexpr int64_t M = int64_t(NX) * NY * NZ;
   constexpr int ES = sizeof(cpx<R>);
-  const int l = blockIdx.x * TBG + threadIdx.x;
-  if (l >= LG::NLINES) return;  // no barriers below
-  const int s0 = LG::site0(l);
+  const int l = blockIdx.x * (TBG / 2) + threadIdx.x / 2;
+  const bool odd = threadIdx.x & 1;
+  if (l >= LG::NLINES) return;  // both lanes of a pair; no barriers below
+  const int s0 = LG::site0(l) + (odd ? ST : 0);
   const int64_t nbeg = int64_t(blockIdx.y) * DG;
   const int nloc = int(nstates - nbeg < DG ? nstates - nbeg : DG);
-  double acc[NL];
+  double acc[HL];
 #pragma unroll
-  for (int k = 0; k < NL; ++k) acc[k] = 0.0;
+  for (int j = 0; j < HL; ++j) acc[j] = 0.0;
   for (int ls = 0; ls < nloc; ++ls) {
     const int64_t n = nbeg + ls;
     const R s = R(scale[n]);
@@ -63,21 +65,21 @@ __global__ __launch_bounds__(TBG) void k_jline(const cpx<R>* __restrict__ X, int
 #pragma unroll 1
     for (int comp = 0; comp < 2; ++comp) {
       const double w = comp ? fv : -fu;
-      if (w == 0.0) continue;
-      cpx<R> d[NL], ny;
+      if (w == 0.0) continue;  // uniform over the block
+      cpx<R> d[HL], ny;
 #pragma unroll
-      for (int k = 0; k < NL; ++k) d[k] = s * bload<R>(rX, s0 * ES, int(comp * M + k * ST) * ES);
-      first_derivative<NL>(d, R(kscale), ny);
+      for (int j = 0; j < HL; ++j) d[j] = s * bload<R>(rX, s0 * ES, int(comp * M + 2 * j * ST) * ES);
+      first_derivative_pair<NL>(d, R(kscale), odd, ny);
 #pragma unroll
-      for (int k = 0; k < NL; ++k) {
-        const cpx<R> f = s * bload<R>(rX, s0 * ES, int(comp * M + k * ST) * ES);  // re-read (cached)
-        acc[k] += w * (double(f.y) * double(d[k].x) - double(f.x) * double(d[k].y));  // Im(f (D1 f)^*)
+      for (int j = 0; j < HL; ++j) {
+        const cpx<R> f = s * bload<R>(rX, s0 * ES, int(comp * M + 2 * j * ST) * ES);  // re-read (cached)
+        acc[j] += w * (double(f.y) * double(d[j].x) - double(f.x) * double(d[j].y));  // Im(f (D1 f)^*)
       }
     }
   }
   double* out = jpart + (int64_t(blockIdx.y) * 3 + AXIS) * M + s0;
 #pragma unroll
-  for (int k = 0; k < NL; ++k) out[k * ST] = acc[k];
+  for (int j = 0; j < HL; ++j) out[2 * j * ST] = acc[j];
 }
 
 // Spin-imbalanced ASLDA (Sec. 2.4, ASLDA item; Eqs. na3D-jb3D), both
@@ -88,56 +90,57 @@ __global__ __launch_bounds__(TBG) void k_jline(const cpx<R>* __restrict__ X, int
 //   tau_a += sum f_u (|D1 u|^2 + (pi/d)^2 |c_u|^2),  tau_b with v, f_v
 //   (AXIS 0 writes, the other axes add), j_a,AXIS = -sum f_u Im(u (D1 u)^*),
 //   j_b,AXIS = sum f_v Im(v (D1 v)^*); D1 with the Nyquist bin zeroed, c the
-//   Nyquist amplitude.
-//   grid = (ceil(NLINES / TBG), number of groups), block = TBG
+//   Nyquist amplitude.  A lane pair per line (lane parity b: samples 2j + b).
+//   grid = (ceil(NLINES / (TBG / 2)), number of groups), block = TBG
 template <typename R, int NX, int NY, int NZ, int AXIS, int TBG, int DG>
 __global__ __launch_bounds__(TBG) void k_taujline(const cpx<R>* __restrict__ X, int64_t nstates,
                                                   const double* __restrict__ scale, const double* __restrict__ wu,
                                                   const double* __restrict__ wv, double kscale, double nyq2,
                                                   double* __restrict__ part) {
   using LG = LineGeo<NX, NY, NZ, AXIS>;
-  constexpr int NL = LG::NL, ST = LG::STRIDE;
+  constexpr int NL = LG::NL, ST = LG::STRIDE, HL = NL / 2;
   constexpr int64_t M = int64_t(NX) * NY * NZ;
   constexpr int ES = sizeof(cpx<R>);
-  const int l = blockIdx.x * TBG + threadIdx.x;
-  if (l >= LG::NLINES) return;  // no barriers below
-  const int s0 = LG::site0(l);
+  const int l = blockIdx.x * (TBG / 2) + threadIdx.x / 2;
+  const bool odd = threadIdx.x & 1;
+  if (l >= LG::NLINES) return;  // both lanes of a pair; no barriers below
+  const int s0 = LG::site0(l) + (odd ? ST : 0);
   const int64_t nbeg = int64_t(blockIdx.y) * DG;
   const int nloc = int(nstates - nbeg < DG ? nstates - nbeg : DG);
   double* gp = part + int64_t(blockIdx.y) * 12 * M + s0;
 #pragma unroll 1
   for (int comp = 0; comp < 2; ++comp) {
     const double sgn = comp ? 1.0 : -1.0;
-    double at[NL], aj[NL];
+    double at[HL], aj[HL];
 #pragma unroll
-    for (int k = 0; k < NL; ++k) at[k] = aj[k] = 0.0;
+    for (int j = 0; j < HL; ++j) at[j] = aj[j] = 0.0;
     for (int ls = 0; ls < nloc; ++ls) {
       const int64_t n = nbeg + ls;
       const double w = comp ? wv[n] : wu[n];
-      if (w == 0.0) continue;
+      if (w == 0.0) continue;  // uniform over the block
       const R s = R(scale[n]);
       const bi32x4 rX = make_rsrc(X + n * 2 * M, uint32_t(2 * M * ES));
-      cpx<R> d[NL], ny;
+      cpx<R> d[HL], ny;
 #pragma unroll
-      for (int k = 0; k < NL; ++k) d[k] = s * bload<R>(rX, s0 * ES, int(comp * M + k * ST) * ES);
-      first_derivative<NL>(d, R(kscale), ny);
+      for (int j = 0; j < HL; ++j) d[j] = s * bload<R>(rX, s0 * ES, int(comp * M + 2 * j * ST) * ES);
+      first_derivative_pair<NL>(d, R(kscale), odd, ny);
       const double cn = nyq2 * norm2(ny);
 #pragma unroll
-      for (int k = 0; k < NL; ++k) {
-        const cpx<R> f = s * bload<R>(rX, s0 * ES, int(comp * M + k * ST) * ES);  // re-read (cached)
-        at[k] += w * (norm2(d[k]) + cn);
-        aj[k] += sgn * w * (double(f.y) * double(d[k].x) - double(f.x) * double(d[k].y));  // Im(f (D1 f)^*)
+      for (int j = 0; j < HL; ++j) {
+        const cpx<R> f = s * bload<R>(rX, s0 * ES, int(comp * M + 2 * j * ST) * ES);  // re-read (cached)
+        at[j] += w * (norm2(d[j]) + cn);
+        aj[j] += sgn * w * (double(f.y) * double(d[j].x) - double(f.x) * double(d[j].y));  // Im(f (D1 f)^*)
       }
     }
     double* ot = gp + (4 + comp) * M;
     double* oj = gp + (6 + 3 * comp + AXIS) * M;
 #pragma unroll
-    for (int k = 0; k < NL; ++k) {
+    for (int j = 0; j < HL; ++j) {
       if constexpr (AXIS == 0)
-        ot[k * ST] = at[k];
+        ot[2 * j * ST] = at[j];
       else
-        ot[k * ST] += at[k];
-      oj[k * ST] = aj[k];
+        ot[2 * j * ST] += at[j];
+      oj[2 * j * ST] = aj[j];
     }
   }
 }
@@ -557,60 +560,62 @@ __global__ void k_field_lap3d(int nx, int ny, int nz, const double* __restrict__
 
 // B'_AXIS group partials over DG states, bpart[g][re|im][site] (AXIS 0
 // writes, the other axes add):  -1/2 (f_v - f_u) [u (D2 v)^* + v^* D2 u]
-//   grid = (ceil(NLINES / TBG), number of groups), block = TBG
+// A lane pair per line (lane parity b: samples 2j + b).
+//   grid = (ceil(NLINES / (TBG / 2)), number of groups), block = TBG
 template <typename R, int NX, int NY, int NZ, int AXIS, int TBG, int DG>
 __global__ __launch_bounds__(TBG) void k_bpline(const cpx<R>* __restrict__ X, int64_t nstates,
                                                 const double* __restrict__ scale, const double* __restrict__ wu,
                                                 const double* __restrict__ wv, double kscale2,
                                                 double* __restrict__ bpart) {
   using LG = LineGeo<NX, NY, NZ, AXIS>;
-  constexpr int NL = LG::NL, ST = LG::STRIDE;
+  constexpr int NL = LG::NL, ST = LG::STRIDE, HL = NL / 2;
   constexpr int64_t M = int64_t(NX) * NY * NZ;
   constexpr int ES = sizeof(cpx<R>);
-  const int l = blockIdx.x * TBG + threadIdx.x;
-  if (l >= LG::NLINES) return;  // no barriers below
-  const int s0 = LG::site0(l);
+  const int l = blockIdx.x * (TBG / 2) + threadIdx.x / 2;
+  const bool odd = threadIdx.x & 1;
+  if (l >= LG::NLINES) return;  // both lanes of a pair; no barriers below
+  const int s0 = LG::site0(l) + (odd ? ST : 0);
   const int64_t nbeg = int64_t(blockIdx.y) * DG;
   const int nloc = int(nstates - nbeg < DG ? nstates - nbeg : DG);
-  double br[NL], bi[NL];
+  double br[HL], bi[HL];
 #pragma unroll
-  for (int k = 0; k < NL; ++k) br[k] = bi[k] = 0.0;
+  for (int j = 0; j < HL; ++j) br[j] = bi[j] = 0.0;
   for (int ls = 0; ls < nloc; ++ls) {
     const int64_t n = nbeg + ls;
     const double fw = wv[n] - wu[n];
-    if (fw == 0.0) continue;
+    if (fw == 0.0) continue;  // uniform over the block
     const R s = R(scale[n]);
     const bi32x4 rX = make_rsrc(X + n * 2 * M, uint32_t(2 * M * ES));
-    // u (D2 v)^* first, then v^* D2 u: one transformed line live
-    cpx<R> t[NL];
+    // u (D2 v)^* first, then v^* D2 u: one transformed half-line live
+    cpx<R> t[HL];
 #pragma unroll 1
     for (int comp = 1; comp >= 0; --comp) {
 #pragma unroll
-      for (int k = 0; k < NL; ++k) t[k] = s * bload<R>(rX, s0 * ES, int(comp * M + k * ST) * ES);
-      second_derivative<NL>(t, R(kscale2));
+      for (int j = 0; j < HL; ++j) t[j] = s * bload<R>(rX, s0 * ES, int(comp * M + 2 * j * ST) * ES);
+      second_derivative_pair<NL>(t, R(kscale2), odd);
 #pragma unroll
-      for (int k = 0; k < NL; ++k) {
+      for (int j = 0; j < HL; ++j) {
         if (comp == 1) {  // u (D2 v)^*
-          const cpx<R> u = s * bload<R>(rX, s0 * ES, k * ST * ES);
-          br[k] += -0.5 * fw * (double(u.x) * t[k].x + double(u.y) * t[k].y);
-          bi[k] += -0.5 * fw * (double(u.y) * t[k].x - double(u.x) * t[k].y);
+          const cpx<R> u = s * bload<R>(rX, s0 * ES, 2 * j * ST * ES);
+          br[j] += -0.5 * fw * (double(u.x) * t[j].x + double(u.y) * t[j].y);
+          bi[j] += -0.5 * fw * (double(u.y) * t[j].x - double(u.x) * t[j].y);
         } else {  // v^* D2 u
-          const cpx<R> v = s * bload<R>(rX, s0 * ES, int(M + k * ST) * ES);
-          br[k] += -0.5 * fw * (double(v.x) * t[k].x + double(v.y) * t[k].y);
-          bi[k] += -0.5 * fw * (double(v.x) * t[k].y - double(v.y) * t[k].x);
+          const cpx<R> v = s * bload<R>(rX, s0 * ES, int(M + 2 * j * ST) * ES);
+          br[j] += -0.5 * fw * (double(v.x) * t[j].x + double(v.y) * t[j].y);
+          bi[j] += -0.5 * fw * (double(v.x) * t[j].y - double(v.y) * t[j].x);
         }
       }
     }
   }
   double* out = bpart + int64_t(blockIdx.y) * 2 * M + s0;
 #pragma unroll
-  for (int k = 0; k < NL; ++k) {
+  for (int j = 0; j < HL; ++j) {
     if constexpr (AXIS == 0) {
-      out[k * ST] = br[k];
-      out[M + k * ST] = bi[k];
+      out[2 * j * ST] = br[j];
+      out[M + 2 * j * ST] = bi[j];
     } else {
-      out[k * ST] += br[k];
-      out[M + k * ST] += bi[k];
+      out[2 * j * ST] += br[j];
+      out[M + 2 * j * ST] += bi[j];
     }
   }
 }
