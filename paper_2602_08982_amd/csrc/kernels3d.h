@@ -77,11 +77,12 @@ struct SlabCfg {
   static constexpr int SX = sx_target();          // x-slabs per workgroup
   static constexpr int NYZ = NY * NZ;
   static constexpr int SS = SX * NYZ;             // sites per workgroup
-  static constexpr int TASKS = ((2 * SX * NMAX + kWave - 1) / kWave) * kWave;  // line tasks
+  // line phases: a lane pair per line (the lane-pair DFT of fft.h)
+  static constexpr int TASKS = ((4 * SX * NMAX + kWave - 1) / kWave) * kWave;  // line lanes
   static constexpr int TB = TASKS > 256 ? TASKS : 256;  // threads (line phases use the first TASKS)
   static constexpr int P = (SS + TB - 1) / TB;    // sites per thread
   static constexpr int NGX = NX / SX;             // workgroups per state
-  static constexpr int PADZ = NZ + 1;             // LDS row pitch (bank spread)
+  static constexpr int PADZ = NZ + 2;             // LDS row pitch (bank spread of the lane pairs)
   static constexpr int LDS_ELEMS = 2 * SX * NY * PADZ;
   __device__ static int lds_index(int comp, int p) {
     int sx = p / NYZ, rem = p - sx * NYZ, y = rem / NZ, z = rem - y * NZ;
@@ -90,56 +91,79 @@ struct SlabCfg {
 };
 
 // in-LDS line transforms of the slab block -----------------------------------
-// z-line transform of every (comp, sx, y) line, in place: SIGN < 0 is the
-// forward transform leaving k_z digit-reversed along the row, SIGN > 0 the
-// inverse taking that order back to natural z.
+// Each line is held by a lane pair: lane parity b owns the samples 2j + b
+// of the line (the LDS row positions 2j + b), in place.  After the forward
+// transform, row position q = 2p + b holds the frequency of position p of
+// lane b (pair_wavenum_at<N>(q) gives its signed wave number).
+//
+// z-line transform of every (comp, sx, y) line: SIGN < 0 forward (natural z
+// in), SIGN > 0 inverse (back to natural z).
 template <class CFG, int SIGN, typename R>
 __device__ __forceinline__ void lds_zlines(cpx<R>* lds) {
-  constexpr int NZ = CFG::NZv, NY = CFG::NYv;
-  constexpr int tasks = 2 * CFG::SX * NY;
-  const int t = threadIdx.x;
-  if (t < tasks) {
-    cpx<R>* base = lds + t * CFG::PADZ;  // (comp*SX + sx)*NY + y == t
-    cpx<R> a[NZ];
+  constexpr int NZ = CFG::NZv, NY = CFG::NYv, HZ = NZ / 2;
+  constexpr int lines = 2 * CFG::SX * NY;
+  const int t = threadIdx.x >> 1;
+  const bool odd = threadIdx.x & 1;
+  if (t < lines) {  // both lanes of a pair
+    cpx<R>* base = lds + t * CFG::PADZ + (odd ? 1 : 0);  // (comp*SX + sx)*NY + y == t
+    cpx<R> a[HZ];
 #pragma unroll
-    for (int j = 0; j < NZ; ++j) a[j] = base[j];
+    for (int j = 0; j < HZ; ++j) a[j] = base[2 * j];
     if constexpr (SIGN < 0) {
-      fwd<NZ>(a);  // natural z in, digit-reversed kz out
+      fwd_pair<NZ>(a, odd);
     } else {
-      inv<NZ>(a);  // digit-reversed kz in, natural z out
+      inv_pair<NZ>(a, odd);
     }
 #pragma unroll
-    for (int j = 0; j < NZ; ++j) base[j] = a[j];
+    for (int j = 0; j < HZ; ++j) base[2 * j] = a[j];
   }
 }
 
+// the y-line of a lane pair after the z-lines' forward transform: its
+// component, slab plane and k_z row position
+template <class CFG>
+struct YLine {
+  int comp, sx, kz;
+  bool odd, live;
+  __device__ YLine() {
+    constexpr int NZ = CFG::NZv;
+    const int t = threadIdx.x >> 1;
+    odd = threadIdx.x & 1;
+    live = t < 2 * CFG::SX * NZ;  // both lanes of a pair
+    comp = t / (CFG::SX * NZ);
+    const int rem = t - comp * CFG::SX * NZ;
+    sx = rem / NZ;
+    kz = rem - sx * NZ;
+  }
+  template <typename R>
+  __device__ cpx<R>* base(cpx<R>* lds) const {
+    return lds + ((comp * CFG::SX + sx) * CFG::NYv + (odd ? 1 : 0)) * CFG::PADZ + kz;
+  }
+};
+
 // (y,z) kinetic part of <H> from a slab whose z-lines were forward
-// transformed in place: each y-line task transforms its column forward and
+// transformed in place: each y-line pair transforms its column forward and
 // returns (+1/2 for u, -1/2 for v) sum_k (ky^2 + kz^2) |phi_k|^2 dV / (NY NZ)
-// (Parseval; zero for threads without a task).
+// over its half of the column (Parseval; zero for threads without a line).
 template <class CFG, typename R>
 __device__ __forceinline__ double lds_yz_kinetic(const cpx<R>* lds, double cy2, double cz2, double dV) {
-  constexpr int NY = CFG::NYv, NZ = CFG::NZv;
-  constexpr int tasks = 2 * CFG::SX * NZ;
-  const int tid = threadIdx.x;
-  if (tid >= tasks) return 0.0;
-  const int comp = tid / (CFG::SX * NZ);
-  const int rem = tid - comp * CFG::SX * NZ;
-  const int sx = rem / NZ, kz = rem - sx * NZ;
-  const cpx<R>* base = lds + ((comp * CFG::SX + sx) * NY) * CFG::PADZ + kz;
-  cpx<R> a[NY];
+  constexpr int NY = CFG::NYv, NZ = CFG::NZv, HY = NY / 2;
+  const YLine<CFG> yl;
+  if (!yl.live) return 0.0;
+  const cpx<R>* base = yl.base(const_cast<cpx<R>*>(lds));
+  cpx<R> a[HY];
 #pragma unroll
-  for (int j = 0; j < NY; ++j) a[j] = base[j * CFG::PADZ];
-  fwd<NY>(a);
-  const int mz = wavenum_at<NZ>(kz);  // kz: digit-reversed position
+  for (int j = 0; j < HY; ++j) a[j] = base[2 * j * CFG::PADZ];
+  fwd_pair<NY>(a, yl.odd);
+  const int mz = pair_wavenum_at<NZ>(yl.kz);
   const double ez = cz2 * double(mz * mz);
   double acc = 0.0;
-  sfor<0, NY>::run([&](auto jc) {
+  sfor<0, HY>::run([&](auto jc) {
     constexpr int j = decltype(jc)::value;
-    constexpr int my = wavenum_at<NY>(j);
+    const int my = pair_wavenum<NY, j>(yl.odd);
     acc += (cy2 * double(my * my) + ez) * norm2(a[j]);
   });
-  return (comp == 0 ? 0.5 : -0.5) * acc * dV / double(CFG::NYZ);
+  return (yl.comp == 0 ? 0.5 : -0.5) * acc * dV / double(CFG::NYZ);
 }
 
 // ---------------------------------------------------------------------------
@@ -574,27 +598,25 @@ __global__ __launch_bounds__((SlabCfg<NX, NY, NZ>::TB)) void k_lap2(Lap2Args<R> 
   lds_zlines<CFG, -1>(lds);
   __syncthreads();
   {  // y-lines: forward, multiply by -(ky^2 + kz^2)/(NY NZ), inverse
-    constexpr int tasks = 2 * CFG::SX * NZ;
-    if (tid < tasks) {
-      const int comp = tid / (CFG::SX * NZ);
-      const int rem = tid - comp * CFG::SX * NZ;
-      const int sx = rem / NZ, kz = rem - sx * NZ;
-      cpx<R>* lb = lds + ((comp * CFG::SX + sx) * NY) * CFG::PADZ + kz;
-      cpx<R> a[NY];
+    constexpr int HY = NY / 2;
+    const YLine<CFG> yl;
+    if (yl.live) {
+      cpx<R>* lb = yl.base(lds);
+      cpx<R> a[HY];
 #pragma unroll
-      for (int j = 0; j < NY; ++j) a[j] = lb[j * CFG::PADZ];
-      fwd<NY>(a);
-      const int mz = wavenum_at<NZ>(kz);  // kz: digit-reversed position
+      for (int j = 0; j < HY; ++j) a[j] = lb[2 * j * CFG::PADZ];
+      fwd_pair<NY>(a, yl.odd);
+      const int mz = pair_wavenum_at<NZ>(yl.kz);
       const R ez = R(A.cz2 * double(mz * mz));
       const R nrm = R(-1.0 / double(NY * NZ));
-      sfor<0, NY>::run([&](auto jc) {
+      sfor<0, HY>::run([&](auto jc) {
         constexpr int j = decltype(jc)::value;
-        constexpr int my = wavenum_at<NY>(j);
+        const int my = pair_wavenum<NY, j>(yl.odd);
         a[j] = (nrm * (R(A.cy2) * R(my * my) + ez)) * a[j];
       });
-      inv<NY>(a);
+      inv_pair<NY>(a, yl.odd);
 #pragma unroll
-      for (int j = 0; j < NY; ++j) lb[j * CFG::PADZ] = a[j];
+      for (int j = 0; j < HY; ++j) lb[2 * j * CFG::PADZ] = a[j];
     }
   }
   __syncthreads();
