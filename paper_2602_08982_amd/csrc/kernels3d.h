@@ -54,11 +54,12 @@ __device__ __forceinline__ double norm2(cpx<R> a) {
 // compile-time tiling of the slab kernels
 // Tiling knobs (compile-time): lines per slab workgroup target and the
 // largest sites-per-thread count for which the fused pass keeps its sites
-// of phi in registers instead of re-reading them.  Defaults: 64 lines, no
-// stash (one x-slab per workgroup with the stash gains 3% on the full pass
-// but loses 14% on the corrector at 32^3 FP64, 2% per step overall).
+// of phi in registers instead of re-reading them.  Defaults: 32 lines (one
+// x-slab per workgroup at 32^3: 35 KB of LDS and 104 VGPRs with the
+// lane-pair lines, four workgroups per CU; two x-slabs took 2% more per
+// 32^3 FP64 step), no stash (the stash gains nothing at 32^3 FP64).
 #ifndef TDSLDA_SLAB_LINES
-#define TDSLDA_SLAB_LINES 64
+#define TDSLDA_SLAB_LINES 32
 #endif
 #ifndef TDSLDA_STASH_MAXP
 #define TDSLDA_STASH_MAXP 0
