@@ -21,7 +21,8 @@ import os
 import re
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = ["csrc/kernels3d.h", "csrc/engine3d.h", "csrc/q2d.hip", "csrc/bufio.h", "csrc/fft.h", "build.py"]
+# the sources of the 3D kernels that the recorded counters cover
+KERNEL_SOURCES = ["csrc/kernels3d.h", "csrc/kernels3d_gen.h", "csrc/engine3d.h", "csrc/bufio.h", "csrc/fft.h", "build.py"]
 COPY_BYTES = 1 << 32
 
 LAP2_MODES = {0: "lap2_h", 1: "lap2_f", 2: "lap2_corr", 3: "lap2_full", 4: "lap2_taylor"}
@@ -68,6 +69,8 @@ def role(name):
                    ("q_densj<", "q1dgen_dens"), ("q_reduce_gen<", "q1dgen_reduce_pot"),
                    ("q_jz<", "q1dgen_dens"), ("q_taujs<", "q1das_dens"), ("q_reduce_aslda<", "q1das_reduce_pot"),
                    ("q2_kz_tau<", "q2d_grad"), ("k_jline<", "gen3d_jline"), ("k_reduce_gen3d<", "gen3d_reduce_pot"),
+                   ("k_taujline<", "as3d_taujline"), ("k_reduce_aslda3d<", "as3d_reduce_pot"),
+                   ("k_bpline<", "fric3d_bpline"),
                    ("k_grad_axis<", "grad"), ("k_grad_reduce", "grad_reduce"),
                    ("k_stream_copy", "stream_copy"), ("k_stream_read", "stream_read")):
         if pat in name:
