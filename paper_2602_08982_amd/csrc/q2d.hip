@@ -28,11 +28,12 @@ template <int NX, int NY>
 struct Q2Cfg {
   static constexpr int M = NX * NY;
   static constexpr int NMAX = NX > NY ? NX : NY;
-  static constexpr int TASKS = ((2 * NMAX + kWave - 1) / kWave) * kWave;  // line tasks (u and v)
+  // line phases: a lane pair per row / column (the lane-pair DFT of fft.h)
+  static constexpr int TASKS = ((4 * NMAX + kWave - 1) / kWave) * kWave;  // line lanes (u and v)
   static constexpr int MW = ((M + kWave - 1) / kWave) * kWave;
   static constexpr int TB = TASKS > (MW < 256 ? MW : 256) ? TASKS : (MW < 256 ? MW : 256);
   static constexpr int P = (M + TB - 1) / TB;  // sites per thread
-  static constexpr int PAD = NY + 1;           // LDS row pitch (bank spread)
+  static constexpr int PAD = NY + 2;           // LDS row pitch (bank spread of the lane pairs)
   static constexpr int LDS_ELEMS = 2 * NX * PAD;
   __device__ static int idx(int comp, int p) {
     const int x = p / NY, y = p - x * NY;
@@ -100,54 +101,60 @@ __global__ __launch_bounds__((Q2Cfg<NX, NY>::TB)) void q2_lap(Lap2Args<R> A, con
     }
   }
   __syncthreads();
-  if (tid < 2 * NX) {  // y rows forward
-    cpx<R>* base = lds + tid * PAD;
-    cpx<R> a[NY];
+  // rows and columns are held by lane pairs: lane parity b owns the samples
+  // 2j + b of its line; after the forward transforms, row (column) position
+  // q holds the wave number pair_wavenum_at(q)
+  const int lt = tid >> 1;
+  const bool odd = tid & 1;
+  constexpr int HX = NX / 2, HY = NY / 2;
+  if (lt < 2 * NX) {  // y rows forward
+    cpx<R>* base = lds + lt * PAD + (odd ? 1 : 0);
+    cpx<R> a[HY];
 #pragma unroll
-    for (int j = 0; j < NY; ++j) a[j] = base[j];
-    fwd<NY>(a);
+    for (int j = 0; j < HY; ++j) a[j] = base[2 * j];
+    fwd_pair<NY>(a, odd);
 #pragma unroll
-    for (int j = 0; j < NY; ++j) base[j] = a[j];
+    for (int j = 0; j < HY; ++j) base[2 * j] = a[j];
   }
   __syncthreads();
   double kin = 0.0;
-  if (tid < 2 * NY) {  // x columns: forward, (Parseval), times -k^2 / M, back
-    const int comp = tid / NY, col = tid - comp * NY;
-    cpx<R>* base = lds + comp * NX * PAD + col;
-    cpx<R> a[NX];
+  if (lt < 2 * NY) {  // x columns: forward, (Parseval), times -k^2 / M, back
+    const int comp = lt / NY, col = lt - comp * NY;
+    cpx<R>* base = lds + (comp * NX + (odd ? 1 : 0)) * PAD + col;
+    cpx<R> a[HX];
 #pragma unroll
-    for (int j = 0; j < NX; ++j) a[j] = base[j * PAD];
-    fwd<NX>(a);
-    const int my = wavenum_at<NY>(col);  // col: digit-reversed position
+    for (int j = 0; j < HX; ++j) a[j] = base[2 * j * PAD];
+    fwd_pair<NX>(a, odd);
+    const int my = pair_wavenum_at<NY>(col);
     const double ey = cy2 * double(my * my);
     // k^2 = cx2 mx^2 + ey: the Parseval sum as two sums with integer
     // weights, the multiplier -k^2 / M formed per mode at its use
     const R fx = R(-cx2 / double(M)), fy = R(-ey / double(M));
     double sx = 0.0, s0 = 0.0;
-    sfor<0, NX>::run([&](auto jc) {
+    sfor<0, HX>::run([&](auto jc) {
       constexpr int j = decltype(jc)::value;
-      constexpr int mx = wavenum_at<NX>(j);
+      const int mx = pair_wavenum<NX, j>(odd);
       if constexpr (OWN_H) {
         const double q = norm2(a[j]);
         s0 += q;
-        if constexpr (mx != 0) sx += double(mx * mx) * q;
+        sx += double(mx * mx) * q;
       }
       a[j] = (fx * R(mx * mx) + fy) * a[j];
     });
     if constexpr (OWN_H) kin = (comp == 0 ? 0.5 : -0.5) * (cx2 * sx + ey * s0) / double(M);
-    inv<NX>(a);
+    inv_pair<NX>(a, odd);
 #pragma unroll
-    for (int j = 0; j < NX; ++j) base[j * PAD] = a[j];
+    for (int j = 0; j < HX; ++j) base[2 * j * PAD] = a[j];
   }
   __syncthreads();
-  if (tid < 2 * NX) {  // y rows back
-    cpx<R>* base = lds + tid * PAD;
-    cpx<R> a[NY];
+  if (lt < 2 * NX) {  // y rows back
+    cpx<R>* base = lds + lt * PAD + (odd ? 1 : 0);
+    cpx<R> a[HY];
 #pragma unroll
-    for (int j = 0; j < NY; ++j) a[j] = base[j];
-    inv<NY>(a);
+    for (int j = 0; j < HY; ++j) a[j] = base[2 * j];
+    inv_pair<NY>(a, odd);
 #pragma unroll
-    for (int j = 0; j < NY; ++j) base[j] = a[j];
+    for (int j = 0; j < HY; ++j) base[2 * j] = a[j];
   }
   // the block sum synchronises before its first read of the shared slots,
   // which also orders the row pass before the pointwise reads below
