@@ -194,6 +194,53 @@ def read_traffic(md_path, prec, nx, kernel):
     return val if src == sources_digest() else None
 
 
+SQ_ROLES = ("lap2_corr", "lap2_full", "lap1", "dens", "stream_copy")
+
+
+def cmd_sq(args):
+    """Per-kernel SQ counters of one --pmc pass (waves, wave-cycles, VALU and
+    LDS activity, LDS bank conflicts, GRBM_GUI_ACTIVE), summed over the
+    dispatches of each role and normalised by the dispatches' own durations.
+    The wave-cycle and active-instruction counters count quad-cycles (x4);
+    GRBM_GUI_ACTIVE sums the 8 XCDs."""
+    rows = list(csv.DictReader(open(args.csv)))
+    agg, dur, disp, name = {}, {}, {}, {}
+    seen = set()
+    for r in rows:
+        k = key(r["Kernel_Name"])
+        if k is None or k.split(":")[2] not in SQ_ROLES:
+            continue
+        a = agg.setdefault(k, {})
+        a[r["Counter_Name"]] = a.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        if (k, r["Dispatch_Id"]) not in seen:
+            seen.add((k, r["Dispatch_Id"]))
+            dur[k] = dur.get(k, 0) + int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+            disp[k] = disp.get(k, 0) + 1
+            name[k] = r["Kernel_Name"]
+    out = [f"# {args.title}", "", "Commands (from the repository root, on one MI355X):", ""]
+    out += ["    " + c for c in args.command]
+    out += ["", "Per role: the counters summed over its dispatches; cycles = the dispatches' durations x the "
+            "GRBM_GUI_ACTIVE clock (GRBM_GUI_ACTIVE / 8 XCDs / duration). waves/CU = 4 SQ_WAVE_CYCLES / (256 CUs "
+            "cycles); VALU busy = 4 SQ_ACTIVE_INST_VALU / (1024 SIMDs cycles); LDS busy = 4 SQ_ACTIVE_INST_LDS / "
+            "(256 CUs cycles); bank-conflict rate = SQ_LDS_BANK_CONFLICT / SQ_ACTIVE_INST_LDS.", "",
+            "| kernel | role | dispatches | avg ms | clock GHz | waves/CU | VALU busy | VALU instr/wave | LDS busy | "
+            "LDS bank-conflict rate |", "|---|---|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    for k in sorted(agg, key=lambda k: (k.split(":")[2], k)):
+        a, n, t = agg[k], disp[k], dur[k] * 1e-9
+        clk = a.get("GRBM_GUI_ACTIVE", 0.0) / 8 / t  # cycles per second
+        cyc = clk * t
+        wav = 4 * a.get("SQ_WAVE_CYCLES", 0.0) / (256 * cyc)
+        valu = 4 * a.get("SQ_ACTIVE_INST_VALU", 0.0) / (1024 * cyc)
+        lds = 4 * a.get("SQ_ACTIVE_INST_LDS", 0.0) / (256 * cyc)
+        ipw = a.get("SQ_INSTS_VALU", 0.0) / max(1.0, a.get("SQ_WAVES", 0.0))
+        bc = a.get("SQ_LDS_BANK_CONFLICT", 0.0) / a["SQ_ACTIVE_INST_LDS"] if a.get("SQ_ACTIVE_INST_LDS") else 0.0
+        out.append(f"| `{short(name[k])}` | {k.split(':')[2]} ({k.split(':')[0]}) | {n} | {1e3 * t / n:.3f} | "
+                   f"{clk / 1e9:.2f} | {wav:.1f} | {valu:.2f} | {ipw:.0f} | {lds:.3f} | {bc:.3f} |")
+    if args.note:
+        out += ["", args.note]
+    open(args.out, "w").write("\n".join(out) + "\n")
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -212,8 +259,14 @@ def main():
     c.add_argument("--command", action="append", required=True)
     c.add_argument("--title", default="HBM traffic counters")
     c.add_argument("--note", default="")
+    q = sub.add_parser("sq")
+    q.add_argument("csv")
+    q.add_argument("out")
+    q.add_argument("--command", action="append", required=True)
+    q.add_argument("--title", default="SQ counters")
+    q.add_argument("--note", default="")
     a = ap.parse_args()
-    (cmd_stats if a.cmd == "stats" else cmd_counters)(a)
+    {"stats": cmd_stats, "counters": cmd_counters, "sq": cmd_sq}[a.cmd](a)
 
 
 if __name__ == "__main__":

@@ -55,3 +55,29 @@ def test_library_copy_calibrates(tmp_path):
     (the largest k_stream_copy reading)."""
     agg = {"tdslda::k_stream_copy(cp_v4i const*, cp_v4i*, long)": [2 ** 31 / 1024 * 1024.0, 100.0]}
     assert abs(P._copy_factor(agg) - 2.0) < 1e-12
+
+
+def test_sq_summary_normalisation(tmp_path):
+    """One dispatch of 1 ms at a 2 GHz GRBM clock (8 XCDs): the wave-cycle,
+    VALU and LDS counters (quad-cycles) become waves per CU and busy
+    fractions, the conflict counter a rate per LDS-active cycle."""
+    lap2 = "void tdslda::k_lap2<double, 32, 32, 32, 2, 4, 5>(tdslda::Lap2Args<double>)"
+    cyc = 2e9 * 1e-3
+    vals = {"GRBM_GUI_ACTIVE": 8 * cyc, "SQ_WAVE_CYCLES": 256 * cyc * 12 / 4, "SQ_ACTIVE_INST_VALU": 1024 * cyc * 0.5 / 4,
+            "SQ_ACTIVE_INST_LDS": 256 * cyc * 0.25 / 4, "SQ_LDS_BANK_CONFLICT": 256 * cyc * 0.25 / 4 * 0.3,
+            "SQ_WAVES": 1000.0, "SQ_INSTS_VALU": 1.5e6}
+    p, out = tmp_path / "sq.csv", tmp_path / "sq.md"
+    with open(p, "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value", "Start_Timestamp", "End_Timestamp"])
+        for k, v in vals.items():
+            w.writerow([1, lap2, k, v, 0, 1000000])
+
+    class A:
+        pass
+
+    a = A()
+    a.csv, a.out, a.command, a.title, a.note = str(p), str(out), ["cmd"], "t", ""
+    P.cmd_sq(a)
+    row = [ln for ln in open(out) if "lap2_corr" in ln][0].split("|")
+    assert [c.strip() for c in row[3:11]] == ["1", "1.000", "2.00", "12.0", "0.50", "1500", "0.250", "0.300"]
