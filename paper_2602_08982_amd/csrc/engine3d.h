@@ -65,27 +65,29 @@ struct Engine3D final : Engine {
   // passes; with hp the <H>_n partials go to the h slots after the NGX raw
   // slots (which the last pass clears)
   void gen_apply(Ctx& c, const void* X, const double* scale, double* hp, void* out, int64_t nst) {
-    require(int(cdiv(NX * NY, OTB / 2)) <= ncb(), TDSLDA_EINVAL, "internal: too few h slots for the z-line pass");
+    require(int(cdiv(NYZ, OTB / 2)) <= ncb(), TDSLDA_EINVAL, "internal: too few h slots for the x-line pass");
     const int64_t fcs = c.aslda ? M : 0;  // ASLDA: fields per spin
     const cpx<R>* x = (const cpx<R>*)X;
     cpx<R>* T = (cpx<R>*)c.T;
     const R *al = (const R*)c.hAl, *la = (const R*)c.hLa, *hA = (const R*)c.hA;
     const cpx<R>* hD = (const cpx<R>*)c.hD;
     constexpr int LPB = OTB / 2;  // lines per block
+    // z first (contiguous lines: its T write is its only pass over T), then
+    // y, then x with the local terms and <H>_n (coalesced lines)
     c.launch(KC_LAP1, [&] {
-      hipLaunchKernelGGL((k_opline<R, NX, NY, NZ, 0, OTB, false>), dim3(cdiv(NYZ, LPB), nst), dim3(OTB), 0, c.stream,
-                         x, scale, T, nullptr, al, la, (const R*)c.hAx, hA, hD, nullptr, c.h_stride, CFG::NGX,
-                         ncb(), 2 * kPi / (NX * c.lat.dx), c.dV, fcs);
+      hipLaunchKernelGGL((k_opline<R, NX, NY, NZ, 2, OTB, true, false>), dim3(cdiv(NX * NY, LPB), nst), dim3(OTB), 0,
+                         c.stream, x, scale, T, nullptr, al, la, (const R*)c.hAz, hA, hD, nullptr, c.h_stride,
+                         CFG::NGX, ncb(), 2 * kPi / (NZ * c.lat.dz), c.dV, fcs);
     });
     c.launch(KC_LAP1, [&] {
-      hipLaunchKernelGGL((k_opline<R, NX, NY, NZ, 1, OTB, false>), dim3(cdiv(NX * NZ, LPB), nst), dim3(OTB), 0,
+      hipLaunchKernelGGL((k_opline<R, NX, NY, NZ, 1, OTB, false, false>), dim3(cdiv(NX * NZ, LPB), nst), dim3(OTB), 0,
                          c.stream, x, scale, T, nullptr, al, la, (const R*)c.hAy, hA, hD, nullptr, c.h_stride,
                          CFG::NGX, ncb(), 2 * kPi / (NY * c.lat.dy), c.dV, fcs);
     });
     c.launch(KC_LAP1, [&] {
-      hipLaunchKernelGGL((k_opline<R, NX, NY, NZ, 2, OTB, true>), dim3(cdiv(NX * NY, LPB), nst), dim3(OTB), 0,
-                         c.stream, x, scale, T, (cpx<R>*)out, al, la, (const R*)c.hAz, hA, hD, hp, c.h_stride,
-                         CFG::NGX, ncb(), 2 * kPi / (NZ * c.lat.dz), c.dV, fcs);
+      hipLaunchKernelGGL((k_opline<R, NX, NY, NZ, 0, OTB, false, true>), dim3(cdiv(NYZ, LPB), nst), dim3(OTB), 0,
+                         c.stream, x, scale, T, (cpx<R>*)out, al, la, (const R*)c.hAx, hA, hD, hp, c.h_stride,
+                         CFG::NGX, ncb(), 2 * kPi / (NX * c.lat.dx), c.dV, fcs);
     });
   }
   // quantum friction: j and B' by line passes over state groups, div j by

@@ -243,8 +243,8 @@ __device__ __forceinline__ cpx<R> minus_half_i(cpx<R> c) {
   return cpx<R>{R(0.5) * c.y, R(-0.5) * c.x};
 }
 
-// The AXIS part of K and C of every state, row-signed, into T (AXIS 0
-// writes, the others add); LAST also adds the local terms,
+// The AXIS part of K and C of every state, row-signed, into T (the FIRST
+// pass writes, the others add); LAST also adds the local terms,
 //   u: + (1/4 lap alpha + hfield) u + Delta v,  v: - (1/4 lap alpha + hfield) v + Delta^* u,
 // so that the destination (out when given, else T) holds H phi, and when
 // h_part is given writes the block's partial of <H>_n = Re int phi^* H phi
@@ -253,7 +253,7 @@ __device__ __forceinline__ cpx<R> minus_half_i(cpx<R> c) {
 // Each line is held by a lane pair (the lane-pair DFT of fft.h: lane parity
 // b owns the samples 2j + b), which halves the registers of a line.
 //   grid = (ceil(NLINES / (TBG / 2)), nstates), block = TBG
-template <typename R, int NX, int NY, int NZ, int AXIS, int TBG, bool LAST>
+template <typename R, int NX, int NY, int NZ, int AXIS, int TBG, bool FIRST, bool LAST>
 __global__ __launch_bounds__(TBG) void k_opline(const cpx<R>* __restrict__ X, const double* __restrict__ scale,
                                                 cpx<R>* __restrict__ T, cpx<R>* __restrict__ out,
                                                 const R* __restrict__ hAl, const R* __restrict__ hLa,
@@ -354,14 +354,18 @@ __global__ __launch_bounds__(TBG) void k_opline(const cpx<R>* __restrict__ X, co
       for (int j = 0; j < HL; ++j) {
         cpx<R> r = acc[j][tx] + minus_half_i(t[j]);
         const int o = (cb + 2 * j * ST) * ES;
-        if constexpr (AXIS > 0) r = r + bload<R>(rT, vo, o);
+        if constexpr (!FIRST) r = r + bload<R>(rT, vo, o);
         if constexpr (LAST) {
-          const int site = s0 + 2 * j * ST;
+          // per-site fields through buffer resources: the sample's row as a
+          // scalar offset, no per-sample address registers
+          const bi32x4 rD = make_rsrc(hD, uint32_t(M * ES));
+          const bi32x4 rLa = make_rsrc(hLa, uint32_t((M + fcs) * RS)), rHA = make_rsrc(hA, uint32_t((M + fcs) * RS));
+          const int fs = int(fo + 2 * j * ST) * RS;
           const cpx<R> x = s * bload<R>(rX, vo, o);
           const cpx<R> y = s * bload<R>(rX, vo, (int((1 - comp) * M) + 2 * j * ST) * ES);
-          const cpx<R> D = hD[site];
+          const cpx<R> D = bload<R>(rD, vo, 2 * j * ST * ES);
           const cpx<R> Dc = comp ? conj(D) : D;
-          r = r + (sg * (R(0.25) * hLa[fo + site] + hA[fo + site])) * x + Dc * y;
+          r = r + (sg * (R(0.25) * bload_real<R>(rLa, va, fs) + bload_real<R>(rHA, va, fs))) * x + Dc * y;
           hloc += double(x.x) * double(r.x) + double(x.y) * double(r.y);
         }
         bstore<R>(r, rO, vo, o);
