@@ -312,6 +312,27 @@ __global__ __launch_bounds__(TBG) void k_opline(const cpx<R>* __restrict__ X, co
       const bi32x4 rAl = make_rsrc(hAl + fo, uint32_t(M * RS)), rAd = make_rsrc(hAd + fo, uint32_t(M * RS));
       cpx<R> t[HL];
       phase_fence();
+      // D2(alpha x) and D1(A_d x) share one inverse transform: the first
+      // spectrum waits in the running-sum slots (each lane's own positions)
+#pragma unroll
+      for (int j = 0; j < HL; ++j)
+        t[j] = bload_real<R>(rAl, va, 2 * j * ST * RS) * (s * bload<R>(rX, vo, (cb + 2 * j * ST) * ES));
+      fwd_pair<NL>(t, odd);
+      d2(t);
+#pragma unroll
+      for (int j = 0; j < HL; ++j) acc[j][tx] = (sg * R(-0.25)) * t[j];
+      phase_fence();
+#pragma unroll
+      for (int j = 0; j < HL; ++j)
+        t[j] = bload_real<R>(rAd, va, 2 * j * ST * RS) * (s * bload<R>(rX, vo, (cb + 2 * j * ST) * ES));
+      fwd_pair<NL>(t, odd);
+      d1(t);
+#pragma unroll
+      for (int j = 0; j < HL; ++j) t[j] = acc[j][tx] + minus_half_i(t[j]);
+      inv_pair<NL>(t, odd);
+#pragma unroll
+      for (int j = 0; j < HL; ++j) acc[j][tx] = t[j];
+      phase_fence();
       // alpha D2 x
 #pragma unroll
       for (int j = 0; j < HL; ++j) t[j] = s * bload<R>(rX, vo, (cb + 2 * j * ST) * ES);
@@ -320,7 +341,7 @@ __global__ __launch_bounds__(TBG) void k_opline(const cpx<R>* __restrict__ X, co
       inv_pair<NL>(t, odd);
 #pragma unroll
       for (int j = 0; j < HL; ++j)
-        acc[j][tx] = (sg * R(-0.25) * bload_real<R>(rAl, va, 2 * j * ST * RS)) * t[j];
+        acc[j][tx] = acc[j][tx] + (sg * R(-0.25) * bload_real<R>(rAl, va, 2 * j * ST * RS)) * t[j];
       phase_fence();
       // A_d D1 x
 #pragma unroll
@@ -328,31 +349,10 @@ __global__ __launch_bounds__(TBG) void k_opline(const cpx<R>* __restrict__ X, co
       fwd_pair<NL>(t, odd);
       d1(t);
       inv_pair<NL>(t, odd);
-#pragma unroll
-      for (int j = 0; j < HL; ++j)
-        acc[j][tx] = acc[j][tx] + minus_half_i(bload_real<R>(rAd, va, 2 * j * ST * RS) * t[j]);
-      phase_fence();
-      // D2(alpha x)
-#pragma unroll
-      for (int j = 0; j < HL; ++j)
-        t[j] = bload_real<R>(rAl, va, 2 * j * ST * RS) * (s * bload<R>(rX, vo, (cb + 2 * j * ST) * ES));
-      fwd_pair<NL>(t, odd);
-      d2(t);
-      inv_pair<NL>(t, odd);
-#pragma unroll
-      for (int j = 0; j < HL; ++j) acc[j][tx] = acc[j][tx] + (sg * R(-0.25)) * t[j];
-      phase_fence();
-      // D1(A_d x)
-#pragma unroll
-      for (int j = 0; j < HL; ++j)
-        t[j] = bload_real<R>(rAd, va, 2 * j * ST * RS) * (s * bload<R>(rX, vo, (cb + 2 * j * ST) * ES));
-      fwd_pair<NL>(t, odd);
-      d1(t);
-      inv_pair<NL>(t, odd);
       phase_fence();
 #pragma unroll
       for (int j = 0; j < HL; ++j) {
-        cpx<R> r = acc[j][tx] + minus_half_i(t[j]);
+        cpx<R> r = acc[j][tx] + minus_half_i(bload_real<R>(rAd, va, 2 * j * ST * RS) * t[j]);
         const int o = (cb + 2 * j * ST) * ES;
         if constexpr (!FIRST) r = r + bload<R>(rT, vo, o);
         if constexpr (LAST) {
